@@ -1,0 +1,227 @@
+"""Pins for the EMD oracle (CPU only).
+
+Independent references: the 1-D closed form int |F0 - F1|, the translation
+identity EMD = |v| (section 4.2), linear programs and a min-cost network flow
+for the anisotropic (l1) grid norm, a polygonal-norm LP bracket and a
+constrained dual solve for the isotropic norm, and the structural properties
+of the Leray projection.
+"""
+import json
+import os
+
+import networkx as nx
+import numpy as np
+import pytest
+from scipy.optimize import NonlinearConstraint, linprog, minimize
+
+import synth
+from oracle import emd, grid
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def beckmann_lp(rho0, rho1, h, directions=None):
+    """min h^2 sum |m|  s.t.  div m = rho1 - rho0 (far-face fluxes zero).
+
+    directions None: anisotropic |mx| + |my| via m = m+ - m-.
+    directions K: isotropic norm replaced by max_k (cos t_k mx + sin t_k my),
+    a polygonal lower bound within a factor cos(pi/K) of the 2-norm."""
+    ny, nxx = rho0.shape
+    f = (rho1 - rho0).ravel()
+    f = f - f.mean()
+    fx = [(i, j) for i in range(ny) for j in range(nxx - 1)]
+    fy = [(i, j) for i in range(ny - 1) for j in range(nxx)]
+    nf = len(fx) + len(fy)
+    Aeq = np.zeros((ny * nxx, nf))
+    for e, (i, j) in enumerate(fx):  # flux from (i,j) to (i,j+1)
+        Aeq[i * nxx + j, e] += 1.0 / h
+        Aeq[i * nxx + j + 1, e] -= 1.0 / h
+    for e, (i, j) in enumerate(fy):
+        Aeq[i * nxx + j, len(fx) + e] += 1.0 / h
+        Aeq[(i + 1) * nxx + j, len(fx) + e] -= 1.0 / h
+    if directions is None:
+        c = h * h * np.ones(2 * nf)
+        res = linprog(c, A_eq=np.hstack([Aeq, -Aeq]), b_eq=f, bounds=(0, None), method="highs")
+        return res.fun
+    K = directions
+    ncell = ny * nxx
+    # variables: m (nf, free), t (ncell, free); minimise h^2 sum t
+    c = np.concatenate([np.zeros(nf), h * h * np.ones(ncell)])
+    rows = []
+    th = 2 * np.pi * np.arange(K) / K
+    xidx = {fj: e for e, fj in enumerate(fx)}
+    yidx = {fj: len(fx) + e for e, fj in enumerate(fy)}
+    for i in range(ny):
+        for j in range(nxx):
+            for k in range(K):
+                r = np.zeros(nf + ncell)
+                if (i, j) in xidx:
+                    r[xidx[(i, j)]] = np.cos(th[k])
+                if (i, j) in yidx:
+                    r[yidx[(i, j)]] = np.sin(th[k])
+                r[nf + i * nxx + j] = -1.0
+                rows.append(r)
+    res = linprog(c, A_ub=np.array(rows), b_ub=np.zeros(len(rows)),
+                  A_eq=np.hstack([Aeq, np.zeros((ncell, ncell))]), b_eq=f,
+                  bounds=(None, None), method="highs")
+    return res.fun
+
+
+def grid_min_cost_flow(c0, c1, h):
+    """Anisotropic EMD of integer masses on the 4-neighbour grid graph (network simplex)."""
+    n = c0.shape[0]
+    G = nx.DiGraph()
+    for i in range(n):
+        for j in range(n):
+            G.add_node((i, j), demand=int(c1[i, j] - c0[i, j]))
+            for di, dj in ((0, 1), (1, 0), (0, -1), (-1, 0)):
+                a, b = i + di, j + dj
+                if 0 <= a < n and 0 <= b < n:
+                    G.add_edge((i, j), (a, b), weight=1)
+    return h * nx.min_cost_flow_cost(G) / float(c0.sum())
+
+
+def manhattan_transport_lp(c0, c1, h):
+    n = c0.shape[0]
+    a = (c0 / c0.sum()).ravel()
+    b = (c1 / c1.sum()).ravel()
+    ii, jj = np.divmod(np.arange(n * n), n)
+    D = h * (np.abs(ii[:, None] - ii[None, :]) + np.abs(jj[:, None] - jj[None, :]))
+    N = n * n
+    Aeq = np.zeros((2 * N, N * N))
+    for k in range(N):
+        Aeq[k, k * N:(k + 1) * N] = 1.0
+        Aeq[N + k, k::N] = 1.0
+    res = linprog(D.ravel(), A_eq=Aeq, b_eq=np.concatenate([a, b]), bounds=(0, None), method="highs")
+    return res.fun
+
+
+def test_anisotropic_matches_lp_flow_and_transport():
+    n, h = 6, 1.0 / 6
+    rho0, rho1, c0, c1 = synth.integer_mass_pair(n, 5)
+    v_lp = beckmann_lp(rho0, rho1, h)
+    v_mcf = grid_min_cost_flow(c0, c1, h)
+    v_ot = manhattan_transport_lp(c0, c1, h)
+    assert abs(v_lp - v_mcf) < 1e-12 and abs(v_lp - v_ot) < 1e-9
+    r = emd.solve(rho0, rho1, h, tau=0.3, tol=1e-10, max_iter=100000, check_every=10, norm=grid.ANISO)
+    assert r.converged
+    assert r.dual <= v_lp * (1 + 1e-12) <= r.primal * (1 + 2e-12)
+    assert abs(r.primal - v_lp) / v_lp < 1e-9
+
+
+def test_isotropic_bracketed_by_polygonal_lp():
+    n, h, K = 6, 1.0 / 6, 256
+    rho0, rho1, _, _ = synth.integer_mass_pair(n, 5)
+    v_k = beckmann_lp(rho0, rho1, h, directions=K)
+    lo, hi = v_k, v_k / np.cos(np.pi / K)
+    r = emd.solve(rho0, rho1, h, tau=0.3, tol=1e-10, max_iter=100000, check_every=10)
+    assert r.converged
+    assert lo <= r.primal * (1 + 1e-12) and r.dual <= hi
+    # sandwich between the isotropic and anisotropic values: iso <= aniso <= sqrt2 iso
+    v_an = beckmann_lp(rho0, rho1, h)
+    assert r.dual <= v_an <= np.sqrt(2) * r.primal
+
+
+@pytest.mark.slow
+def test_isotropic_matches_constrained_dual_solve():
+    n, h = 6, 1.0 / 6
+    rho0, rho1, _, _ = synth.integer_mass_pair(n, 5)
+    f = rho1 - rho0
+    f = f - f.mean()
+
+    def cons(phi):
+        gx, gy = grid.grad(phi.reshape(n, n), h)
+        return (gx * gx + gy * gy).ravel()
+
+    res = minimize(lambda x: h * h * np.sum(x * f.ravel()), np.zeros(n * n), method="trust-constr",
+                   constraints=[NonlinearConstraint(cons, -np.inf, 1.0)],
+                   options=dict(xtol=1e-14, gtol=1e-14, maxiter=20000))
+    v_dual = -res.fun
+    r = emd.solve(rho0, rho1, h, tau=0.3, tol=1e-10, max_iter=100000, check_every=10)
+    assert abs(r.primal - v_dual) / v_dual < 1e-6
+
+
+def test_one_dimensional_closed_form():
+    ny, nxx = 5, 64
+    h = 1.0 / nxx
+    x = (np.arange(nxx) + 0.5) / nxx
+    g0 = np.exp(-(x - 0.3) ** 2 / 0.005) + 0.01
+    g1 = np.exp(-(x - 0.6) ** 2 / 0.02) + 0.01
+    g0, g1 = g0 / (g0.sum() * h), g1 / (g1.sum() * h)
+    rho0, rho1 = np.tile(g0, (ny, 1)), np.tile(g1, (ny, 1))
+    F0, F1 = h * np.cumsum(g0), h * np.cumsum(g1)
+    # 1-D value int |F0 - F1| times the strip height ny * h
+    exact = ny * h * h * np.sum(np.abs(F0 - F1))
+    r = emd.solve(rho0, rho1, h, tau=0.5, tol=0.0, max_iter=1, check_every=1)
+    # u stays 0 after one step from p0 = 0, so m = grad psi: the unique 1-D flux
+    assert abs(r.primal - exact) < 1e-12
+    r = emd.solve(rho0, rho1, h, tau=0.5, tol=1e-6, max_iter=100000, check_every=20)
+    assert r.converged and r.dual <= exact * (1 + 1e-12) <= r.primal * (1 + 1e-12)
+
+
+def test_translation_identity():
+    n = 32
+    rho0, rho1, s = synth.translated_gaussian_pair(n)
+    exact = s / (1 + synth.scenes.DENSITY_FLOOR)
+    r = emd.solve(rho0, rho1, 1.0 / n, tau=0.1, tol=1e-6, max_iter=100000, check_every=50)
+    assert r.converged
+    assert r.dual <= exact * (1 + 1e-9) and exact <= r.primal * (1 + 1e-9)
+    assert abs(r.primal - exact) / exact < 2e-6
+
+
+def test_golden_translation_value():
+    with open(os.path.join(GOLDEN, "paper_values.json")) as fh:
+        g = json.load(fh)["emd_translation"]
+    assert abs(np.hypot(*g["shift"]) - g["emd"]) < 1e-15
+
+
+def test_symmetry_bounds_and_identity():
+    n, h = 24, 1.0 / 24
+    rho0, rho1 = synth.emd_mixture_pair(n, 17, k=3)
+    a = emd.solve(rho0, rho1, h, tau=0.3, tol=0.0, max_iter=200, check_every=200)
+    b = emd.solve(rho1, rho0, h, tau=0.3, tol=0.0, max_iter=200, check_every=200)
+    assert abs(a.primal - b.primal) < 1e-12 * a.primal and abs(a.dual - b.dual) < 1e-12 * a.primal
+    # section 3.2: EMD <= int |rho1 - rho0|
+    assert a.dual <= h * h * np.abs(rho1 - rho0).sum()
+    same = emd.solve(rho0, rho0, h, tau=0.3, tol=0.0, max_iter=5, check_every=5)
+    assert same.primal == 0.0 and abs(same.dual) < 1e-15
+
+
+def test_leray_is_a_projector_onto_divergence_free():
+    rng = np.random.default_rng(8)
+    vx, vy = rng.standard_normal((2, 12, 15))
+    vx[:, -1] = 0
+    vy[-1, :] = 0
+    h = 0.1
+    lx, ly = emd.leray(vx, vy, h)
+    assert np.abs(grid.div(lx, ly, h)).max() < 1e-10
+    l2x, l2y = emd.leray(lx, ly, h)
+    assert np.allclose(l2x, lx, atol=1e-12) and np.allclose(l2y, ly, atol=1e-12)
+    gx, gy = grid.grad(rng.standard_normal((12, 15)), h)
+    z = emd.leray(gx, gy, h)
+    assert np.abs(z[0]).max() < 1e-9 and np.abs(z[1]).max() < 1e-9
+    # orthogonality to gradients
+    assert abs(grid.inner(lx, gx, h) + grid.inner(ly, gy, h)) < 1e-9
+
+
+def test_mass_and_sign_checks():
+    rho0 = np.ones((8, 8))
+    with pytest.raises(emd.MassMismatch):
+        emd.setup(rho0, rho0 * (1 + 1e-4), 1 / 8)
+    bad = rho0.copy()
+    bad[0, 0] = -1
+    with pytest.raises(ValueError):
+        emd.setup(bad, rho0, 1 / 8)
+
+
+def test_flux_reprojection():
+    n, h = 16, 1.0 / 16
+    rho0, rho1 = synth.emd_mixture_pair(n, 4, k=2)
+    r = emd.solve(rho0, rho1, h, tau=0.3, tol=0.0, max_iter=50, check_every=50)
+    mx, my = r.m
+    val, resid = emd.flux_value(mx, my, r.f, h)
+    assert resid < 1e-10 and abs(val - r.primal) < 1e-12
+    # perturbing the flux off the constraint is undone by the re-projection
+    gx, gy = grid.grad(np.random.default_rng(1).standard_normal((n, n)), h)
+    v2, resid2 = emd.flux_value(mx + 1e-3 * gx, my + 1e-3 * gy, r.f, h)
+    assert resid2 > 1e-6 and abs(v2 - val) < 1e-10
