@@ -1,0 +1,148 @@
+/* gprox.h - C ABI of libgprox: G-prox PDHG on 2-D grids for MI355X (gfx950).
+ *
+ * Method: Jacobs, Leger, Li, Osher, "Solving large-scale optimization problems
+ * with a convergence rate independent of grid size" (arXiv 1805.09453):
+ * Algorithm 2 (G-prox PDHG) applied to
+ *   - ROF total-variation denoising (section 3.1):
+ *       min_u ||u||_TV + lambda/2 ||u - I||^2,
+ *   - the L1 earth mover's distance in Beckmann form (section 3.2):
+ *       EMD(rho1, rho0) = min { int |m| : div m = rho1 - rho0, m.n = 0 }.
+ *
+ * Grid and operators.  ny x nx cell-centred grid with spacing h (the paper's
+ * unit square is h = 1/n; h = 1 gives per-pixel units).  Scalar fields are
+ * row-major float[ny][nx]; vector fields are planar float[2][ny][nx] (x
+ * component first).  grad is the forward difference with zero normal
+ * component on the far faces, div = -grad^T, Delta = div grad (Neumann), and
+ * the pointwise norm is Euclidean (norm = 0) or l1 (norm = 1).  The Laplace
+ * inversions (the u-step of Algorithm 2 in both problems) run as
+ * DCT-II -> diagonal scale -> inverse DCT-II (section 4, appendix A).
+ *
+ * Memory and ownership.  Every float pointer argument is a DEVICE pointer
+ * (hipMalloc'd or a torch tensor's data_ptr) to contiguous memory owned by
+ * the caller; the library keeps no pointer after a call returns.  All work is
+ * enqueued on the context's stream.  The library owns only the workspace in
+ * its context, sized at gp_create for grids up to max_ny x max_nx (solve
+ * calls may grow it; pd_step and pd_gap never allocate).
+ *
+ * Sizes.  ny and nx must be powers of two in [64, 4096] and at most the
+ * context's maxima; other sizes return GP_EUNSUPPORTED.
+ *
+ * Errors.  Every entry point returns GP_OK (0), a negative GP_E* code, or
+ * GP_ENOTCONV (> 0: max_iter reached, outputs valid, report filled).  No C++
+ * exception crosses this boundary.  gp_last_error() gives a message for the
+ * last failure on a context.
+ */
+#ifndef GPROX_H
+#define GPROX_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GP_OK 0
+#define GP_ENOTCONV 1       /* max_iter reached before tol; outputs valid */
+#define GP_EINVAL (-1)      /* null pointer, bad size/step/h/lambda, NaN/Inf or negative input */
+#define GP_EMASS (-2)       /* |sum rho0 - sum rho1| > 1e-6 sum rho0 (FP64) */
+#define GP_ENOMEM (-3)      /* device allocation failed */
+#define GP_EHIP (-4)        /* HIP runtime error (see gp_last_error) */
+#define GP_EUNSUPPORTED (-5)/* grid size or option not supported */
+
+#define GP_KIND_ROF 0
+#define GP_KIND_EMD 1
+#define GP_NORM_ISO 0
+#define GP_NORM_ANISO 1
+
+typedef struct gp_ctx gp_ctx; /* opaque: stream, twiddle tables, workspace */
+
+/* Step sizes and stopping rule of Algorithm 2.
+ * tau, sigma: primal / dual steps; sigma <= 0 selects sigma = 1/tau, the
+ *   choice of every step rule in the paper (sections 3.1, 3.2, 4).  The
+ *   convergence theorem of section 3 needs tau * sigma < 1; tau * sigma <= 1
+ *   is accepted (the boundary case is the Douglas-Rachford equivalent).
+ * tol: stop when the relative duality gap (P - D)/|P| of the last iterate
+ *   (section 4 stops on the last iterate) is <= tol; 0 runs max_iter.
+ * check_every: evaluate the gap every this many iterations (>= 1).
+ * norm: GP_NORM_ISO or GP_NORM_ANISO.
+ * warm_start: nonzero uses the caller's u/p (ROF) or phi (EMD) as the start.
+ */
+typedef struct {
+  double tau, sigma, tol;
+  int max_iter, check_every, norm, warm_start;
+} gp_opts;
+
+/* Filled by the solvers and by pd_gap. primal/dual are P(u) and D(p)
+ * (section 2.1 primal-dual gap); div_residual is max |div m - (rho1-rho0)|
+ * of the returned EMD flux (0 for ROF). */
+typedef struct {
+  int iters, converged;
+  double primal, dual, rel_gap, div_residual;
+  double seconds_setup, seconds_loop;
+} gp_report;
+
+/* Device-resident iterate for pd_step / pd_gap (all buffers caller-owned).
+ *   kind  GP_KIND_ROF: f = image I [ny][nx]; u = u_n [ny][nx].
+ *         GP_KIND_EMD: f = rho1 - rho0 - mean [ny][nx]; gpsi = grad psi
+ *                      [2][ny][nx] with Delta psi = f (emd_setup fills both);
+ *                      u = divergence-free part u_n [2][ny][nx].
+ *   p, pbar: dual iterate p_n and its extrapolation 2 p_n - p_{n-1} [2][ny][nx]
+ *            (pbar = p at n = 0).
+ *   iter: iterations done; pd_step adds n_iter. */
+typedef struct {
+  int kind, ny, nx, norm;
+  double h, lambda, tau, sigma;
+  const float* f;
+  const float* gpsi;
+  float* u;
+  float* p;
+  float* pbar;
+  long long iter;
+} gp_state;
+
+/* Context on a HIP stream (NULL = default stream).  max_ny, max_nx bound the
+ * grids later calls may use.  Returns GP_OK and *ctx, or an error. */
+int gp_create(gp_ctx** ctx, int max_ny, int max_nx, void* stream);
+int gp_destroy(gp_ctx* ctx);
+const char* gp_strerror(int code);
+const char* gp_last_error(const gp_ctx* ctx);
+
+/* Screened Poisson solve (alpha I - Delta) x = b with Neumann boundary (the
+ * linear solve of the ROF u-update, section 3.1, with alpha = lambda tau; the
+ * Laplace inversion of the Leray projection, section 3.2, with alpha = 0).
+ * alpha = 0: b is projected to mean zero (mean taken in FP64) and x has mean
+ * zero.  b and x are float[ny][nx] device buffers and may alias. */
+int dct_poisson(gp_ctx* ctx, const float* b, float* x, int ny, int nx, double h, double alpha);
+/* The same in FP64 (used for the EMD set-up potential). */
+int dct_poisson_f64(gp_ctx* ctx, const double* b, double* x, int ny, int nx, double h, double alpha);
+
+/* ROF denoising of I (section 3.1 updates of Algorithm 2).  u: out (and in
+ * when opts->warm_start) [ny][nx]; p: nullable [2][ny][nx] dual out (and in
+ * when warm_start).  Stops on opts->tol or opts->max_iter; rep may be NULL. */
+int rof_solve(gp_ctx* ctx, const float* I, float* u, float* p, int ny, int nx, double h, double lambda,
+              const gp_opts* opts, gp_report* rep);
+
+/* EMD between densities rho0, rho1 >= 0 of equal mass (section 3.2 updates).
+ * m: out flux u + grad psi [2][ny][nx]; phi: nullable [ny][nx]; in: warm-start
+ * potential phi0 (p0 = proj(grad phi0)) when opts->warm_start, out: the
+ * scaled dual potential of the certificate (|grad phi| <= 1).  rep->primal is
+ * the EMD upper bound h^2 sum |m|, rep->dual the certificate's lower bound. */
+int emd_solve(gp_ctx* ctx, const float* rho0, const float* rho1, float* m, float* phi, int ny, int nx, double h,
+              const gp_opts* opts, gp_report* rep);
+
+/* EMD set-up (section 3.2, Hodge split): mass check in FP64, f = rho1 - rho0
+ * - mean (FP64), psi = Delta^{-1} f solved in FP64, gpsi = grad psi stored
+ * FP32.  f: out [ny][nx]; gpsi: out [2][ny][nx]. */
+int emd_setup(gp_ctx* ctx, const float* rho0, const float* rho1, float* f, float* gpsi, int ny, int nx,
+              double h);
+
+/* Advance a device-resident iterate by n_iter G-prox PDHG iterations (ROF or
+ * EMD updates).  Enqueues work only: never synchronises, never allocates. */
+int pd_step(gp_ctx* ctx, gp_state* st, int n_iter);
+
+/* Primal value, dual value and relative gap of the state's (u_n, p_n);
+ * synchronises the stream once. */
+int pd_gap(gp_ctx* ctx, gp_state* st, gp_report* rep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPROX_H */

@@ -1,0 +1,13 @@
+"""G-prox PDHG for ROF denoising and L1 EMD on MI355X: Python binding of libgprox.
+
+Every call forwards to the HIP library (include/gprox.h) through ctypes; this
+module only checks tensor shapes/dtypes/devices and passes device pointers and
+the current HIP stream.  There is no CPU fallback: if the library is missing or
+no GPU is present, the calls raise.
+"""
+from .api import (  # noqa: F401
+    GPError,
+    Context,
+    Options,
+    lib_path,
+)

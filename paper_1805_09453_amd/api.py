@@ -1,0 +1,206 @@
+"""Thin Python layer over libgprox (argument marshalling only).
+
+Tensors are torch CUDA (HIP) tensors used as device buffers; the library runs
+every step of the method in its own kernels on the context's stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+from . import _lib as L
+from .build import LIB
+
+
+def lib_path() -> str:
+    return LIB
+
+
+class GPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+@dataclass
+class Options:
+    """Step sizes and stopping rule (gp_opts).  sigma <= 0 means 1/tau."""
+    tau: float
+    sigma: float = 0.0
+    tol: float = 1e-5
+    max_iter: int = 10000
+    check_every: int = 10
+    norm: int = L.GP_NORM_ISO
+    warm_start: bool = False
+
+    def c(self) -> L.gp_opts:
+        return L.gp_opts(float(self.tau), float(self.sigma), float(self.tol), int(self.max_iter),
+                         int(self.check_every), int(self.norm), int(bool(self.warm_start)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype, shape, name):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class State:
+    """A device-resident iterate for pd_step / pd_gap (gp_state plus the tensors it points to)."""
+
+    def __init__(self, kind, ny, nx, h, lam, tau, sigma, norm, f, gpsi, u, p, pbar):
+        self.tensors = dict(f=f, gpsi=gpsi, u=u, p=p, pbar=pbar)
+        sig = sigma if sigma > 0 else 1.0 / tau
+        self.c = L.gp_state(kind, ny, nx, norm, h, lam, tau, sig,
+                            ctypes.c_void_p(f.data_ptr()),
+                            ctypes.c_void_p(gpsi.data_ptr()) if gpsi is not None else None,
+                            ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(p.data_ptr()),
+                            ctypes.c_void_p(pbar.data_ptr()), 0)
+
+    @property
+    def iter(self):
+        return int(self.c.iter)
+
+    def __getattr__(self, k):
+        t = self.__dict__.get("tensors", {})
+        if k in t:
+            return t[k]
+        raise AttributeError(k)
+
+
+class Context:
+    """gp_ctx on a HIP stream (default: torch's current stream on the current device)."""
+
+    def __init__(self, max_ny: int, max_nx: int, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise GPError(L.GP_EHIP, "no GPU available: libgprox has no CPU path")
+        self._lib = L.load()
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        self.max_ny, self.max_nx = max_ny, max_nx
+        h = ctypes.c_void_p()
+        rc = self._lib.gp_create(ctypes.byref(h), int(max_ny), int(max_nx),
+                                 ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != L.GP_OK:
+            raise GPError(rc, self._lib.gp_strerror(rc).decode())
+        self._h = h
+
+    # -- plumbing
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc, allow_notconv=False):
+        if rc == L.GP_OK or (allow_notconv and rc == L.GP_ENOTCONV):
+            return rc
+        msg = self._lib.gp_last_error(self._h).decode() or self._lib.gp_strerror(rc).decode()
+        raise GPError(rc, msg)
+
+    # -- entry points
+    def dct_poisson(self, b, x=None, h=1.0, alpha=0.0):
+        torch = _torch()
+        ny, nx = b.shape
+        x = torch.empty_like(b) if x is None else x
+        self._check(self._lib.dct_poisson(self._h, _ptr(b, torch.float32, (ny, nx), "b"),
+                                          _ptr(x, torch.float32, (ny, nx), "x"), ny, nx, float(h), float(alpha)))
+        return x
+
+    def dct_poisson_f64(self, b, x=None, h=1.0, alpha=0.0):
+        torch = _torch()
+        ny, nx = b.shape
+        x = torch.empty_like(b) if x is None else x
+        self._check(self._lib.dct_poisson_f64(self._h, _ptr(b, torch.float64, (ny, nx), "b"),
+                                              _ptr(x, torch.float64, (ny, nx), "x"), ny, nx, float(h),
+                                              float(alpha)))
+        return x
+
+    def rof_solve(self, I, h, lam, opts: Options, u=None, p=None):
+        torch = _torch()
+        ny, nx = I.shape
+        u = torch.empty_like(I) if u is None else u
+        p = torch.empty((2, ny, nx), device=I.device, dtype=I.dtype) if p is None else p
+        rep = L.gp_report()
+        rc = self._lib.rof_solve(self._h, _ptr(I, torch.float32, (ny, nx), "I"),
+                                 _ptr(u, torch.float32, (ny, nx), "u"), _ptr(p, torch.float32, (2, ny, nx), "p"),
+                                 ny, nx, float(h), float(lam), ctypes.byref(opts.c()), ctypes.byref(rep))
+        self._check(rc, allow_notconv=True)
+        return u, p, rep.as_dict()
+
+    def emd_solve(self, rho0, rho1, h, opts: Options, phi=None, want_phi=True):
+        torch = _torch()
+        ny, nx = rho0.shape
+        m = torch.empty((2, ny, nx), device=rho0.device, dtype=rho0.dtype)
+        if phi is None and want_phi:
+            phi = torch.empty_like(rho0)
+        rep = L.gp_report()
+        rc = self._lib.emd_solve(self._h, _ptr(rho0, torch.float32, (ny, nx), "rho0"),
+                                 _ptr(rho1, torch.float32, (ny, nx), "rho1"),
+                                 _ptr(m, torch.float32, (2, ny, nx), "m"),
+                                 _ptr(phi, torch.float32, (ny, nx), "phi"), ny, nx, float(h),
+                                 ctypes.byref(opts.c()), ctypes.byref(rep))
+        self._check(rc, allow_notconv=True)
+        return m, phi, rep.as_dict()
+
+    def emd_setup(self, rho0, rho1, h):
+        torch = _torch()
+        ny, nx = rho0.shape
+        f = torch.empty_like(rho0)
+        gpsi = torch.empty((2, ny, nx), device=rho0.device, dtype=rho0.dtype)
+        self._check(self._lib.emd_setup(self._h, _ptr(rho0, torch.float32, (ny, nx), "rho0"),
+                                        _ptr(rho1, torch.float32, (ny, nx), "rho1"),
+                                        _ptr(f, torch.float32, (ny, nx), "f"),
+                                        _ptr(gpsi, torch.float32, (2, ny, nx), "gpsi"), ny, nx, float(h)))
+        return f, gpsi
+
+    def make_state(self, kind, f, h, tau, sigma=0.0, lam=0.0, gpsi=None, u=None, p=None, pbar=None,
+                   norm=L.GP_NORM_ISO):
+        """Wrap caller tensors as a gp_state; missing u/p/pbar start at zero (pbar = p)."""
+        torch = _torch()
+        ny, nx = f.shape
+        ushape = (ny, nx) if kind == L.GP_KIND_ROF else (2, ny, nx)
+        u = torch.zeros(ushape, device=f.device, dtype=torch.float32) if u is None else u
+        p = torch.zeros((2, ny, nx), device=f.device, dtype=torch.float32) if p is None else p
+        pbar = p.clone() if pbar is None else pbar
+        _ptr(f, torch.float32, (ny, nx), "f")
+        _ptr(u, torch.float32, ushape, "u")
+        _ptr(p, torch.float32, (2, ny, nx), "p")
+        _ptr(pbar, torch.float32, (2, ny, nx), "pbar")
+        if kind == L.GP_KIND_EMD:
+            _ptr(gpsi, torch.float32, (2, ny, nx), "gpsi")
+        return State(kind, ny, nx, float(h), float(lam), float(tau), float(sigma), int(norm), f, gpsi, u, p, pbar)
+
+    def pd_step(self, st: State, n_iter: int):
+        self._check(self._lib.pd_step(self._h, ctypes.byref(st.c), int(n_iter)))
+
+    def pd_gap(self, st: State):
+        rep = L.gp_report()
+        self._check(self._lib.pd_gap(self._h, ctypes.byref(st.c), ctypes.byref(rep)))
+        return rep.as_dict()

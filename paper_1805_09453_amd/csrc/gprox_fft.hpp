@@ -1,0 +1,392 @@
+// Register-resident FFT-based DCT-II / inverse DCT-II for gfx950.
+//
+// The Neumann Laplace inversion of the G-prox u-step (section 3.1 and 3.2
+// updates; section 4 and appendix A: the inversion is done by FFT after even
+// reflection, i.e. in the cosine basis) is a DCT-II -> diagonal scale ->
+// inverse DCT-II along each axis.  Each 1-D DCT of length N is computed as
+// one complex FFT of length N over TWO real sequences packed as (re, im),
+// after Makhoul's even/odd reordering (J. Makhoul, "A fast cosine transform in
+// one and two dimensions", IEEE TASSP 1980):
+//     v_m = x_{2m},  v_{N-1-m} = x_{2m+1}           (m < N/2)
+//     X_k = Re(exp(-i pi k / 2N) V_k),              V = FFT(v)
+// and for the inverse
+//     V_k = exp(+i pi k / 2N) (X_k - i X_{N-k}),   X_N = 0,   v = N * IFFT(V).
+//
+// FFT layout: a "group" of T = N/32 threads owns one complex sequence; each
+// thread holds 32 complex values in registers.  Passes are Stockham
+// (self-sorting, natural-order output) with radix 16, plus one leading
+// radix-2/4/8 pass when log2 N is not a multiple of 4.  Between passes the
+// group exchanges through its own LDS region.  Butterfly-to-thread assignment:
+//   * first forward pass: butterflies (b, N/R-1-b) on one thread, so the
+//     Makhoul reordering is done by the global loads themselves (one float2
+//     load gives x_{2m}, x_{2m+1} = v_m, v_{N-1-m});
+//   * last forward pass: butterflies (b, N/R-b), so each thread holds both
+//     Z_k and Z_{N-k} for the real/imaginary split and the DCT twiddle, and
+//     the inverse's first pass (same radix, same indices) needs no exchange;
+//   * last inverse pass: (b, N/R-1-b) again, so stores are float2 pairs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gp {
+
+// ---------------------------------------------------------------- complex
+// C is float2 (the per-iteration path) or double2 (the FP64 set-up solves).
+template <class C> struct Cx;
+template <> struct Cx<float2> { using R = float; };
+template <> struct Cx<double2> { using R = double; };
+template <class C> __device__ __forceinline__ C mk(typename Cx<C>::R x, typename Cx<C>::R y) {
+  C c;
+  c.x = x;
+  c.y = y;
+  return c;
+}
+template <class C> __device__ __forceinline__ C cmul(C a, C b) {
+  return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <class C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <class C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <class C> __device__ __forceinline__ C conjc(C a) { return mk<C>(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, class C> __device__ __forceinline__ C mul_mi(C a) {
+  return INV ? mk<C>(-a.y, a.x) : mk<C>(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------- small DFTs
+template <bool INV, class C> __device__ __forceinline__ void dft2(C& a, C& b) {
+  C t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <bool INV, class C> __device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+  C t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+// y_s = sum_r a_r W_R^{rs}, W_R = exp(-+2 pi i / R); in place on a[0..R)
+template <int R, bool INV, class C> struct DFT;
+
+template <bool INV, class C> struct DFT<2, INV, C> {
+  __device__ __forceinline__ static void run(C* a) { dft2<INV>(a[0], a[1]); }
+};
+template <bool INV, class C> struct DFT<4, INV, C> {
+  __device__ __forceinline__ static void run(C* a) { dft4<INV>(a[0], a[1], a[2], a[3]); }
+};
+template <bool INV, class C> struct DFT<8, INV, C> {
+  __device__ __forceinline__ static void run(C* a) {
+    using Re = typename Cx<C>::R;
+    constexpr Re h = Re(0.70710678118654752440);
+    constexpr Re sg = INV ? Re(1) : Re(-1);
+    C e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+    C o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+    dft4<INV>(e0, e1, e2, e3);
+    dft4<INV>(o0, o1, o2, o3);
+    // W8^1 = (h, -+h), W8^2 = -+i, W8^3 = (-h, -+h)
+    o1 = cmul(o1, mk<C>(h, sg * h));
+    o2 = mul_mi<INV>(o2);
+    o3 = cmul(o3, mk<C>(-h, sg * h));
+    a[0] = cadd(e0, o0); a[4] = csub(e0, o0);
+    a[1] = cadd(e1, o1); a[5] = csub(e1, o1);
+    a[2] = cadd(e2, o2); a[6] = csub(e2, o2);
+    a[3] = cadd(e3, o3); a[7] = csub(e3, o3);
+  }
+};
+template <bool INV, class C> struct DFT<16, INV, C> {
+  // n = r + 4m, k = s + 4q:  y_{s+4q} = sum_r W4^{rq} W16^{rs} [DFT4_m a_{r+4m}]_s
+  __device__ __forceinline__ static void run(C* a) {
+    using Re = typename Cx<C>::R;
+    constexpr Re sg = INV ? Re(1) : Re(-1);
+    constexpr Re c1 = Re(0.92387953251128675613), s1 = Re(0.38268343236508977173);
+    constexpr Re h = Re(0.70710678118654752440);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dft4<INV>(a[r], a[r + 4], a[r + 8], a[r + 12]);
+    // twiddles W16^{r s} on element (r, s) stored at a[r + 4 s]
+    a[1 + 4 * 1] = cmul(a[1 + 4 * 1], mk<C>(c1, sg * s1));   // W^1
+    a[1 + 4 * 2] = cmul(a[1 + 4 * 2], mk<C>(h, sg * h));     // W^2
+    a[1 + 4 * 3] = cmul(a[1 + 4 * 3], mk<C>(s1, sg * c1));   // W^3
+    a[2 + 4 * 1] = cmul(a[2 + 4 * 1], mk<C>(h, sg * h));     // W^2
+    a[2 + 4 * 2] = mul_mi<INV>(a[2 + 4 * 2]);                // W^4
+    a[2 + 4 * 3] = cmul(a[2 + 4 * 3], mk<C>(-h, sg * h));    // W^6
+    a[3 + 4 * 1] = cmul(a[3 + 4 * 1], mk<C>(s1, sg * c1));   // W^3
+    a[3 + 4 * 2] = cmul(a[3 + 4 * 2], mk<C>(-h, sg * h));    // W^6
+    a[3 + 4 * 3] = cmul(a[3 + 4 * 3], mk<C>(-c1, -sg * s1)); // W^9
+    C y[16];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      C b0 = a[0 + 4 * s], b1 = a[1 + 4 * s], b2 = a[2 + 4 * s], b3 = a[3 + 4 * s];
+      dft4<INV>(b0, b1, b2, b3);
+      y[s] = b0; y[s + 4] = b1; y[s + 8] = b2; y[s + 12] = b3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = y[i];
+  }
+};
+
+// ---------------------------------------------------------------- schedule
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+template <int N> struct Sched {
+  static_assert(N >= 64 && N <= 4096 && (N & (N - 1)) == 0, "power-of-two N in [64, 4096]");
+  static constexpr int E = 32;          // complex values per thread
+  static constexpr int T = N / E;       // threads per sequence
+  static constexpr int L2 = ilog2c(N);
+  static constexpr int REM = L2 % 4;
+  static constexpr int NP = L2 / 4 + (REM ? 1 : 0);
+  // forward radix of pass p; the inverse runs the sequence reversed
+  static constexpr int rad(int p) { return (REM && p == 0) ? (1 << REM) : 16; }
+  static constexpr int irad(int p) { return rad(NP - 1 - p); }
+  static constexpr int ls(int p) { int l = 1; for (int i = 0; i < p; ++i) l *= rad(i); return l; }
+  static constexpr int ils(int p) { int l = 1; for (int i = 0; i < p; ++i) l *= irad(i); return l; }
+  // twiddle tables: per pass, LS rows of R entries (entry r = W_{LS R}^{j r})
+  static constexpr int toff(int p) { int o = 0; for (int i = 0; i < p; ++i) o += ls(i) * rad(i); return o; }
+  static constexpr int tsize() { return toff(NP); }
+  static constexpr int itoff(int p) { int o = tsize(); for (int i = 0; i < p; ++i) o += ils(i) * irad(i); return o; }
+  static constexpr int total_tw() { return itoff(NP); }
+  // padded LDS index and region size (one pad slot per 16 complex values)
+  static constexpr int LDS = N + N / 16 + 2;
+};
+
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// One Stockham pass on NB = 32/R butterflies held by this thread.
+//   inputs of butterfly b:  x[b + r N/R], twiddled by W_{LS R}^{(b mod LS) r}
+//   outputs:                 y[(b/LS) LS R + (b mod LS) + s LS]
+template <int N, int R, int LS, bool INV, bool FROM_LDS, bool TO_LDS, class C>
+__device__ __forceinline__ void stockham_pass(C (&v)[32], const int (&bi)[32 / R], C* lds,
+                                              const C* __restrict__ tw) {
+  constexpr int NB = 32 / R;
+  if constexpr (FROM_LDS) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q * R + r] = lds[lpad(bi[q] + r * (N / R))];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if constexpr (LS > 1) {
+      const int j = bi[q] & (LS - 1);
+      const C* __restrict__ tj = tw + j * R;
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], tj[r]);
+    }
+    DFT<R, INV, C>::run(&v[q * R]);
+  }
+  if constexpr (TO_LDS) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int j = bi[q] & (LS - 1);
+      const int base = (bi[q] / LS) * LS * R + j;
+#pragma unroll
+      for (int s = 0; s < R; ++s) lds[lpad(base + s * LS)] = v[q * R + s];
+    }
+    __syncthreads();
+  }
+}
+
+// butterfly index lists
+template <int N, int R> __device__ __forceinline__ void bidx_seq(int t, int (&bi)[32 / R]) {
+  constexpr int T = N / 32;
+#pragma unroll
+  for (int q = 0; q < 32 / R; ++q) bi[q] = t + q * T;
+}
+template <int N, int R> __device__ __forceinline__ void bidx_mk(int t, int (&bi)[32 / R]) {
+  constexpr int T = N / 32;
+#pragma unroll
+  for (int q = 0; q < 16 / R; ++q) {
+    bi[2 * q] = t + q * T;
+    bi[2 * q + 1] = N / R - 1 - (t + q * T);
+  }
+}
+template <int N, int R> __device__ __forceinline__ void bidx_dc(int t, int (&bi)[32 / R]) {
+  constexpr int T = N / 32;
+#pragma unroll
+  for (int q = 0; q < 16 / R; ++q) {
+    const int b = t + q * T;
+    bi[2 * q] = b;
+    bi[2 * q + 1] = (b == 0) ? N / (2 * R) : N / R - b;
+  }
+}
+
+// Middle passes p in [P, PEND) of the forward (INV=false) or inverse FFT.
+template <int N, bool INV, int P, int PEND, class C>
+__device__ __forceinline__ void middle_passes(int t, C (&v)[32], C* lds, const C* __restrict__ tw) {
+  if constexpr (P < PEND) {
+    using S = Sched<N>;
+    constexpr int R = INV ? S::irad(P) : S::rad(P);
+    constexpr int LS = INV ? S::ils(P) : S::ls(P);
+    constexpr int OFF = INV ? S::itoff(P) : S::toff(P);
+    int bi[32 / R];
+    bidx_seq<N, R>(t, bi);
+    stockham_pass<N, R, LS, INV, true, true>(v, bi, lds, tw + OFF);
+    middle_passes<N, INV, P + 1, PEND, C>(t, v, lds, tw);
+  }
+}
+
+// Forward DCT-II of two real sequences a, b of length N.
+// ld(m, A, B) must return A = (a_{2m}, a_{2m+1}), B = (b_{2m}, b_{2m+1}) for m < N/2.
+// On return, spec[slot*16 + s] = (A_k, B_k) with k = dc_index(slot, s), the
+// unnormalised DCT-II X_k = sum_j x_j cos(pi k (2j+1) / 2N).
+template <int N, class C, class Loader>
+__device__ __forceinline__ void dct2_fwd(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+                                         const C* __restrict__ dctw, Loader&& ld) {
+  using Re = typename Cx<C>::R;
+  using S = Sched<N>;
+  constexpr int T = S::T;
+  constexpr int R0 = S::rad(0);
+  // ---- pass 0 with the Makhoul reordering done by the loads
+  {
+    int bi[32 / R0];
+    bidx_mk<N, R0>(t, bi);
+#pragma unroll
+    for (int q = 0; q < 16 / R0; ++q) {
+      const int b = t + q * T;
+      const int bp = N / R0 - 1 - b;
+#pragma unroll
+      for (int r = 0; r < R0 / 2; ++r) {
+        // m = b + r N/R0 gives input r of b and input R0-1-r of bp; m = bp + r N/R0 the converse
+        C A, B;
+        ld(b + r * (N / R0), A, B);
+        v[(2 * q) * R0 + r] = mk<C>(A.x, B.x);
+        v[(2 * q + 1) * R0 + (R0 - 1 - r)] = mk<C>(A.y, B.y);
+        ld(bp + r * (N / R0), A, B);
+        v[(2 * q + 1) * R0 + r] = mk<C>(A.x, B.x);
+        v[(2 * q) * R0 + (R0 - 1 - r)] = mk<C>(A.y, B.y);
+      }
+    }
+    stockham_pass<N, R0, 1, false, false, true>(v, bi, lds, tw + S::toff(0));
+  }
+  // ---- middle passes
+  middle_passes<N, false, 1, S::NP - 1, C>(t, v, lds, tw);
+  // ---- last pass (radix 16), pairs (b, N/16 - b): outputs stay in registers
+  {
+    constexpr int PL = S::NP - 1;
+    int bi[2];
+    bidx_dc<N, 16>(t, bi);
+    stockham_pass<N, 16, S::ls(PL), false, true, false>(v, bi, lds, tw + S::toff(PL));
+  }
+  // ---- split the two real transforms and apply exp(-i pi k / 2N).  Output s
+  // of butterfly b is index b + s N/16; Z_{N-k} sits at (slot1, 15 - s).
+  const int b = t;
+  const C* __restrict__ w = dctw;
+  if (b != 0) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k0 = b + s * (N / 16);
+      const int k1 = N - k0;  // = (N/16 - b) + (15 - s) N/16
+      C z0 = v[s], z1 = v[16 + 15 - s];
+      C w0 = w[k0], w1 = w[k1];
+      C a0 = cmul(w0, z0), c0 = cmul(w0, mk<C>(z1.x, -z1.y));
+      C a1 = cmul(w1, z1), c1 = cmul(w1, mk<C>(z0.x, -z0.y));
+      v[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
+      v[16 + 15 - s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
+    }
+  } else {
+    // thread 0: slot 0 holds k = s N/16 (pairs s <-> 16 - s, s = 0 and 8 self),
+    //           slot 1 holds k = N/32 + s N/16 (pairs s <-> 15 - s)
+    C o[32];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k0 = s * (N / 16);
+      C z0 = v[s], zp = v[(16 - s) & 15];
+      C w0 = w[k0];
+      C a0 = cmul(w0, z0), c0 = cmul(w0, mk<C>(zp.x, -zp.y));
+      o[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
+      const int k1 = N / 32 + s * (N / 16);
+      C z1 = v[16 + s], zq = v[16 + 15 - s];
+      C w1 = w[k1];
+      C a1 = cmul(w1, z1), c1 = cmul(w1, mk<C>(zq.x, -zq.y));
+      o[16 + s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = o[i];
+  }
+}
+
+// DCT index held in spec slot (slot in {0,1}, s in [0,16)) by thread t.
+template <int N> __device__ __forceinline__ int dc_index(int t, int slot, int s) {
+  const int b = (slot == 0) ? t : ((t == 0) ? N / 32 : N / 16 - t);
+  return b + s * (N / 16);
+}
+
+// Inverse of the unnormalised DCT-II, times N, for two real spectra held as
+// spec[slot*16+s] = (A_k, B_k) (layout of dct2_fwd).  st(m, A, B) receives
+// A = N (a_{2m}, a_{2m+1}), B = N (b_{2m}, b_{2m+1}).
+template <int N, class C, class Storer>
+__device__ __forceinline__ void dct2_inv(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+                                         const C* __restrict__ dctw, Storer&& st) {
+  using Re = typename Cx<C>::R;
+  using S = Sched<N>;
+  constexpr int T = S::T;
+  const C* __restrict__ w = dctw;  // exp(-i pi k / 2N); the inverse uses its conjugate
+  // ---- V_k = conj(w_k) (X_k - i X_{N-k}) for both spectra, Z_k = V^a_k + i V^b_k
+  if (t != 0) {
+    // pairs (slot0, s) <-> (slot1, 15 - s), s in [0, 16)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k0 = t + s * (N / 16);
+      const int k1 = N - k0;
+      C y0 = v[s], y1 = v[16 + 15 - s];
+      C c0 = w[k0], c1 = w[k1];
+      c0.y = -c0.y;
+      c1.y = -c1.y;
+      C va0 = cmul(c0, mk<C>(y0.x, -y1.x)), vb0 = cmul(c0, mk<C>(y0.y, -y1.y));
+      C va1 = cmul(c1, mk<C>(y1.x, -y0.x)), vb1 = cmul(c1, mk<C>(y1.y, -y0.y));
+      v[s] = mk<C>(va0.x - vb0.y, va0.y + vb0.x);
+      v[16 + 15 - s] = mk<C>(va1.x - vb1.y, va1.y + vb1.x);
+    }
+  } else {
+    C o[32];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k0 = s * (N / 16);
+      C y0 = v[s];
+      C yp = (s == 0) ? mk<C>(Re(0), Re(0)) : v[(16 - s) & 15];  // X_N = 0
+      C c0 = w[k0];
+      c0.y = -c0.y;
+      C va = cmul(c0, mk<C>(y0.x, -yp.x)), vb = cmul(c0, mk<C>(y0.y, -yp.y));
+      o[s] = mk<C>(va.x - vb.y, va.y + vb.x);
+      const int k1 = N / 32 + s * (N / 16);
+      C y1 = v[16 + s], yq = v[16 + 15 - s];
+      C c1 = w[k1];
+      c1.y = -c1.y;
+      C va1 = cmul(c1, mk<C>(y1.x, -yq.x)), vb1 = cmul(c1, mk<C>(y1.y, -yq.y));
+      o[16 + s] = mk<C>(va1.x - vb1.y, va1.y + vb1.x);
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = o[i];
+  }
+  // ---- inverse pass 0 (radix 16) directly on the registers: butterfly b's
+  // inputs b + r N/16 are exactly what this thread holds
+  {
+    int bi[2];
+    bidx_dc<N, 16>(t, bi);
+    stockham_pass<N, 16, 1, true, false, true>(v, bi, lds, tw + S::itoff(0));
+  }
+  middle_passes<N, true, 1, S::NP - 1, C>(t, v, lds, tw);
+  // ---- last inverse pass with Makhoul pairs, outputs in registers
+  {
+    constexpr int PL = S::NP - 1;
+    constexpr int RL = S::irad(PL);
+    int bi[32 / RL];
+    bidx_mk<N, RL>(t, bi);
+    stockham_pass<N, RL, S::ils(PL), true, true, false>(v, bi, lds, tw + S::itoff(PL));
+#pragma unroll
+    for (int q = 0; q < 16 / RL; ++q) {
+      const int b = t + q * T;
+      const int bp = N / RL - 1 - b;
+#pragma unroll
+      for (int s = 0; s < RL / 2; ++s) {
+        C x0 = v[(2 * q) * RL + s], x1 = v[(2 * q + 1) * RL + (RL - 1 - s)];
+        st(b + s * (N / RL), mk<C>(x0.x, x1.x), mk<C>(x0.y, x1.y));
+        C y0 = v[(2 * q + 1) * RL + s], y1 = v[(2 * q) * RL + (RL - 1 - s)];
+        st(bp + s * (N / RL), mk<C>(y0.x, y1.x), mk<C>(y0.y, y1.y));
+      }
+    }
+  }
+}
+
+}  // namespace gp

@@ -1,0 +1,442 @@
+// HIP kernels for G-prox PDHG on 2-D grids (gfx950).
+//
+// Discretisation: n_y x n_x cell-centred grid, spacing h, row-major [ny][nx].
+//   grad u : forward differences, zero normal component on the far faces;
+//   div p  : -grad^T (backward differences);
+//   Delta  : div grad, diagonalised by the 2-D DCT-II (appendix A: even
+//            reflection turns the Neumann Laplacian into a cosine series);
+//   |p|    : collocated Euclidean norm sqrt(px^2 + py^2) (sections 3.1, 3.2).
+// Vector fields are planar: component x at [0][ny][nx], y at [1][ny][nx].
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "gprox_fft.hpp"
+
+namespace gp {
+
+// ------------------------------------------------------------ launch shapes
+template <int N, class C> struct RowShape {
+  static constexpr int T = Sched<N>::T;
+  static constexpr int G = 256 / T;  // row pairs per block
+  static constexpr int THREADS = 256;
+  static constexpr size_t LDS_BYTES = size_t(G) * Sched<N>::LDS * sizeof(C);
+};
+template <int N, class C> struct ColShape {
+  static constexpr int T = Sched<N>::T;
+  static constexpr int G0 = int(147456 / (size_t(Sched<N>::LDS) * sizeof(C)));
+  static constexpr int G = G0 > 16 ? 16 : (G0 < 1 ? 1 : G0);  // column pairs per block
+  static constexpr int THREADS = T * G;
+  static constexpr size_t LDS_BYTES = size_t(G) * Sched<N>::LDS * sizeof(C);
+};
+
+template <class C> struct Vec2Of;
+template <> struct Vec2Of<float2> { using V = float2; };
+template <> struct Vec2Of<double2> { using V = double2; };
+
+// ------------------------------------------------------------ DCT passes
+// Forward DCT-II along rows, two rows per FFT group.  out may alias in.
+template <int N, class C>
+__global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
+                                                  int ld, const C* __restrict__ tw, const C* __restrict__ dctw) {
+  using Re = typename Cx<C>::R;
+  using SH = RowShape<N, C>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* smem = reinterpret_cast<C*>(smem_raw);
+  const int g = threadIdx.x / SH::T, t = threadIdx.x % SH::T;
+  C* lds = smem + g * Sched<N>::LDS;
+  const int ra = 2 * (blockIdx.x * SH::G + g), rb = ra + 1;
+  const bool va = ra < ny, vb = rb < ny;
+  const Re* pa = in + size_t(va ? ra : 0) * ld;
+  const Re* pb = in + size_t(vb ? rb : 0) * ld;
+  C v[32];
+  dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
+    A = va ? *reinterpret_cast<const C*>(pa + 2 * m) : mk<C>(Re(0), Re(0));
+    B = vb ? *reinterpret_cast<const C*>(pb + 2 * m) : mk<C>(Re(0), Re(0));
+  });
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = dc_index<N>(t, slot, s);
+      if (va) out[size_t(ra) * ld + k] = v[slot * 16 + s].x;
+      if (vb) out[size_t(rb) * ld + k] = v[slot * 16 + s].y;
+    }
+}
+
+// Inverse of the (unnormalised) DCT-II along rows times N.  out may alias in.
+template <int N, class C>
+__global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
+                                                  int ld, const C* __restrict__ tw, const C* __restrict__ dctw) {
+  using Re = typename Cx<C>::R;
+  using SH = RowShape<N, C>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* smem = reinterpret_cast<C*>(smem_raw);
+  const int g = threadIdx.x / SH::T, t = threadIdx.x % SH::T;
+  C* lds = smem + g * Sched<N>::LDS;
+  const int ra = 2 * (blockIdx.x * SH::G + g), rb = ra + 1;
+  const bool va = ra < ny, vb = rb < ny;
+  C v[32];
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = dc_index<N>(t, slot, s);
+      v[slot * 16 + s] = mk<C>(va ? in[size_t(ra) * ld + k] : Re(0), vb ? in[size_t(rb) * ld + k] : Re(0));
+    }
+  dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
+    if (va) *reinterpret_cast<C*>(out + size_t(ra) * ld + 2 * m) = A;
+    if (vb) *reinterpret_cast<C*>(out + size_t(rb) * ld + 2 * m) = B;
+  });
+}
+
+// Column pass of the screened Poisson solve, in place on the row-transformed
+// field: DCT-II along y, scale by 1/(nx ny (alpha + mu_y[k] + mu_x[l])) (the
+// zero mode is dropped when alpha = 0), inverse DCT-II along y.  Two adjacent
+// columns per FFT group; consecutive lanes take consecutive column pairs so
+// every row access of a wave covers G*2 contiguous values.
+template <int N, class C>
+__global__ __launch_bounds__((ColShape<N, C>::THREADS)) void k_cols_solve(
+    typename Cx<C>::R* buf, int nx, int ld, const C* __restrict__ tw, const C* __restrict__ dctw,
+    const typename Cx<C>::R* __restrict__ mux, const typename Cx<C>::R* __restrict__ muy, typename Cx<C>::R alpha,
+    typename Cx<C>::R inv_nn) {
+  using Re = typename Cx<C>::R;
+  using SH = ColShape<N, C>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* smem = reinterpret_cast<C*>(smem_raw);
+  const int g = threadIdx.x % SH::G, t = threadIdx.x / SH::G;
+  C* lds = smem + g * Sched<N>::LDS;
+  const int c = 2 * (blockIdx.x * SH::G + g);
+  const bool valid = c < nx;
+  Re* col = buf + (valid ? c : 0);
+  C v[32];
+  dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
+    if (valid) {
+      C L0 = *reinterpret_cast<const C*>(col + size_t(2 * m) * ld);
+      C L1 = *reinterpret_cast<const C*>(col + size_t(2 * m + 1) * ld);
+      A = mk<C>(L0.x, L1.x);
+      B = mk<C>(L0.y, L1.y);
+    } else {
+      A = mk<C>(Re(0), Re(0));
+      B = A;
+    }
+  });
+  const Re mxa = valid ? mux[c] : Re(0), mxb = valid ? mux[c + 1] : Re(0);
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = dc_index<N>(t, slot, s);
+      const Re da = alpha + muy[k] + mxa, db = alpha + muy[k] + mxb;
+      C& z = v[slot * 16 + s];
+      z.x = da > Re(0) ? z.x * (inv_nn / da) : Re(0);
+      z.y = db > Re(0) ? z.y * (inv_nn / db) : Re(0);
+    }
+  dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
+    if (valid) {
+      *reinterpret_cast<C*>(col + size_t(2 * m) * ld) = mk<C>(A.x, B.x);
+      *reinterpret_cast<C*>(col + size_t(2 * m + 1) * ld) = mk<C>(A.y, B.y);
+    }
+  });
+}
+
+// ------------------------------------------------------------ reductions
+// Block-level FP64 reductions over 256 threads (4 waves of 64).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// reduces K values per thread; thread 0 writes partials[blockIdx.x * K + i]
+template <int K>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[K], const bool (&is_max)[K], double* partials) {
+  __shared__ double red[4][K];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    double r = is_max[i] ? wave_max(acc[i]) : wave_sum(acc[i]);
+    if (lane == 0) red[w][i] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      double r = red[0][i];
+      for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = is_max[i] ? fmax(r, red[q][i]) : r + red[q][i];
+      partials[size_t(blockIdx.x) * K + i] = r;
+    }
+  }
+}
+
+// Sum (or max) partials over nb blocks; one block of 256 threads, fixed order.
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nb, int K,
+                                                  unsigned max_mask, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = 0; i < K; ++i) {
+    const bool mx = (max_mask >> i) & 1u;
+    double a = mx ? -INFINITY : 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      double x = partials[size_t(b) * K + i];
+      a = mx ? fmax(a, x) : a + x;
+    }
+    a = mx ? wave_max(a) : wave_sum(a);
+    if (lane == 0) red[w] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r = red[0];
+      for (int q = 1; q < 4; ++q) r = mx ? fmax(r, red[q]) : r + red[q];
+      out[i] = r;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ helpers
+__device__ __forceinline__ void proj_ball(float& qx, float& qy, int aniso) {
+  if (aniso) {
+    qx = fminf(1.f, fmaxf(-1.f, qx));
+    qy = fminf(1.f, fmaxf(-1.f, qy));
+  } else {
+    const float n = sqrtf(qx * qx + qy * qy);
+    if (n > 1.f) {
+      const float s = 1.f / n;
+      qx *= s;
+      qy *= s;
+    }
+  }
+}
+__device__ __forceinline__ float pnorm(float x, float y, int aniso) {
+  return aniso ? fabsf(x) + fabsf(y) : sqrtf(x * x + y * y);
+}
+
+// divergence of a planar vector field at (i, j), far-face components treated as 0
+__device__ __forceinline__ float div_at(const float* __restrict__ px, const float* __restrict__ py, int i, int j,
+                                        int ny, int nx) {
+  const size_t o = size_t(i) * nx + j;
+  const float xr = (j < nx - 1) ? px[o] : 0.f;
+  const float xl = (j > 0) ? px[o - 1] : 0.f;
+  const float yu = (i < ny - 1) ? py[o] : 0.f;
+  const float yd = (i > 0) ? py[o - nx] : 0.f;
+  return (xr - xl) + (yu - yd);
+}
+
+// ------------------------------------------------------------ ROF stencils
+// r = lambda tau (I - u) + tau div pbar   (incremental form of the section 3.1
+// u-update: u+ = u + (lambda tau - Delta)^{-1} r)
+__global__ __launch_bounds__(256) void k_rof_rhs(const float* __restrict__ I, const float* __restrict__ u,
+                                                 const float* __restrict__ pbx, const float* __restrict__ pby,
+                                                 float* __restrict__ r, int ny, int nx, float lt, float tau_h) {
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    r[o] = lt * (I[o] - u[o]) + tau_h * div_at(pbx, pby, i, j, ny, nx);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_axpy(float* __restrict__ u, const float* __restrict__ d, size_t n) {
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
+    u[o] += d[o];
+}
+
+// p+ = proj(p + sigma grad u+), pbar+ = 2 p+ - p
+__global__ __launch_bounds__(256) void k_rof_dual(const float* __restrict__ u, float* __restrict__ px,
+                                                  float* __restrict__ py, float* __restrict__ pbx,
+                                                  float* __restrict__ pby, int ny, int nx, float sig_h, int aniso) {
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const float uc = u[o];
+    const float gx = (j < nx - 1) ? (u[o + 1] - uc) : 0.f;
+    const float gy = (i < ny - 1) ? (u[o + nx] - uc) : 0.f;
+    const float ox = px[o], oy = py[o];
+    float qx = ox + sig_h * gx, qy = oy + sig_h * gy;
+    proj_ball(qx, qy, aniso);
+    px[o] = qx;
+    py[o] = qy;
+    pbx[o] = 2.f * qx - ox;
+    pby[o] = 2.f * qy - oy;
+  }
+}
+
+// partial sums for the ROF gap: [sum |grad u| (per-h units), sum (u-I)^2,
+// sum I div p, sum (div p)^2]; gradients and divergences in 1/h units
+__global__ __launch_bounds__(256) void k_rof_energy(const float* __restrict__ u, const float* __restrict__ px,
+                                                    const float* __restrict__ py, const float* __restrict__ I,
+                                                    int ny, int nx, float inv_h, int aniso,
+                                                    double* __restrict__ partials) {
+  double acc[4] = {0, 0, 0, 0};
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const float uc = u[o];
+    const float gx = (j < nx - 1) ? (u[o + 1] - uc) * inv_h : 0.f;
+    const float gy = (i < ny - 1) ? (u[o + nx] - uc) * inv_h : 0.f;
+    const float d = div_at(px, py, i, j, ny, nx) * inv_h;
+    const float e = uc - I[o];
+    acc[0] += double(pnorm(gx, gy, aniso));
+    acc[1] += double(e) * double(e);
+    acc[2] += double(I[o]) * double(d);
+    acc[3] += double(d) * double(d);
+  }
+  const bool mx[4] = {false, false, false, false};
+  block_reduce_store<4>(acc, mx, partials);
+}
+
+// ------------------------------------------------------------ EMD stencils
+// r = s div v (s = +-1/h); T = float or double output
+template <class T>
+__global__ __launch_bounds__(256) void k_div(const float* __restrict__ vx, const float* __restrict__ vy,
+                                             T* __restrict__ r, int ny, int nx, float s) {
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    r[o] = T(div_at(vx, vy, i, j, ny, nx)) * T(s);
+  }
+}
+
+// w = u - tau pbar (the argument of the Leray projection)
+__global__ __launch_bounds__(256) void k_emd_shift(const float* __restrict__ u, const float* __restrict__ pb,
+                                                   float* __restrict__ w, size_t n2, float tau) {
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n2; o += size_t(gridDim.x) * blockDim.x)
+    w[o] = u[o] - tau * pb[o];
+}
+
+// Projected form of the section 3.2 u-update: u+ = w - grad phi, phi = Delta^{-1} div w,
+// w = u - tau pbar; then p+ = proj(p + sigma (u+ + grad psi)), pbar+ = 2 p+ - p.
+// Optionally accumulates sum |u+ + grad psi| (block partials) for the primal value.
+__global__ __launch_bounds__(256) void k_emd_update(const double* __restrict__ phi, const float* __restrict__ wx,
+                                                    const float* __restrict__ wy, float* __restrict__ ux,
+                                                    float* __restrict__ uy, float* __restrict__ px,
+                                                    float* __restrict__ py, float* __restrict__ pbx,
+                                                    float* __restrict__ pby, const float* __restrict__ gpx,
+                                                    const float* __restrict__ gpy, int ny, int nx, double inv_h,
+                                                    float sigma, int aniso, double* __restrict__ partials) {
+  double acc[1] = {0};
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    // grad phi from the FP64 potential: differencing an FP32 potential would
+    // lose ~log10(n) digits to cancellation
+    const double fc = phi[o];
+    const float fx = (j < nx - 1) ? float((phi[o + 1] - fc) * inv_h) : 0.f;
+    const float fy = (i < ny - 1) ? float((phi[o + nx] - fc) * inv_h) : 0.f;
+    const float nux = (j < nx - 1) ? wx[o] - fx : 0.f;
+    const float nuy = (i < ny - 1) ? wy[o] - fy : 0.f;
+    const float mx = nux + gpx[o], my = nuy + gpy[o];
+    const float ox = px[o], oy = py[o];
+    float qx = ox + sigma * mx, qy = oy + sigma * my;
+    proj_ball(qx, qy, aniso);
+    ux[o] = nux;
+    uy[o] = nuy;
+    px[o] = qx;
+    py[o] = qy;
+    pbx[o] = 2.f * qx - ox;
+    pby[o] = 2.f * qy - oy;
+    if (partials) acc[0] += double(pnorm(mx, my, aniso));
+  }
+  if (partials) {
+    const bool m[1] = {false};
+    block_reduce_store<1>(acc, m, partials);
+  }
+}
+
+// primal value of the state (u, grad psi): sum |u + grad psi|
+__global__ __launch_bounds__(256) void k_emd_primal(const float* __restrict__ ux, const float* __restrict__ uy,
+                                                    const float* __restrict__ gpx, const float* __restrict__ gpy,
+                                                    size_t n, int aniso, double* __restrict__ partials) {
+  double acc[1] = {0};
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
+    acc[0] += double(pnorm(ux[o] + gpx[o], uy[o] + gpy[o], aniso));
+  const bool m[1] = {false};
+  block_reduce_store<1>(acc, m, partials);
+}
+
+// certificate partials: [sum phi f, max |grad phi|] (gradient in 1/h units)
+__global__ __launch_bounds__(256) void k_emd_cert(const double* __restrict__ phi, const float* __restrict__ f,
+                                                  int ny, int nx, double inv_h, int aniso,
+                                                  double* __restrict__ partials) {
+  double acc[2] = {0, 0};
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const double fc = phi[o];
+    const double gx = (j < nx - 1) ? (phi[o + 1] - fc) * inv_h : 0.0;
+    const double gy = (i < ny - 1) ? (phi[o + nx] - fc) * inv_h : 0.0;
+    acc[0] += fc * double(f[o]);
+    const double L = aniso ? fmax(fabs(gx), fabs(gy)) : sqrt(gx * gx + gy * gy);
+    acc[1] = fmax(acc[1], L);
+  }
+  const bool m[2] = {false, true};
+  block_reduce_store<2>(acc, m, partials);
+}
+
+// out = s * in
+template <class T>
+__global__ __launch_bounds__(256) void k_scale(const T* __restrict__ in, float* __restrict__ out, size_t n,
+                                               double s) {
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
+    out[o] = float(s * in[o]);
+}
+
+// m = u + grad psi
+__global__ __launch_bounds__(256) void k_add2(const float* __restrict__ a, const float* __restrict__ b,
+                                              float* __restrict__ out, size_t n) {
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
+    out[o] = a[o] + b[o];
+}
+
+// ------------------------------------------------------------ set-up (FP64)
+// partials: [sum rho0, sum rho1, count(rho0 < 0 or rho1 < 0 or non-finite)]
+__global__ __launch_bounds__(256) void k_mass(const float* __restrict__ r0, const float* __restrict__ r1, size_t n,
+                                              double* __restrict__ partials) {
+  double acc[3] = {0, 0, 0};
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const float a = r0[o], b = r1[o];
+    acc[0] += double(a);
+    acc[1] += double(b);
+    if (!(a >= 0.f) || !(b >= 0.f) || !isfinite(a) || !isfinite(b)) acc[2] += 1.0;
+  }
+  const bool m[3] = {false, false, false};
+  block_reduce_store<3>(acc, m, partials);
+}
+
+// f = rho1 - rho0 - mean (FP64), written in FP64 (for the set-up solve) and FP32
+__global__ __launch_bounds__(256) void k_f64_diff(const float* __restrict__ r0, const float* __restrict__ r1,
+                                                  const double* __restrict__ sums, double inv_n, size_t n,
+                                                  double* __restrict__ f64, float* __restrict__ f32) {
+  const double mean = (sums[1] - sums[0]) * inv_n;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const double v = (double(r1[o]) - double(r0[o])) - mean;
+    f64[o] = -v;  // the set-up solve is (0 I - Delta) psi = -f
+    f32[o] = float(v);
+  }
+}
+
+// grad psi from the FP64 potential, stored FP32 (planar)
+__global__ __launch_bounds__(256) void k_grad_f64(const double* __restrict__ psi, float* __restrict__ gx,
+                                                  float* __restrict__ gy, int ny, int nx, double inv_h) {
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const double c = psi[o];
+    gx[o] = (j < nx - 1) ? float((psi[o + 1] - c) * inv_h) : 0.f;
+    gy[o] = (i < ny - 1) ? float((psi[o + nx] - c) * inv_h) : 0.f;
+  }
+}
+
+// count of non-finite values (block partials)
+__global__ __launch_bounds__(256) void k_nonfinite(const float* __restrict__ x, size_t n,
+                                                   double* __restrict__ partials) {
+  double acc[1] = {0};
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
+    if (!isfinite(x[o])) acc[0] += 1.0;
+  const bool m[1] = {false};
+  block_reduce_store<1>(acc, m, partials);
+}
+
+}  // namespace gp

@@ -9,3 +9,27 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU oracle runs")
+
+
+import pytest  # noqa: E402
+
+
+@pytest.fixture(scope="session")
+def gpctx():
+    """One library context for the GPU tests (grids up to 4096 x 4096)."""
+    import torch
+    from paper_1805_09453_amd import Context
+    from paper_1805_09453_amd import build as B
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(B.LIB):
+        B.build()
+    ctx = Context(4096, 4096)
+    yield ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def announce(msg):
+    """Name the case before a GPU step (flushed, so a crash log still shows it)."""
+    print(f"\n[gpu case] {msg}", flush=True)

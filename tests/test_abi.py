@@ -1,0 +1,72 @@
+"""CPU checks of the C ABI: the library builds/loads, exports every function
+include/gprox.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gprox.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1805_09453_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    from paper_1805_09453_amd import _lib
+    return _lib.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ("gp_create", "gp_destroy", "dct_poisson", "rof_solve", "emd_solve", "pd_step", "pd_gap",
+                     "gp_strerror"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"libgprox.so does not export {name}"
+
+
+def test_python_binding_covers_every_symbol():
+    from paper_1805_09453_amd import _lib
+    assert set(declared_functions()) == set(_lib._SIGS)
+
+
+def test_strerror_and_null_arguments(lib):
+    assert lib.gp_strerror(0) == b"ok"
+    assert b"invalid" in lib.gp_strerror(-1)
+    assert lib.gp_strerror(12345) == b"unknown error code"
+    # NULL out-pointer and NULL contexts are rejected on the host
+    assert lib.gp_create(None, 64, 64, None) == -1
+    assert lib.gp_destroy(None) == 0
+    assert lib.dct_poisson(None, None, None, 64, 64, 1.0, 0.0) == -1
+    assert lib.pd_step(None, None, 1) == -1
+    assert lib.pd_gap(None, None, None) == -1
+    assert lib.rof_solve(None, None, None, None, 64, 64, 1.0, 8.0, None, None) == -1
+
+
+def test_unsupported_sizes_rejected_before_allocation(lib):
+    h = ctypes.c_void_p()
+    assert lib.gp_create(ctypes.byref(h), 100, 64, None) == -5
+    assert lib.gp_create(ctypes.byref(h), 64, 8192, None) == -5
+    assert not h.value
+
+
+def test_python_layer_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    from paper_1805_09453_amd import Context, GPError
+    with pytest.raises(GPError):
+        Context(64, 64)
