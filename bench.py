@@ -1,0 +1,212 @@
+"""Benchmark: G-prox PDHG iterations on a 4096x4096 grid on one MI355X.
+
+A step is `--iters-per-step` G-prox PDHG iterations (gradient/divergence
+stencils, pointwise prox, DCT Poisson solve) followed by one duality-gap
+evaluation (the solver's convergence check), on device-resident state.  The
+headline value is pixel-iterations per second of the ROF workload (noisy
+piecewise-constant 4096x4096 image, 50 shapes, sigma 0.1 noise, lambda 8 per
+pixel); the EMD workload (16-Gaussian mixtures, 4096x4096, h = 1/4096) is
+reported beside it.  Prints ONE JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--iters-per-step", type=int, default=20)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--rof-tau", type=float, default=0.01)
+    ap.add_argument("--emd-tau", type=float, default=0.3)
+    ap.add_argument("--no-emd", action="store_true")
+    ap.add_argument("--solve", action="store_true", help="also time full solves to --tol")
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("gprox.hip", "gprox_fft.hpp", "gprox_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1805_09453_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(n, iters_budget_s):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload:
+    whole ROF iterations on the same 4096x4096 image, timed with perf_counter."""
+    import numpy as np
+
+    import synth
+    from oracle import rof as orof
+    I = synth.rof_scene(n, synth.config_seed(2), n_shapes=50, size_range=(0.02, 0.15))
+    u = np.zeros_like(I)
+    px, py = np.zeros_like(I), np.zeros_like(I)
+    pbx, pby = px.copy(), py.copy()
+    tau = 0.01
+    t0 = time.perf_counter()
+    it = 0
+    while True:
+        u, px, py, pbx, pby = orof.step(u, px, py, pbx, pby, I, 1.0, 8.0, tau, 1.0 / tau)
+        it += 1
+        if time.perf_counter() - t0 >= iters_budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n * n * it / dt, "unit": "pixel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{it} ROF iterations of the FP64 NumPy/SciPy oracle on the same {n}x{n} image "
+                      f"({dt:.1f} s; scipy.fft single-threaded, NumPy elementwise single-threaded)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1805_09453_amd import Context
+    from paper_1805_09453_amd import build as B
+    from paper_1805_09453_amd._lib import GP_KIND_EMD, GP_KIND_ROF
+
+    if not os.path.exists(B.LIB):
+        B.build()
+    n = args.n
+    dev = torch.device("cuda:0")
+    if args.calib_copy:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    ctx = Context(n, n)
+    K, W, C = args.steps, args.warmup, args.iters_per_step
+
+    def run(st):
+        for _ in range(W):
+            ctx.pd_step(st, C)
+            ctx.pd_gap(st)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        gaps = []
+        for _ in range(K):
+            ctx.pd_step(st, C)
+            gaps.append(ctx.pd_gap(st)["rel_gap"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        return dt, prof, gaps
+
+    # ---- ROF workload (headline)
+    I = synth.rof_scene(n, synth.config_seed(2), n_shapes=50, size_range=(0.02, 0.15))
+    I_d = torch.tensor(I, dtype=torch.float32, device=dev)
+    st = ctx.make_state(GP_KIND_ROF, I_d, 1.0, args.rof_tau, lam=8.0)
+    dt, prof, gaps = run(st)
+    rof_pxit = n * n * C * K / dt
+    ms_per_step = 1e3 * dt / K
+    dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    dname, d = dom
+    achieved = d["bytes"] / d["calls"] / (d["avg_ms"] * 1e6)
+    iter_bytes = sum(v["bytes"] for k, v in prof.items() if k != "reduce") / (C * K)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dname), "kernel": dname,
+                "bytes_per_launch": d["bytes"] / d["calls"], "avg_launch_ms": d["avg_ms"]}
+    extra = {"rof": {"pixel_iters_per_s": rof_pxit, "iters": C * K, "last_rel_gap": gaps[-1],
+                     "algorithmic_bytes_per_pixel_iter": iter_bytes / (n * n),
+                     "iteration_hbm_frac": iter_bytes * C * K / dt / 1e9 / HBM_PEAK_GBPS,
+                     "kernels": {k: {"avg_ms": v["avg_ms"], "calls": v["calls"], "gbps": v["gbps"]}
+                                 for k, v in prof.items()}}}
+    del st
+    # ---- EMD workload
+    if not args.no_emd:
+        rho0, rho1 = synth.emd_mixture_pair(n, synth.config_seed(2), k=16)
+        r0 = torch.tensor(rho0, dtype=torch.float32, device=dev)
+        r1 = torch.tensor(rho1, dtype=torch.float32, device=dev)
+        f, gpsi = ctx.emd_setup(r0, r1, 1.0 / n)
+        st = ctx.make_state(GP_KIND_EMD, f, 1.0 / n, args.emd_tau, gpsi=gpsi)
+        edt, eprof, egaps = run(st)
+        ebytes = sum(v["bytes"] for k, v in eprof.items() if k != "reduce") / (C * K)
+        extra["emd"] = {"pixel_iters_per_s": n * n * C * K / edt, "iters": C * K, "last_rel_gap": egaps[-1],
+                        "ms_per_step": 1e3 * edt / K,
+                        "algorithmic_bytes_per_pixel_iter": ebytes / (n * n),
+                        "iteration_hbm_frac": ebytes * C * K / edt / 1e9 / HBM_PEAK_GBPS,
+                        "kernels": {k: {"avg_ms": v["avg_ms"], "calls": v["calls"], "gbps": v["gbps"]}
+                                    for k, v in eprof.items()}}
+        del st
+    # ---- optional: time to tolerance (outside the timed steps)
+    if args.solve:
+        from paper_1805_09453_amd import Options
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, rep = ctx.rof_solve(I_d, 1.0, 8.0, Options(tau=args.rof_tau, tol=args.tol, max_iter=20000,
+                                                         check_every=10))
+        torch.cuda.synchronize()
+        extra["rof"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
+        if not args.no_emd:
+            t0 = time.perf_counter()
+            _, _, rep = ctx.emd_solve(r0, r1, 1.0 / n, Options(tau=args.emd_tau, tol=args.tol, max_iter=20000,
+                                                                check_every=50), want_phi=False)
+            torch.cuda.synchronize()
+            extra["emd"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
+    ctx.close()
+    cpu = None if args.no_cpu else cpu_baseline(n, args.cpu_seconds)
+    out = {
+        "metric": "pixel-iters/s",
+        "value": rof_pxit,
+        "unit": "pixel-iters/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ROF TV denoising, {n}x{n} noisy piecewise-constant image (50 shapes, "
+                               f"sigma 0.1), lambda 8, h 1, tau {args.rof_tau}; step = {C} G-prox iterations "
+                               f"+ 1 duality-gap check",
+                   "grid": [n, n], "iters_per_step": C, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

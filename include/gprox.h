@@ -142,6 +142,23 @@ int pd_step(gp_ctx* ctx, gp_state* st, int n_iter);
  * synchronises the stream once. */
 int pd_gap(gp_ctx* ctx, gp_state* st, gp_report* rep);
 
+/* Per-kernel timing on the context's stream (HIP events around each kernel
+ * launch; for measurement, not needed by the solvers).  gp_profile(ctx, 1)
+ * clears and starts recording (allocates the event pool), gp_profile(ctx, 0)
+ * stops.  gp_profile_read synchronises the stream and fills up to max entries
+ * (one per kernel kind that ran): total elapsed ms, launch count, and the
+ * algorithmic HBM bytes those launches must move (sum over launches of what
+ * the kernel's definition reads and writes once).  *n_out receives the
+ * number of entries.  Recording stops silently when the pool (16384 launches)
+ * is full; the 'dropped' field counts unrecorded launches. */
+typedef struct {
+  char name[32];
+  long long calls, dropped;
+  double total_ms, bytes;
+} gp_kstat;
+int gp_profile(gp_ctx* ctx, int enable);
+int gp_profile_read(gp_ctx* ctx, gp_kstat* out, int max, int* n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,11 @@ class gp_state(ctypes.Structure):
                 ("iter", c_longlong)]
 
 
+class gp_kstat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("calls", c_longlong), ("dropped", c_longlong),
+                ("total_ms", c_double), ("bytes", c_double)]
+
+
 _SIGS = {
     "gp_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_void_p]),
     "gp_destroy": (c_int, [c_void_p]),
@@ -46,6 +51,8 @@ _SIGS = {
     "emd_setup": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double]),
     "pd_step": (c_int, [c_void_p, ctypes.POINTER(gp_state), c_int]),
     "pd_gap": (c_int, [c_void_p, ctypes.POINTER(gp_state), ctypes.POINTER(gp_report)]),
+    "gp_profile": (c_int, [c_void_p, c_int]),
+    "gp_profile_read": (c_int, [c_void_p, ctypes.POINTER(gp_kstat), c_int, ctypes.POINTER(c_int)]),
 }
 
 _lib = None

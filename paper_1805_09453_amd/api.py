@@ -200,6 +200,22 @@ class Context:
     def pd_step(self, st: State, n_iter: int):
         self._check(self._lib.pd_step(self._h, ctypes.byref(st.c), int(n_iter)))
 
+    def profile(self, enable: bool):
+        """Start (clear) or stop per-kernel HIP-event timing on this context's stream."""
+        self._check(self._lib.gp_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{kernel: {calls, dropped, total_ms, avg_ms, bytes, gbps}} (synchronises)."""
+        buf = (L.gp_kstat * 64)()
+        n = ctypes.c_int()
+        self._check(self._lib.gp_profile_read(self._h, buf, 64, ctypes.byref(n)))
+        out = {}
+        for k in buf[:min(n.value, 64)]:
+            avg = k.total_ms / k.calls if k.calls else 0.0
+            out[k.name.decode()] = dict(calls=k.calls, dropped=k.dropped, total_ms=k.total_ms, avg_ms=avg,
+                                        bytes=k.bytes, gbps=(k.bytes / (k.total_ms * 1e6)) if k.total_ms else 0.0)
+        return out
+
     def pd_gap(self, st: State):
         rep = L.gp_report()
         self._check(self._lib.pd_gap(self._h, ctypes.byref(st.c), ctypes.byref(rep)))

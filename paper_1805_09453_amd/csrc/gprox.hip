@@ -52,10 +52,44 @@ struct gp_ctx {
   // solver arena (grow-only)
   float* arena = nullptr;
   size_t arena_floats = 0;
+  // per-kernel timing (gp_profile)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;  // 2 per recorded launch
+  std::vector<int> prof_id;
+  std::vector<double> prof_bytes;
+  int prof_used = 0;
+  long long prof_dropped[32] = {0};
   char err[512] = {0};
 };
 
 namespace {
+
+// kernel kinds for gp_profile
+enum KId {
+  K_ROWS_FWD, K_COLS, K_ROWS_INV, K_ROWS_FWD64, K_COLS64, K_ROWS_INV64, K_ROF_RHS, K_AXPY, K_ROF_DUAL,
+  K_EMD_SHIFT, K_DIV64, K_EMD_UPDATE, K_REDUCE, K_COUNT
+};
+const char* kKName[K_COUNT] = {"rows_fwd_dct2", "cols_solve", "rows_inv_dct2", "rows_fwd_dct2_f64",
+                               "cols_solve_f64", "rows_inv_dct2_f64", "rof_rhs", "axpy", "rof_dual_prox",
+                               "emd_shift", "div_f64", "emd_update_prox", "reduce"};
+constexpr int kProfPool = 16384;
+
+// records a start event for a launch of kind id moving `bytes`; returns the slot or -1
+int prof_begin(gp_ctx* c, int id, double bytes) {
+  if (!c->prof_on) return -1;
+  if (c->prof_used >= kProfPool) {
+    c->prof_dropped[id]++;
+    return -1;
+  }
+  const int s = c->prof_used++;
+  c->prof_id[s] = id;
+  c->prof_bytes[s] = bytes;
+  (void)hipEventRecord(c->prof_ev[2 * s], c->stream);
+  return s;
+}
+void prof_end(gp_ctx* c, int s) {
+  if (s >= 0) (void)hipEventRecord(c->prof_ev[2 * s + 1], c->stream);
+}
 
 void set_err(gp_ctx* c, const char* fmt, ...) {
   if (!c) return;
@@ -264,20 +298,34 @@ template <class C> struct Solve {
 
 // (alpha I - Delta) x = b on the device, b and x may alias.  Tables and mu must be set.
 int poisson_f32(gp_ctx* c, const float* b, float* x, int ny, int nx, double alpha) {
+  const double fb = 8.0 * double(nx) * ny;  // each pass reads and writes one FP32 field
+  int ps = prof_begin(c, K_ROWS_FWD, fb);
   GP_DISPATCH_N(nx, Solve<float2>::rows_fwd, c, b, x, ny);
+  prof_end(c, ps);
   LAUNCHCHK(c);
+  ps = prof_begin(c, K_COLS, fb);
   GP_DISPATCH_N(ny, Solve<float2>::cols, c, x, nx, c->mux32, c->muy32, float(alpha), float(1.0 / (double(nx) * ny)));
+  prof_end(c, ps);
   LAUNCHCHK(c);
+  ps = prof_begin(c, K_ROWS_INV, fb);
   GP_DISPATCH_N(nx, Solve<float2>::rows_inv, c, x, x, ny);
+  prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
 int poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, double alpha) {
+  const double fb = 16.0 * double(nx) * ny;
+  int ps = prof_begin(c, K_ROWS_FWD64, fb);
   GP_DISPATCH_N(nx, Solve<double2>::rows_fwd, c, b, x, ny);
+  prof_end(c, ps);
   LAUNCHCHK(c);
+  ps = prof_begin(c, K_COLS64, fb);
   GP_DISPATCH_N(ny, Solve<double2>::cols, c, x, nx, c->mux64, c->muy64, alpha, 1.0 / (double(nx) * ny));
+  prof_end(c, ps);
   LAUNCHCHK(c);
+  ps = prof_begin(c, K_ROWS_INV64, fb);
   GP_DISPATCH_N(nx, Solve<double2>::rows_inv, c, x, x, ny);
+  prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
@@ -369,15 +417,21 @@ int rof_iter(gp_ctx* c, const gp_state* s) {
   float* py = s->p + n;
   float* bx = s->pbar;
   float* by = s->pbar + n;
+  int ps = prof_begin(c, K_ROF_RHS, 20.0 * n);
   hipLaunchKernelGGL(k_rof_rhs, dim3(grid_for(n)), dim3(256), 0, c->stream, s->f, s->u, bx, by, c->work, s->ny,
                      s->nx, float(s->lambda * s->tau), float(s->tau / s->h));
+  prof_end(c, ps);
   LAUNCHCHK(c);
   int rc = poisson_f32(c, c->work, c->work, s->ny, s->nx, s->lambda * s->tau);
   if (rc) return rc;
+  ps = prof_begin(c, K_AXPY, 12.0 * n);
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, c->stream, s->u, c->work, n);
+  prof_end(c, ps);
   LAUNCHCHK(c);
+  ps = prof_begin(c, K_ROF_DUAL, 28.0 * n);
   hipLaunchKernelGGL(k_rof_dual, dim3(grid_for(n)), dim3(256), 0, c->stream, s->u, px, py, bx, by, s->ny, s->nx,
                      float(s->sigma / s->h), s->norm);
+  prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
@@ -386,22 +440,28 @@ int rof_iter(gp_ctx* c, const gp_state* s) {
 int emd_iter(gp_ctx* c, const gp_state* s, bool want_primal, int* nb_out) {
   const size_t n = size_t(s->ny) * s->nx;
   float* w = c->work2;
+  int ps = prof_begin(c, K_EMD_SHIFT, 24.0 * n);
   hipLaunchKernelGGL(k_emd_shift, dim3(grid_for(2 * n)), dim3(256), 0, c->stream, s->u, s->pbar, w, 2 * n,
                      float(s->tau));
+  prof_end(c, ps);
   LAUNCHCHK(c);
   // -div w, so that the solve (0 I - Delta) phi = -div w gives phi = Delta^{-1} div w;
   // div w has zero mean exactly and the solve drops the zero mode.  The solve
   // runs in FP64 so that grad phi keeps FP32 accuracy (see k_emd_update).
   double* phi = c->work64;
+  ps = prof_begin(c, K_DIV64, 16.0 * n);
   hipLaunchKernelGGL(k_div<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, w, w + n, phi, s->ny, s->nx,
                      float(-1.0 / s->h));
+  prof_end(c, ps);
   LAUNCHCHK(c);
   int rc = poisson_f64(c, phi, phi, s->ny, s->nx, 0.0);
   if (rc) return rc;
   const int nb = want_primal ? red_blocks(n) : grid_for(n);
+  ps = prof_begin(c, K_EMD_UPDATE, 56.0 * n);
   hipLaunchKernelGGL(k_emd_update, dim3(nb), dim3(256), 0, c->stream, phi, w, w + n, s->u, s->u + n, s->p,
                      s->p + n, s->pbar, s->pbar + n, s->gpsi, s->gpsi + n, s->ny, s->nx, 1.0 / s->h,
                      float(s->sigma), s->norm, want_primal ? c->partials : nullptr);
+  prof_end(c, ps);
   LAUNCHCHK(c);
   if (nb_out) *nb_out = nb;
   return GP_OK;
@@ -410,8 +470,10 @@ int emd_iter(gp_ctx* c, const gp_state* s, bool want_primal, int* nb_out) {
 int rof_gap(gp_ctx* c, const gp_state* s, double* P, double* D) {
   const size_t n = size_t(s->ny) * s->nx;
   const int nb = red_blocks(n);
+  int ps = prof_begin(c, K_REDUCE, 16.0 * n);
   hipLaunchKernelGGL(k_rof_energy, dim3(nb), dim3(256), 0, c->stream, s->u, s->p, s->p + n, s->f, s->ny, s->nx,
                      float(1.0 / s->h), s->norm, c->partials);
+  prof_end(c, ps);
   LAUNCHCHK(c);
   double r[4];
   int rc = finalize_read(c, nb, 4, 0u, r);
@@ -554,6 +616,7 @@ int gp_destroy(gp_ctx* c) {
   double* db[] = {c->work64, c->partials, c->result, c->mux64, c->muy64};
   for (double* p : db)
     if (p) (void)hipFree(p);
+  for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
   if (c->host_result) (void)hipHostFree(c->host_result);
   if (c->mu_host) (void)hipHostFree(c->mu_host);
   if (c->mu_host32) (void)hipHostFree(c->mu_host32);
@@ -838,6 +901,51 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
     rep->seconds_loop = t2 - t1;
   }
   return conv ? GP_OK : GP_ENOTCONV;
+}
+
+int gp_profile(gp_ctx* c, int enable) {
+  if (!c) return GP_EINVAL;
+  if (enable) {
+    if (c->prof_ev.empty()) {
+      c->prof_ev.resize(2 * kProfPool);
+      for (auto& e : c->prof_ev) HIPCHK(c, hipEventCreate(&e));
+      c->prof_id.resize(kProfPool);
+      c->prof_bytes.resize(kProfPool);
+    }
+    c->prof_used = 0;
+    for (auto& d : c->prof_dropped) d = 0;
+  }
+  c->prof_on = enable != 0;
+  return GP_OK;
+}
+
+int gp_profile_read(gp_ctx* c, gp_kstat* out, int max, int* n_out) {
+  if (!c || (!out && max > 0)) return GP_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double ms[K_COUNT] = {0}, by[K_COUNT] = {0};
+  long long cnt[K_COUNT] = {0};
+  for (int s = 0; s < c->prof_used; ++s) {
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->prof_ev[2 * s], c->prof_ev[2 * s + 1]));
+    ms[c->prof_id[s]] += t;
+    by[c->prof_id[s]] += c->prof_bytes[s];
+    cnt[c->prof_id[s]]++;
+  }
+  int k = 0;
+  for (int id = 0; id < K_COUNT; ++id) {
+    if (!cnt[id] && !c->prof_dropped[id]) continue;
+    if (k < max) {
+      std::memset(&out[k], 0, sizeof(gp_kstat));
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", kKName[id]);
+      out[k].calls = cnt[id];
+      out[k].dropped = c->prof_dropped[id];
+      out[k].total_ms = ms[id];
+      out[k].bytes = by[id];
+    }
+    ++k;
+  }
+  if (n_out) *n_out = k;
+  return GP_OK;
 }
 
 }  // extern "C"
