@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/gprox.h"
+#include "gprox_fused.hpp"
 #include "gprox_kernels.hpp"
 
 using namespace gp;
@@ -37,7 +38,8 @@ struct gp_ctx {
   int max_ny = 0, max_nx = 0;
   Tables tab[13];            // index log2 N
   float* work = nullptr;     // [max_n] transform buffer
-  float* work2 = nullptr;    // [2 max_n] (EMD projection argument)
+  float* work2 = nullptr;    // [2 max_n] EMD stored field wt (ping)
+  float* work3 = nullptr;    // [2 max_n] EMD stored field wt (pong)
   double* work64 = nullptr;  // [2 max_n] FP64 set-up buffers
   double* partials = nullptr;
   double* result = nullptr;  // [kMaxK] finalized reductions (device)
@@ -66,12 +68,13 @@ namespace {
 
 // kernel kinds for gp_profile
 enum KId {
-  K_ROWS_FWD, K_COLS, K_ROWS_INV, K_ROWS_FWD64, K_COLS64, K_ROWS_INV64, K_ROF_RHS, K_AXPY, K_ROF_DUAL,
-  K_EMD_SHIFT, K_DIV64, K_EMD_UPDATE, K_REDUCE, K_COUNT
+  K_ROWS_FWD, K_COLS, K_ROWS_INV, K_ROWS_FWD64, K_COLS64, K_ROWS_INV64, K_ROF_A, K_ROF_B, K_ROF_FINISH,
+  K_EMD_A, K_EMD_B, K_EMD_FINISH, K_DIV64, K_REDUCE, K_COUNT
 };
 const char* kKName[K_COUNT] = {"rows_fwd_dct2", "cols_solve", "rows_inv_dct2", "rows_fwd_dct2_f64",
-                               "cols_solve_f64", "rows_inv_dct2_f64", "rof_rhs", "axpy", "rof_dual_prox",
-                               "emd_shift", "div_f64", "emd_update_prox", "reduce"};
+                               "cols_solve_f64", "rows_inv_dct2_f64", "rof_A_prox_rhs_dct", "rof_B_idct_update",
+                               "rof_finish", "emd_A_prox_rhs_dct", "emd_B_idct", "emd_finish", "div_f64",
+                               "reduce"};
 constexpr int kProfPool = 16384;
 
 // records a start event for a launch of kind id moving `bytes`; returns the slot or -1
@@ -136,8 +139,8 @@ template <int N> void fill_tw(std::vector<double>& re, std::vector<double>& im) 
     for (int j = 0; j < LS; ++j)
       for (int r = 0; r < R; ++r) {
         const double a = -2.0 * M_PI * double(j) * double(r) / double(LS * R);
-        re[S::toff(p) + j * R + r] = cos(a);
-        im[S::toff(p) + j * R + r] = sin(a);
+        re[S::toff(p) + r * LS + j] = cos(a);
+        im[S::toff(p) + r * LS + j] = sin(a);
       }
   }
   for (int p = 0; p < S::NP; ++p) {
@@ -145,8 +148,8 @@ template <int N> void fill_tw(std::vector<double>& re, std::vector<double>& im) 
     for (int j = 0; j < LS; ++j)
       for (int r = 0; r < R; ++r) {
         const double a = 2.0 * M_PI * double(j) * double(r) / double(LS * R);
-        re[S::itoff(p) + j * R + r] = cos(a);
-        im[S::itoff(p) + j * R + r] = sin(a);
+        re[S::itoff(p) + r * LS + j] = cos(a);
+        im[S::itoff(p) + r * LS + j] = sin(a);
       }
   }
 }
@@ -268,6 +271,17 @@ template <> const double2* tw_of<double2>(const Tables& T) { return T.tw64; }
 template <class C> const C* dw_of(const Tables& T);
 template <> const float2* dw_of<float2>(const Tables& T) { return T.dw32; }
 template <> const double2* dw_of<double2>(const Tables& T) { return T.dw64; }
+
+#define GP_DISPATCH_NM(n, T, M, ...)             \
+  switch (n) {                                   \
+    case 64: T<64>::M(__VA_ARGS__); break;       \
+    case 128: T<128>::M(__VA_ARGS__); break;     \
+    case 256: T<256>::M(__VA_ARGS__); break;     \
+    case 512: T<512>::M(__VA_ARGS__); break;     \
+    case 1024: T<1024>::M(__VA_ARGS__); break;   \
+    case 2048: T<2048>::M(__VA_ARGS__); break;   \
+    case 4096: T<4096>::M(__VA_ARGS__); break;   \
+  }
 
 #define GP_DISPATCH_N(n, F, ...)            \
   switch (n) {                              \
@@ -410,61 +424,188 @@ int check_opts(gp_ctx* c, const gp_opts* o, double* tau, double* sigma) {
   return GP_OK;
 }
 
-// ---------------------------------------------------------------- iterations
-int rof_iter(gp_ctx* c, const gp_state* s) {
-  const size_t n = size_t(s->ny) * s->nx;
-  float* px = s->p;
-  float* py = s->p + n;
-  float* bx = s->pbar;
-  float* by = s->pbar + n;
-  int ps = prof_begin(c, K_ROF_RHS, 20.0 * n);
-  hipLaunchKernelGGL(k_rof_rhs, dim3(grid_for(n)), dim3(256), 0, c->stream, s->f, s->u, bx, by, c->work, s->ny,
-                     s->nx, float(s->lambda * s->tau), float(s->tau / s->h));
+// ---------------------------------------------------------------- fused iterations
+template <int N> struct Fused {
+  static void rof_A(gp_ctx* c, const float* u, const float* pin, float* pout, const float* I, float* rhat, int ny,
+                    float lt, float tau_h, float sig_h, int aniso, int mode, double* partials) {
+    using SH = RowShape<N, float2>;
+    const int blocks = (ny / 2 + SH::G - 1) / SH::G;
+    const Tables& T = c->tab[ilog2i(N)];
+    hipLaunchKernelGGL((k_rof_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, u, pin, pout, I,
+                       rhat, ny, lt, tau_h, sig_h, aniso, mode, partials, T.tw32, T.dw32);
+  }
+  static void rof_B(gp_ctx* c, const float* dhat, float* u, int ny) {
+    using SH = RowShape<N, float2>;
+    const int blocks = (ny / 2 + SH::G - 1) / SH::G;
+    const Tables& T = c->tab[ilog2i(N)];
+    hipLaunchKernelGGL((k_rof_B<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, dhat, u, ny, T.tw32,
+                       T.dw32);
+  }
+  static void emd_A(gp_ctx* c, const float* wt_in, const double* phi, const float* pin, const float* gpsi,
+                    const float* f, float* pout, float* wt_out, double* rhat, int ny, double inv_h, float tau,
+                    float sigma, int aniso, int mode, double* partials) {
+    using SH = RowShape<N, double2>;
+    const int blocks = (ny / 2 + SH::G - 1) / SH::G;
+    const Tables& T = c->tab[ilog2i(N)];
+    hipLaunchKernelGGL((k_emd_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, wt_in, phi, pin,
+                       gpsi, f, pout, wt_out, rhat, ny, inv_h, tau, sigma, aniso, mode, partials, T.tw64, T.dw64);
+  }
+};
+
+int rows_blocks_f32(int nx, int ny) {
+  switch (nx) {
+#define GP_RB(NN) case NN: return (ny / 2 + RowShape<NN, float2>::G - 1) / RowShape<NN, float2>::G;
+    GP_RB(64) GP_RB(128) GP_RB(256) GP_RB(512) GP_RB(1024) GP_RB(2048) GP_RB(4096)
+#undef GP_RB
+  }
+  return 0;
+}
+int rows_blocks_f64(int nx, int ny) {
+  switch (nx) {
+#define GP_RB(NN) case NN: return (ny / 2 + RowShape<NN, double2>::G - 1) / RowShape<NN, double2>::G;
+    GP_RB(64) GP_RB(128) GP_RB(256) GP_RB(512) GP_RB(1024) GP_RB(2048) GP_RB(4096)
+#undef GP_RB
+  }
+  return 0;
+}
+
+// ROF pipeline.  A(entry) builds rhat from (u_n, pbar_n); each later A advances the
+// dual (p ping-pong between the two state buffers) and builds the next rhat.
+struct RofPipe {
+  gp_ctx* c;
+  const gp_state* s;
+  float* X;  // buffer holding the latest complete dual iterate
+  float* Y;  // the other dual buffer
+  size_t n;
+  float lt, tau_h, sig_h;
+};
+
+int rof_A(RofPipe& P, int mode, double* partials) {
+  gp_ctx* c = P.c;
+  const gp_state* s = P.s;
+  const double by = (mode == 1 ? 20.0 : 28.0) * double(P.n);
+  const int ps = prof_begin(c, K_ROF_A, by);
+  const float* pin = (mode == 1) ? s->pbar : P.X;
+  GP_DISPATCH_NM(s->nx, Fused, rof_A, c, s->u, pin, P.Y, s->f, c->work, s->ny, P.lt, P.tau_h, P.sig_h, s->norm,
+                mode, partials);
   prof_end(c, ps);
   LAUNCHCHK(c);
-  int rc = poisson_f32(c, c->work, c->work, s->ny, s->nx, s->lambda * s->tau);
-  if (rc) return rc;
-  ps = prof_begin(c, K_AXPY, 12.0 * n);
-  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, c->stream, s->u, c->work, n);
+  if (mode == 0) std::swap(P.X, P.Y);
+  return GP_OK;
+}
+
+int rof_CB(RofPipe& P) {
+  gp_ctx* c = P.c;
+  const gp_state* s = P.s;
+  const double fb = 8.0 * double(P.n);
+  int ps = prof_begin(c, K_COLS, fb);
+  GP_DISPATCH_N(s->ny, Solve<float2>::cols, c, c->work, s->nx, c->mux32, c->muy32, float(s->lambda * s->tau),
+                float(1.0 / double(P.n)));
   prof_end(c, ps);
   LAUNCHCHK(c);
-  ps = prof_begin(c, K_ROF_DUAL, 28.0 * n);
-  hipLaunchKernelGGL(k_rof_dual, dim3(grid_for(n)), dim3(256), 0, c->stream, s->u, px, py, bx, by, s->ny, s->nx,
-                     float(s->sigma / s->h), s->norm);
+  ps = prof_begin(c, K_ROF_B, 12.0 * double(P.n));
+  GP_DISPATCH_NM(s->nx, Fused, rof_B, c, c->work, s->u, s->ny);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
 
-// one EMD iteration; partials != nullptr accumulates sum |u+ + grad psi| into c->partials
-int emd_iter(gp_ctx* c, const gp_state* s, bool want_primal, int* nb_out) {
-  const size_t n = size_t(s->ny) * s->nx;
-  float* w = c->work2;
-  int ps = prof_begin(c, K_EMD_SHIFT, 24.0 * n);
-  hipLaunchKernelGGL(k_emd_shift, dim3(grid_for(2 * n)), dim3(256), 0, c->stream, s->u, s->pbar, w, 2 * n,
-                     float(s->tau));
+int rof_finish(RofPipe& P) {
+  gp_ctx* c = P.c;
+  const gp_state* s = P.s;
+  const int ps = prof_begin(c, K_ROF_FINISH, 28.0 * double(P.n));
+  hipLaunchKernelGGL(k_rof_finish, dim3(grid_for(P.n)), dim3(256), 0, c->stream, s->u, P.X, s->p, s->pbar, s->ny,
+                     s->nx, P.sig_h, s->norm);
   prof_end(c, ps);
   LAUNCHCHK(c);
-  // -div w, so that the solve (0 I - Delta) phi = -div w gives phi = Delta^{-1} div w;
-  // div w has zero mean exactly and the solve drops the zero mode.  The solve
-  // runs in FP64 so that grad phi keeps FP32 accuracy (see k_emd_update).
-  double* phi = c->work64;
-  ps = prof_begin(c, K_DIV64, 16.0 * n);
-  hipLaunchKernelGGL(k_div<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, w, w + n, phi, s->ny, s->nx,
-                     float(-1.0 / s->h));
-  prof_end(c, ps);
-  LAUNCHCHK(c);
-  int rc = poisson_f64(c, phi, phi, s->ny, s->nx, 0.0);
-  if (rc) return rc;
-  const int nb = want_primal ? red_blocks(n) : grid_for(n);
-  ps = prof_begin(c, K_EMD_UPDATE, 56.0 * n);
-  hipLaunchKernelGGL(k_emd_update, dim3(nb), dim3(256), 0, c->stream, phi, w, w + n, s->u, s->u + n, s->p,
-                     s->p + n, s->pbar, s->pbar + n, s->gpsi, s->gpsi + n, s->ny, s->nx, 1.0 / s->h,
-                     float(s->sigma), s->norm, want_primal ? c->partials : nullptr);
-  prof_end(c, ps);
-  LAUNCHCHK(c);
-  if (nb_out) *nb_out = nb;
   return GP_OK;
+}
+
+RofPipe rof_pipe(gp_ctx* c, const gp_state* s) {
+  RofPipe P{c, s, s->p, s->pbar, size_t(s->ny) * s->nx, float(s->lambda * s->tau), float(s->tau / s->h),
+            float(s->sigma / s->h)};
+  return P;
+}
+
+// advance (u_n, p_n, pbar_n) by k >= 1 iterations
+int rof_advance(gp_ctx* c, const gp_state* s, int k) {
+  RofPipe P = rof_pipe(c, s);
+  int rc = rof_A(P, 1, nullptr);
+  for (int i = 0; !rc && i < k; ++i) {
+    rc = rof_CB(P);
+    if (!rc && i + 1 < k) rc = rof_A(P, 0, nullptr);
+  }
+  if (!rc) rc = rof_finish(P);
+  return rc;
+}
+
+// EMD pipeline: wt ping-pong in work2/work3, phi in work64[0, n), rhat in work64[n, 2n).
+struct EmdPipe {
+  gp_ctx* c;
+  const gp_state* s;
+  float *X, *Y;    // dual buffers
+  float *WX, *WY;  // wt buffers (WX = latest)
+  double *phi, *rhat;
+  size_t n;
+};
+
+EmdPipe emd_pipe(gp_ctx* c, const gp_state* s) {
+  const size_t n = size_t(s->ny) * s->nx;
+  EmdPipe P{c, s, s->p, s->pbar, c->work3, c->work2, c->work64, c->work64 + n, n};
+  return P;
+}
+
+int emd_A(EmdPipe& P, int mode, double* partials) {
+  gp_ctx* c = P.c;
+  const gp_state* s = P.s;
+  const double by = (mode == 1 ? 44.0 : 52.0) * double(P.n);
+  const int ps = prof_begin(c, K_EMD_A, by);
+  const float* win = (mode == 1) ? s->u : P.WX;
+  const float* pin = (mode == 1) ? s->pbar : P.X;
+  GP_DISPATCH_NM(s->nx, Fused, emd_A, c, win, P.phi, pin, s->gpsi, s->f, P.Y, P.WY, P.rhat, s->ny, 1.0 / s->h,
+                float(s->tau), float(s->sigma), s->norm, mode, partials);
+  prof_end(c, ps);
+  LAUNCHCHK(c);
+  std::swap(P.WX, P.WY);
+  if (mode == 0) std::swap(P.X, P.Y);
+  return GP_OK;
+}
+
+int emd_CB(EmdPipe& P) {
+  gp_ctx* c = P.c;
+  const gp_state* s = P.s;
+  int ps = prof_begin(c, K_COLS64, 16.0 * double(P.n));
+  GP_DISPATCH_N(s->ny, Solve<double2>::cols, c, P.rhat, s->nx, c->mux64, c->muy64, 0.0, 1.0 / double(P.n));
+  prof_end(c, ps);
+  LAUNCHCHK(c);
+  ps = prof_begin(c, K_EMD_B, 16.0 * double(P.n));
+  GP_DISPATCH_N(s->nx, Solve<double2>::rows_inv, c, P.rhat, P.phi, s->ny);
+  prof_end(c, ps);
+  LAUNCHCHK(c);
+  return GP_OK;
+}
+
+// write (u, p, pbar) of the state from (wt, phi, latest p); m and partials optional
+int emd_finish(EmdPipe& P, float* m, double* partials, int nb) {
+  gp_ctx* c = P.c;
+  const gp_state* s = P.s;
+  const int ps = prof_begin(c, K_EMD_FINISH, 56.0 * double(P.n));
+  hipLaunchKernelGGL(k_emd_finish, dim3(nb), dim3(256), 0, c->stream, P.WX, P.phi, P.X, s->gpsi, s->p, s->pbar,
+                     s->u, m, s->ny, s->nx, 1.0 / s->h, float(s->sigma), s->norm, partials);
+  prof_end(c, ps);
+  LAUNCHCHK(c);
+  return GP_OK;
+}
+
+int emd_advance(gp_ctx* c, const gp_state* s, int k) {
+  EmdPipe P = emd_pipe(c, s);
+  int rc = emd_A(P, 1, nullptr);
+  for (int i = 0; !rc && i < k; ++i) {
+    rc = emd_CB(P);
+    if (!rc && i + 1 < k) rc = emd_A(P, 0, nullptr);
+  }
+  if (!rc) rc = emd_finish(P, nullptr, nullptr, grid_for(P.n));
+  return rc;
 }
 
 int rof_gap(gp_ctx* c, const gp_state* s, double* P, double* D) {
@@ -486,23 +627,27 @@ int rof_gap(gp_ctx* c, const gp_state* s, double* P, double* D) {
 
 // certificate D from p: phi = Delta^{-1} div p, D = -h^2 sum phi f / max(1, max|grad phi|).
 // Leaves -phi (FP64) in c->work64; *L receives max|grad phi|.
-int emd_cert(gp_ctx* c, const gp_state* s, double* D, double* L) {
+int emd_cert(gp_ctx* c, const gp_state* s, double* D, double* L, double* phi) {
   const size_t n = size_t(s->ny) * s->nx;
-  double* phi = c->work64;
+  int ps = prof_begin(c, K_DIV64, 16.0 * n);
   hipLaunchKernelGGL(k_div<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, s->p, s->p + n, phi, s->ny, s->nx,
                      float(1.0 / s->h));
+  prof_end(c, ps);
   LAUNCHCHK(c);
-  // Delta phi = div p  <=>  (0 I - Delta) phi = -div p: solve for -phi and flip in the certificate
+  // Delta phi = div p  <=>  (0 I - Delta) phi = -div p: this solves for -phi; the sign is
+  // folded into D below
   int rc = poisson_f64(c, phi, phi, s->ny, s->nx, 0.0);
   if (rc) return rc;
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_emd_cert, dim3(nb), dim3(256), 0, c->stream, phi, s->f, s->ny, s->nx, 1.0 / s->h,
-                     s->norm, c->partials);
+  ps = prof_begin(c, K_REDUCE, 12.0 * n);
+  hipLaunchKernelGGL(k_emd_cert, dim3(nb), dim3(256), 0, c->stream, phi, s->f, s->ny, s->nx, 1.0 / s->h, s->norm,
+                     c->partials);
+  prof_end(c, ps);
   LAUNCHCHK(c);
   double r[2];
   rc = finalize_read(c, nb, 2, 2u, r);
   if (rc) return rc;
-  // c->work holds -phi; sum(-phi f) = r[0]
+  // phi holds -phi_c; sum(-phi_c f) = r[0]
   *L = r[1];
   *D = s->h * s->h * r[0] / (r[1] > 1.0 ? r[1] : 1.0);
   return GP_OK;
@@ -576,6 +721,7 @@ int gp_create(gp_ctx** out, int max_ny, int max_nx, void* stream) {
   const size_t n = size_t(max_ny) * max_nx;
   bool ok = hipMalloc(&c->work, n * sizeof(float)) == hipSuccess &&
             hipMalloc(&c->work2, 2 * n * sizeof(float)) == hipSuccess &&
+            hipMalloc(&c->work3, 2 * n * sizeof(float)) == hipSuccess &&
             hipMalloc(&c->work64, 2 * n * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->partials, size_t(kRedBlocks) * kMaxK * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->result, kMaxK * sizeof(double)) == hipSuccess &&
@@ -610,7 +756,7 @@ int gp_destroy(gp_ctx* c) {
     if (T.dw32) (void)hipFree(T.dw32);
     if (T.dw64) (void)hipFree(T.dw64);
   }
-  float* fb[] = {c->work, c->work2, c->mux32, c->muy32, c->arena};
+  float* fb[] = {c->work, c->work2, c->work3, c->mux32, c->muy32, c->arena};
   for (float* p : fb)
     if (p) (void)hipFree(p);
   double* db[] = {c->work64, c->partials, c->result, c->mux64, c->muy64};
@@ -661,12 +807,10 @@ int pd_step(gp_ctx* c, gp_state* s, int n_iter) {
     return GP_EINVAL;
   }
   int rc = validate_state(c, s);
+  if (rc || n_iter == 0) return rc;
+  rc = (s->kind == GP_KIND_ROF) ? rof_advance(c, s, n_iter) : emd_advance(c, s, n_iter);
   if (rc) return rc;
-  for (int k = 0; k < n_iter; ++k) {
-    rc = (s->kind == GP_KIND_ROF) ? rof_iter(c, s) : emd_iter(c, s, false, nullptr);
-    if (rc) return rc;
-    ++s->iter;
-  }
+  s->iter += n_iter;
   return GP_OK;
 }
 
@@ -679,7 +823,7 @@ int pd_gap(gp_ctx* c, gp_state* s, gp_report* rep) {
     rc = rof_gap(c, s, &P, &D);
   } else {
     rc = emd_primal(c, s, &P);
-    if (!rc) rc = emd_cert(c, s, &D, &L);
+    if (!rc) rc = emd_cert(c, s, &D, &L, c->work64);
   }
   if (rc) return rc;
   if (rep) {
@@ -722,28 +866,40 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
     set_err(c, "arena allocation of %zu floats failed", 4 * n);
     return GP_ENOMEM;
   }
-  float* pp = p ? p : ar;
-  float* pb = ar + 2 * n;
-  if (!o->warm_start) {
-    HIPCHK(c, hipMemsetAsync(u, 0, n * sizeof(float), c->stream));
-    HIPCHK(c, hipMemsetAsync(pp, 0, 2 * n * sizeof(float), c->stream));
-  } else if (!p) {
-    HIPCHK(c, hipMemsetAsync(pp, 0, 2 * n * sizeof(float), c->stream));
+  // dual buffers: P0 holds p_0 (and the final p), P1 holds pbar_0
+  float* P0 = ar;
+  float* P1 = ar + 2 * n;
+  if (o->warm_start && p) {
+    HIPCHK(c, hipMemcpyAsync(P0, p, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    HIPCHK(c, hipMemsetAsync(P0, 0, 2 * n * sizeof(float), c->stream));
   }
-  HIPCHK(c, hipMemcpyAsync(pb, pp, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-  gp_state s{GP_KIND_ROF, ny, nx, o->norm, h, lambda, tau, sigma, I, nullptr, u, pp, pb, 0};
+  if (!o->warm_start) HIPCHK(c, hipMemsetAsync(u, 0, n * sizeof(float), c->stream));
+  HIPCHK(c, hipMemcpyAsync(P1, P0, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  gp_state s{GP_KIND_ROF, ny, nx, o->norm, h, lambda, tau, sigma, I, nullptr, u, P0, P1, 0};
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t1 = now_s();
   double P = NAN, D = NAN, g = NAN;
   bool conv = false;
   int it = 0;
+  RofPipe pipe = rof_pipe(c, &s);
+  rc = rof_A(pipe, 1, nullptr);
+  if (rc) return rc;
+  const int nb = rows_blocks_f32(nx, ny);
   while (it < o->max_iter) {
-    rc = rof_iter(c, &s);
+    rc = rof_CB(pipe);  // u_{it+1}
     if (rc) return rc;
     ++it;
-    if (it % o->check_every == 0 || it == o->max_iter) {
-      rc = rof_gap(c, &s, &P, &D);
+    const bool chk = (it % o->check_every == 0) || (it == o->max_iter);
+    // A computes p_it from (u_it, p_{it-1}) and, on checks, the gap of (u_it, p_it)
+    rc = rof_A(pipe, 0, chk ? c->partials : nullptr);
+    if (rc) return rc;
+    if (chk) {
+      double r[4];
+      rc = finalize_read(c, nb, 4, 0u, r);
       if (rc) return rc;
+      P = h * r[0] + 0.5 * lambda * h * h * r[1];
+      D = -h * r[2] - r[3] / (2.0 * lambda);
       g = rel_gap(P, D);
       if (!std::isfinite(g)) {
         set_err(c, "duality gap became non-finite at iteration %d", it);
@@ -755,6 +911,7 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
       }
     }
   }
+  if (p) HIPCHK(c, hipMemcpyAsync(p, pipe.X, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t2 = now_s();
   if (rep) {
@@ -825,40 +982,44 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   rc = prepare(c, ny, nx, h);
   if (rc) return rc;
   const size_t n = size_t(ny) * nx;
-  float* ar = arena(c, 9 * n);
+  // arena: f, grad psi, u, P0, P1, certificate scratch (n doubles)
+  float* ar = arena(c, 11 * n);
   if (!ar) {
-    set_err(c, "arena allocation of %zu floats failed", 9 * n);
+    set_err(c, "arena allocation of %zu floats failed", 11 * n);
     return GP_ENOMEM;
   }
   float* f = ar;
   float* gpsi = ar + n;
   float* u = ar + 3 * n;
-  float* p = ar + 5 * n;
-  float* pb = ar + 7 * n;
+  float* P0 = ar + 5 * n;
+  float* P1 = ar + 7 * n;
+  double* cphi = reinterpret_cast<double*>(ar + 9 * n);
   rc = emd_setup(c, rho0, rho1, f, gpsi, ny, nx, h);
   if (rc) return rc;
   HIPCHK(c, hipMemsetAsync(u, 0, 2 * n * sizeof(float), c->stream));
+  HIPCHK(c, hipMemsetAsync(P0, 0, 2 * n * sizeof(float), c->stream));
   if (o->warm_start) {
-    // p0 = proj(grad phi0), reusing the dual-update kernel with u = 0, grad psi -> grad phi0
-    float* g = c->work2;
-    HIPCHK(c, hipMemsetAsync(p, 0, 2 * n * sizeof(float), c->stream));
-    hipLaunchKernelGGL(k_rof_dual, dim3(grid_for(n)), dim3(256), 0, c->stream, phi, p, p + n, g, g + n, ny, nx,
+    // p0 = proj(grad phi0): the ROF dual step with u = phi0, p = 0, sigma/h = 1/h
+    hipLaunchKernelGGL(k_rof_finish, dim3(grid_for(n)), dim3(256), 0, c->stream, phi, P0, P0, P1, ny, nx,
                        float(1.0 / h), o->norm);
     LAUNCHCHK(c);
-  } else {
-    HIPCHK(c, hipMemsetAsync(p, 0, 2 * n * sizeof(float), c->stream));
   }
-  HIPCHK(c, hipMemcpyAsync(pb, p, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-  gp_state s{GP_KIND_EMD, ny, nx, o->norm, h, 0.0, tau, sigma, f, gpsi, u, p, pb, 0};
+  HIPCHK(c, hipMemcpyAsync(P1, P0, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  gp_state s{GP_KIND_EMD, ny, nx, o->norm, h, 0.0, tau, sigma, f, gpsi, u, P0, P1, 0};
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t1 = now_s();
   double P = NAN, D = NAN, g = NAN, L = 0;
   bool conv = false;
   int it = 0;
+  EmdPipe pipe = emd_pipe(c, &s);
+  rc = emd_A(pipe, 1, nullptr);
+  if (rc) return rc;
+  const int nb = rows_blocks_f64(nx, ny);
   while (it < o->max_iter) {
+    rc = emd_CB(pipe);  // phi_it
+    if (rc) return rc;
     const bool chk = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter);
-    int nb = 0;
-    rc = emd_iter(c, &s, chk, &nb);
+    rc = emd_A(pipe, 0, chk ? c->partials : nullptr);  // u_{it+1}, p_{it+1}
     if (rc) return rc;
     ++it;
     if (chk) {
@@ -866,7 +1027,9 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
       rc = finalize_read(c, nb, 1, 0u, r);
       if (rc) return rc;
       P = h * h * r[0];
-      rc = emd_cert(c, &s, &D, &L);
+      gp_state cs = s;
+      cs.p = pipe.X;
+      rc = emd_cert(c, &cs, &D, &L, cphi);
       if (rc) return rc;
       g = rel_gap(P, D);
       if (!std::isfinite(g)) {
@@ -879,12 +1042,13 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
       }
     }
   }
-  // outputs: flux m = u + grad psi; scaled certificate potential phi
-  hipLaunchKernelGGL(k_add2, dim3(grid_for(2 * n)), dim3(256), 0, c->stream, u, gpsi, m, 2 * n);
+  // flux m_it = wt_{it-1} - grad phi_{it-1} (the A that produced p_it read these)
+  hipLaunchKernelGGL(k_emd_finish, dim3(grid_for(n)), dim3(256), 0, c->stream, pipe.WY, pipe.phi, nullptr, gpsi,
+                     nullptr, nullptr, nullptr, m, ny, nx, 1.0 / h, float(sigma), o->norm, nullptr);
   LAUNCHCHK(c);
   if (phi) {
-    // c->work64 holds -phi_c from the last certificate; phi~ = phi_c / max(1, L)
-    hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, c->work64, phi, n,
+    // cphi holds -phi_c from the last certificate; phi~ = phi_c / max(1, L)
+    hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, cphi, phi, n,
                        -1.0 / (L > 1.0 ? L : 1.0));
     LAUNCHCHK(c);
   }

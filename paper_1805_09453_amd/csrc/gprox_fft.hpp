@@ -140,13 +140,16 @@ template <int N> struct Sched {
   static constexpr int irad(int p) { return rad(NP - 1 - p); }
   static constexpr int ls(int p) { int l = 1; for (int i = 0; i < p; ++i) l *= rad(i); return l; }
   static constexpr int ils(int p) { int l = 1; for (int i = 0; i < p; ++i) l *= irad(i); return l; }
-  // twiddle tables: per pass, LS rows of R entries (entry r = W_{LS R}^{j r})
+  // twiddle tables: per pass, R rows of LS entries (entry [r][j] = W_{LS R}^{j r}),
+  // so a wave's lanes (consecutive j) read one contiguous span per r
   static constexpr int toff(int p) { int o = 0; for (int i = 0; i < p; ++i) o += ls(i) * rad(i); return o; }
   static constexpr int tsize() { return toff(NP); }
   static constexpr int itoff(int p) { int o = tsize(); for (int i = 0; i < p; ++i) o += ils(i) * irad(i); return o; }
   static constexpr int total_tw() { return itoff(NP); }
-  // padded LDS index and region size (one pad slot per 16 complex values)
-  static constexpr int LDS = N + N / 16 + 2;
+  // padded LDS index and per-sequence region size: one pad slot per 16 complex
+  // values, and a region stride of 8 mod 32 complex values so that groups
+  // interleaved lane-by-lane (the column pass) start on different banks
+  static constexpr int LDS = ((N + N / 16 + 31) / 32) * 32 + 8;
 };
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
@@ -169,9 +172,8 @@ __device__ __forceinline__ void stockham_pass(C (&v)[32], const int (&bi)[32 / R
   for (int q = 0; q < NB; ++q) {
     if constexpr (LS > 1) {
       const int j = bi[q] & (LS - 1);
-      const C* __restrict__ tj = tw + j * R;
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], tj[r]);
+      for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], tw[r * LS + j]);
     }
     DFT<R, INV, C>::run(&v[q * R]);
   }

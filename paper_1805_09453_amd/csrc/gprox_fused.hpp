@@ -1,0 +1,541 @@
+// Fused G-prox PDHG iteration kernels (gfx950).
+//
+// One iteration of Algorithm 2 is split into three launches so that no FFT
+// ever needs a neighbouring row:
+//
+//   A (row pass):  the pointwise dual step of the PREVIOUS iteration together
+//                  with the right-hand side of the next u-step, evaluated from
+//                  stored fields with a one-row / one-column halo, written to
+//                  LDS in Makhoul order and transformed by a row DCT-II;
+//                  duality-gap partial sums are fused in.
+//   C (column pass): DCT-II -> 1/(alpha + mu) -> inverse DCT-II along y
+//                  (k_cols_solve in gprox_kernels.hpp).
+//   B (row pass):  row inverse DCT-II fused with the primal update.
+//
+// ROF (section 3.1 updates, incremental form u+ = u + (lambda tau - Delta)^{-1} r):
+//   A: p_n = proj(p_{n-1} + sigma grad u_n), pbar_n = 2 p_n - p_{n-1},
+//      r_n = lambda tau (I - u_n) + tau div pbar_n            -> row DCT
+//   B: u_{n+1} = u_n + delta                                   (row IDCT)
+//   HBM bytes per pixel-iteration: A reads u, p, I (16) and writes p, r (12);
+//   C reads and writes r (8); B reads r, u and writes u (12): 48 B.
+//
+// EMD (section 3.2 updates, projected form u+ = P(u - tau pbar)), with the
+// stored field wt = u - tau pbar + grad psi:
+//   A: m_{n+1} = wt_n - grad phi_n            (= u_{n+1} + grad psi)
+//      p_{n+1} = proj(p_n + sigma m_{n+1}), pbar = 2 p_{n+1} - p_n,
+//      wt_{n+1} = m_{n+1} - tau pbar,
+//      r = f - div wt_{n+1}   (= -div(u_{n+1} - tau pbar), since div grad psi = f)
+//                                                             -> row DCT (FP64)
+//   B: phi_{n+1} = Delta^{-1} div(u_{n+1} - tau pbar_{n+1})  (row IDCT, FP64)
+//   The potential stays FP64 so that grad phi keeps FP32 accuracy.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "gprox_fft.hpp"
+#include "gprox_kernels.hpp"
+
+namespace gp {
+
+// Forward DCT-II of two real sequences already in LDS in Makhoul order
+// (lds[lpad(m)] = (a, b)-packed v_m).  Layout of the result as dct2_fwd.
+template <int N, class C>
+__device__ __forceinline__ void dct2_fwd_lds(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+                                             const C* __restrict__ dctw) {
+  using S = Sched<N>;
+  using Re = typename Cx<C>::R;
+  constexpr int R0 = S::rad(0);
+  {
+    int bi[32 / R0];
+    bidx_seq<N, R0>(t, bi);
+    stockham_pass<N, R0, 1, false, true, true>(v, bi, lds, tw + S::toff(0));
+  }
+  middle_passes<N, false, 1, S::NP - 1, C>(t, v, lds, tw);
+  {
+    constexpr int PL = S::NP - 1;
+    int bi[2];
+    bidx_dc<N, 16>(t, bi);
+    stockham_pass<N, 16, S::ls(PL), false, true, false>(v, bi, lds, tw + S::toff(PL));
+  }
+  const C* __restrict__ w = dctw;
+  if (t != 0) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k0 = t + s * (N / 16);
+      const int k1 = N - k0;
+      C z0 = v[s], z1 = v[16 + 15 - s];
+      C w0 = w[k0], w1 = w[k1];
+      C a0 = cmul(w0, z0), c0 = cmul(w0, conjc(z1));
+      C a1 = cmul(w1, z1), c1 = cmul(w1, conjc(z0));
+      v[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
+      v[16 + 15 - s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
+    }
+  } else {
+    C o[32];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k0 = s * (N / 16);
+      C z0 = v[s], zp = v[(16 - s) & 15];
+      C w0 = w[k0];
+      C a0 = cmul(w0, z0), c0 = cmul(w0, conjc(zp));
+      o[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
+      const int k1 = N / 32 + s * (N / 16);
+      C z1 = v[16 + s], zq = v[16 + 15 - s];
+      C w1 = w[k1];
+      C a1 = cmul(w1, z1), c1 = cmul(w1, conjc(zq));
+      o[16 + s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = o[i];
+  }
+}
+
+// store (ra, rb) of column j (natural order) into the Makhoul-ordered LDS sequence
+template <int N, class C>
+__device__ __forceinline__ void mk_put(C* lds, int j, typename Cx<C>::R ra, typename Cx<C>::R rb) {
+  const int m = (j & 1) ? (N - 1 - (j >> 1)) : (j >> 1);
+  lds[lpad(m)] = mk<C>(ra, rb);
+}
+
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+__device__ __forceinline__ float f4(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+
+// pointwise ROF dual step at one cell: p_new = proj(p + s grad u)
+__device__ __forceinline__ void rof_dual_pt(float px, float py, float gx, float gy, float s, int aniso, float& ox,
+                                            float& oy) {
+  ox = px + s * gx;
+  oy = py + s * gy;
+  proj_ball(ox, oy, aniso);
+}
+
+// ---------------------------------------------------------------- ROF A
+// mode 0 (steady): p_in = p_{n-1}; computes p_n (written to p_out) and pbar_n.
+// mode 1 (entry):  p_in = pbar_n given by the caller; p_out unused.
+// Gap partials (mode 0, partials != nullptr): [sum|grad u|, sum (u-I)^2,
+// sum I div p_n, sum (div p_n)^2] in 1/h units.
+template <int N>
+__global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, const float* __restrict__ pin,
+                                               float* __restrict__ pout, const float* __restrict__ I,
+                                               float* __restrict__ rhat, int ny, float lt, float tau_h, float sig_h,
+                                               int aniso, int mode, double* __restrict__ partials,
+                                               const float2* __restrict__ tw, const float2* __restrict__ dctw) {
+  using SH = RowShape<N, float2>;
+  constexpr int T = SH::T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* smem = reinterpret_cast<float2*>(smem_raw);
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  float2* lds = smem + g * Sched<N>::LDS;
+  const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
+  const bool valid = a < ny;  // ny is even
+  const size_t n = size_t(ny) * N;
+  const float* pinx = pin;
+  const float* piny = pin + n;
+  double acc[4] = {0, 0, 0, 0};
+  if (valid) {
+    const bool has_up = a > 0, has_dn = b + 1 < ny;
+    const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+      const int c = 4 * (t + T * k);
+      const bool has_l = c > 0, has_r = c + 4 < N;
+      float ra[4], rb[4];
+      if (mode == 0) {
+        // u at rows a-1, a, b, b+1 (columns c-1 .. c+4 where needed)
+        const float4 uU = has_up ? ld4(u + ou + c) : make_float4(0, 0, 0, 0);
+        const float4 uA = ld4(u + oa + c), uB = ld4(u + ob + c);
+        const float4 uD = has_dn ? ld4(u + od + c) : uB;
+        const float uU4 = (has_up && has_r) ? u[ou + c + 4] : 0.f;
+        const float uA4 = has_r ? u[oa + c + 4] : 0.f, uB4 = has_r ? u[ob + c + 4] : 0.f;
+        const float uAl = has_l ? u[oa + c - 1] : 0.f, uBl = has_l ? u[ob + c - 1] : 0.f;
+        const float uDl = has_l ? (has_dn ? u[od + c - 1] : uBl) : 0.f;
+        // p_{n-1}
+        const float4 pxU = has_up ? ld4(pinx + ou + c) : make_float4(0, 0, 0, 0);
+        const float4 pyU = has_up ? ld4(piny + ou + c) : make_float4(0, 0, 0, 0);
+        const float4 pxA = ld4(pinx + oa + c), pyA = ld4(piny + oa + c);
+        const float4 pxB = ld4(pinx + ob + c), pyB = ld4(piny + ob + c);
+        const float pxAl = has_l ? pinx[oa + c - 1] : 0.f, pyAl = has_l ? piny[oa + c - 1] : 0.f;
+        const float pxBl = has_l ? pinx[ob + c - 1] : 0.f, pyBl = has_l ? piny[ob + c - 1] : 0.f;
+        const float4 IA = ld4(I + oa + c), IB = ld4(I + ob + c);
+        // p_n and pbar_n at (a-1, c..c+3), (a, c-1..c+3), (b, c-1..c+3); index e = -1..3
+        float nxA[5], nyA[5], nxB[5], nyB[5], byU[4], bxA[5], byA[5], bxB[5], byB[5];
+#pragma unroll
+        for (int e = -1; e < 4; ++e) {
+          const int j = c + e;
+          const bool inx = j >= 0;
+          // row a
+          const float ua = e < 0 ? uAl : f4(uA, e);
+          const float uan = e < 3 ? f4(uA, e + 1) : uA4;
+          const float ub = e < 0 ? uBl : f4(uB, e);
+          const float gxa = (j < N - 1) ? (uan - ua) : 0.f;
+          const float gya = ub - ua;  // b = a + 1 < ny always
+          const float pxa = e < 0 ? pxAl : f4(pxA, e), pya = e < 0 ? pyAl : f4(pyA, e);
+          float ox, oy;
+          rof_dual_pt(pxa, pya, gxa, gya, sig_h, aniso, ox, oy);
+          nxA[e + 1] = inx ? ox : 0.f;
+          nyA[e + 1] = inx ? oy : 0.f;
+          bxA[e + 1] = inx ? 2.f * ox - pxa : 0.f;
+          byA[e + 1] = inx ? 2.f * oy - pya : 0.f;
+          // row b
+          const float ubn = e < 3 ? f4(uB, e + 1) : uB4;
+          const float ud = e < 0 ? uDl : f4(uD, e);
+          const float gxb = (j < N - 1) ? (ubn - ub) : 0.f;
+          const float gyb = has_dn ? (ud - ub) : 0.f;
+          const float pxb = e < 0 ? pxBl : f4(pxB, e), pyb = e < 0 ? pyBl : f4(pyB, e);
+          rof_dual_pt(pxb, pyb, gxb, gyb, sig_h, aniso, ox, oy);
+          nxB[e + 1] = inx ? ox : 0.f;
+          nyB[e + 1] = inx ? oy : 0.f;
+          bxB[e + 1] = inx ? 2.f * ox - pxb : 0.f;
+          byB[e + 1] = inx ? 2.f * oy - pyb : 0.f;
+          if (e >= 0) {
+            // row a-1 (only pbar_y is needed)
+            const float uu = f4(uU, e), uun = e < 3 ? f4(uU, e + 1) : uU4;
+            const float gxu = (j < N - 1) ? (uun - uu) : 0.f;
+            const float gyu = f4(uA, e) - uu;
+            rof_dual_pt(f4(pxU, e), f4(pyU, e), gxu, gyu, sig_h, aniso, ox, oy);
+            byU[e] = has_up ? 2.f * oy - f4(pyU, e) : 0.f;
+            // gap partials of (u_n, p_n) at rows a, b
+            if (partials) {
+              acc[0] += double(pnorm(gxa, gya, aniso)) + double(pnorm(gxb, gyb, aniso));
+              const float ea = f4(uA, e) - f4(IA, e), eb = f4(uB, e) - f4(IB, e);
+              acc[1] += double(ea) * ea + double(eb) * eb;
+              const float nyU = has_up ? oy : 0.f;
+              const float da = ((j < N - 1 ? nxA[e + 1] : 0.f) - nxA[e]) + (nyA[e + 1] - nyU);
+              const float db = ((j < N - 1 ? nxB[e + 1] : 0.f) - nxB[e]) + ((has_dn ? nyB[e + 1] : 0.f) - nyA[e + 1]);
+              acc[2] += double(f4(IA, e)) * da + double(f4(IB, e)) * db;
+              acc[3] += double(da) * da + double(db) * db;
+            }
+          }
+        }
+        // the far faces carry no flux
+        if (!has_r) {
+          nxA[4] = nxB[4] = bxA[4] = bxB[4] = 0.f;
+        }
+        if (!has_dn) {
+#pragma unroll
+          for (int e = 0; e < 5; ++e) nyB[e] = byB[e] = 0.f;
+        }
+        st4(pout + oa + c, make_float4(nxA[1], nxA[2], nxA[3], nxA[4]));
+        st4(pout + n + oa + c, make_float4(nyA[1], nyA[2], nyA[3], nyA[4]));
+        st4(pout + ob + c, make_float4(nxB[1], nxB[2], nxB[3], nxB[4]));
+        st4(pout + n + ob + c, make_float4(nyB[1], nyB[2], nyB[3], nyB[4]));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float dva = (bxA[e + 1] - bxA[e]) + (byA[e + 1] - byU[e]);
+          const float dvb = (bxB[e + 1] - bxB[e]) + (byB[e + 1] - byA[e + 1]);
+          ra[e] = lt * (f4(IA, e) - f4(uA, e)) + tau_h * dva;
+          rb[e] = lt * (f4(IB, e) - f4(uB, e)) + tau_h * dvb;
+        }
+      } else {
+        // entry: pbar given
+        const float4 uA = ld4(u + oa + c), uB = ld4(u + ob + c);
+        const float4 IA = ld4(I + oa + c), IB = ld4(I + ob + c);
+        const float4 xA = ld4(pinx + oa + c), yA = ld4(piny + oa + c);
+        const float4 xB = ld4(pinx + ob + c), yB = ld4(piny + ob + c);
+        const float4 yU = has_up ? ld4(piny + ou + c) : make_float4(0, 0, 0, 0);
+        const float xAl = has_l ? pinx[oa + c - 1] : 0.f, xBl = has_l ? pinx[ob + c - 1] : 0.f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = c + e;
+          const float xa = (j < N - 1) ? f4(xA, e) : 0.f, xb = (j < N - 1) ? f4(xB, e) : 0.f;
+          const float xal = e == 0 ? xAl : f4(xA, e - 1), xbl = e == 0 ? xBl : f4(xB, e - 1);
+          const float ya = f4(yA, e), yb = has_dn ? f4(yB, e) : 0.f;
+          const float dva = (xa - xal) + (ya - f4(yU, e));
+          const float dvb = (xb - xbl) + (yb - ya);
+          ra[e] = lt * (f4(IA, e) - f4(uA, e)) + tau_h * dva;
+          rb[e] = lt * (f4(IB, e) - f4(uB, e)) + tau_h * dvb;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) mk_put<N, float2>(lds, c + e, ra[e], rb[e]);
+    }
+  } else {
+    // keep the FFT well defined for an idle group (its results are discarded)
+#pragma unroll 1
+    for (int m = t; m < N; m += T) lds[lpad(m)] = make_float2(0.f, 0.f);
+  }
+  if (partials) {
+    const bool mx[4] = {false, false, false, false};
+    block_reduce_store<4>(acc, mx, partials);
+  }
+  __syncthreads();
+  float2 v[32];
+  dct2_fwd_lds<N>(t, v, lds, tw, dctw);
+  if (valid) {
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int k = dc_index<N>(t, slot, s);
+        rhat[size_t(a) * N + k] = v[slot * 16 + s].x;
+        rhat[size_t(b) * N + k] = v[slot * 16 + s].y;
+      }
+  }
+}
+
+// ---------------------------------------------------------------- ROF B
+// u += inverse row DCT of the column-solved field
+template <int N>
+__global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, float* __restrict__ u, int ny,
+                                               const float2* __restrict__ tw, const float2* __restrict__ dctw) {
+  using SH = RowShape<N, float2>;
+  constexpr int T = SH::T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* smem = reinterpret_cast<float2*>(smem_raw);
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  float2* lds = smem + g * Sched<N>::LDS;
+  const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
+  const bool valid = a < ny;
+  float2 v[32];
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = dc_index<N>(t, slot, s);
+      v[slot * 16 + s] = valid ? make_float2(dhat[size_t(a) * N + k], dhat[size_t(b) * N + k]) : make_float2(0, 0);
+    }
+  dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, float2 A, float2 B) {
+    if (valid) {
+      float2* pa = reinterpret_cast<float2*>(u + size_t(a) * N + 2 * m);
+      float2* pb = reinterpret_cast<float2*>(u + size_t(b) * N + 2 * m);
+      float2 xa = *pa, xb = *pb;
+      *pa = make_float2(xa.x + A.x, xa.y + A.y);
+      *pb = make_float2(xb.x + B.x, xb.y + B.y);
+    }
+  });
+}
+
+// ---------------------------------------------------------------- ROF finish
+// p_out = proj(p_in + sigma grad u), pbar_out = 2 p_out - p_in (pointwise in p:
+// p_in may alias p_out or pbar_out)
+__global__ __launch_bounds__(256) void k_rof_finish(const float* __restrict__ u, const float* pin, float* pout,
+                                                    float* pbar, int ny, int nx, float sig_h, int aniso) {
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const float uc = u[o];
+    const float gx = (j < nx - 1) ? (u[o + 1] - uc) : 0.f;
+    const float gy = (i < ny - 1) ? (u[o + nx] - uc) : 0.f;
+    const float ox = pin[o], oy = pin[o + n];
+    float qx, qy;
+    rof_dual_pt(ox, oy, gx, gy, sig_h, aniso, qx, qy);
+    pout[o] = qx;
+    pout[o + n] = qy;
+    pbar[o] = 2.f * qx - ox;
+    pbar[o + n] = 2.f * qy - oy;
+  }
+}
+
+// ---------------------------------------------------------------- EMD A (FP64 transform)
+// mode 0 (steady): wt_in = wt_n, phi = phi_n, p_in = p_n -> p_out = p_{n+1}, wt_out = wt_{n+1};
+//                  partials (nullable): [sum |m_{n+1}|].
+// mode 1 (entry):  u = u_n (in wt_in's place), p_in = pbar_n, gpsi = grad psi -> wt_out = wt_n.
+template <int N>
+__global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, const double* __restrict__ phi,
+                                               const float* __restrict__ pin, const float* __restrict__ gpsi,
+                                               const float* __restrict__ f, float* __restrict__ pout,
+                                               float* __restrict__ wt_out, double* __restrict__ rhat, int ny,
+                                               double inv_h, float tau, float sigma, int aniso, int mode,
+                                               double* __restrict__ partials, const double2* __restrict__ tw,
+                                               const double2* __restrict__ dctw) {
+  using SH = RowShape<N, double2>;
+  constexpr int T = SH::T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* smem = reinterpret_cast<double2*>(smem_raw);
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  double2* lds = smem + g * Sched<N>::LDS;
+  const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
+  const bool valid = a < ny;
+  const size_t n = size_t(ny) * N;
+  double acc[1] = {0};
+  if (valid) {
+    const bool has_up = a > 0, has_dn = b + 1 < ny;
+    const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+      const int c = 4 * (t + T * k);
+      const bool has_l = c > 0, has_r = c + 4 < N;
+      // new wt at (a-1, c..c+3) [y only], (a, c-1..c+3), (b, c-1..c+3)
+      float wxA[5], wyA[5], wxB[5], wyB[5], wyU[4];
+      if (mode == 0) {
+        // phi_n rows a-1..b+1
+        double fA[6], fB[6], fU[5], fD[5];  // index e+1 for columns c-1..c+4 (fU, fD: c..c+4 / c-1..c+3)
+        {
+          const double2* pa = reinterpret_cast<const double2*>(phi + oa + c);
+          const double2* pb = reinterpret_cast<const double2*>(phi + ob + c);
+          double2 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+          fA[1] = a0.x; fA[2] = a0.y; fA[3] = a1.x; fA[4] = a1.y;
+          fB[1] = b0.x; fB[2] = b0.y; fB[3] = b1.x; fB[4] = b1.y;
+          fA[0] = has_l ? phi[oa + c - 1] : 0.0;
+          fB[0] = has_l ? phi[ob + c - 1] : 0.0;
+          fA[5] = has_r ? phi[oa + c + 4] : 0.0;
+          fB[5] = has_r ? phi[ob + c + 4] : 0.0;
+          if (has_up) {
+            const double2* pu = reinterpret_cast<const double2*>(phi + ou + c);
+            double2 u0 = pu[0], u1 = pu[1];
+            fU[0] = u0.x; fU[1] = u0.y; fU[2] = u1.x; fU[3] = u1.y;
+            fU[4] = has_r ? phi[ou + c + 4] : 0.0;
+          } else {
+            fU[0] = fU[1] = fU[2] = fU[3] = fU[4] = 0.0;
+          }
+          if (has_dn) {
+            const double2* pd = reinterpret_cast<const double2*>(phi + od + c);
+            double2 d0 = pd[0], d1 = pd[1];
+            fD[1] = d0.x; fD[2] = d0.y; fD[3] = d1.x; fD[4] = d1.y;
+            fD[0] = has_l ? phi[od + c - 1] : 0.0;
+          } else {
+            fD[0] = fD[1] = fD[2] = fD[3] = fD[4] = 0.0;
+          }
+        }
+        const float4 wxa = ld4(wt_in + oa + c), wya = ld4(wt_in + n + oa + c);
+        const float4 wxb = ld4(wt_in + ob + c), wyb = ld4(wt_in + n + ob + c);
+        const float4 wyu = has_up ? ld4(wt_in + n + ou + c) : make_float4(0, 0, 0, 0);
+        const float4 wxu = has_up ? ld4(wt_in + ou + c) : make_float4(0, 0, 0, 0);
+        const float wxal = has_l ? wt_in[oa + c - 1] : 0.f, wyal = has_l ? wt_in[n + oa + c - 1] : 0.f;
+        const float wxbl = has_l ? wt_in[ob + c - 1] : 0.f, wybl = has_l ? wt_in[n + ob + c - 1] : 0.f;
+        const float4 pxa = ld4(pin + oa + c), pya = ld4(pin + n + oa + c);
+        const float4 pxb = ld4(pin + ob + c), pyb = ld4(pin + n + ob + c);
+        const float4 pxu = has_up ? ld4(pin + ou + c) : make_float4(0, 0, 0, 0);
+        const float4 pyu = has_up ? ld4(pin + n + ou + c) : make_float4(0, 0, 0, 0);
+        const float pxal = has_l ? pin[oa + c - 1] : 0.f, pyal = has_l ? pin[n + oa + c - 1] : 0.f;
+        const float pxbl = has_l ? pin[ob + c - 1] : 0.f, pybl = has_l ? pin[n + ob + c - 1] : 0.f;
+        float nxA[4], nyA[4], nxB[4], nyB[4];
+#pragma unroll
+        for (int e = -1; e < 4; ++e) {
+          const int j = c + e;
+          const bool inx = j >= 0, xin = j < N - 1;
+          // m = wt - grad phi at rows a and b
+          const float mxa = xin ? (e < 0 ? wxal : f4(wxa, e)) - float((fA[e + 2] - fA[e + 1]) * inv_h) : 0.f;
+          const float mya = (e < 0 ? wyal : f4(wya, e)) - float((fB[e + 1] - fA[e + 1]) * inv_h);
+          const float mxb = xin ? (e < 0 ? wxbl : f4(wxb, e)) - float((fB[e + 2] - fB[e + 1]) * inv_h) : 0.f;
+          const float myb = has_dn ? (e < 0 ? wybl : f4(wyb, e)) - float((fD[e + 1] - fB[e + 1]) * inv_h) : 0.f;
+          const float oxa = e < 0 ? pxal : f4(pxa, e), oya = e < 0 ? pyal : f4(pya, e);
+          const float oxb = e < 0 ? pxbl : f4(pxb, e), oyb = e < 0 ? pybl : f4(pyb, e);
+          float qxa = oxa + sigma * mxa, qya = oya + sigma * mya;
+          float qxb = oxb + sigma * mxb, qyb = oyb + sigma * myb;
+          proj_ball(qxa, qya, aniso);
+          proj_ball(qxb, qyb, aniso);
+          const float bxa = 2.f * qxa - oxa, bya = 2.f * qya - oya;
+          const float bxb = 2.f * qxb - oxb, byb = 2.f * qyb - oyb;
+          wxA[e + 1] = inx && xin ? mxa - tau * bxa : 0.f;
+          wyA[e + 1] = inx ? mya - tau * bya : 0.f;
+          wxB[e + 1] = inx && xin ? mxb - tau * bxb : 0.f;
+          wyB[e + 1] = inx && has_dn ? myb - tau * byb : 0.f;
+          if (e >= 0) {
+            nxA[e] = xin ? qxa : 0.f;
+            nyA[e] = qya;
+            nxB[e] = xin ? qxb : 0.f;
+            nyB[e] = has_dn ? qyb : 0.f;
+            if (partials) acc[0] += double(pnorm(mxa, mya, aniso)) + double(pnorm(mxb, myb, aniso));
+            // row a-1: y component of the new wt
+            if (has_up) {
+              const float mxu = xin ? f4(wxu, e) - float((fU[e + 1] - fU[e]) * inv_h) : 0.f;
+              const float myu = f4(wyu, e) - float((fA[e + 1] - fU[e]) * inv_h);
+              float qxu = f4(pxu, e) + sigma * mxu, qyu = f4(pyu, e) + sigma * myu;
+              proj_ball(qxu, qyu, aniso);
+              wyU[e] = myu - tau * (2.f * qyu - f4(pyu, e));
+            } else {
+              wyU[e] = 0.f;
+            }
+          }
+        }
+        st4(pout + oa + c, make_float4(nxA[0], nxA[1], nxA[2], nxA[3]));
+        st4(pout + n + oa + c, make_float4(nyA[0], nyA[1], nyA[2], nyA[3]));
+        st4(pout + ob + c, make_float4(nxB[0], nxB[1], nxB[2], nxB[3]));
+        st4(pout + n + ob + c, make_float4(nyB[0], nyB[1], nyB[2], nyB[3]));
+      } else {
+        // entry: wt_n = u_n - tau pbar_n + grad psi
+        const float* ux = wt_in;
+        const float* uy = wt_in + n;
+#pragma unroll
+        for (int e = -1; e < 4; ++e) {
+          const int j = c + e;
+          const bool inx = j >= 0, xin = j < N - 1;
+          const size_t ja = oa + (inx ? j : 0), jb = ob + (inx ? j : 0);
+          wxA[e + 1] = inx && xin ? ux[ja] - tau * pin[ja] + gpsi[ja] : 0.f;
+          wyA[e + 1] = inx ? uy[ja] - tau * pin[n + ja] + gpsi[n + ja] : 0.f;
+          wxB[e + 1] = inx && xin ? ux[jb] - tau * pin[jb] + gpsi[jb] : 0.f;
+          wyB[e + 1] = inx && has_dn ? uy[jb] - tau * pin[n + jb] + gpsi[n + jb] : 0.f;
+          if (e >= 0) {
+            const size_t ju = ou + j;
+            wyU[e] = has_up ? uy[ju] - tau * pin[n + ju] + gpsi[n + ju] : 0.f;
+          }
+        }
+      }
+      st4(wt_out + oa + c, make_float4(wxA[1], wxA[2], wxA[3], wxA[4]));
+      st4(wt_out + n + oa + c, make_float4(wyA[1], wyA[2], wyA[3], wyA[4]));
+      st4(wt_out + ob + c, make_float4(wxB[1], wxB[2], wxB[3], wxB[4]));
+      st4(wt_out + n + ob + c, make_float4(wyB[1], wyB[2], wyB[3], wyB[4]));
+      const float4 FA = ld4(f + oa + c), FB = ld4(f + ob + c);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float dva = (wxA[e + 1] - wxA[e]) + (wyA[e + 1] - wyU[e]);
+        const float dvb = (wxB[e + 1] - wxB[e]) + (wyB[e + 1] - wyA[e + 1]);
+        mk_put<N, double2>(lds, c + e, double(f4(FA, e)) - double(dva) * inv_h,
+                           double(f4(FB, e)) - double(dvb) * inv_h);
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int m = t; m < N; m += T) lds[lpad(m)] = make_double2(0.0, 0.0);
+  }
+  if (partials) {
+    const bool mx[1] = {false};
+    block_reduce_store<1>(acc, mx, partials);
+  }
+  __syncthreads();
+  double2 v[32];
+  dct2_fwd_lds<N>(t, v, lds, tw, dctw);
+  if (valid) {
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int k = dc_index<N>(t, slot, s);
+        rhat[size_t(a) * N + k] = v[slot * 16 + s].x;
+        rhat[size_t(b) * N + k] = v[slot * 16 + s].y;
+      }
+  }
+}
+
+// ---------------------------------------------------------------- EMD finish
+// m = wt - grad phi; p_out = proj(p_in + sigma m), pbar = 2 p_out - p_in,
+// u = m - grad psi (if u != nullptr), flux = m (if mout != nullptr),
+// partials (nullable): [sum |m|].  Pointwise in p (p_in may alias p_out or pbar).
+__global__ __launch_bounds__(256) void k_emd_finish(const float* __restrict__ wt, const double* __restrict__ phi,
+                                                    const float* pin, const float* __restrict__ gpsi, float* pout,
+                                                    float* pbar, float* __restrict__ u, float* __restrict__ mout,
+                                                    int ny, int nx, double inv_h, float sigma, int aniso,
+                                                    double* __restrict__ partials) {
+  double acc[1] = {0};
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const double fc = phi[o];
+    const float mx = (j < nx - 1) ? wt[o] - float((phi[o + 1] - fc) * inv_h) : 0.f;
+    const float my = (i < ny - 1) ? wt[o + n] - float((phi[o + nx] - fc) * inv_h) : 0.f;
+    if (pout) {
+      const float ox = pin[o], oy = pin[o + n];
+      float qx = ox + sigma * mx, qy = oy + sigma * my;
+      proj_ball(qx, qy, aniso);
+      pout[o] = qx;
+      pout[o + n] = qy;
+      pbar[o] = 2.f * qx - ox;
+      pbar[o + n] = 2.f * qy - oy;
+    }
+    if (u) {
+      u[o] = mx - gpsi[o];
+      u[o + n] = my - gpsi[o + n];
+    }
+    if (mout) {
+      mout[o] = mx;
+      mout[o + n] = my;
+    }
+    if (partials) acc[0] += double(pnorm(mx, my, aniso));
+  }
+  if (partials) {
+    const bool m[1] = {false};
+    block_reduce_store<1>(acc, m, partials);
+  }
+}
+
+}  // namespace gp

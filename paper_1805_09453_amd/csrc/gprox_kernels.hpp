@@ -17,8 +17,14 @@ namespace gp {
 // ------------------------------------------------------------ launch shapes
 template <int N, class C> struct RowShape {
   static constexpr int T = Sched<N>::T;
-  static constexpr int G = 256 / T;  // row pairs per block
-  static constexpr int THREADS = 256;
+  static constexpr int G1 = 256 / T;
+  static constexpr int G2 = int(147456 / (size_t(Sched<N>::LDS) * sizeof(C)));
+  static constexpr int G3 = G1 < G2 ? G1 : G2;
+  // whole 64-lane waves (the fused kernels reduce across waves)
+  static constexpr int GM = T >= 64 ? 1 : 64 / T;
+  static constexpr int G = (G3 / GM) * GM;  // row pairs per block
+  static constexpr int THREADS = G * T;
+  static_assert(G >= 1 && THREADS % 64 == 0 && THREADS <= 256, "row-pass shape");
   static constexpr size_t LDS_BYTES = size_t(G) * Sched<N>::LDS * sizeof(C);
 };
 template <int N, class C> struct ColShape {
@@ -105,7 +111,12 @@ __global__ __launch_bounds__((ColShape<N, C>::THREADS)) void k_cols_solve(
   C* smem = reinterpret_cast<C*>(smem_raw);
   const int g = threadIdx.x % SH::G, t = threadIdx.x / SH::G;
   C* lds = smem + g * Sched<N>::LDS;
-  const int c = 2 * (blockIdx.x * SH::G + g);
+  // XCD-aware strip order: workgroups are dealt round-robin to the 8 XCDs, so
+  // give each XCD a contiguous run of strips; strips that share cache lines
+  // then run together under one L2.
+  const int nstrip = gridDim.x, b = blockIdx.x;
+  const int strip = (nstrip % 8 == 0) ? (b % 8) * (nstrip / 8) + b / 8 : b;
+  const int c = 2 * (strip * SH::G + g);
   const bool valid = c < nx;
   Re* col = buf + (valid ? c : 0);
   C v[32];
@@ -225,44 +236,7 @@ __device__ __forceinline__ float div_at(const float* __restrict__ px, const floa
   return (xr - xl) + (yu - yd);
 }
 
-// ------------------------------------------------------------ ROF stencils
-// r = lambda tau (I - u) + tau div pbar   (incremental form of the section 3.1
-// u-update: u+ = u + (lambda tau - Delta)^{-1} r)
-__global__ __launch_bounds__(256) void k_rof_rhs(const float* __restrict__ I, const float* __restrict__ u,
-                                                 const float* __restrict__ pbx, const float* __restrict__ pby,
-                                                 float* __restrict__ r, int ny, int nx, float lt, float tau_h) {
-  const size_t n = size_t(ny) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
-    const int i = int(o / nx), j = int(o - size_t(i) * nx);
-    r[o] = lt * (I[o] - u[o]) + tau_h * div_at(pbx, pby, i, j, ny, nx);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_axpy(float* __restrict__ u, const float* __restrict__ d, size_t n) {
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
-    u[o] += d[o];
-}
-
-// p+ = proj(p + sigma grad u+), pbar+ = 2 p+ - p
-__global__ __launch_bounds__(256) void k_rof_dual(const float* __restrict__ u, float* __restrict__ px,
-                                                  float* __restrict__ py, float* __restrict__ pbx,
-                                                  float* __restrict__ pby, int ny, int nx, float sig_h, int aniso) {
-  const size_t n = size_t(ny) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
-    const int i = int(o / nx), j = int(o - size_t(i) * nx);
-    const float uc = u[o];
-    const float gx = (j < nx - 1) ? (u[o + 1] - uc) : 0.f;
-    const float gy = (i < ny - 1) ? (u[o + nx] - uc) : 0.f;
-    const float ox = px[o], oy = py[o];
-    float qx = ox + sig_h * gx, qy = oy + sig_h * gy;
-    proj_ball(qx, qy, aniso);
-    px[o] = qx;
-    py[o] = qy;
-    pbx[o] = 2.f * qx - ox;
-    pby[o] = 2.f * qy - oy;
-  }
-}
-
+// ------------------------------------------------------------ gap evaluation
 // partial sums for the ROF gap: [sum |grad u| (per-h units), sum (u-I)^2,
 // sum I div p, sum (div p)^2]; gradients and divergences in 1/h units
 __global__ __launch_bounds__(256) void k_rof_energy(const float* __restrict__ u, const float* __restrict__ px,
@@ -287,7 +261,6 @@ __global__ __launch_bounds__(256) void k_rof_energy(const float* __restrict__ u,
   block_reduce_store<4>(acc, mx, partials);
 }
 
-// ------------------------------------------------------------ EMD stencils
 // r = s div v (s = +-1/h); T = float or double output
 template <class T>
 __global__ __launch_bounds__(256) void k_div(const float* __restrict__ vx, const float* __restrict__ vy,
@@ -296,52 +269,6 @@ __global__ __launch_bounds__(256) void k_div(const float* __restrict__ vx, const
   for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
     const int i = int(o / nx), j = int(o - size_t(i) * nx);
     r[o] = T(div_at(vx, vy, i, j, ny, nx)) * T(s);
-  }
-}
-
-// w = u - tau pbar (the argument of the Leray projection)
-__global__ __launch_bounds__(256) void k_emd_shift(const float* __restrict__ u, const float* __restrict__ pb,
-                                                   float* __restrict__ w, size_t n2, float tau) {
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n2; o += size_t(gridDim.x) * blockDim.x)
-    w[o] = u[o] - tau * pb[o];
-}
-
-// Projected form of the section 3.2 u-update: u+ = w - grad phi, phi = Delta^{-1} div w,
-// w = u - tau pbar; then p+ = proj(p + sigma (u+ + grad psi)), pbar+ = 2 p+ - p.
-// Optionally accumulates sum |u+ + grad psi| (block partials) for the primal value.
-__global__ __launch_bounds__(256) void k_emd_update(const double* __restrict__ phi, const float* __restrict__ wx,
-                                                    const float* __restrict__ wy, float* __restrict__ ux,
-                                                    float* __restrict__ uy, float* __restrict__ px,
-                                                    float* __restrict__ py, float* __restrict__ pbx,
-                                                    float* __restrict__ pby, const float* __restrict__ gpx,
-                                                    const float* __restrict__ gpy, int ny, int nx, double inv_h,
-                                                    float sigma, int aniso, double* __restrict__ partials) {
-  double acc[1] = {0};
-  const size_t n = size_t(ny) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
-    const int i = int(o / nx), j = int(o - size_t(i) * nx);
-    // grad phi from the FP64 potential: differencing an FP32 potential would
-    // lose ~log10(n) digits to cancellation
-    const double fc = phi[o];
-    const float fx = (j < nx - 1) ? float((phi[o + 1] - fc) * inv_h) : 0.f;
-    const float fy = (i < ny - 1) ? float((phi[o + nx] - fc) * inv_h) : 0.f;
-    const float nux = (j < nx - 1) ? wx[o] - fx : 0.f;
-    const float nuy = (i < ny - 1) ? wy[o] - fy : 0.f;
-    const float mx = nux + gpx[o], my = nuy + gpy[o];
-    const float ox = px[o], oy = py[o];
-    float qx = ox + sigma * mx, qy = oy + sigma * my;
-    proj_ball(qx, qy, aniso);
-    ux[o] = nux;
-    uy[o] = nuy;
-    px[o] = qx;
-    py[o] = qy;
-    pbx[o] = 2.f * qx - ox;
-    pby[o] = 2.f * qy - oy;
-    if (partials) acc[0] += double(pnorm(mx, my, aniso));
-  }
-  if (partials) {
-    const bool m[1] = {false};
-    block_reduce_store<1>(acc, m, partials);
   }
 }
 
