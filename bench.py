@@ -42,21 +42,28 @@ def parse():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("gprox.hip", "gprox_fft.hpp", "gprox_kernels.hpp"):
+    for f in ("gprox.hip", "gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp"):
         with open(os.path.join(ROOT, "paper_1805_09453_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel):
+# gp_profile kernel kind -> kernel symbol (as summarised from rocprofv3) for an n x n grid
+PROF2SYM = {"rof_A_prox_rhs_dct": "k_rof_A<{n}>", "rof_B_idct_update": "k_rof_B<{n}>",
+            "cols_solve": "k_cols_solve<{n}, f32>", "cols_solve_f64": "k_cols_solve<{n}, f64>",
+            "emd_A_prox_rhs_dct": "k_emd_A<{n}>", "emd_B_idct": "k_rows_inv<{n}, f64>",
+            "rows_fwd_dct2": "k_rows_fwd<{n}, f32>", "rows_inv_dct2": "k_rows_inv<{n}, f32>"}
+
+
+def traffic_for(kernel, n):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel sources; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(p):
+    if not os.path.exists(p) or kernel not in PROF2SYM:
         return None
     with open(p) as fh:
         d = json.load(fh)
-    e = d.get(kernel)
+    e = d.get(PROF2SYM[kernel].format(n=n))
     if not e or e.get("source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
@@ -143,7 +150,7 @@ def main():
     achieved = d["bytes"] / d["calls"] / (d["avg_ms"] * 1e6)
     iter_bytes = sum(v["bytes"] for k, v in prof.items() if k != "reduce") / (C * K)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dname), "kernel": dname,
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dname, n), "kernel": dname,
                 "bytes_per_launch": d["bytes"] / d["calls"], "avg_launch_ms": d["avg_ms"]}
     extra = {"rof": {"pixel_iters_per_s": rof_pxit, "iters": C * K, "last_rel_gap": gaps[-1],
                      "algorithmic_bytes_per_pixel_iter": iter_bytes / (n * n),

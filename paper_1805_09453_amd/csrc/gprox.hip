@@ -134,24 +134,21 @@ template <int N> void fill_tw(std::vector<double>& re, std::vector<double>& im) 
   using S = Sched<N>;
   re.assign(S::total_tw(), 1.0);
   im.assign(S::total_tw(), 0.0);
-  for (int p = 0; p < S::NP; ++p) {
-    const int R = S::rad(p), LS = S::ls(p);
-    for (int j = 0; j < LS; ++j)
-      for (int r = 0; r < R; ++r) {
-        const double a = -2.0 * M_PI * double(j) * double(r) / double(LS * R);
-        re[S::toff(p) + r * LS + j] = cos(a);
-        im[S::toff(p) + r * LS + j] = sin(a);
+  // per pass: W_{LS R}^{j} (j < LS) then W_{LS R}^{4 j}; the inverse passes hold the conjugates
+  for (int dir = 0; dir < 2; ++dir)
+    for (int p = 0; p < S::NP; ++p) {
+      const int R = dir ? S::irad(p) : S::rad(p), LS = dir ? S::ils(p) : S::ls(p);
+      const int off = dir ? S::itoff(p) : S::toff(p);
+      const double sg = dir ? 1.0 : -1.0;
+      for (int j = 0; j < LS; ++j) {
+        const double a1 = sg * 2.0 * M_PI * double(j) / double(LS * R);
+        const double a4 = sg * 2.0 * M_PI * double((4 * j) % (LS * R)) / double(LS * R);
+        re[off + j] = cos(a1);
+        im[off + j] = sin(a1);
+        re[off + LS + j] = cos(a4);
+        im[off + LS + j] = sin(a4);
       }
-  }
-  for (int p = 0; p < S::NP; ++p) {
-    const int R = S::irad(p), LS = S::ils(p);
-    for (int j = 0; j < LS; ++j)
-      for (int r = 0; r < R; ++r) {
-        const double a = 2.0 * M_PI * double(j) * double(r) / double(LS * R);
-        re[S::itoff(p) + r * LS + j] = cos(a);
-        im[S::itoff(p) + r * LS + j] = sin(a);
-      }
-  }
+    }
 }
 
 int total_tw(int n) {
@@ -239,13 +236,23 @@ int set_mu(gp_ctx* c, int ny, int nx, double h) {
 }
 
 // ---------------------------------------------------------------- DCT launchers
+// log2 of the strip width of the tiled intermediate, fixed by the column pass over ny
+template <class C> int col_lgtw(int ny) {
+  switch (ny) {
+#define GP_TW(NN) case NN: return ilog2i(2 * ColShape<NN, C>::G);
+    GP_TW(64) GP_TW(128) GP_TW(256) GP_TW(512) GP_TW(1024) GP_TW(2048) GP_TW(4096)
+#undef GP_TW
+  }
+  return 0;
+}
+
 template <int N, class C> void launch_rows_fwd(gp_ctx* c, const typename Cx<C>::R* in, typename Cx<C>::R* out,
                                                int ny, const C* tw, const C* dw) {
   using SH = RowShape<N, C>;
   const int pairs = (ny + 1) / 2;
   const int blocks = (pairs + SH::G - 1) / SH::G;
   hipLaunchKernelGGL((k_rows_fwd<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, in, out, ny,
-                     N, tw, dw);
+                     col_lgtw<C>(ny), tw, dw);
 }
 template <int N, class C> void launch_rows_inv(gp_ctx* c, const typename Cx<C>::R* in, typename Cx<C>::R* out,
                                                int ny, const C* tw, const C* dw) {
@@ -253,7 +260,7 @@ template <int N, class C> void launch_rows_inv(gp_ctx* c, const typename Cx<C>::
   const int pairs = (ny + 1) / 2;
   const int blocks = (pairs + SH::G - 1) / SH::G;
   hipLaunchKernelGGL((k_rows_inv<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, in, out, ny,
-                     N, tw, dw);
+                     col_lgtw<C>(ny), tw, dw);
 }
 template <int N, class C> void launch_cols(gp_ctx* c, typename Cx<C>::R* buf, int nx, const C* tw, const C* dw,
                                            const typename Cx<C>::R* mux, const typename Cx<C>::R* muy,
@@ -261,8 +268,8 @@ template <int N, class C> void launch_cols(gp_ctx* c, typename Cx<C>::R* buf, in
   using SH = ColShape<N, C>;
   const int pairs = nx / 2;
   const int blocks = (pairs + SH::G - 1) / SH::G;
-  hipLaunchKernelGGL((k_cols_solve<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, buf, nx, nx,
-                     tw, dw, mux, muy, alpha, inv_nn);
+  hipLaunchKernelGGL((k_cols_solve<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, buf, nx, tw,
+                     dw, mux, muy, alpha, inv_nn);
 }
 
 template <class C> const C* tw_of(const Tables& T);
@@ -311,34 +318,36 @@ template <class C> struct Solve {
 };
 
 // (alpha I - Delta) x = b on the device, b and x may alias.  Tables and mu must be set.
-int poisson_f32(gp_ctx* c, const float* b, float* x, int ny, int nx, double alpha) {
+// (alpha I - Delta) x = b: row DCT into the tiled intermediate tmp, column solve,
+// row inverse into x.  b and x may alias; tmp must not alias either.
+int poisson_f32(gp_ctx* c, const float* b, float* x, int ny, int nx, double alpha, float* tmp) {
   const double fb = 8.0 * double(nx) * ny;  // each pass reads and writes one FP32 field
   int ps = prof_begin(c, K_ROWS_FWD, fb);
-  GP_DISPATCH_N(nx, Solve<float2>::rows_fwd, c, b, x, ny);
+  GP_DISPATCH_N(nx, Solve<float2>::rows_fwd, c, b, tmp, ny);
   prof_end(c, ps);
   LAUNCHCHK(c);
   ps = prof_begin(c, K_COLS, fb);
-  GP_DISPATCH_N(ny, Solve<float2>::cols, c, x, nx, c->mux32, c->muy32, float(alpha), float(1.0 / (double(nx) * ny)));
+  GP_DISPATCH_N(ny, Solve<float2>::cols, c, tmp, nx, c->mux32, c->muy32, float(alpha), float(1.0 / (double(nx) * ny)));
   prof_end(c, ps);
   LAUNCHCHK(c);
   ps = prof_begin(c, K_ROWS_INV, fb);
-  GP_DISPATCH_N(nx, Solve<float2>::rows_inv, c, x, x, ny);
+  GP_DISPATCH_N(nx, Solve<float2>::rows_inv, c, tmp, x, ny);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
-int poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, double alpha) {
+int poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, double alpha, double* tmp) {
   const double fb = 16.0 * double(nx) * ny;
   int ps = prof_begin(c, K_ROWS_FWD64, fb);
-  GP_DISPATCH_N(nx, Solve<double2>::rows_fwd, c, b, x, ny);
+  GP_DISPATCH_N(nx, Solve<double2>::rows_fwd, c, b, tmp, ny);
   prof_end(c, ps);
   LAUNCHCHK(c);
   ps = prof_begin(c, K_COLS64, fb);
-  GP_DISPATCH_N(ny, Solve<double2>::cols, c, x, nx, c->mux64, c->muy64, alpha, 1.0 / (double(nx) * ny));
+  GP_DISPATCH_N(ny, Solve<double2>::cols, c, tmp, nx, c->mux64, c->muy64, alpha, 1.0 / (double(nx) * ny));
   prof_end(c, ps);
   LAUNCHCHK(c);
   ps = prof_begin(c, K_ROWS_INV64, fb);
-  GP_DISPATCH_N(nx, Solve<double2>::rows_inv, c, x, x, ny);
+  GP_DISPATCH_N(nx, Solve<double2>::rows_inv, c, tmp, x, ny);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
@@ -432,14 +441,14 @@ template <int N> struct Fused {
     const int blocks = (ny / 2 + SH::G - 1) / SH::G;
     const Tables& T = c->tab[ilog2i(N)];
     hipLaunchKernelGGL((k_rof_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, u, pin, pout, I,
-                       rhat, ny, lt, tau_h, sig_h, aniso, mode, partials, T.tw32, T.dw32);
+                       rhat, ny, col_lgtw<float2>(ny), lt, tau_h, sig_h, aniso, mode, partials, T.tw32, T.dw32);
   }
   static void rof_B(gp_ctx* c, const float* dhat, float* u, int ny) {
     using SH = RowShape<N, float2>;
     const int blocks = (ny / 2 + SH::G - 1) / SH::G;
     const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_rof_B<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, dhat, u, ny, T.tw32,
-                       T.dw32);
+    hipLaunchKernelGGL((k_rof_B<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, dhat, u, ny,
+                       col_lgtw<float2>(ny), T.tw32, T.dw32);
   }
   static void emd_A(gp_ctx* c, const float* wt_in, const double* phi, const float* pin, const float* gpsi,
                     const float* f, float* pout, float* wt_out, double* rhat, int ny, double inv_h, float tau,
@@ -448,7 +457,8 @@ template <int N> struct Fused {
     const int blocks = (ny / 2 + SH::G - 1) / SH::G;
     const Tables& T = c->tab[ilog2i(N)];
     hipLaunchKernelGGL((k_emd_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, wt_in, phi, pin,
-                       gpsi, f, pout, wt_out, rhat, ny, inv_h, tau, sigma, aniso, mode, partials, T.tw64, T.dw64);
+                       gpsi, f, pout, wt_out, rhat, ny, col_lgtw<double2>(ny), inv_h, tau, sigma, aniso, mode, partials,
+                       T.tw64, T.dw64);
   }
 };
 
@@ -627,7 +637,7 @@ int rof_gap(gp_ctx* c, const gp_state* s, double* P, double* D) {
 
 // certificate D from p: phi = Delta^{-1} div p, D = -h^2 sum phi f / max(1, max|grad phi|).
 // Leaves -phi (FP64) in c->work64; *L receives max|grad phi|.
-int emd_cert(gp_ctx* c, const gp_state* s, double* D, double* L, double* phi) {
+int emd_cert(gp_ctx* c, const gp_state* s, double* D, double* L, double* phi, double* tmp) {
   const size_t n = size_t(s->ny) * s->nx;
   int ps = prof_begin(c, K_DIV64, 16.0 * n);
   hipLaunchKernelGGL(k_div<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, s->p, s->p + n, phi, s->ny, s->nx,
@@ -636,7 +646,7 @@ int emd_cert(gp_ctx* c, const gp_state* s, double* D, double* L, double* phi) {
   LAUNCHCHK(c);
   // Delta phi = div p  <=>  (0 I - Delta) phi = -div p: this solves for -phi; the sign is
   // folded into D below
-  int rc = poisson_f64(c, phi, phi, s->ny, s->nx, 0.0);
+  int rc = poisson_f64(c, phi, phi, s->ny, s->nx, 0.0, tmp);
   if (rc) return rc;
   const int nb = red_blocks(n);
   ps = prof_begin(c, K_REDUCE, 12.0 * n);
@@ -782,7 +792,7 @@ int dct_poisson(gp_ctx* c, const float* b, float* x, int ny, int nx, double h, d
   }
   int rc = prepare(c, ny, nx, h);
   if (rc) return rc;
-  return poisson_f32(c, b, x, ny, nx, alpha);
+  return poisson_f32(c, b, x, ny, nx, alpha, c->work);
 }
 
 int dct_poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, double h, double alpha) {
@@ -797,7 +807,7 @@ int dct_poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, doubl
   }
   int rc = prepare(c, ny, nx, h);
   if (rc) return rc;
-  return poisson_f64(c, b, x, ny, nx, alpha);
+  return poisson_f64(c, b, x, ny, nx, alpha, c->work64);
 }
 
 int pd_step(gp_ctx* c, gp_state* s, int n_iter) {
@@ -823,7 +833,7 @@ int pd_gap(gp_ctx* c, gp_state* s, gp_report* rep) {
     rc = rof_gap(c, s, &P, &D);
   } else {
     rc = emd_primal(c, s, &P);
-    if (!rc) rc = emd_cert(c, s, &D, &L, c->work64);
+    if (!rc) rc = emd_cert(c, s, &D, &L, c->work64, c->work64 + size_t(s->ny) * s->nx);
   }
   if (rc) return rc;
   if (rep) {
@@ -953,11 +963,12 @@ int emd_setup(gp_ctx* c, const float* rho0, const float* rho1, float* f, float* 
     return GP_EMASS;
   }
   double* f64 = c->work64;
-  double* psi = c->work64 + n;
+  double* psi = c->work64;  // the solve consumes f64 before writing psi over it
+  double* tmp = c->work64 + n;
   hipLaunchKernelGGL(k_f64_diff, dim3(grid_for(n)), dim3(256), 0, c->stream, rho0, rho1, c->result,
                      1.0 / double(n), n, f64, f);
   LAUNCHCHK(c);
-  rc = poisson_f64(c, f64, psi, ny, nx, 0.0);
+  rc = poisson_f64(c, f64, psi, ny, nx, 0.0, tmp);
   if (rc) return rc;
   hipLaunchKernelGGL(k_grad_f64, dim3(grid_for(n)), dim3(256), 0, c->stream, psi, gpsi, gpsi + n, ny, nx, 1.0 / h);
   LAUNCHCHK(c);
@@ -982,10 +993,10 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   rc = prepare(c, ny, nx, h);
   if (rc) return rc;
   const size_t n = size_t(ny) * nx;
-  // arena: f, grad psi, u, P0, P1, certificate scratch (n doubles)
-  float* ar = arena(c, 11 * n);
+  // arena: f, grad psi, u, P0, P1, certificate potential and its transform intermediate (n doubles each)
+  float* ar = arena(c, 13 * n);
   if (!ar) {
-    set_err(c, "arena allocation of %zu floats failed", 11 * n);
+    set_err(c, "arena allocation of %zu floats failed", 13 * n);
     return GP_ENOMEM;
   }
   float* f = ar;
@@ -994,6 +1005,7 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   float* P0 = ar + 5 * n;
   float* P1 = ar + 7 * n;
   double* cphi = reinterpret_cast<double*>(ar + 9 * n);
+  double* ctmp = reinterpret_cast<double*>(ar + 11 * n);
   rc = emd_setup(c, rho0, rho1, f, gpsi, ny, nx, h);
   if (rc) return rc;
   HIPCHK(c, hipMemsetAsync(u, 0, 2 * n * sizeof(float), c->stream));
@@ -1029,7 +1041,7 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
       P = h * h * r[0];
       gp_state cs = s;
       cs.p = pipe.X;
-      rc = emd_cert(c, &cs, &D, &L, cphi);
+      rc = emd_cert(c, &cs, &D, &L, cphi, ctmp);
       if (rc) return rc;
       g = rel_gap(P, D);
       if (!std::isfinite(g)) {

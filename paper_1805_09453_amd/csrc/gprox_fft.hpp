@@ -125,6 +125,64 @@ template <bool INV, class C> struct DFT<16, INV, C> {
   }
 };
 
+// exp(-i pi s / 32), s = 0..15: the ratio of DCT twiddles 16 apart in a thread's
+// slot (w_{b + s N/16} = w_b exp(-i pi s/32)); and exp(-i pi / 64)
+constexpr double kCS32[16][2] = {
+    {1.00000000000000000000, -0.00000000000000000000}, {0.99518472667219692873, -0.09801714032956060363},
+    {0.98078528040323043058, -0.19509032201612824808}, {0.95694033573220882438, -0.29028467725446233105},
+    {0.92387953251128673848, -0.38268343236508978178}, {0.88192126434835504956, -0.47139673682599764204},
+    {0.83146961230254523567, -0.55557023301960217765}, {0.77301045336273699338, -0.63439328416364548779},
+    {0.70710678118654757274, -0.70710678118654746172}, {0.63439328416364548779, -0.77301045336273699338},
+    {0.55557023301960228867, -0.83146961230254523567}, {0.47139673682599780857, -0.88192126434835493853},
+    {0.38268343236508983729, -0.92387953251128673848}, {0.29028467725446233105, -0.95694033573220893540},
+    {0.19509032201612833135, -0.98078528040323043058}, {0.09801714032956077016, -0.99518472667219681771}};
+constexpr double kE64[2] = {0.99879545620517239271, -0.04906767432741801425};
+
+template <class C> __device__ __forceinline__ C cs32(int s) {
+  using Re = typename Cx<C>::R;
+  return mk<C>(Re(kCS32[s][0]), Re(kCS32[s][1]));
+}
+// DCT twiddle w_k = exp(-i pi k / 2N) for k = b + s N/16 from w_b; and the
+// partner w_{N-k} = -i conj(w_k)
+template <class C> __device__ __forceinline__ C dcw(C wb, int s) { return cmul(wb, cs32<C>(s)); }
+template <class C> __device__ __forceinline__ C dcw_partner(C w) { return mk<C>(-w.y, -w.x); }
+
+// Stockham twiddles W^{j r}, r = 1..R-1, from W^j (w1) and, for R = 16, W^{4j}
+// (w4): at most three roundings deep, applied to x[1..R-1]
+template <int R, class C> __device__ __forceinline__ void apply_tw(C* x, C w1, C w4) {
+  if constexpr (R == 2) {
+    x[1] = cmul(x[1], w1);
+  } else if constexpr (R == 4) {
+    const C a2 = cmul(w1, w1), a3 = cmul(a2, w1);
+    x[1] = cmul(x[1], w1);
+    x[2] = cmul(x[2], a2);
+    x[3] = cmul(x[3], a3);
+  } else if constexpr (R == 8) {
+    const C a2 = cmul(w1, w1), a3 = cmul(a2, w1), a4 = cmul(a2, a2);
+    x[1] = cmul(x[1], w1);
+    x[2] = cmul(x[2], a2);
+    x[3] = cmul(x[3], a3);
+    x[4] = cmul(x[4], a4);
+    x[5] = cmul(x[5], cmul(a4, w1));
+    x[6] = cmul(x[6], cmul(a4, a2));
+    x[7] = cmul(x[7], cmul(a4, a3));
+  } else {
+    static_assert(R == 16, "radix");
+    const C a2 = cmul(w1, w1), a3 = cmul(a2, w1);
+    const C b2 = cmul(w4, w4), b3 = cmul(b2, w4);
+    const C av[4] = {w1, w1, a2, a3}, bv[4] = {w4, w4, b2, b3};
+#pragma unroll
+    for (int r2 = 0; r2 < 4; ++r2)
+#pragma unroll
+      for (int r1 = 0; r1 < 4; ++r1) {
+        const int r = r1 + 4 * r2;
+        if (r == 0) continue;
+        const C w = (r2 == 0) ? av[r1] : (r1 == 0 ? bv[r2] : cmul(av[r1], bv[r2]));
+        x[r] = cmul(x[r], w);
+      }
+  }
+}
+
 // ---------------------------------------------------------------- schedule
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
@@ -140,11 +198,11 @@ template <int N> struct Sched {
   static constexpr int irad(int p) { return rad(NP - 1 - p); }
   static constexpr int ls(int p) { int l = 1; for (int i = 0; i < p; ++i) l *= rad(i); return l; }
   static constexpr int ils(int p) { int l = 1; for (int i = 0; i < p; ++i) l *= irad(i); return l; }
-  // twiddle tables: per pass, R rows of LS entries (entry [r][j] = W_{LS R}^{j r}),
-  // so a wave's lanes (consecutive j) read one contiguous span per r
-  static constexpr int toff(int p) { int o = 0; for (int i = 0; i < p; ++i) o += ls(i) * rad(i); return o; }
+  // twiddle tables: per pass, W_{LS R}^{j} for j < LS followed by W_{LS R}^{4 j}
+  // (the other powers are generated in registers, see apply_tw)
+  static constexpr int toff(int p) { int o = 0; for (int i = 0; i < p; ++i) o += 2 * ls(i); return o; }
   static constexpr int tsize() { return toff(NP); }
-  static constexpr int itoff(int p) { int o = tsize(); for (int i = 0; i < p; ++i) o += ils(i) * irad(i); return o; }
+  static constexpr int itoff(int p) { int o = tsize(); for (int i = 0; i < p; ++i) o += 2 * ils(i); return o; }
   static constexpr int total_tw() { return itoff(NP); }
   // padded LDS index and per-sequence region size: one pad slot per 16 complex
   // values, and a region stride of 8 mod 32 complex values so that groups
@@ -161,6 +219,16 @@ template <int N, int R, int LS, bool INV, bool FROM_LDS, bool TO_LDS, class C>
 __device__ __forceinline__ void stockham_pass(C (&v)[32], const int (&bi)[32 / R], C* lds,
                                               const C* __restrict__ tw) {
   constexpr int NB = 32 / R;
+  // twiddle bases are loaded before the LDS exchange so their latency overlaps it
+  C w1[NB], w4[NB];
+  if constexpr (LS > 1) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int j = bi[q] & (LS - 1);
+      w1[q] = tw[j];
+      w4[q] = (R == 16) ? tw[LS + j] : w1[q];
+    }
+  }
   if constexpr (FROM_LDS) {
 #pragma unroll
     for (int q = 0; q < NB; ++q)
@@ -170,11 +238,7 @@ __device__ __forceinline__ void stockham_pass(C (&v)[32], const int (&bi)[32 / R
   }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    if constexpr (LS > 1) {
-      const int j = bi[q] & (LS - 1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[q * R + r] = cmul(v[q * R + r], tw[r * LS + j]);
-    }
+    if constexpr (LS > 1) apply_tw<R>(&v[q * R], w1[q], w4[q]);
     DFT<R, INV, C>::run(&v[q * R]);
   }
   if constexpr (TO_LDS) {
@@ -239,6 +303,7 @@ __device__ __forceinline__ void dct2_fwd(int t, C (&v)[32], C* lds, const C* __r
   using S = Sched<N>;
   constexpr int T = S::T;
   constexpr int R0 = S::rad(0);
+  const C wt = dctw[t];  // exp(-i pi t / 2N), base of this thread's DCT twiddles
   // ---- pass 0 with the Makhoul reordering done by the loads
   {
     int bi[32 / R0];
@@ -273,14 +338,12 @@ __device__ __forceinline__ void dct2_fwd(int t, C (&v)[32], C* lds, const C* __r
   // ---- split the two real transforms and apply exp(-i pi k / 2N).  Output s
   // of butterfly b is index b + s N/16; Z_{N-k} sits at (slot1, 15 - s).
   const int b = t;
-  const C* __restrict__ w = dctw;
   if (b != 0) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int k0 = b + s * (N / 16);
-      const int k1 = N - k0;  // = (N/16 - b) + (15 - s) N/16
+      // k0 = b + s N/16 and its partner k1 = N - k0 = (N/16 - b) + (15 - s) N/16
       C z0 = v[s], z1 = v[16 + 15 - s];
-      C w0 = w[k0], w1 = w[k1];
+      C w0 = dcw(wt, s), w1 = dcw_partner(w0);
       C a0 = cmul(w0, z0), c0 = cmul(w0, mk<C>(z1.x, -z1.y));
       C a1 = cmul(w1, z1), c1 = cmul(w1, mk<C>(z0.x, -z0.y));
       v[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
@@ -292,14 +355,12 @@ __device__ __forceinline__ void dct2_fwd(int t, C (&v)[32], C* lds, const C* __r
     C o[32];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int k0 = s * (N / 16);
       C z0 = v[s], zp = v[(16 - s) & 15];
-      C w0 = w[k0];
+      C w0 = cs32<C>(s);
       C a0 = cmul(w0, z0), c0 = cmul(w0, mk<C>(zp.x, -zp.y));
       o[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
-      const int k1 = N / 32 + s * (N / 16);
       C z1 = v[16 + s], zq = v[16 + 15 - s];
-      C w1 = w[k1];
+      C w1 = dcw(mk<C>(Re(kE64[0]), Re(kE64[1])), s);
       C a1 = cmul(w1, z1), c1 = cmul(w1, mk<C>(zq.x, -zq.y));
       o[16 + s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
     }
@@ -317,22 +378,20 @@ template <int N> __device__ __forceinline__ int dc_index(int t, int slot, int s)
 // Inverse of the unnormalised DCT-II, times N, for two real spectra held as
 // spec[slot*16+s] = (A_k, B_k) (layout of dct2_fwd).  st(m, A, B) receives
 // A = N (a_{2m}, a_{2m+1}), B = N (b_{2m}, b_{2m+1}).
-template <int N, class C, class Storer>
-__device__ __forceinline__ void dct2_inv(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
-                                         const C* __restrict__ dctw, Storer&& st) {
+template <int N, class C, class Hook>
+__device__ __forceinline__ void dct2_inv_core(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+                                              const C* __restrict__ dctw, Hook&& before_last) {
   using Re = typename Cx<C>::R;
   using S = Sched<N>;
   constexpr int T = S::T;
-  const C* __restrict__ w = dctw;  // exp(-i pi k / 2N); the inverse uses its conjugate
+  const C wt = dctw[t];  // exp(-i pi t / 2N); the inverse uses conjugates
   // ---- V_k = conj(w_k) (X_k - i X_{N-k}) for both spectra, Z_k = V^a_k + i V^b_k
   if (t != 0) {
     // pairs (slot0, s) <-> (slot1, 15 - s), s in [0, 16)
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int k0 = t + s * (N / 16);
-      const int k1 = N - k0;
       C y0 = v[s], y1 = v[16 + 15 - s];
-      C c0 = w[k0], c1 = w[k1];
+      C c0 = dcw(wt, s), c1 = dcw_partner(c0);
       c0.y = -c0.y;
       c1.y = -c1.y;
       C va0 = cmul(c0, mk<C>(y0.x, -y1.x)), vb0 = cmul(c0, mk<C>(y0.y, -y1.y));
@@ -344,16 +403,14 @@ __device__ __forceinline__ void dct2_inv(int t, C (&v)[32], C* lds, const C* __r
     C o[32];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int k0 = s * (N / 16);
       C y0 = v[s];
       C yp = (s == 0) ? mk<C>(Re(0), Re(0)) : v[(16 - s) & 15];  // X_N = 0
-      C c0 = w[k0];
+      C c0 = cs32<C>(s);
       c0.y = -c0.y;
       C va = cmul(c0, mk<C>(y0.x, -yp.x)), vb = cmul(c0, mk<C>(y0.y, -yp.y));
       o[s] = mk<C>(va.x - vb.y, va.y + vb.x);
-      const int k1 = N / 32 + s * (N / 16);
       C y1 = v[16 + s], yq = v[16 + 15 - s];
-      C c1 = w[k1];
+      C c1 = dcw(mk<C>(Re(kE64[0]), Re(kE64[1])), s);
       c1.y = -c1.y;
       C va1 = cmul(c1, mk<C>(y1.x, -yq.x)), vb1 = cmul(c1, mk<C>(y1.y, -yq.y));
       o[16 + s] = mk<C>(va1.x - vb1.y, va1.y + vb1.x);
@@ -369,6 +426,7 @@ __device__ __forceinline__ void dct2_inv(int t, C (&v)[32], C* lds, const C* __r
     stockham_pass<N, 16, 1, true, false, true>(v, bi, lds, tw + S::itoff(0));
   }
   middle_passes<N, true, 1, S::NP - 1, C>(t, v, lds, tw);
+  before_last();
   // ---- last inverse pass with Makhoul pairs, outputs in registers
   {
     constexpr int PL = S::NP - 1;
@@ -376,6 +434,36 @@ __device__ __forceinline__ void dct2_inv(int t, C (&v)[32], C* lds, const C* __r
     int bi[32 / RL];
     bidx_mk<N, RL>(t, bi);
     stockham_pass<N, RL, S::ils(PL), true, true, false>(v, bi, lds, tw + S::itoff(PL));
+  }
+}
+
+// Positions held after dct2_inv_core: for q < 16/RL and s < RL/2 the thread holds
+// output pairs (x_{2m}, x_{2m+1}) for m = inv_m<N>(t, 2q, s) and m = inv_m<N>(t, 2q+1, s):
+//   slot 2q:   x_{2m} = v[2q RL + s],     x_{2m+1} = v[(2q+1) RL + RL-1-s],  m = b + s N/RL
+//   slot 2q+1: x_{2m} = v[(2q+1) RL + s], x_{2m+1} = v[2q RL + RL-1-s],      m = bp + s N/RL
+template <int N> struct InvOut {
+  static constexpr int RL = Sched<N>::irad(Sched<N>::NP - 1);
+  static constexpr int NQ = 16 / RL;   // butterfly pairs per thread
+  static constexpr int NS = RL / 2;    // outputs per butterfly
+  __device__ __forceinline__ static int m(int t, int q, int half, int s) {
+    const int b = t + q * Sched<N>::T;
+    return (half ? N / RL - 1 - b : b) + s * (N / RL);
+  }
+  template <class C> __device__ __forceinline__ static void get(const C (&v)[32], int q, int half, int s, C& x0,
+                                                                 C& x1) {
+    x0 = v[(2 * q + half) * RL + s];
+    x1 = v[(2 * q + 1 - half) * RL + (RL - 1 - s)];
+  }
+};
+
+template <int N, class C, class Storer>
+__device__ __forceinline__ void dct2_inv(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+                                         const C* __restrict__ dctw, Storer&& st) {
+  using S = Sched<N>;
+  constexpr int T = S::T;
+  dct2_inv_core<N>(t, v, lds, tw, dctw, [] {});
+  {
+    constexpr int RL = S::irad(S::NP - 1);
 #pragma unroll
     for (int q = 0; q < 16 / RL; ++q) {
       const int b = t + q * T;

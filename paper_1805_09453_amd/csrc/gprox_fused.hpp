@@ -44,6 +44,7 @@ __device__ __forceinline__ void dct2_fwd_lds(int t, C (&v)[32], C* lds, const C*
   using S = Sched<N>;
   using Re = typename Cx<C>::R;
   constexpr int R0 = S::rad(0);
+  const C wt = dctw[t];  // exp(-i pi t / 2N), base of this thread's DCT twiddles
   {
     int bi[32 / R0];
     bidx_seq<N, R0>(t, bi);
@@ -56,14 +57,11 @@ __device__ __forceinline__ void dct2_fwd_lds(int t, C (&v)[32], C* lds, const C*
     bidx_dc<N, 16>(t, bi);
     stockham_pass<N, 16, S::ls(PL), false, true, false>(v, bi, lds, tw + S::toff(PL));
   }
-  const C* __restrict__ w = dctw;
   if (t != 0) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int k0 = t + s * (N / 16);
-      const int k1 = N - k0;
       C z0 = v[s], z1 = v[16 + 15 - s];
-      C w0 = w[k0], w1 = w[k1];
+      C w0 = dcw(wt, s), w1 = dcw_partner(w0);
       C a0 = cmul(w0, z0), c0 = cmul(w0, conjc(z1));
       C a1 = cmul(w1, z1), c1 = cmul(w1, conjc(z0));
       v[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
@@ -73,14 +71,12 @@ __device__ __forceinline__ void dct2_fwd_lds(int t, C (&v)[32], C* lds, const C*
     C o[32];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int k0 = s * (N / 16);
       C z0 = v[s], zp = v[(16 - s) & 15];
-      C w0 = w[k0];
+      C w0 = cs32<C>(s);
       C a0 = cmul(w0, z0), c0 = cmul(w0, conjc(zp));
       o[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
-      const int k1 = N / 32 + s * (N / 16);
       C z1 = v[16 + s], zq = v[16 + 15 - s];
-      C w1 = w[k1];
+      C w1 = dcw(mk<C>(Re(kE64[0]), Re(kE64[1])), s);
       C a1 = cmul(w1, z1), c1 = cmul(w1, conjc(zq));
       o[16 + s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
     }
@@ -116,8 +112,8 @@ __device__ __forceinline__ void rof_dual_pt(float px, float py, float gx, float 
 template <int N>
 __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, const float* __restrict__ pin,
                                                float* __restrict__ pout, const float* __restrict__ I,
-                                               float* __restrict__ rhat, int ny, float lt, float tau_h, float sig_h,
-                                               int aniso, int mode, double* __restrict__ partials,
+                                               float* __restrict__ rhat, int ny, int lgtw, float lt, float tau_h,
+                                               float sig_h, int aniso, int mode, double* __restrict__ partials,
                                                const float2* __restrict__ tw, const float2* __restrict__ dctw) {
   using SH = RowShape<N, float2>;
   constexpr int T = SH::T;
@@ -134,7 +130,7 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
   if (valid) {
     const bool has_up = a > 0, has_dn = b + 1 < ny;
     const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
-#pragma unroll 1
+#pragma unroll 2
     for (int k = 0; k < 8; ++k) {
       const int c = 4 * (t + T * k);
       const bool has_l = c > 0, has_r = c + 4 < N;
@@ -266,8 +262,8 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const int k = dc_index<N>(t, slot, s);
-        rhat[size_t(a) * N + k] = v[slot * 16 + s].x;
-        rhat[size_t(b) * N + k] = v[slot * 16 + s].y;
+        rhat[tile_idx(a, k, ny, lgtw)] = v[slot * 16 + s].x;
+        rhat[tile_idx(b, k, ny, lgtw)] = v[slot * 16 + s].y;
       }
   }
 }
@@ -276,8 +272,10 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
 // u += inverse row DCT of the column-solved field
 template <int N>
 __global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, float* __restrict__ u, int ny,
-                                               const float2* __restrict__ tw, const float2* __restrict__ dctw) {
+                                               int lgtw, const float2* __restrict__ tw,
+                                               const float2* __restrict__ dctw) {
   using SH = RowShape<N, float2>;
+  using IO = InvOut<N>;
   constexpr int T = SH::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float2* smem = reinterpret_cast<float2*>(smem_raw);
@@ -285,23 +283,46 @@ __global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, f
   float2* lds = smem + g * Sched<N>::LDS;
   const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
   const bool valid = a < ny;
+  float* ua = u + size_t(valid ? a : 0) * N;
+  float* ub = u + size_t(valid ? b : 0) * N;
   float2 v[32];
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      v[slot * 16 + s] = valid ? make_float2(dhat[size_t(a) * N + k], dhat[size_t(b) * N + k]) : make_float2(0, 0);
+      v[slot * 16 + s] = valid ? make_float2(dhat[tile_idx(a, k, ny, lgtw)], dhat[tile_idx(b, k, ny, lgtw)])
+                               : make_float2(0, 0);
     }
-  dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, float2 A, float2 B) {
-    if (valid) {
-      float2* pa = reinterpret_cast<float2*>(u + size_t(a) * N + 2 * m);
-      float2* pb = reinterpret_cast<float2*>(u + size_t(b) * N + 2 * m);
-      float2 xa = *pa, xb = *pb;
-      *pa = make_float2(xa.x + A.x, xa.y + A.y);
-      *pb = make_float2(xb.x + B.x, xb.y + B.y);
-    }
+  // u at this thread's output positions, loaded before the last pass so the
+  // latency overlaps it
+  float2 oa[IO::NQ][2][IO::NS], ob[IO::NQ][2][IO::NS];
+  dct2_inv_core<N>(t, v, lds, tw, dctw, [&] {
+#pragma unroll
+    for (int q = 0; q < IO::NQ; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int s = 0; s < IO::NS; ++s) {
+          const int m = IO::m(t, q, h, s);
+          oa[q][h][s] = *reinterpret_cast<const float2*>(ua + 2 * m);
+          ob[q][h][s] = *reinterpret_cast<const float2*>(ub + 2 * m);
+        }
   });
+  if (valid) {
+#pragma unroll
+    for (int q = 0; q < IO::NQ; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int s = 0; s < IO::NS; ++s) {
+          const int m = IO::m(t, q, h, s);
+          float2 x0, x1;
+          IO::get(v, q, h, s, x0, x1);
+          *reinterpret_cast<float2*>(ua + 2 * m) = make_float2(oa[q][h][s].x + x0.x, oa[q][h][s].y + x1.x);
+          *reinterpret_cast<float2*>(ub + 2 * m) = make_float2(ob[q][h][s].x + x0.y, ob[q][h][s].y + x1.y);
+        }
+  }
 }
 
 // ---------------------------------------------------------------- ROF finish
@@ -334,7 +355,7 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
                                                const float* __restrict__ pin, const float* __restrict__ gpsi,
                                                const float* __restrict__ f, float* __restrict__ pout,
                                                float* __restrict__ wt_out, double* __restrict__ rhat, int ny,
-                                               double inv_h, float tau, float sigma, int aniso, int mode,
+                                               int lgtw, double inv_h, float tau, float sigma, int aniso, int mode,
                                                double* __restrict__ partials, const double2* __restrict__ tw,
                                                const double2* __restrict__ dctw) {
   using SH = RowShape<N, double2>;
@@ -350,7 +371,7 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
   if (valid) {
     const bool has_up = a > 0, has_dn = b + 1 < ny;
     const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
-#pragma unroll 1
+#pragma unroll 2
     for (int k = 0; k < 8; ++k) {
       const int c = 4 * (t + T * k);
       const bool has_l = c > 0, has_r = c + 4 < N;
@@ -491,8 +512,8 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const int k = dc_index<N>(t, slot, s);
-        rhat[size_t(a) * N + k] = v[slot * 16 + s].x;
-        rhat[size_t(b) * N + k] = v[slot * 16 + s].y;
+        rhat[tile_idx(a, k, ny, lgtw)] = v[slot * 16 + s].x;
+        rhat[tile_idx(b, k, ny, lgtw)] = v[slot * 16 + s].y;
       }
   }
 }

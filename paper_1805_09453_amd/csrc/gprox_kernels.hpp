@@ -33,17 +33,24 @@ template <int N, class C> struct ColShape {
   static constexpr int G = G0 > 16 ? 16 : (G0 < 1 ? 1 : G0);  // column pairs per block
   static constexpr int THREADS = T * G;
   static constexpr size_t LDS_BYTES = size_t(G) * Sched<N>::LDS * sizeof(C);
+  // FP32: keep to 256 registers so two workgroups fit a CU; FP64 needs more
+  static constexpr int MINW = sizeof(C) == 8 ? 2 : 1;
 };
 
-template <class C> struct Vec2Of;
-template <> struct Vec2Of<float2> { using V = float2; };
-template <> struct Vec2Of<double2> { using V = double2; };
+// Layout of the row-transformed intermediate (the field between the row and
+// column passes): column strips of TW = 2^lgtw columns, each strip stored
+// row-major and contiguous, so the column pass streams whole strips and a row
+// pass writes TW consecutive values of each of its rows next to each other.
+__device__ __forceinline__ size_t tile_idx(int i, int k, int ny, int lgtw) {
+  return (size_t(k >> lgtw) * size_t(ny) + size_t(i)) * (size_t(1) << lgtw) + (k & ((1 << lgtw) - 1));
+}
 
 // ------------------------------------------------------------ DCT passes
 // Forward DCT-II along rows, two rows per FFT group.  out may alias in.
 template <int N, class C>
 __global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
-                                                  int ld, const C* __restrict__ tw, const C* __restrict__ dctw) {
+                                                  int lgtw, const C* __restrict__ tw, const C* __restrict__ dctw) {
+  constexpr int ld = N;
   using Re = typename Cx<C>::R;
   using SH = RowShape<N, C>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -64,15 +71,16 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, t
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      if (va) out[size_t(ra) * ld + k] = v[slot * 16 + s].x;
-      if (vb) out[size_t(rb) * ld + k] = v[slot * 16 + s].y;
+      if (va) out[tile_idx(ra, k, ny, lgtw)] = v[slot * 16 + s].x;
+      if (vb) out[tile_idx(rb, k, ny, lgtw)] = v[slot * 16 + s].y;
     }
 }
 
 // Inverse of the (unnormalised) DCT-II along rows times N.  out may alias in.
 template <int N, class C>
 __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
-                                                  int ld, const C* __restrict__ tw, const C* __restrict__ dctw) {
+                                                  int lgtw, const C* __restrict__ tw, const C* __restrict__ dctw) {
+  constexpr int ld = N;
   using Re = typename Cx<C>::R;
   using SH = RowShape<N, C>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -87,7 +95,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, t
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      v[slot * 16 + s] = mk<C>(va ? in[size_t(ra) * ld + k] : Re(0), vb ? in[size_t(rb) * ld + k] : Re(0));
+      v[slot * 16 + s] = mk<C>(va ? in[tile_idx(ra, k, ny, lgtw)] : Re(0), vb ? in[tile_idx(rb, k, ny, lgtw)] : Re(0));
     }
   dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
     if (va) *reinterpret_cast<C*>(out + size_t(ra) * ld + 2 * m) = A;
@@ -101,8 +109,8 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, t
 // columns per FFT group; consecutive lanes take consecutive column pairs so
 // every row access of a wave covers G*2 contiguous values.
 template <int N, class C>
-__global__ __launch_bounds__((ColShape<N, C>::THREADS)) void k_cols_solve(
-    typename Cx<C>::R* buf, int nx, int ld, const C* __restrict__ tw, const C* __restrict__ dctw,
+__global__ __launch_bounds__((ColShape<N, C>::THREADS), (ColShape<N, C>::MINW)) void k_cols_solve(
+    typename Cx<C>::R* buf, int nx, const C* __restrict__ tw, const C* __restrict__ dctw,
     const typename Cx<C>::R* __restrict__ mux, const typename Cx<C>::R* __restrict__ muy, typename Cx<C>::R alpha,
     typename Cx<C>::R inv_nn) {
   using Re = typename Cx<C>::R;
@@ -116,9 +124,12 @@ __global__ __launch_bounds__((ColShape<N, C>::THREADS)) void k_cols_solve(
   // then run together under one L2.
   const int nstrip = gridDim.x, b = blockIdx.x;
   const int strip = (nstrip % 8 == 0) ? (b % 8) * (nstrip / 8) + b / 8 : b;
-  const int c = 2 * (strip * SH::G + g);
+  // this block's strip of TW = 2G columns is contiguous (tile_idx layout)
+  constexpr int TW = 2 * SH::G;
+  const int c = strip * TW + 2 * g;
   const bool valid = c < nx;
-  Re* col = buf + (valid ? c : 0);
+  Re* col = buf + (valid ? size_t(strip) * N * TW + 2 * g : 0);
+  constexpr int ld = TW;
   C v[32];
   dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
     if (valid) {
