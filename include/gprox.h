@@ -142,6 +142,39 @@ int pd_step(gp_ctx* ctx, gp_state* st, int n_iter);
  * synchronises the stream once. */
 int pd_gap(gp_ctx* ctx, gp_state* st, gp_report* rep);
 
+/* One problem of a batch.
+ *   GP_KIND_ROF: in0 = image I [ny][nx]; out = u [ny][nx]; lambda > 0.
+ *   GP_KIND_EMD: in0 = rho0, in1 = rho1 [ny][nx] (equal mass); out = flux m
+ *                [2][ny][nx] (lambda ignored).
+ * tau is the instance's primal step (sigma = 1/tau, as in every step rule of
+ * sections 3.1, 3.2 and 4). */
+typedef struct {
+  int kind, ny, nx;
+  double h, lambda, tau;
+  const float* in0;
+  const float* in1;
+  float* out;
+} gp_instance;
+
+/* Solve count independent instances (each one the solve of rof_solve or
+ * emd_solve from a zero start; the iteration is section 3's Algorithm 2 per
+ * instance, nothing couples instances).  Instances of the same kind, size, h,
+ * lambda and tau run stacked in one set of launches; one hipGraph holds a
+ * chunk of iterations of every group plus their duality gaps, and is replayed
+ * on a private stream of the context until every instance has met opts->tol
+ * or run opts->max_iter iterations.  A converged instance retires at the
+ * check where it converged: its kernels skip it from then on, so its outputs
+ * equal those of the matching single-instance solve with the same
+ * check_every (rounded up to even, the chunk length; iteration counts are
+ * multiples of it).  opts->tau/sigma are ignored (per-instance tau) and
+ * opts->warm_start must be 0.  reps: nullable array of count reports;
+ * seconds_loop is the time from the first replay to the instance's last
+ * check.  Allocates the batch workspace (grow-only, kept in the context) and
+ * synchronises.  Returns GP_OK when every instance converged, GP_ENOTCONV
+ * when some reached max_iter (all outputs valid), or an error (GP_EMASS names
+ * the first instance with unequal masses in gp_last_error). */
+int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opts* opts, gp_report* reps);
+
 /* Per-kernel timing on the context's stream (HIP events around each kernel
  * launch; for measurement, not needed by the solvers).  gp_profile(ctx, 1)
  * clears and starts recording (allocates the event pool), gp_profile(ctx, 0)

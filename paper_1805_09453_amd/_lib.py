@@ -32,6 +32,11 @@ class gp_state(ctypes.Structure):
                 ("iter", c_longlong)]
 
 
+class gp_instance(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("ny", c_int), ("nx", c_int), ("h", c_double), ("lam", c_double),
+                ("tau", c_double), ("in0", c_void_p), ("in1", c_void_p), ("out", c_void_p)]
+
+
 class gp_kstat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("calls", c_longlong), ("dropped", c_longlong),
                 ("total_ms", c_double), ("bytes", c_double)]
@@ -51,6 +56,8 @@ _SIGS = {
     "emd_setup": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double]),
     "pd_step": (c_int, [c_void_p, ctypes.POINTER(gp_state), c_int]),
     "pd_gap": (c_int, [c_void_p, ctypes.POINTER(gp_state), ctypes.POINTER(gp_report)]),
+    "gp_batch_solve": (c_int, [c_void_p, ctypes.POINTER(gp_instance), c_int, ctypes.POINTER(gp_opts),
+                               ctypes.POINTER(gp_report)]),
     "gp_profile": (c_int, [c_void_p, c_int]),
     "gp_profile_read": (c_int, [c_void_p, ctypes.POINTER(gp_kstat), c_int, ctypes.POINTER(c_int)]),
 }

@@ -216,6 +216,35 @@ class Context:
                                         bytes=k.bytes, gbps=(k.bytes / (k.total_ms * 1e6)) if k.total_ms else 0.0)
         return out
 
+    def batch_solve(self, problems, opts: Options, outs=None):
+        """Solve independent instances together (gp_batch_solve).
+
+        problems: sequence of dicts, ROF: {"kind": GP_KIND_ROF, "I": (ny, nx) tensor, "h", "lam", "tau"};
+        EMD: {"kind": GP_KIND_EMD, "rho0", "rho1": (ny, nx) tensors, "h", "tau"}.
+        Returns (outs, reports, rc): outs[i] is u (ROF) or the flux m (EMD)."""
+        torch = _torch()
+        n = len(problems)
+        arr = (L.gp_instance * n)()
+        keep = []
+        outs = [None] * n if outs is None else list(outs)
+        for i, q in enumerate(problems):
+            kind = int(q["kind"])
+            a = q["I"] if kind == L.GP_KIND_ROF else q["rho0"]
+            ny, nx = a.shape
+            oshape = (ny, nx) if kind == L.GP_KIND_ROF else (2, ny, nx)
+            if outs[i] is None:
+                outs[i] = torch.empty(oshape, device=a.device, dtype=torch.float32)
+            in0 = _ptr(a, torch.float32, (ny, nx), f"problems[{i}] input")
+            in1 = _ptr(q["rho1"], torch.float32, (ny, nx), f"problems[{i}].rho1") if kind == L.GP_KIND_EMD else None
+            out = _ptr(outs[i], torch.float32, oshape, f"outs[{i}]")
+            arr[i] = L.gp_instance(kind, ny, nx, float(q["h"]), float(q.get("lam", 0.0)), float(q["tau"]),
+                                   in0, in1, out)
+            keep.append(a)
+        reps = (L.gp_report * n)()
+        rc = self._lib.gp_batch_solve(self._h, arr, n, ctypes.byref(opts.c()), reps)
+        self._check(rc, allow_notconv=True)
+        return outs, [r.as_dict() for r in reps], rc
+
     def pd_gap(self, st: State):
         rep = L.gp_report()
         self._check(self._lib.pd_gap(self._h, ctypes.byref(st.c), ctypes.byref(rep)))

@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libgprox.so")
 SOURCES = [os.path.join(PKG, "csrc", "gprox.hip")]
-DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("gprox_fft.hpp", "gprox_kernels.hpp")] + [
+DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp")] + [
     os.path.join(ROOT, "include", "gprox.h")]
 
 HIPCC_FLAGS = [

@@ -1,12 +1,22 @@
 // libgprox: host orchestration and the C ABI declared in include/gprox.h.
+//
+// Every solve runs on a Group: m instances of one grid size stacked into tall
+// device buffers (btile in gprox_kernels.hpp gives the layout).  The
+// single-instance entry points are the m = 1 case; gp_batch_solve groups its
+// instances by kind, size, h, lambda and tau, captures chunks of iterations of
+// all groups in one hipGraph and retires converged instances between replays
+// through per-instance active flags.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gprox.h"
@@ -18,8 +28,9 @@ using namespace gp;
 namespace {
 
 constexpr int kMinN = 64, kMaxN = 4096;
-constexpr int kRedBlocks = 1024;  // partial-sum blocks of the reductions
+constexpr int kRedBlocks = 1024;  // partial-sum blocks of the grid-stride reductions
 constexpr int kMaxK = 8;
+constexpr int kResult = 16;       // doubles in the finalized-result buffers
 
 bool is_pow2_in_range(int n) { return n >= kMinN && n <= kMaxN && (n & (n - 1)) == 0; }
 int ilog2i(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
@@ -27,33 +38,35 @@ int ilog2i(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
 struct Tables {  // per transform length N
   float2* tw32 = nullptr;
   double2* tw64 = nullptr;
-  float2* dw32 = nullptr;   // exp(-i pi k / 2N)
+  float2* dw32 = nullptr;  // exp(-i pi k / 2N)
   double2* dw64 = nullptr;
 };
 
 }  // namespace
 
 struct gp_ctx {
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // the caller's stream
+  hipStream_t bstream = nullptr;  // private stream of gp_batch_solve (graph capture and replay)
   int max_ny = 0, max_nx = 0;
   Tables tab[13];            // index log2 N
-  float* work = nullptr;     // [max_n] transform buffer
-  float* work2 = nullptr;    // [2 max_n] EMD stored field wt (ping)
-  float* work3 = nullptr;    // [2 max_n] EMD stored field wt (pong)
-  double* work64 = nullptr;  // [2 max_n] FP64 set-up buffers
-  double* partials = nullptr;
-  double* result = nullptr;  // [kMaxK] finalized reductions (device)
-  double* host_result = nullptr;  // pinned
-  // eigenvalue tables of -Delta along each axis for the current (n, h)
+  float* work = nullptr;     // [max_n] FP32 tiled intermediate
+  float* work2 = nullptr;    // [2 max_n] EMD stored field (ping)
+  float* work3 = nullptr;    // [2 max_n] EMD stored field (pong)
+  double* work64 = nullptr;  // [2 max_n] FP64 potential and intermediate
+  double* partials = nullptr;     // [kRedBlocks * kMaxK]
+  double* result = nullptr;       // [kResult] finalized reductions (device)
+  double* host_result = nullptr;  // [kResult] pinned
+  // eigenvalue tables of -Delta for the single-instance calls (current ny, nx, h)
   float *mux32 = nullptr, *muy32 = nullptr;
   double *mux64 = nullptr, *muy64 = nullptr;
-  double *mu_host = nullptr;  // pinned staging [2 * kMaxN]
-  float *mu_host32 = nullptr;
   int mu_ny = -1, mu_nx = -1;
   double mu_h = -1.0;
   // solver arena (grow-only)
   float* arena = nullptr;
   size_t arena_floats = 0;
+  // batch arena (grow-only)
+  char* barena = nullptr;
+  size_t barena_bytes = 0;
   // per-kernel timing (gp_profile)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;  // 2 per recorded launch
@@ -120,6 +133,12 @@ void set_err(gp_ctx* c, const char* fmt, ...) {
     }                                                                                      \
   } while (0)
 
+#define RCHK(expr)       \
+  do {                   \
+    int rc_ = (expr);    \
+    if (rc_) return rc_; \
+  } while (0)
+
 int grid_for(size_t n) {
   size_t b = (n + 255) / 256;
   return int(b < 2048 ? (b ? b : 1) : 2048);
@@ -149,19 +168,6 @@ template <int N> void fill_tw(std::vector<double>& re, std::vector<double>& im) 
         im[off + LS + j] = sin(a4);
       }
     }
-}
-
-int total_tw(int n) {
-  switch (n) {
-    case 64: return Sched<64>::total_tw();
-    case 128: return Sched<128>::total_tw();
-    case 256: return Sched<256>::total_tw();
-    case 512: return Sched<512>::total_tw();
-    case 1024: return Sched<1024>::total_tw();
-    case 2048: return Sched<2048>::total_tw();
-    case 4096: return Sched<4096>::total_tw();
-  }
-  return 0;
 }
 
 void fill_tw_n(int n, std::vector<double>& re, std::vector<double>& im) {
@@ -206,36 +212,34 @@ int build_tables(gp_ctx* c, int n) {
   return GP_OK;
 }
 
-// eigenvalues of -Delta along each axis: (4/h^2) sin^2(pi k / 2n)
+// eigenvalues of -Delta along one axis, (4/h^2) sin^2(pi k / 2n), computed in FP64
+__global__ void k_mu(double* __restrict__ m64, float* __restrict__ m32, int n, double h) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const double s = sin(M_PI * double(k) / (2.0 * n));
+    const double v = 4.0 / (h * h) * s * s;
+    m64[k] = v;
+    m32[k] = float(v);
+  }
+}
+
+int fill_mu(gp_ctx* c, double* y64, float* y32, double* x64, float* x32, int ny, int nx, double h) {
+  hipLaunchKernelGGL(k_mu, dim3((ny + 255) / 256), dim3(256), 0, c->stream, y64, y32, ny, h);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL(k_mu, dim3((nx + 255) / 256), dim3(256), 0, c->stream, x64, x32, nx, h);
+  LAUNCHCHK(c);
+  return GP_OK;
+}
+
 int set_mu(gp_ctx* c, int ny, int nx, double h) {
   if (c->mu_ny == ny && c->mu_nx == nx && c->mu_h == h) return GP_OK;
-  // the staging buffer is reused: wait for any pending upload to finish
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  double* hy = c->mu_host;
-  double* hx = c->mu_host + kMaxN;
-  float* fy = c->mu_host32;
-  float* fx = c->mu_host32 + kMaxN;
-  for (int k = 0; k < ny; ++k) {
-    const double s = sin(M_PI * k / (2.0 * ny));
-    hy[k] = 4.0 / (h * h) * s * s;
-    fy[k] = float(hy[k]);
-  }
-  for (int l = 0; l < nx; ++l) {
-    const double s = sin(M_PI * l / (2.0 * nx));
-    hx[l] = 4.0 / (h * h) * s * s;
-    fx[l] = float(hx[l]);
-  }
-  HIPCHK(c, hipMemcpyAsync(c->muy64, hy, ny * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->mux64, hx, nx * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->muy32, fy, ny * sizeof(float), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->mux32, fx, nx * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  RCHK(fill_mu(c, c->muy64, c->muy32, c->mux64, c->mux32, ny, nx, h));
   c->mu_ny = ny;
   c->mu_nx = nx;
   c->mu_h = h;
   return GP_OK;
 }
 
-// ---------------------------------------------------------------- DCT launchers
+// ---------------------------------------------------------------- launchers
 // log2 of the strip width of the tiled intermediate, fixed by the column pass over ny
 template <class C> int col_lgtw(int ny) {
   switch (ny) {
@@ -246,32 +250,6 @@ template <class C> int col_lgtw(int ny) {
   return 0;
 }
 
-template <int N, class C> void launch_rows_fwd(gp_ctx* c, const typename Cx<C>::R* in, typename Cx<C>::R* out,
-                                               int ny, const C* tw, const C* dw) {
-  using SH = RowShape<N, C>;
-  const int pairs = (ny + 1) / 2;
-  const int blocks = (pairs + SH::G - 1) / SH::G;
-  hipLaunchKernelGGL((k_rows_fwd<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, in, out, ny,
-                     col_lgtw<C>(ny), tw, dw);
-}
-template <int N, class C> void launch_rows_inv(gp_ctx* c, const typename Cx<C>::R* in, typename Cx<C>::R* out,
-                                               int ny, const C* tw, const C* dw) {
-  using SH = RowShape<N, C>;
-  const int pairs = (ny + 1) / 2;
-  const int blocks = (pairs + SH::G - 1) / SH::G;
-  hipLaunchKernelGGL((k_rows_inv<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, in, out, ny,
-                     col_lgtw<C>(ny), tw, dw);
-}
-template <int N, class C> void launch_cols(gp_ctx* c, typename Cx<C>::R* buf, int nx, const C* tw, const C* dw,
-                                           const typename Cx<C>::R* mux, const typename Cx<C>::R* muy,
-                                           typename Cx<C>::R alpha, typename Cx<C>::R inv_nn) {
-  using SH = ColShape<N, C>;
-  const int pairs = nx / 2;
-  const int blocks = (pairs + SH::G - 1) / SH::G;
-  hipLaunchKernelGGL((k_cols_solve<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, buf, nx, tw,
-                     dw, mux, muy, alpha, inv_nn);
-}
-
 template <class C> const C* tw_of(const Tables& T);
 template <> const float2* tw_of<float2>(const Tables& T) { return T.tw32; }
 template <> const double2* tw_of<double2>(const Tables& T) { return T.tw64; }
@@ -279,81 +257,117 @@ template <class C> const C* dw_of(const Tables& T);
 template <> const float2* dw_of<float2>(const Tables& T) { return T.dw32; }
 template <> const double2* dw_of<double2>(const Tables& T) { return T.dw64; }
 
-#define GP_DISPATCH_NM(n, T, M, ...)             \
-  switch (n) {                                   \
-    case 64: T<64>::M(__VA_ARGS__); break;       \
-    case 128: T<128>::M(__VA_ARGS__); break;     \
-    case 256: T<256>::M(__VA_ARGS__); break;     \
-    case 512: T<512>::M(__VA_ARGS__); break;     \
-    case 1024: T<1024>::M(__VA_ARGS__); break;   \
-    case 2048: T<2048>::M(__VA_ARGS__); break;   \
-    case 4096: T<4096>::M(__VA_ARGS__); break;   \
+#define GP_DISPATCH_NM(n, T, M, ...)           \
+  switch (n) {                                 \
+    case 64: T<64>::M(__VA_ARGS__); break;     \
+    case 128: T<128>::M(__VA_ARGS__); break;   \
+    case 256: T<256>::M(__VA_ARGS__); break;   \
+    case 512: T<512>::M(__VA_ARGS__); break;   \
+    case 1024: T<1024>::M(__VA_ARGS__); break; \
+    case 2048: T<2048>::M(__VA_ARGS__); break; \
+    case 4096: T<4096>::M(__VA_ARGS__); break; \
   }
 
-#define GP_DISPATCH_N(n, F, ...)            \
-  switch (n) {                              \
-    case 64: F<64>(__VA_ARGS__); break;     \
-    case 128: F<128>(__VA_ARGS__); break;   \
-    case 256: F<256>(__VA_ARGS__); break;   \
-    case 512: F<512>(__VA_ARGS__); break;   \
-    case 1024: F<1024>(__VA_ARGS__); break; \
-    case 2048: F<2048>(__VA_ARGS__); break; \
-    case 4096: F<4096>(__VA_ARGS__); break; \
-  }
-
-template <class C> struct Solve {
+// DCT passes over a stack of m instances of nyi rows
+template <class C> struct Pass {
   using Re = typename Cx<C>::R;
-  template <int N> static void rows_fwd(gp_ctx* c, const Re* in, Re* out, int ny) {
+  template <int N> struct At {
+    static void rows_fwd(gp_ctx* c, const Re* in, Re* out, int nyi, int m, const int* active) {
+      using SH = RowShape<N, C>;
+      const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
+      const Tables& T = c->tab[ilog2i(N)];
+      hipLaunchKernelGGL((k_rows_fwd<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, in, out,
+                         ny, nyi, active, col_lgtw<C>(nyi), tw_of<C>(T), dw_of<C>(T));
+    }
+    static void rows_inv(gp_ctx* c, const Re* in, Re* out, int nyi, int m, const int* active) {
+      using SH = RowShape<N, C>;
+      const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
+      const Tables& T = c->tab[ilog2i(N)];
+      hipLaunchKernelGGL((k_rows_inv<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, in, out,
+                         ny, nyi, active, col_lgtw<C>(nyi), tw_of<C>(T), dw_of<C>(T));
+    }
+    // here N is the column length nyi
+    static void cols(gp_ctx* c, Re* buf, int nx, int m, const int* active, const Re* mux, const Re* muy, Re alpha,
+                     Re inv_nn) {
+      using SH = ColShape<N, C>;
+      const int blocks = (nx / 2 + SH::G - 1) / SH::G;
+      const Tables& T = c->tab[ilog2i(N)];
+      hipLaunchKernelGGL((k_cols_solve<N, C>), dim3(blocks, m), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, buf,
+                         nx, active, tw_of<C>(T), dw_of<C>(T), mux, muy, alpha, inv_nn);
+    }
+  };
+};
+template <int N> using P32 = Pass<float2>::At<N>;
+template <int N> using P64 = Pass<double2>::At<N>;
+
+template <int N> struct Fused {
+  static void rof_A(gp_ctx* c, const float* u, const float* pin, float* pout, const float* I, float* rhat, int nyi,
+                    int m, const int* active, float lt, float tau_h, float sig_h, int aniso, int mode,
+                    double* partials) {
+    using SH = RowShape<N, float2>;
+    const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
     const Tables& T = c->tab[ilog2i(N)];
-    launch_rows_fwd<N, C>(c, in, out, ny, tw_of<C>(T), dw_of<C>(T));
+    hipLaunchKernelGGL((k_rof_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, u, pin, pout, I,
+                       rhat, ny, nyi, active, col_lgtw<float2>(nyi), lt, tau_h, sig_h, aniso, mode, partials, T.tw32,
+                       T.dw32);
   }
-  template <int N> static void rows_inv(gp_ctx* c, const Re* in, Re* out, int ny) {
+  static void rof_B(gp_ctx* c, const float* dhat, float* u, int nyi, int m, const int* active) {
+    using SH = RowShape<N, float2>;
+    const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
     const Tables& T = c->tab[ilog2i(N)];
-    launch_rows_inv<N, C>(c, in, out, ny, tw_of<C>(T), dw_of<C>(T));
+    hipLaunchKernelGGL((k_rof_B<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, dhat, u, ny, nyi,
+                       active, col_lgtw<float2>(nyi), T.tw32, T.dw32);
   }
-  template <int N> static void cols(gp_ctx* c, Re* buf, int nx, const Re* mux, const Re* muy, Re alpha, Re inv_nn) {
+  static void emd_A(gp_ctx* c, const float* wt_in, const double* phi, const float* pin, const float* gpsi,
+                    const float* f, float* pout, float* wt_out, double* rhat, int nyi, int m, const int* active,
+                    double inv_h, float tau, float sigma, int aniso, int mode, double* partials) {
+    using SH = RowShape<N, double2>;
+    const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
     const Tables& T = c->tab[ilog2i(N)];
-    launch_cols<N, C>(c, buf, nx, tw_of<C>(T), dw_of<C>(T), mux, muy, alpha, inv_nn);
+    hipLaunchKernelGGL((k_emd_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, wt_in, phi, pin,
+                       gpsi, f, pout, wt_out, rhat, ny, nyi, active, col_lgtw<double2>(nyi), inv_h, tau, sigma, aniso,
+                       mode, partials, T.tw64, T.dw64);
   }
 };
 
-// (alpha I - Delta) x = b on the device, b and x may alias.  Tables and mu must be set.
-// (alpha I - Delta) x = b: row DCT into the tiled intermediate tmp, column solve,
-// row inverse into x.  b and x may alias; tmp must not alias either.
-int poisson_f32(gp_ctx* c, const float* b, float* x, int ny, int nx, double alpha, float* tmp) {
-  const double fb = 8.0 * double(nx) * ny;  // each pass reads and writes one FP32 field
+// (alpha I - Delta) x = b for m stacked instances: row DCT into the tiled
+// intermediate tmp, column solve, row inverse into x.  b and x may alias; tmp must not.
+int poisson_f32(gp_ctx* c, const float* b, float* x, int nyi, int nx, int m, const float* mux, const float* muy,
+                double alpha, float* tmp) {
+  const double fb = 8.0 * double(nx) * nyi * m;  // each pass reads and writes one FP32 field
   int ps = prof_begin(c, K_ROWS_FWD, fb);
-  GP_DISPATCH_N(nx, Solve<float2>::rows_fwd, c, b, tmp, ny);
+  GP_DISPATCH_NM(nx, P32, rows_fwd, c, b, tmp, nyi, m, nullptr);
   prof_end(c, ps);
   LAUNCHCHK(c);
   ps = prof_begin(c, K_COLS, fb);
-  GP_DISPATCH_N(ny, Solve<float2>::cols, c, tmp, nx, c->mux32, c->muy32, float(alpha), float(1.0 / (double(nx) * ny)));
+  GP_DISPATCH_NM(nyi, P32, cols, c, tmp, nx, m, nullptr, mux, muy, float(alpha), float(1.0 / (double(nx) * nyi)));
   prof_end(c, ps);
   LAUNCHCHK(c);
   ps = prof_begin(c, K_ROWS_INV, fb);
-  GP_DISPATCH_N(nx, Solve<float2>::rows_inv, c, tmp, x, ny);
+  GP_DISPATCH_NM(nx, P32, rows_inv, c, tmp, x, nyi, m, nullptr);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
-int poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, double alpha, double* tmp) {
-  const double fb = 16.0 * double(nx) * ny;
+int poisson_f64(gp_ctx* c, const double* b, double* x, int nyi, int nx, int m, const int* active, const double* mux,
+                const double* muy, double alpha, double* tmp) {
+  const double fb = 16.0 * double(nx) * nyi * m;
   int ps = prof_begin(c, K_ROWS_FWD64, fb);
-  GP_DISPATCH_N(nx, Solve<double2>::rows_fwd, c, b, tmp, ny);
+  GP_DISPATCH_NM(nx, P64, rows_fwd, c, b, tmp, nyi, m, active);
   prof_end(c, ps);
   LAUNCHCHK(c);
   ps = prof_begin(c, K_COLS64, fb);
-  GP_DISPATCH_N(ny, Solve<double2>::cols, c, tmp, nx, c->mux64, c->muy64, alpha, 1.0 / (double(nx) * ny));
+  GP_DISPATCH_NM(nyi, P64, cols, c, tmp, nx, m, active, mux, muy, alpha, 1.0 / (double(nx) * nyi));
   prof_end(c, ps);
   LAUNCHCHK(c);
   ps = prof_begin(c, K_ROWS_INV64, fb);
-  GP_DISPATCH_N(nx, Solve<double2>::rows_inv, c, tmp, x, ny);
+  GP_DISPATCH_NM(nx, P64, rows_inv, c, tmp, x, nyi, m, active);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
 
-int prepare(gp_ctx* c, int ny, int nx, double h) {
+int check_size(gp_ctx* c, int ny, int nx, double h) {
   if (!is_pow2_in_range(ny) || !is_pow2_in_range(nx)) {
     set_err(c, "grid %dx%d unsupported: sides must be powers of two in [%d, %d]", ny, nx, kMinN, kMaxN);
     return GP_EUNSUPPORTED;
@@ -366,20 +380,23 @@ int prepare(gp_ctx* c, int ny, int nx, double h) {
     set_err(c, "h must be positive and finite");
     return GP_EINVAL;
   }
-  int rc = build_tables(c, ny);
-  if (rc) return rc;
-  rc = build_tables(c, nx);
-  if (rc) return rc;
+  return GP_OK;
+}
+
+int prepare(gp_ctx* c, int ny, int nx, double h) {
+  RCHK(check_size(c, ny, nx, h));
   return set_mu(c, ny, nx, h);
 }
 
-// reductions: finalize K partial columns from nb blocks into c->result and copy to host (sync)
-int finalize_read(gp_ctx* c, int nb, int K, unsigned max_mask, double* out) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, c->partials, nb, K, max_mask, c->result);
+// finalizes m segments of seg partials (K values each) into c->result and copies
+// them to out (synchronises); m * K <= kResult
+int finalize_read(gp_ctx* c, const double* partials, int seg, int m, int K, unsigned max_mask, double* out) {
+  hipLaunchKernelGGL(k_finalize, dim3(m), dim3(256), 0, c->stream, partials, seg, K, max_mask, c->result);
   LAUNCHCHK(c);
-  HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, K * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, size_t(m) * K * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int i = 0; i < K; ++i) out[i] = c->host_result[i];
+  for (int i = 0; i < m * K; ++i) out[i] = c->host_result[i];
   return GP_OK;
 }
 
@@ -387,7 +404,7 @@ int count_nonfinite(gp_ctx* c, const float* x, size_t n, double* cnt) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_nonfinite, dim3(nb), dim3(256), 0, c->stream, x, n, c->partials);
   LAUNCHCHK(c);
-  return finalize_read(c, nb, 1, 0u, cnt);
+  return finalize_read(c, c->partials, nb, 1, 1, 0u, cnt);
 }
 
 float* arena(gp_ctx* c, size_t floats) {
@@ -433,71 +450,41 @@ int check_opts(gp_ctx* c, const gp_opts* o, double* tau, double* sigma) {
   return GP_OK;
 }
 
-// ---------------------------------------------------------------- fused iterations
-template <int N> struct Fused {
-  static void rof_A(gp_ctx* c, const float* u, const float* pin, float* pout, const float* I, float* rhat, int ny,
-                    float lt, float tau_h, float sig_h, int aniso, int mode, double* partials) {
-    using SH = RowShape<N, float2>;
-    const int blocks = (ny / 2 + SH::G - 1) / SH::G;
-    const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_rof_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, u, pin, pout, I,
-                       rhat, ny, col_lgtw<float2>(ny), lt, tau_h, sig_h, aniso, mode, partials, T.tw32, T.dw32);
-  }
-  static void rof_B(gp_ctx* c, const float* dhat, float* u, int ny) {
-    using SH = RowShape<N, float2>;
-    const int blocks = (ny / 2 + SH::G - 1) / SH::G;
-    const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_rof_B<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, dhat, u, ny,
-                       col_lgtw<float2>(ny), T.tw32, T.dw32);
-  }
-  static void emd_A(gp_ctx* c, const float* wt_in, const double* phi, const float* pin, const float* gpsi,
-                    const float* f, float* pout, float* wt_out, double* rhat, int ny, double inv_h, float tau,
-                    float sigma, int aniso, int mode, double* partials) {
-    using SH = RowShape<N, double2>;
-    const int blocks = (ny / 2 + SH::G - 1) / SH::G;
-    const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_emd_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, wt_in, phi, pin,
-                       gpsi, f, pout, wt_out, rhat, ny, col_lgtw<double2>(ny), inv_h, tau, sigma, aniso, mode, partials,
-                       T.tw64, T.dw64);
-  }
+double rel_gap(double P, double D) { return P != 0.0 ? (P - D) / fabs(P) : fabs(P - D); }
+
+// ---------------------------------------------------------------- groups and pipelines
+struct Group {
+  int kind = GP_KIND_ROF, nyi = 0, nx = 0, m = 1, norm = GP_NORM_ISO;
+  double h = 1, lambda = 0, tau = 1, sigma = 1;
+  const float* f = nullptr;     // ROF: the image I; EMD: rho1 - rho0 (mean removed)   [m nyi][nx]
+  const float* gpsi = nullptr;  // EMD: grad psi                                       [2][m nyi][nx]
+  float *u = nullptr, *p = nullptr, *pbar = nullptr;
+  const int* active = nullptr;  // device flag per instance; nullptr: all active
+  const float *mux32 = nullptr, *muy32 = nullptr;
+  const double *mux64 = nullptr, *muy64 = nullptr;
+  float* rhat = nullptr;                     // ROF tiled intermediate [m nyi nx]
+  double *rhat64 = nullptr, *phi = nullptr;  // EMD intermediate and potential [m nyi nx]
+  float *w0 = nullptr, *w1 = nullptr;        // EMD stored field ping-pong [2][m nyi][nx]
+  double* gpart = nullptr;                   // per-row-pair gap partials (ROF 4, EMD 1 per pair)
+  size_t ntot() const { return size_t(m) * nyi * nx; }
 };
 
-int rows_blocks_f32(int nx, int ny) {
-  switch (nx) {
-#define GP_RB(NN) case NN: return (ny / 2 + RowShape<NN, float2>::G - 1) / RowShape<NN, float2>::G;
-    GP_RB(64) GP_RB(128) GP_RB(256) GP_RB(512) GP_RB(1024) GP_RB(2048) GP_RB(4096)
-#undef GP_RB
-  }
-  return 0;
-}
-int rows_blocks_f64(int nx, int ny) {
-  switch (nx) {
-#define GP_RB(NN) case NN: return (ny / 2 + RowShape<NN, double2>::G - 1) / RowShape<NN, double2>::G;
-    GP_RB(64) GP_RB(128) GP_RB(256) GP_RB(512) GP_RB(1024) GP_RB(2048) GP_RB(4096)
-#undef GP_RB
-  }
-  return 0;
-}
-
-// ROF pipeline.  A(entry) builds rhat from (u_n, pbar_n); each later A advances the
-// dual (p ping-pong between the two state buffers) and builds the next rhat.
+// ROF pipeline.  A(entry) builds rhat from (u_n, pbar_n); each later A advances
+// the dual (ping-pong between the two dual buffers) and builds the next rhat.
 struct RofPipe {
   gp_ctx* c;
-  const gp_state* s;
+  const Group* g;
   float* X;  // buffer holding the latest complete dual iterate
   float* Y;  // the other dual buffer
-  size_t n;
-  float lt, tau_h, sig_h;
 };
 
-int rof_A(RofPipe& P, int mode, double* partials) {
+int rof_A(RofPipe& P, int mode, bool partials) {
   gp_ctx* c = P.c;
-  const gp_state* s = P.s;
-  const double by = (mode == 1 ? 20.0 : 28.0) * double(P.n);
-  const int ps = prof_begin(c, K_ROF_A, by);
-  const float* pin = (mode == 1) ? s->pbar : P.X;
-  GP_DISPATCH_NM(s->nx, Fused, rof_A, c, s->u, pin, P.Y, s->f, c->work, s->ny, P.lt, P.tau_h, P.sig_h, s->norm,
-                mode, partials);
+  const Group& g = *P.g;
+  const int ps = prof_begin(c, K_ROF_A, (mode == 1 ? 20.0 : 28.0) * double(g.ntot()));
+  const float* pin = (mode == 1) ? g.pbar : P.X;
+  GP_DISPATCH_NM(g.nx, Fused, rof_A, c, g.u, pin, P.Y, g.f, g.rhat, g.nyi, g.m, g.active, float(g.lambda * g.tau),
+                 float(g.tau / g.h), float(g.sigma / g.h), g.norm, mode, partials ? g.gpart : nullptr);
   prof_end(c, ps);
   LAUNCHCHK(c);
   if (mode == 0) std::swap(P.X, P.Y);
@@ -506,74 +493,48 @@ int rof_A(RofPipe& P, int mode, double* partials) {
 
 int rof_CB(RofPipe& P) {
   gp_ctx* c = P.c;
-  const gp_state* s = P.s;
-  const double fb = 8.0 * double(P.n);
-  int ps = prof_begin(c, K_COLS, fb);
-  GP_DISPATCH_N(s->ny, Solve<float2>::cols, c, c->work, s->nx, c->mux32, c->muy32, float(s->lambda * s->tau),
-                float(1.0 / double(P.n)));
+  const Group& g = *P.g;
+  int ps = prof_begin(c, K_COLS, 8.0 * double(g.ntot()));
+  GP_DISPATCH_NM(g.nyi, P32, cols, c, g.rhat, g.nx, g.m, g.active, g.mux32, g.muy32, float(g.lambda * g.tau),
+                 float(1.0 / (double(g.nyi) * g.nx)));
   prof_end(c, ps);
   LAUNCHCHK(c);
-  ps = prof_begin(c, K_ROF_B, 12.0 * double(P.n));
-  GP_DISPATCH_NM(s->nx, Fused, rof_B, c, c->work, s->u, s->ny);
+  ps = prof_begin(c, K_ROF_B, 12.0 * double(g.ntot()));
+  GP_DISPATCH_NM(g.nx, Fused, rof_B, c, g.rhat, g.u, g.nyi, g.m, g.active);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
 
+// the state's (p, pbar) from u and the latest dual iterate
 int rof_finish(RofPipe& P) {
   gp_ctx* c = P.c;
-  const gp_state* s = P.s;
-  const int ps = prof_begin(c, K_ROF_FINISH, 28.0 * double(P.n));
-  hipLaunchKernelGGL(k_rof_finish, dim3(grid_for(P.n)), dim3(256), 0, c->stream, s->u, P.X, s->p, s->pbar, s->ny,
-                     s->nx, P.sig_h, s->norm);
+  const Group& g = *P.g;
+  const int ps = prof_begin(c, K_ROF_FINISH, 28.0 * double(g.ntot()));
+  hipLaunchKernelGGL(k_rof_finish, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, g.u, P.X, g.p, g.pbar,
+                     g.nyi * g.m, g.nx, g.nyi, float(g.sigma / g.h), g.norm);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
 
-RofPipe rof_pipe(gp_ctx* c, const gp_state* s) {
-  RofPipe P{c, s, s->p, s->pbar, size_t(s->ny) * s->nx, float(s->lambda * s->tau), float(s->tau / s->h),
-            float(s->sigma / s->h)};
-  return P;
-}
-
-// advance (u_n, p_n, pbar_n) by k >= 1 iterations
-int rof_advance(gp_ctx* c, const gp_state* s, int k) {
-  RofPipe P = rof_pipe(c, s);
-  int rc = rof_A(P, 1, nullptr);
-  for (int i = 0; !rc && i < k; ++i) {
-    rc = rof_CB(P);
-    if (!rc && i + 1 < k) rc = rof_A(P, 0, nullptr);
-  }
-  if (!rc) rc = rof_finish(P);
-  return rc;
-}
-
-// EMD pipeline: wt ping-pong in work2/work3, phi in work64[0, n), rhat in work64[n, 2n).
+// EMD pipeline: the stored field ping-pongs between w0 and w1, phi and the
+// intermediate are FP64.
 struct EmdPipe {
   gp_ctx* c;
-  const gp_state* s;
-  float *X, *Y;    // dual buffers
-  float *WX, *WY;  // wt buffers (WX = latest)
-  double *phi, *rhat;
-  size_t n;
+  const Group* g;
+  float *X, *Y;    // dual buffers (X = latest)
+  float *WX, *WY;  // stored-field buffers (WX = latest)
 };
 
-EmdPipe emd_pipe(gp_ctx* c, const gp_state* s) {
-  const size_t n = size_t(s->ny) * s->nx;
-  EmdPipe P{c, s, s->p, s->pbar, c->work3, c->work2, c->work64, c->work64 + n, n};
-  return P;
-}
-
-int emd_A(EmdPipe& P, int mode, double* partials) {
+int emd_A(EmdPipe& P, int mode, bool partials) {
   gp_ctx* c = P.c;
-  const gp_state* s = P.s;
-  const double by = (mode == 1 ? 44.0 : 52.0) * double(P.n);
-  const int ps = prof_begin(c, K_EMD_A, by);
-  const float* win = (mode == 1) ? s->u : P.WX;
-  const float* pin = (mode == 1) ? s->pbar : P.X;
-  GP_DISPATCH_NM(s->nx, Fused, emd_A, c, win, P.phi, pin, s->gpsi, s->f, P.Y, P.WY, P.rhat, s->ny, 1.0 / s->h,
-                float(s->tau), float(s->sigma), s->norm, mode, partials);
+  const Group& g = *P.g;
+  const int ps = prof_begin(c, K_EMD_A, (mode == 1 ? 44.0 : 52.0) * double(g.ntot()));
+  const float* win = (mode == 1) ? g.u : P.WX;
+  const float* pin = (mode == 1) ? g.pbar : P.X;
+  GP_DISPATCH_NM(g.nx, Fused, emd_A, c, win, g.phi, pin, g.gpsi, g.f, P.Y, P.WY, g.rhat64, g.nyi, g.m, g.active,
+                 1.0 / g.h, float(g.tau), float(g.sigma), g.norm, mode, partials ? g.gpart : nullptr);
   prof_end(c, ps);
   LAUNCHCHK(c);
   std::swap(P.WX, P.WY);
@@ -583,100 +544,138 @@ int emd_A(EmdPipe& P, int mode, double* partials) {
 
 int emd_CB(EmdPipe& P) {
   gp_ctx* c = P.c;
-  const gp_state* s = P.s;
-  int ps = prof_begin(c, K_COLS64, 16.0 * double(P.n));
-  GP_DISPATCH_N(s->ny, Solve<double2>::cols, c, P.rhat, s->nx, c->mux64, c->muy64, 0.0, 1.0 / double(P.n));
+  const Group& g = *P.g;
+  int ps = prof_begin(c, K_COLS64, 16.0 * double(g.ntot()));
+  GP_DISPATCH_NM(g.nyi, P64, cols, c, g.rhat64, g.nx, g.m, g.active, g.mux64, g.muy64, 0.0,
+                 1.0 / (double(g.nyi) * g.nx));
   prof_end(c, ps);
   LAUNCHCHK(c);
-  ps = prof_begin(c, K_EMD_B, 16.0 * double(P.n));
-  GP_DISPATCH_N(s->nx, Solve<double2>::rows_inv, c, P.rhat, P.phi, s->ny);
+  ps = prof_begin(c, K_EMD_B, 16.0 * double(g.ntot()));
+  GP_DISPATCH_NM(g.nx, P64, rows_inv, c, g.rhat64, g.phi, g.nyi, g.m, g.active);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
 
-// write (u, p, pbar) of the state from (wt, phi, latest p); m and partials optional
-int emd_finish(EmdPipe& P, float* m, double* partials, int nb) {
+// m = wt - grad phi; with state: (u, p, pbar) of the state from (wt, phi, latest p);
+// with mout: the flux
+int emd_finish(EmdPipe& P, const float* wt, bool state, float* mout) {
   gp_ctx* c = P.c;
-  const gp_state* s = P.s;
-  const int ps = prof_begin(c, K_EMD_FINISH, 56.0 * double(P.n));
-  hipLaunchKernelGGL(k_emd_finish, dim3(nb), dim3(256), 0, c->stream, P.WX, P.phi, P.X, s->gpsi, s->p, s->pbar,
-                     s->u, m, s->ny, s->nx, 1.0 / s->h, float(s->sigma), s->norm, partials);
+  const Group& g = *P.g;
+  const int ps = prof_begin(c, K_EMD_FINISH, (state ? 56.0 : 24.0) * double(g.ntot()));
+  hipLaunchKernelGGL(k_emd_finish, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, wt, g.phi, P.X, g.gpsi,
+                     state ? g.p : nullptr, g.pbar, state ? g.u : nullptr, mout, g.nyi * g.m, g.nx, g.nyi, 1.0 / g.h,
+                     float(g.sigma), g.norm);
   prof_end(c, ps);
   LAUNCHCHK(c);
   return GP_OK;
 }
 
-int emd_advance(gp_ctx* c, const gp_state* s, int k) {
-  EmdPipe P = emd_pipe(c, s);
-  int rc = emd_A(P, 1, nullptr);
-  for (int i = 0; !rc && i < k; ++i) {
-    rc = emd_CB(P);
-    if (!rc && i + 1 < k) rc = emd_A(P, 0, nullptr);
-  }
-  if (!rc) rc = emd_finish(P, nullptr, nullptr, grid_for(P.n));
-  return rc;
+// EMD certificates of the dual iterates p of all m instances: phi_c = Delta^{-1} div p,
+// D = h^2 sum phi_c (rho0 - rho1) / max(1, max |grad phi_c|).  Enqueues only: per
+// instance [sum(-phi_c f), max |grad phi_c|] lands in out[2 i], out[2 i + 1].
+// phi, tmp: m n doubles (phi is left holding -phi_c); cpart: m * red_blocks(n) * 2.
+int emd_cert_enqueue(gp_ctx* c, const Group& g, const float* p, double* phi, double* tmp, double* cpart, double* out) {
+  const size_t n = size_t(g.nyi) * g.nx, nt = g.ntot();
+  int ps = prof_begin(c, K_DIV64, 16.0 * double(nt));
+  hipLaunchKernelGGL(k_div<double>, dim3(grid_for(nt)), dim3(256), 0, c->stream, p, p + nt, phi, g.nyi * g.m, g.nx,
+                     g.nyi, float(1.0 / g.h));
+  prof_end(c, ps);
+  LAUNCHCHK(c);
+  // Delta phi_c = div p  <=>  (0 I - Delta) phi_c = -div p: solving with div p gives -phi_c
+  RCHK(poisson_f64(c, phi, phi, g.nyi, g.nx, g.m, g.active, g.mux64, g.muy64, 0.0, tmp));
+  const int nbc = red_blocks(n);
+  ps = prof_begin(c, K_REDUCE, 12.0 * double(nt));
+  hipLaunchKernelGGL(k_emd_cert, dim3(nbc, g.m), dim3(256), 0, c->stream, phi, g.f, g.nyi, g.nx, 1.0 / g.h, g.norm,
+                     cpart);
+  prof_end(c, ps);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL(k_finalize, dim3(g.m), dim3(256), 0, c->stream, cpart, nbc, 2, 2u, out);
+  LAUNCHCHK(c);
+  return GP_OK;
 }
 
-int rof_gap(gp_ctx* c, const gp_state* s, double* P, double* D) {
+double emd_dual_from(const double* r, double h) { return h * h * r[0] / (r[1] > 1.0 ? r[1] : 1.0); }
+
+// single-instance Group over a gp_state and the context workspace
+Group state_group(gp_ctx* c, const gp_state* s) {
+  Group g;
+  g.kind = s->kind;
+  g.nyi = s->ny;
+  g.nx = s->nx;
+  g.m = 1;
+  g.norm = s->norm;
+  g.h = s->h;
+  g.lambda = s->lambda;
+  g.tau = s->tau;
+  g.sigma = s->sigma;
+  g.f = s->f;
+  g.gpsi = s->gpsi;
+  g.u = s->u;
+  g.p = s->p;
+  g.pbar = s->pbar;
+  g.mux32 = c->mux32;
+  g.muy32 = c->muy32;
+  g.mux64 = c->mux64;
+  g.muy64 = c->muy64;
+  const size_t n = size_t(s->ny) * s->nx;
+  g.rhat = c->work;
+  g.phi = c->work64;
+  g.rhat64 = c->work64 + n;
+  g.w0 = c->work3;
+  g.w1 = c->work2;
+  g.gpart = c->partials;
+  return g;
+}
+
+// advance (u_n, p_n, pbar_n) by k >= 1 iterations
+int rof_advance(gp_ctx* c, const Group& g, int k) {
+  RofPipe P{c, &g, g.p, g.pbar};
+  RCHK(rof_A(P, 1, false));
+  for (int i = 0; i < k; ++i) {
+    RCHK(rof_CB(P));
+    if (i + 1 < k) RCHK(rof_A(P, 0, false));
+  }
+  return rof_finish(P);
+}
+
+int emd_advance(gp_ctx* c, const Group& g, int k) {
+  EmdPipe P{c, &g, g.p, g.pbar, g.w0, g.w1};
+  RCHK(emd_A(P, 1, false));
+  for (int i = 0; i < k; ++i) {
+    RCHK(emd_CB(P));
+    if (i + 1 < k) RCHK(emd_A(P, 0, false));
+  }
+  return emd_finish(P, P.WX, true, nullptr);
+}
+
+int rof_gap_state(gp_ctx* c, const gp_state* s, double* P, double* D) {
   const size_t n = size_t(s->ny) * s->nx;
   const int nb = red_blocks(n);
-  int ps = prof_begin(c, K_REDUCE, 16.0 * n);
+  const int ps = prof_begin(c, K_REDUCE, 16.0 * n);
   hipLaunchKernelGGL(k_rof_energy, dim3(nb), dim3(256), 0, c->stream, s->u, s->p, s->p + n, s->f, s->ny, s->nx,
                      float(1.0 / s->h), s->norm, c->partials);
   prof_end(c, ps);
   LAUNCHCHK(c);
   double r[4];
-  int rc = finalize_read(c, nb, 4, 0u, r);
-  if (rc) return rc;
+  RCHK(finalize_read(c, c->partials, nb, 1, 4, 0u, r));
   const double h2 = s->h * s->h;
   *P = h2 * (r[0] + 0.5 * s->lambda * r[1]);
   *D = -h2 * (r[2] + r[3] / (2.0 * s->lambda));
   return GP_OK;
 }
 
-// certificate D from p: phi = Delta^{-1} div p, D = -h^2 sum phi f / max(1, max|grad phi|).
-// Leaves -phi (FP64) in c->work64; *L receives max|grad phi|.
-int emd_cert(gp_ctx* c, const gp_state* s, double* D, double* L, double* phi, double* tmp) {
-  const size_t n = size_t(s->ny) * s->nx;
-  int ps = prof_begin(c, K_DIV64, 16.0 * n);
-  hipLaunchKernelGGL(k_div<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, s->p, s->p + n, phi, s->ny, s->nx,
-                     float(1.0 / s->h));
-  prof_end(c, ps);
-  LAUNCHCHK(c);
-  // Delta phi = div p  <=>  (0 I - Delta) phi = -div p: this solves for -phi; the sign is
-  // folded into D below
-  int rc = poisson_f64(c, phi, phi, s->ny, s->nx, 0.0, tmp);
-  if (rc) return rc;
-  const int nb = red_blocks(n);
-  ps = prof_begin(c, K_REDUCE, 12.0 * n);
-  hipLaunchKernelGGL(k_emd_cert, dim3(nb), dim3(256), 0, c->stream, phi, s->f, s->ny, s->nx, 1.0 / s->h, s->norm,
-                     c->partials);
-  prof_end(c, ps);
-  LAUNCHCHK(c);
-  double r[2];
-  rc = finalize_read(c, nb, 2, 2u, r);
-  if (rc) return rc;
-  // phi holds -phi_c; sum(-phi_c f) = r[0]
-  *L = r[1];
-  *D = s->h * s->h * r[0] / (r[1] > 1.0 ? r[1] : 1.0);
-  return GP_OK;
-}
-
-int emd_primal(gp_ctx* c, const gp_state* s, double* P) {
+int emd_primal_state(gp_ctx* c, const gp_state* s, double* P) {
   const size_t n = size_t(s->ny) * s->nx;
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_emd_primal, dim3(nb), dim3(256), 0, c->stream, s->u, s->u + n, s->gpsi, s->gpsi + n, n,
                      s->norm, c->partials);
   LAUNCHCHK(c);
   double r[1];
-  int rc = finalize_read(c, nb, 1, 0u, r);
-  if (rc) return rc;
+  RCHK(finalize_read(c, c->partials, nb, 1, 1, 0u, r));
   *P = s->h * s->h * r[0];
   return GP_OK;
 }
-
-double rel_gap(double P, double D) { return P != 0.0 ? (P - D) / fabs(P) : fabs(P - D); }
 
 int validate_state(gp_ctx* c, const gp_state* s) {
   if (!s || !s->f || !s->u || !s->p || !s->pbar || (s->kind == GP_KIND_EMD && !s->gpsi)) {
@@ -697,6 +696,67 @@ int validate_state(gp_ctx* c, const gp_state* s) {
     return GP_EINVAL;
   }
   return prepare(c, s->ny, s->nx, s->h);
+}
+
+// ---------------------------------------------------------------- batch
+struct BatchGroup {
+  Group g;
+  std::vector<int> idx;        // the caller's instance indices, in stack order
+  int* active_dev = nullptr;
+  float *mu32 = nullptr;       // [nyi + nx]: muy then mux
+  double* mu64 = nullptr;
+  double* gap_dev = nullptr;   // ROF: [m][4] gap sums; EMD: [m] primal sums
+  double* cert_dev = nullptr;  // EMD: [m][2] certificate sums
+  double *cphi = nullptr, *ctmp = nullptr, *cpart = nullptr;  // EMD certificate workspace
+  float* mflux = nullptr;      // EMD: flux [2][m nyi][nx]
+};
+
+// sub-allocator over the batch arena; with base == nullptr it only measures
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T> T* take(size_t count) {
+    const size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+void carve(Carver& A, BatchGroup& bg) {
+  Group& g = bg.g;
+  const size_t nt = g.ntot(), n = size_t(g.nyi) * g.nx, pairs = size_t(g.m) * g.nyi / 2;
+  bg.active_dev = A.take<int>(g.m);
+  bg.mu32 = A.take<float>(g.nyi + g.nx);
+  bg.mu64 = A.take<double>(g.nyi + g.nx);
+  g.active = bg.active_dev;
+  g.muy32 = bg.mu32;
+  g.mux32 = bg.mu32 ? bg.mu32 + g.nyi : nullptr;
+  g.muy64 = bg.mu64;
+  g.mux64 = bg.mu64 ? bg.mu64 + g.nyi : nullptr;
+  const int vec = g.kind == GP_KIND_ROF ? 1 : 2;  // components of u
+  g.f = A.take<float>(nt);
+  g.u = A.take<float>(vec * nt);
+  g.p = A.take<float>(2 * nt);
+  g.pbar = A.take<float>(2 * nt);
+  if (g.kind == GP_KIND_ROF) {
+    g.rhat = A.take<float>(nt);
+    g.gpart = A.take<double>(pairs * 4);
+    bg.gap_dev = A.take<double>(size_t(g.m) * 4);
+  } else {
+    g.gpsi = A.take<float>(2 * nt);
+    g.w0 = A.take<float>(2 * nt);
+    g.w1 = A.take<float>(2 * nt);
+    g.rhat64 = A.take<double>(nt);
+    g.phi = A.take<double>(nt);
+    bg.cphi = A.take<double>(nt);
+    bg.ctmp = A.take<double>(nt);
+    g.gpart = A.take<double>(pairs);
+    bg.cpart = A.take<double>(size_t(g.m) * red_blocks(n) * 2);
+    bg.gap_dev = A.take<double>(g.m);
+    bg.cert_dev = A.take<double>(size_t(g.m) * 2);
+    bg.mflux = A.take<float>(2 * nt);
+  }
 }
 
 }  // namespace
@@ -734,14 +794,12 @@ int gp_create(gp_ctx** out, int max_ny, int max_nx, void* stream) {
             hipMalloc(&c->work3, 2 * n * sizeof(float)) == hipSuccess &&
             hipMalloc(&c->work64, 2 * n * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->partials, size_t(kRedBlocks) * kMaxK * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->result, kMaxK * sizeof(double)) == hipSuccess &&
-            hipHostMalloc(&c->host_result, kMaxK * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->result, kResult * sizeof(double)) == hipSuccess &&
+            hipHostMalloc(&c->host_result, kResult * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->mux32, kMaxN * sizeof(float)) == hipSuccess &&
             hipMalloc(&c->muy32, kMaxN * sizeof(float)) == hipSuccess &&
             hipMalloc(&c->mux64, kMaxN * sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->muy64, kMaxN * sizeof(double)) == hipSuccess &&
-            hipHostMalloc(&c->mu_host, 2 * kMaxN * sizeof(double)) == hipSuccess &&
-            hipHostMalloc(&c->mu_host32, 2 * kMaxN * sizeof(float)) == hipSuccess;
+            hipMalloc(&c->muy64, kMaxN * sizeof(double)) == hipSuccess;
   if (!ok) {
     gp_destroy(c);
     return GP_ENOMEM;
@@ -759,7 +817,11 @@ int gp_create(gp_ctx** out, int max_ny, int max_nx, void* stream) {
 
 int gp_destroy(gp_ctx* c) {
   if (!c) return GP_OK;
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->bstream) {
+    (void)hipStreamSynchronize(c->bstream);
+    (void)hipStreamDestroy(c->bstream);
+  }
   for (auto& T : c->tab) {
     if (T.tw32) (void)hipFree(T.tw32);
     if (T.tw64) (void)hipFree(T.tw64);
@@ -772,10 +834,9 @@ int gp_destroy(gp_ctx* c) {
   double* db[] = {c->work64, c->partials, c->result, c->mux64, c->muy64};
   for (double* p : db)
     if (p) (void)hipFree(p);
+  if (c->barena) (void)hipFree(c->barena);
   for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
   if (c->host_result) (void)hipHostFree(c->host_result);
-  if (c->mu_host) (void)hipHostFree(c->mu_host);
-  if (c->mu_host32) (void)hipHostFree(c->mu_host32);
   delete c;
   return GP_OK;
 }
@@ -790,9 +851,8 @@ int dct_poisson(gp_ctx* c, const float* b, float* x, int ny, int nx, double h, d
     set_err(c, "alpha must be >= 0 and finite");
     return GP_EINVAL;
   }
-  int rc = prepare(c, ny, nx, h);
-  if (rc) return rc;
-  return poisson_f32(c, b, x, ny, nx, alpha, c->work);
+  RCHK(prepare(c, ny, nx, h));
+  return poisson_f32(c, b, x, ny, nx, 1, c->mux32, c->muy32, alpha, c->work);
 }
 
 int dct_poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, double h, double alpha) {
@@ -805,9 +865,8 @@ int dct_poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, doubl
     set_err(c, "alpha must be >= 0 and finite");
     return GP_EINVAL;
   }
-  int rc = prepare(c, ny, nx, h);
-  if (rc) return rc;
-  return poisson_f64(c, b, x, ny, nx, alpha, c->work64);
+  RCHK(prepare(c, ny, nx, h));
+  return poisson_f64(c, b, x, ny, nx, 1, nullptr, c->mux64, c->muy64, alpha, c->work64);
 }
 
 int pd_step(gp_ctx* c, gp_state* s, int n_iter) {
@@ -816,26 +875,31 @@ int pd_step(gp_ctx* c, gp_state* s, int n_iter) {
     set_err(c, "n_iter < 0");
     return GP_EINVAL;
   }
-  int rc = validate_state(c, s);
-  if (rc || n_iter == 0) return rc;
-  rc = (s->kind == GP_KIND_ROF) ? rof_advance(c, s, n_iter) : emd_advance(c, s, n_iter);
-  if (rc) return rc;
+  RCHK(validate_state(c, s));
+  if (n_iter == 0) return GP_OK;
+  const Group g = state_group(c, s);
+  RCHK(s->kind == GP_KIND_ROF ? rof_advance(c, g, n_iter) : emd_advance(c, g, n_iter));
   s->iter += n_iter;
   return GP_OK;
 }
 
 int pd_gap(gp_ctx* c, gp_state* s, gp_report* rep) {
   if (!c) return GP_EINVAL;
-  int rc = validate_state(c, s);
-  if (rc) return rc;
-  double P = 0, D = 0, L = 0;
+  RCHK(validate_state(c, s));
+  double P = 0, D = 0;
   if (s->kind == GP_KIND_ROF) {
-    rc = rof_gap(c, s, &P, &D);
+    RCHK(rof_gap_state(c, s, &P, &D));
   } else {
-    rc = emd_primal(c, s, &P);
-    if (!rc) rc = emd_cert(c, s, &D, &L, c->work64, c->work64 + size_t(s->ny) * s->nx);
+    RCHK(emd_primal_state(c, s, &P));
+    // the certificate overwrites the pipeline's phi: the next pd_step starts
+    // from the state (its entry step does not read phi)
+    const Group g = state_group(c, s);
+    const size_t n = size_t(s->ny) * s->nx;
+    RCHK(emd_cert_enqueue(c, g, s->p, c->work64, c->work64 + n, c->partials, c->result));
+    HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    D = emd_dual_from(c->host_result, s->h);
   }
-  if (rc) return rc;
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
     rep->iters = int(s->iter);
@@ -859,14 +923,11 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
     return GP_EINVAL;
   }
   double tau, sigma;
-  int rc = check_opts(c, o, &tau, &sigma);
-  if (rc) return rc;
-  rc = prepare(c, ny, nx, h);
-  if (rc) return rc;
+  RCHK(check_opts(c, o, &tau, &sigma));
+  RCHK(prepare(c, ny, nx, h));
   const size_t n = size_t(ny) * nx;
   double bad = 0;
-  rc = count_nonfinite(c, I, n, &bad);
-  if (rc) return rc;
+  RCHK(count_nonfinite(c, I, n, &bad));
   if (bad > 0) {
     set_err(c, "image has %.0f non-finite values", bad);
     return GP_EINVAL;
@@ -876,7 +937,7 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
     set_err(c, "arena allocation of %zu floats failed", 4 * n);
     return GP_ENOMEM;
   }
-  // dual buffers: P0 holds p_0 (and the final p), P1 holds pbar_0
+  // dual buffers: P0 holds p_0, P1 pbar_0
   float* P0 = ar;
   float* P1 = ar + 2 * n;
   if (o->warm_start && p) {
@@ -886,36 +947,32 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
   }
   if (!o->warm_start) HIPCHK(c, hipMemsetAsync(u, 0, n * sizeof(float), c->stream));
   HIPCHK(c, hipMemcpyAsync(P1, P0, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-  gp_state s{GP_KIND_ROF, ny, nx, o->norm, h, lambda, tau, sigma, I, nullptr, u, P0, P1, 0};
+  const gp_state s{GP_KIND_ROF, ny, nx, o->norm, h, lambda, tau, sigma, I, nullptr, u, P0, P1, 0};
+  const Group g = state_group(c, &s);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t1 = now_s();
-  double P = NAN, D = NAN, g = NAN;
+  double P = NAN, D = NAN, gap = NAN;
   bool conv = false;
   int it = 0;
-  RofPipe pipe = rof_pipe(c, &s);
-  rc = rof_A(pipe, 1, nullptr);
-  if (rc) return rc;
-  const int nb = rows_blocks_f32(nx, ny);
+  RofPipe pipe{c, &g, g.p, g.pbar};
+  RCHK(rof_A(pipe, 1, false));
   while (it < o->max_iter) {
-    rc = rof_CB(pipe);  // u_{it+1}
-    if (rc) return rc;
+    RCHK(rof_CB(pipe));  // u_{it+1}
     ++it;
     const bool chk = (it % o->check_every == 0) || (it == o->max_iter);
-    // A computes p_it from (u_it, p_{it-1}) and, on checks, the gap of (u_it, p_it)
-    rc = rof_A(pipe, 0, chk ? c->partials : nullptr);
-    if (rc) return rc;
+    // A computes p_it from (u_it, p_{it-1}) and, on checks, the gap partials of (u_it, p_it)
+    RCHK(rof_A(pipe, 0, chk));
     if (chk) {
       double r[4];
-      rc = finalize_read(c, nb, 4, 0u, r);
-      if (rc) return rc;
+      RCHK(finalize_read(c, g.gpart, ny / 2, 1, 4, 0u, r));
       P = h * r[0] + 0.5 * lambda * h * h * r[1];
       D = -h * r[2] - r[3] / (2.0 * lambda);
-      g = rel_gap(P, D);
-      if (!std::isfinite(g)) {
+      gap = rel_gap(P, D);
+      if (!std::isfinite(gap)) {
         set_err(c, "duality gap became non-finite at iteration %d", it);
         return GP_EHIP;
       }
-      if (g <= o->tol) {
+      if (gap <= o->tol) {
         conv = true;
         break;
       }
@@ -929,7 +986,7 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
     rep->converged = conv;
     rep->primal = P;
     rep->dual = D;
-    rep->rel_gap = g;
+    rep->rel_gap = gap;
     rep->div_residual = 0;
     rep->seconds_setup = t1 - t0;
     rep->seconds_loop = t2 - t1;
@@ -943,17 +1000,14 @@ int emd_setup(gp_ctx* c, const float* rho0, const float* rho1, float* f, float* 
     set_err(c, "NULL buffer");
     return GP_EINVAL;
   }
-  int rc = prepare(c, ny, nx, h);
-  if (rc) return rc;
+  RCHK(prepare(c, ny, nx, h));
   const size_t n = size_t(ny) * nx;
   const int nb = red_blocks(n);
   hipLaunchKernelGGL(k_mass, dim3(nb), dim3(256), 0, c->stream, rho0, rho1, n, c->partials);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, c->partials, nb, 3, 0u, c->result);
-  LAUNCHCHK(c);
-  HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  const double m0 = c->host_result[0], m1 = c->host_result[1], bad = c->host_result[2];
+  double r[3];
+  RCHK(finalize_read(c, c->partials, nb, 1, 3, 0u, r));
+  const double m0 = r[0], m1 = r[1], bad = r[2];
   if (bad > 0) {
     set_err(c, "densities have %.0f negative or non-finite values", bad);
     return GP_EINVAL;
@@ -962,14 +1016,14 @@ int emd_setup(gp_ctx* c, const float* rho0, const float* rho1, float* f, float* 
     set_err(c, "mass mismatch: sum rho0 = %.17g, sum rho1 = %.17g", m0, m1);
     return GP_EMASS;
   }
+  // c->result still holds [sum rho0, sum rho1] for the FP64 mean
   double* f64 = c->work64;
   double* psi = c->work64;  // the solve consumes f64 before writing psi over it
   double* tmp = c->work64 + n;
   hipLaunchKernelGGL(k_f64_diff, dim3(grid_for(n)), dim3(256), 0, c->stream, rho0, rho1, c->result,
                      1.0 / double(n), n, f64, f);
   LAUNCHCHK(c);
-  rc = poisson_f64(c, f64, psi, ny, nx, 0.0, tmp);
-  if (rc) return rc;
+  RCHK(poisson_f64(c, f64, psi, ny, nx, 1, nullptr, c->mux64, c->muy64, 0.0, tmp));
   hipLaunchKernelGGL(k_grad_f64, dim3(grid_for(n)), dim3(256), 0, c->stream, psi, gpsi, gpsi + n, ny, nx, 1.0 / h);
   LAUNCHCHK(c);
   return GP_OK;
@@ -984,16 +1038,14 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
     return GP_EINVAL;
   }
   double tau, sigma;
-  int rc = check_opts(c, o, &tau, &sigma);
-  if (rc) return rc;
+  RCHK(check_opts(c, o, &tau, &sigma));
   if (o->warm_start && !phi) {
     set_err(c, "warm_start needs phi");
     return GP_EINVAL;
   }
-  rc = prepare(c, ny, nx, h);
-  if (rc) return rc;
+  RCHK(prepare(c, ny, nx, h));
   const size_t n = size_t(ny) * nx;
-  // arena: f, grad psi, u, P0, P1, certificate potential and its transform intermediate (n doubles each)
+  // arena: f, grad psi, u, P0, P1, certificate potential and its intermediate (n doubles each)
   float* ar = arena(c, 13 * n);
   if (!ar) {
     set_err(c, "arena allocation of %zu floats failed", 13 * n);
@@ -1006,58 +1058,54 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   float* P1 = ar + 7 * n;
   double* cphi = reinterpret_cast<double*>(ar + 9 * n);
   double* ctmp = reinterpret_cast<double*>(ar + 11 * n);
-  rc = emd_setup(c, rho0, rho1, f, gpsi, ny, nx, h);
-  if (rc) return rc;
+  RCHK(emd_setup(c, rho0, rho1, f, gpsi, ny, nx, h));
   HIPCHK(c, hipMemsetAsync(u, 0, 2 * n * sizeof(float), c->stream));
   HIPCHK(c, hipMemsetAsync(P0, 0, 2 * n * sizeof(float), c->stream));
   if (o->warm_start) {
     // p0 = proj(grad phi0): the ROF dual step with u = phi0, p = 0, sigma/h = 1/h
-    hipLaunchKernelGGL(k_rof_finish, dim3(grid_for(n)), dim3(256), 0, c->stream, phi, P0, P0, P1, ny, nx,
+    hipLaunchKernelGGL(k_rof_finish, dim3(grid_for(n)), dim3(256), 0, c->stream, phi, P0, P0, P1, ny, nx, ny,
                        float(1.0 / h), o->norm);
     LAUNCHCHK(c);
   }
   HIPCHK(c, hipMemcpyAsync(P1, P0, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-  gp_state s{GP_KIND_EMD, ny, nx, o->norm, h, 0.0, tau, sigma, f, gpsi, u, P0, P1, 0};
+  const gp_state s{GP_KIND_EMD, ny, nx, o->norm, h, 0.0, tau, sigma, f, gpsi, u, P0, P1, 0};
+  const Group g = state_group(c, &s);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t1 = now_s();
-  double P = NAN, D = NAN, g = NAN, L = 0;
+  double P = NAN, D = NAN, gap = NAN, L = 0;
   bool conv = false;
   int it = 0;
-  EmdPipe pipe = emd_pipe(c, &s);
-  rc = emd_A(pipe, 1, nullptr);
-  if (rc) return rc;
-  const int nb = rows_blocks_f64(nx, ny);
+  EmdPipe pipe{c, &g, g.p, g.pbar, g.w0, g.w1};
+  RCHK(emd_A(pipe, 1, false));
+  // device result slots: [0] primal sum, [8..9] certificate sums
+  double* cpart = c->partials + size_t(ny / 2);
   while (it < o->max_iter) {
-    rc = emd_CB(pipe);  // phi_it
-    if (rc) return rc;
+    RCHK(emd_CB(pipe));  // phi_it
     const bool chk = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter);
-    rc = emd_A(pipe, 0, chk ? c->partials : nullptr);  // u_{it+1}, p_{it+1}
-    if (rc) return rc;
+    RCHK(emd_A(pipe, 0, chk));  // u_{it+1}, p_{it+1}
     ++it;
     if (chk) {
-      double r[1];
-      rc = finalize_read(c, nb, 1, 0u, r);
-      if (rc) return rc;
-      P = h * h * r[0];
-      gp_state cs = s;
-      cs.p = pipe.X;
-      rc = emd_cert(c, &cs, &D, &L, cphi, ctmp);
-      if (rc) return rc;
-      g = rel_gap(P, D);
-      if (!std::isfinite(g)) {
+      RCHK(emd_cert_enqueue(c, g, pipe.X, cphi, ctmp, cpart, c->result + 8));
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, g.gpart, ny / 2, 1, 0u, c->result);
+      LAUNCHCHK(c);
+      HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      P = h * h * c->host_result[0];
+      D = emd_dual_from(c->host_result + 8, h);
+      L = c->host_result[9];
+      gap = rel_gap(P, D);
+      if (!std::isfinite(gap)) {
         set_err(c, "duality gap became non-finite at iteration %d", it);
         return GP_EHIP;
       }
-      if (g <= o->tol) {
+      if (gap <= o->tol) {
         conv = true;
         break;
       }
     }
   }
-  // flux m_it = wt_{it-1} - grad phi_{it-1} (the A that produced p_it read these)
-  hipLaunchKernelGGL(k_emd_finish, dim3(grid_for(n)), dim3(256), 0, c->stream, pipe.WY, pipe.phi, nullptr, gpsi,
-                     nullptr, nullptr, nullptr, m, ny, nx, 1.0 / h, float(sigma), o->norm, nullptr);
-  LAUNCHCHK(c);
+  // flux m_it = wt_{it-1} - grad phi_{it-1}: the stored field the last A read, now in WY
+  RCHK(emd_finish(pipe, pipe.WY, false, m));
   if (phi) {
     // cphi holds -phi_c from the last certificate; phi~ = phi_c / max(1, L)
     hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, cphi, phi, n,
@@ -1071,12 +1119,297 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
     rep->converged = conv;
     rep->primal = P;
     rep->dual = D;
-    rep->rel_gap = g;
+    rep->rel_gap = gap;
     rep->div_residual = 0;
     rep->seconds_setup = t1 - t0;
     rep->seconds_loop = t2 - t1;
   }
   return conv ? GP_OK : GP_ENOTCONV;
+}
+
+int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts* o, gp_report* reps) {
+  if (!c) return GP_EINVAL;
+  const double t0 = now_s();
+  if (!inst || count < 1 || !o) {
+    set_err(c, "batch needs instances (count >= 1) and options");
+    return GP_EINVAL;
+  }
+  if (o->max_iter < 1 || o->check_every < 1 || !(o->tol >= 0) ||
+      (o->norm != GP_NORM_ISO && o->norm != GP_NORM_ANISO)) {
+    set_err(c, "max_iter and check_every must be >= 1, tol >= 0 and norm valid");
+    return GP_EINVAL;
+  }
+  // the chunk between checks has an even length, so the ping-pong buffers hold
+  // the same roles at every check
+  const int C = (o->check_every + 1) / 2 * 2;
+  // ---- validate and group
+  std::map<std::tuple<int, int, int, double, double, double>, std::vector<int>> groups;
+  for (int i = 0; i < count; ++i) {
+    const gp_instance& q = inst[i];
+    if ((q.kind != GP_KIND_ROF && q.kind != GP_KIND_EMD) || !q.in0 || !q.out ||
+        (q.kind == GP_KIND_EMD && !q.in1)) {
+      set_err(c, "instance %d: bad kind or NULL buffer", i);
+      return GP_EINVAL;
+    }
+    if (!(q.tau > 0) || !std::isfinite(q.tau) ||
+        (q.kind == GP_KIND_ROF && (!(q.lambda > 0) || !std::isfinite(q.lambda)))) {
+      set_err(c, "instance %d: tau (and lambda for ROF) must be positive and finite", i);
+      return GP_EINVAL;
+    }
+    const int rc = check_size(c, q.ny, q.nx, q.h);
+    if (rc) {
+      char msg[512];
+      std::snprintf(msg, sizeof(msg), "instance %d: %s", i, c->err);
+      std::snprintf(c->err, sizeof(c->err), "%s", msg);
+      return rc;
+    }
+    groups[std::make_tuple(q.kind, q.ny, q.nx, q.h, q.kind == GP_KIND_ROF ? q.lambda : 0.0, q.tau)].push_back(i);
+  }
+  std::vector<BatchGroup> G;
+  for (auto& kv : groups) {
+    BatchGroup bg;
+    Group& g = bg.g;
+    g.kind = std::get<0>(kv.first);
+    g.nyi = std::get<1>(kv.first);
+    g.nx = std::get<2>(kv.first);
+    g.h = std::get<3>(kv.first);
+    g.lambda = std::get<4>(kv.first);
+    g.tau = std::get<5>(kv.first);
+    g.sigma = 1.0 / g.tau;
+    g.m = int(kv.second.size());
+    g.norm = o->norm;
+    bg.idx = kv.second;
+    G.push_back(bg);
+  }
+  // ---- arena
+  Carver measure{nullptr};
+  for (auto& bg : G) carve(measure, bg);
+  if (c->barena_bytes < measure.off) {
+    if (c->barena) (void)hipFree(c->barena);
+    c->barena = nullptr;
+    c->barena_bytes = 0;
+    if (hipMalloc(&c->barena, measure.off) != hipSuccess) {
+      set_err(c, "batch arena allocation of %zu bytes failed", measure.off);
+      return GP_ENOMEM;
+    }
+    c->barena_bytes = measure.off;
+  }
+  if (!c->bstream) HIPCHK(c, hipStreamCreateWithFlags(&c->bstream, hipStreamNonBlocking));
+  Carver A{c->barena};
+  for (auto& bg : G) carve(A, bg);
+  // ---- set-up on the caller's stream (outside any graph)
+  for (auto& bg : G) {
+    Group& g = bg.g;
+    const size_t nt = g.ntot(), n = size_t(g.nyi) * g.nx;
+    float* f = const_cast<float*>(g.f);
+    if (g.kind == GP_KIND_ROF) {
+      for (int k = 0; k < g.m; ++k)
+        HIPCHK(c, hipMemcpyAsync(f + k * n, inst[bg.idx[k]].in0, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                 c->stream));
+      HIPCHK(c, hipMemsetAsync(g.u, 0, nt * sizeof(float), c->stream));
+    } else {
+      // per instance: FP64 mass check and potential, then scatter grad psi into the stack
+      float* gp = const_cast<float*>(g.gpsi);
+      for (int k = 0; k < g.m; ++k) {
+        const gp_instance& q = inst[bg.idx[k]];
+        const int rc = emd_setup(c, q.in0, q.in1, f + k * n, c->work2, g.nyi, g.nx, g.h);
+        if (rc) {
+          char msg[512];
+          std::snprintf(msg, sizeof(msg), "instance %d: %s", bg.idx[k], c->err);
+          std::snprintf(c->err, sizeof(c->err), "%s", msg);
+          return rc;
+        }
+        HIPCHK(c, hipMemcpyAsync(gp + k * n, c->work2, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(gp + nt + k * n, c->work2 + n, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                 c->stream));
+      }
+      HIPCHK(c, hipMemsetAsync(g.u, 0, 2 * nt * sizeof(float), c->stream));
+    }
+    HIPCHK(c, hipMemsetAsync(g.p, 0, 2 * nt * sizeof(float), c->stream));
+    HIPCHK(c, hipMemsetAsync(g.pbar, 0, 2 * nt * sizeof(float), c->stream));
+    std::vector<int> ones(g.m, 1);
+    HIPCHK(c, hipMemcpyAsync(bg.active_dev, ones.data(), g.m * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    RCHK(fill_mu(c, bg.mu64, bg.mu32, bg.mu64 + g.nyi, bg.mu32 + g.nyi, g.nyi, g.nx, g.h));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // `ones` leaves scope
+  }
+  // ---- pipelines: the entry step eagerly, then one captured chunk of C iterations
+  std::vector<RofPipe> rp(G.size());
+  std::vector<EmdPipe> ep(G.size());
+  for (size_t k = 0; k < G.size(); ++k) {
+    const Group& g = G[k].g;
+    rp[k] = RofPipe{c, &g, g.p, g.pbar};
+    ep[k] = EmdPipe{c, &g, g.p, g.pbar, g.w0, g.w1};
+  }
+  hipStream_t user = c->stream;
+  const bool prof = c->prof_on;
+  c->prof_on = false;  // no event records inside a captured graph
+  c->stream = c->bstream;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto restore = [&](int r) {
+    (void)hipStreamSynchronize(c->bstream);
+    c->stream = user;
+    c->prof_on = prof;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return r;
+  };
+  int rc = GP_OK;
+  for (size_t k = 0; k < G.size() && !rc; ++k) {
+    if (G[k].g.kind == GP_KIND_ROF) {
+      rc = rof_A(rp[k], 1, false);
+      if (!rc) rc = rof_CB(rp[k]);
+    } else {
+      rc = emd_A(ep[k], 1, false);
+      if (!rc) rc = emd_CB(ep[k]);
+    }
+  }
+  if (rc) return restore(rc);
+  // chunk: C steady A's (the last one with gap partials) with the column pass and
+  // B between them, then the per-instance reductions; the column pass and B that
+  // follow the last A run outside the graph, after retirement
+  if (hipStreamBeginCapture(c->bstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    set_err(c, "hipStreamBeginCapture failed");
+    return restore(GP_EHIP);
+  }
+  for (int it = 0; it < C && !rc; ++it) {
+    const bool last = it + 1 == C;
+    for (size_t k = 0; k < G.size() && !rc; ++k) {
+      if (G[k].g.kind == GP_KIND_ROF) {
+        rc = rof_A(rp[k], 0, last);
+        if (!rc && !last) rc = rof_CB(rp[k]);
+      } else {
+        rc = emd_A(ep[k], 0, last);
+        if (!rc && !last) rc = emd_CB(ep[k]);
+      }
+    }
+  }
+  for (size_t k = 0; k < G.size() && !rc; ++k) {
+    const Group& g = G[k].g;
+    hipLaunchKernelGGL(k_finalize, dim3(g.m), dim3(256), 0, c->stream, g.gpart, g.nyi / 2,
+                       g.kind == GP_KIND_ROF ? 4 : 1, 0u, G[k].gap_dev);
+    if (hipGetLastError() != hipSuccess) {
+      set_err(c, "k_finalize launch failed during capture");
+      rc = GP_EHIP;
+    }
+    if (!rc && g.kind == GP_KIND_EMD) rc = emd_cert_enqueue(c, g, ep[k].X, G[k].cphi, G[k].ctmp, G[k].cpart,
+                                                           G[k].cert_dev);
+  }
+  const hipError_t ce = hipStreamEndCapture(c->bstream, &graph);
+  if (rc || ce != hipSuccess) {
+    if (!rc) set_err(c, "hipStreamEndCapture failed: %s", hipGetErrorString(ce));
+    return restore(rc ? rc : GP_EHIP);
+  }
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    set_err(c, "hipGraphInstantiate failed");
+    return restore(GP_EHIP);
+  }
+  // ---- replay until every instance has retired
+  std::vector<char> retired(count, 0);
+  std::vector<int> iters(count, 0);
+  std::vector<double> Pv(count, NAN), Dv(count, NAN), gv(count, NAN), tv(count, 0.0);
+  int left = count, done = 0;
+  const double t1 = now_s();
+  std::vector<double> hbuf;
+  std::vector<int> flags;
+  while (left > 0) {
+    if (hipGraphLaunch(exec, c->bstream) != hipSuccess) {
+      set_err(c, "hipGraphLaunch failed");
+      return restore(GP_EHIP);
+    }
+    done += C;
+    for (auto& bg : G) {
+      const Group& g = bg.g;
+      const int K = g.kind == GP_KIND_ROF ? 4 : 1;
+      hbuf.assign(size_t(g.m) * (K + 2), 0.0);
+      if (hipMemcpyAsync(hbuf.data(), bg.gap_dev, size_t(g.m) * K * sizeof(double), hipMemcpyDeviceToHost,
+                         c->bstream) != hipSuccess ||
+          (g.kind == GP_KIND_EMD &&
+           hipMemcpyAsync(hbuf.data() + g.m, bg.cert_dev, size_t(g.m) * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                          c->bstream) != hipSuccess) ||
+          hipStreamSynchronize(c->bstream) != hipSuccess) {
+        set_err(c, "gap read-back failed");
+        return restore(GP_EHIP);
+      }
+      const double now = now_s() - t1;
+      flags.assign(g.m, 1);
+      bool changed = false;
+      for (int k = 0; k < g.m; ++k) {
+        const int i = bg.idx[k];
+        if (retired[i]) {
+          flags[k] = 0;
+          continue;
+        }
+        double P, D;
+        if (g.kind == GP_KIND_ROF) {
+          const double* r = &hbuf[size_t(k) * 4];
+          P = g.h * r[0] + 0.5 * g.lambda * g.h * g.h * r[1];
+          D = -g.h * r[2] - r[3] / (2.0 * g.lambda);
+        } else {
+          P = g.h * g.h * hbuf[k];
+          D = emd_dual_from(&hbuf[g.m + 2 * size_t(k)], g.h);
+        }
+        const double gp = rel_gap(P, D);
+        Pv[i] = P;
+        Dv[i] = D;
+        gv[i] = gp;
+        iters[i] = done;
+        tv[i] = now;
+        if (gp <= o->tol || done >= o->max_iter || !std::isfinite(gp)) {
+          retired[i] = 1;
+          flags[k] = 0;
+          --left;
+          changed = true;
+        }
+      }
+      if (changed && hipMemcpy(bg.active_dev, flags.data(), g.m * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        set_err(c, "active-flag update failed");
+        return restore(GP_EHIP);
+      }
+    }
+    if (left == 0) break;
+    // the column pass and B after the chunk's last A, for the instances still running
+    for (size_t k = 0; k < G.size() && !rc; ++k) rc = G[k].g.kind == GP_KIND_ROF ? rof_CB(rp[k]) : emd_CB(ep[k]);
+    if (rc) return restore(rc);
+  }
+  // ---- outputs: ROF u_t (B never ran after an instance's last check); EMD flux
+  // m_t = wt_{t-1} - grad phi_{t-1} (neither was touched after retirement)
+  for (size_t k = 0; k < G.size(); ++k) {
+    const BatchGroup& bg = G[k];
+    const Group& g = bg.g;
+    const size_t n = size_t(g.nyi) * g.nx, nt = g.ntot();
+    if (g.kind == GP_KIND_ROF) {
+      for (int q = 0; q < g.m; ++q)
+        HIPCHK(c, hipMemcpyAsync(inst[bg.idx[q]].out, g.u + q * n, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                 c->bstream));
+    } else {
+      rc = emd_finish(ep[k], ep[k].WY, false, bg.mflux);
+      if (rc) return restore(rc);
+      for (int q = 0; q < g.m; ++q) {
+        float* out = inst[bg.idx[q]].out;
+        HIPCHK(c, hipMemcpyAsync(out, bg.mflux + q * n, n * sizeof(float), hipMemcpyDeviceToDevice, c->bstream));
+        HIPCHK(c, hipMemcpyAsync(out + n, bg.mflux + nt + q * n, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                 c->bstream));
+      }
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->bstream));
+  bool all_conv = true;
+  for (int i = 0; i < count; ++i) {
+    const bool conv = gv[i] <= o->tol;
+    all_conv = all_conv && conv;
+    if (reps) {
+      std::memset(&reps[i], 0, sizeof(gp_report));
+      reps[i].iters = iters[i];
+      reps[i].converged = conv;
+      reps[i].primal = Pv[i];
+      reps[i].dual = Dv[i];
+      reps[i].rel_gap = gv[i];
+      reps[i].seconds_setup = t1 - t0;
+      reps[i].seconds_loop = tv[i];
+    }
+  }
+  return restore(all_conv ? GP_OK : GP_ENOTCONV);
 }
 
 int gp_profile(gp_ctx* c, int enable) {

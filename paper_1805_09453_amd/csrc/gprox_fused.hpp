@@ -112,9 +112,10 @@ __device__ __forceinline__ void rof_dual_pt(float px, float py, float gx, float 
 template <int N>
 __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, const float* __restrict__ pin,
                                                float* __restrict__ pout, const float* __restrict__ I,
-                                               float* __restrict__ rhat, int ny, int lgtw, float lt, float tau_h,
-                                               float sig_h, int aniso, int mode, double* __restrict__ partials,
-                                               const float2* __restrict__ tw, const float2* __restrict__ dctw) {
+                                               float* __restrict__ rhat, int ny, int nyi, const int* __restrict__ active,
+                                               int lgtw, float lt, float tau_h, float sig_h, int aniso, int mode,
+                                               double* __restrict__ partials, const float2* __restrict__ tw,
+                                               const float2* __restrict__ dctw) {
   using SH = RowShape<N, float2>;
   constexpr int T = SH::T;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -122,13 +123,13 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   float2* lds = smem + g * Sched<N>::LDS;
   const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
-  const bool valid = a < ny;  // ny is even
+  const bool valid = a < ny && inst_active(active, a / nyi);  // nyi is even
   const size_t n = size_t(ny) * N;
   const float* pinx = pin;
   const float* piny = pin + n;
   double acc[4] = {0, 0, 0, 0};
   if (valid) {
-    const bool has_up = a > 0, has_dn = b + 1 < ny;
+    const bool has_up = (a % nyi) > 0, has_dn = ((a + 2) % nyi) != 0;
     const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
 #pragma unroll 2
     for (int k = 0; k < 8; ++k) {
@@ -249,10 +250,8 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
 #pragma unroll 1
     for (int m = t; m < N; m += T) lds[lpad(m)] = make_float2(0.f, 0.f);
   }
-  if (partials) {
-    const bool mx[4] = {false, false, false, false};
-    block_reduce_store<4>(acc, mx, partials);
-  }
+  // gap partials per row pair (so that each instance of a batch has its own)
+  if (partials) group_reduce_store<4, T>(acc, valid ? partials + size_t(a / 2) * 4 : nullptr, t);
   __syncthreads();
   float2 v[32];
   dct2_fwd_lds<N>(t, v, lds, tw, dctw);
@@ -262,8 +261,8 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const int k = dc_index<N>(t, slot, s);
-        rhat[tile_idx(a, k, ny, lgtw)] = v[slot * 16 + s].x;
-        rhat[tile_idx(b, k, ny, lgtw)] = v[slot * 16 + s].y;
+        rhat[btile(a, k, nyi, N, lgtw)] = v[slot * 16 + s].x;
+        rhat[btile(b, k, nyi, N, lgtw)] = v[slot * 16 + s].y;
       }
   }
 }
@@ -272,8 +271,8 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
 // u += inverse row DCT of the column-solved field
 template <int N>
 __global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, float* __restrict__ u, int ny,
-                                               int lgtw, const float2* __restrict__ tw,
-                                               const float2* __restrict__ dctw) {
+                                               int nyi, const int* __restrict__ active, int lgtw,
+                                               const float2* __restrict__ tw, const float2* __restrict__ dctw) {
   using SH = RowShape<N, float2>;
   using IO = InvOut<N>;
   constexpr int T = SH::T;
@@ -282,7 +281,7 @@ __global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, f
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   float2* lds = smem + g * Sched<N>::LDS;
   const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
-  const bool valid = a < ny;
+  const bool valid = a < ny && inst_active(active, a / nyi);
   float* ua = u + size_t(valid ? a : 0) * N;
   float* ub = u + size_t(valid ? b : 0) * N;
   float2 v[32];
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, f
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      v[slot * 16 + s] = valid ? make_float2(dhat[tile_idx(a, k, ny, lgtw)], dhat[tile_idx(b, k, ny, lgtw)])
+      v[slot * 16 + s] = valid ? make_float2(dhat[btile(a, k, nyi, N, lgtw)], dhat[btile(b, k, nyi, N, lgtw)])
                                : make_float2(0, 0);
     }
   // u at this thread's output positions, loaded before the last pass so the
@@ -329,13 +328,13 @@ __global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, f
 // p_out = proj(p_in + sigma grad u), pbar_out = 2 p_out - p_in (pointwise in p:
 // p_in may alias p_out or pbar_out)
 __global__ __launch_bounds__(256) void k_rof_finish(const float* __restrict__ u, const float* pin, float* pout,
-                                                    float* pbar, int ny, int nx, float sig_h, int aniso) {
+                                                    float* pbar, int ny, int nx, int nyi, float sig_h, int aniso) {
   const size_t n = size_t(ny) * nx;
   for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
     const int i = int(o / nx), j = int(o - size_t(i) * nx);
     const float uc = u[o];
     const float gx = (j < nx - 1) ? (u[o + 1] - uc) : 0.f;
-    const float gy = (i < ny - 1) ? (u[o + nx] - uc) : 0.f;
+    const float gy = (i % nyi < nyi - 1) ? (u[o + nx] - uc) : 0.f;
     const float ox = pin[o], oy = pin[o + n];
     float qx, qy;
     rof_dual_pt(ox, oy, gx, gy, sig_h, aniso, qx, qy);
@@ -355,7 +354,8 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
                                                const float* __restrict__ pin, const float* __restrict__ gpsi,
                                                const float* __restrict__ f, float* __restrict__ pout,
                                                float* __restrict__ wt_out, double* __restrict__ rhat, int ny,
-                                               int lgtw, double inv_h, float tau, float sigma, int aniso, int mode,
+                                               int nyi, const int* __restrict__ active, int lgtw, double inv_h,
+                                               float tau, float sigma, int aniso, int mode,
                                                double* __restrict__ partials, const double2* __restrict__ tw,
                                                const double2* __restrict__ dctw) {
   using SH = RowShape<N, double2>;
@@ -365,11 +365,11 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   double2* lds = smem + g * Sched<N>::LDS;
   const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
-  const bool valid = a < ny;
+  const bool valid = a < ny && inst_active(active, a / nyi);
   const size_t n = size_t(ny) * N;
   double acc[1] = {0};
   if (valid) {
-    const bool has_up = a > 0, has_dn = b + 1 < ny;
+    const bool has_up = (a % nyi) > 0, has_dn = ((a + 2) % nyi) != 0;
     const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
 #pragma unroll 2
     for (int k = 0; k < 8; ++k) {
@@ -499,10 +499,7 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
 #pragma unroll 1
     for (int m = t; m < N; m += T) lds[lpad(m)] = make_double2(0.0, 0.0);
   }
-  if (partials) {
-    const bool mx[1] = {false};
-    block_reduce_store<1>(acc, mx, partials);
-  }
+  if (partials) group_reduce_store<1, T>(acc, valid ? partials + size_t(a / 2) : nullptr, t);
   __syncthreads();
   double2 v[32];
   dct2_fwd_lds<N>(t, v, lds, tw, dctw);
@@ -512,28 +509,26 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const int k = dc_index<N>(t, slot, s);
-        rhat[tile_idx(a, k, ny, lgtw)] = v[slot * 16 + s].x;
-        rhat[tile_idx(b, k, ny, lgtw)] = v[slot * 16 + s].y;
+        rhat[btile(a, k, nyi, N, lgtw)] = v[slot * 16 + s].x;
+        rhat[btile(b, k, nyi, N, lgtw)] = v[slot * 16 + s].y;
       }
   }
 }
 
 // ---------------------------------------------------------------- EMD finish
-// m = wt - grad phi; p_out = proj(p_in + sigma m), pbar = 2 p_out - p_in,
-// u = m - grad psi (if u != nullptr), flux = m (if mout != nullptr),
-// partials (nullable): [sum |m|].  Pointwise in p (p_in may alias p_out or pbar).
+// m = wt - grad phi; if pout: p_out = proj(p_in + sigma m), pbar = 2 p_out - p_in;
+// u = m - grad psi (if u); flux = m (if mout).  Pointwise in p (p_in may alias
+// p_out or pbar).  Tall batch layout: y-neighbours stop at instance edges.
 __global__ __launch_bounds__(256) void k_emd_finish(const float* __restrict__ wt, const double* __restrict__ phi,
                                                     const float* pin, const float* __restrict__ gpsi, float* pout,
                                                     float* pbar, float* __restrict__ u, float* __restrict__ mout,
-                                                    int ny, int nx, double inv_h, float sigma, int aniso,
-                                                    double* __restrict__ partials) {
-  double acc[1] = {0};
+                                                    int ny, int nx, int nyi, double inv_h, float sigma, int aniso) {
   const size_t n = size_t(ny) * nx;
   for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
     const int i = int(o / nx), j = int(o - size_t(i) * nx);
     const double fc = phi[o];
     const float mx = (j < nx - 1) ? wt[o] - float((phi[o + 1] - fc) * inv_h) : 0.f;
-    const float my = (i < ny - 1) ? wt[o + n] - float((phi[o + nx] - fc) * inv_h) : 0.f;
+    const float my = (i % nyi < nyi - 1) ? wt[o + n] - float((phi[o + nx] - fc) * inv_h) : 0.f;
     if (pout) {
       const float ox = pin[o], oy = pin[o + n];
       float qx = ox + sigma * mx, qy = oy + sigma * my;
@@ -551,11 +546,6 @@ __global__ __launch_bounds__(256) void k_emd_finish(const float* __restrict__ wt
       mout[o] = mx;
       mout[o + n] = my;
     }
-    if (partials) acc[0] += double(pnorm(mx, my, aniso));
-  }
-  if (partials) {
-    const bool m[1] = {false};
-    block_reduce_store<1>(acc, m, partials);
   }
 }
 

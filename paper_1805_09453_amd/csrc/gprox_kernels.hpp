@@ -45,11 +45,22 @@ __device__ __forceinline__ size_t tile_idx(int i, int k, int ny, int lgtw) {
   return (size_t(k >> lgtw) * size_t(ny) + size_t(i)) * (size_t(1) << lgtw) + (k & ((1 << lgtw) - 1));
 }
 
+// Batches: m instances of one size are stacked into one tall image of m * nyi
+// rows (instance-major; vector fields component-major over the whole batch).
+// Row a of the tall image is row a % nyi of instance a / nyi; the tiled
+// intermediate is tiled per instance.
+__device__ __forceinline__ size_t btile(int a, int k, int nyi, int nx, int lgtw) {
+  const int inst = a / nyi;
+  return size_t(inst) * size_t(nyi) * size_t(nx) + tile_idx(a - inst * nyi, k, nyi, lgtw);
+}
+__device__ __forceinline__ bool inst_active(const int* active, int inst) { return !active || active[inst] != 0; }
+
 // ------------------------------------------------------------ DCT passes
 // Forward DCT-II along rows, two rows per FFT group.  out may alias in.
 template <int N, class C>
 __global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
-                                                  int lgtw, const C* __restrict__ tw, const C* __restrict__ dctw) {
+                                                  int nyi, const int* __restrict__ active, int lgtw,
+                                                  const C* __restrict__ tw, const C* __restrict__ dctw) {
   constexpr int ld = N;
   using Re = typename Cx<C>::R;
   using SH = RowShape<N, C>;
@@ -58,7 +69,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, t
   const int g = threadIdx.x / SH::T, t = threadIdx.x % SH::T;
   C* lds = smem + g * Sched<N>::LDS;
   const int ra = 2 * (blockIdx.x * SH::G + g), rb = ra + 1;
-  const bool va = ra < ny, vb = rb < ny;
+  const bool va = ra < ny && inst_active(active, ra / nyi), vb = va && rb < ny;
   const Re* pa = in + size_t(va ? ra : 0) * ld;
   const Re* pb = in + size_t(vb ? rb : 0) * ld;
   C v[32];
@@ -71,15 +82,16 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, t
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      if (va) out[tile_idx(ra, k, ny, lgtw)] = v[slot * 16 + s].x;
-      if (vb) out[tile_idx(rb, k, ny, lgtw)] = v[slot * 16 + s].y;
+      if (va) out[btile(ra, k, nyi, N, lgtw)] = v[slot * 16 + s].x;
+      if (vb) out[btile(rb, k, nyi, N, lgtw)] = v[slot * 16 + s].y;
     }
 }
 
 // Inverse of the (unnormalised) DCT-II along rows times N.  out may alias in.
 template <int N, class C>
 __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
-                                                  int lgtw, const C* __restrict__ tw, const C* __restrict__ dctw) {
+                                                  int nyi, const int* __restrict__ active, int lgtw,
+                                                  const C* __restrict__ tw, const C* __restrict__ dctw) {
   constexpr int ld = N;
   using Re = typename Cx<C>::R;
   using SH = RowShape<N, C>;
@@ -88,14 +100,14 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, t
   const int g = threadIdx.x / SH::T, t = threadIdx.x % SH::T;
   C* lds = smem + g * Sched<N>::LDS;
   const int ra = 2 * (blockIdx.x * SH::G + g), rb = ra + 1;
-  const bool va = ra < ny, vb = rb < ny;
+  const bool va = ra < ny && inst_active(active, ra / nyi), vb = va && rb < ny;
   C v[32];
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      v[slot * 16 + s] = mk<C>(va ? in[tile_idx(ra, k, ny, lgtw)] : Re(0), vb ? in[tile_idx(rb, k, ny, lgtw)] : Re(0));
+      v[slot * 16 + s] = mk<C>(va ? in[btile(ra, k, nyi, N, lgtw)] : Re(0), vb ? in[btile(rb, k, nyi, N, lgtw)] : Re(0));
     }
   dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
     if (va) *reinterpret_cast<C*>(out + size_t(ra) * ld + 2 * m) = A;
@@ -110,11 +122,13 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, t
 // every row access of a wave covers G*2 contiguous values.
 template <int N, class C>
 __global__ __launch_bounds__((ColShape<N, C>::THREADS), (ColShape<N, C>::MINW)) void k_cols_solve(
-    typename Cx<C>::R* buf, int nx, const C* __restrict__ tw, const C* __restrict__ dctw,
-    const typename Cx<C>::R* __restrict__ mux, const typename Cx<C>::R* __restrict__ muy, typename Cx<C>::R alpha,
-    typename Cx<C>::R inv_nn) {
+    typename Cx<C>::R* buf, int nx, const int* __restrict__ active, const C* __restrict__ tw,
+    const C* __restrict__ dctw, const typename Cx<C>::R* __restrict__ mux,
+    const typename Cx<C>::R* __restrict__ muy, typename Cx<C>::R alpha, typename Cx<C>::R inv_nn) {
   using Re = typename Cx<C>::R;
   using SH = ColShape<N, C>;
+  if (!inst_active(active, blockIdx.y)) return;  // whole workgroup: instance retired
+  buf += size_t(blockIdx.y) * N * nx;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* smem = reinterpret_cast<C*>(smem_raw);
   const int g = threadIdx.x % SH::G, t = threadIdx.x / SH::G;
@@ -194,16 +208,53 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[K], const bool 
   }
 }
 
-// Sum (or max) partials over nb blocks; one block of 256 threads, fixed order.
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nb, int K,
+// Reduce K values over the T consecutive threads of one FFT group (T a power of
+// two, groups aligned to T lanes); the group's thread 0 writes out[0..K).  Must be
+// called by every thread of the block (it synchronises when T > 64).
+template <int K, int T>
+__device__ __forceinline__ void group_reduce_store(double (&acc)[K], double* out, int t) {
+  if constexpr (T <= 64) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      double r = acc[i];
+#pragma unroll
+      for (int o = T / 2; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+      if (t == 0 && out) out[i] = r;
+    }
+  } else {
+    constexpr int WPG = T / 64;  // waves per group
+    __shared__ double red[4][K];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const double r = wave_sum(acc[i]);
+      if (lane == 0) red[w][i] = r;
+    }
+    __syncthreads();
+    if (t == 0 && out) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        double r = 0;
+        for (int q = 0; q < WPG; ++q) r += red[w + q][i];
+        out[i] = r;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Per segment s = blockIdx.x: sum (or max) partials[(s*seg + b)*K + i] over
+// b < seg into out[s*K + i]; one block of 256 threads per segment, fixed order.
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int seg, int K,
                                                   unsigned max_mask, double* __restrict__ out) {
   __shared__ double red[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* P = partials + size_t(blockIdx.x) * seg * K;
   for (int i = 0; i < K; ++i) {
     const bool mx = (max_mask >> i) & 1u;
     double a = mx ? -INFINITY : 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      double x = partials[size_t(b) * K + i];
+    for (int b = threadIdx.x; b < seg; b += blockDim.x) {
+      double x = P[size_t(b) * K + i];
       a = mx ? fmax(a, x) : a + x;
     }
     a = mx ? wave_max(a) : wave_sum(a);
@@ -212,7 +263,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
     if (threadIdx.x == 0) {
       double r = red[0];
       for (int q = 1; q < 4; ++q) r = mx ? fmax(r, red[q]) : r + red[q];
-      out[i] = r;
+      out[size_t(blockIdx.x) * K + i] = r;
     }
     __syncthreads();
   }
@@ -275,11 +326,16 @@ __global__ __launch_bounds__(256) void k_rof_energy(const float* __restrict__ u,
 // r = s div v (s = +-1/h); T = float or double output
 template <class T>
 __global__ __launch_bounds__(256) void k_div(const float* __restrict__ vx, const float* __restrict__ vy,
-                                             T* __restrict__ r, int ny, int nx, float s) {
+                                             T* __restrict__ r, int ny, int nx, int nyi, float s) {
   const size_t n = size_t(ny) * nx;
   for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
     const int i = int(o / nx), j = int(o - size_t(i) * nx);
-    r[o] = T(div_at(vx, vy, i, j, ny, nx)) * T(s);
+    const int il = i % nyi;
+    const float xr = (j < nx - 1) ? vx[o] : 0.f;
+    const float xl = (j > 0) ? vx[o - 1] : 0.f;
+    const float yu = (il < nyi - 1) ? vy[o] : 0.f;
+    const float yd = (il > 0) ? vy[o - nx] : 0.f;
+    r[o] = T((xr - xl) + (yu - yd)) * T(s);
   }
 }
 
@@ -294,23 +350,24 @@ __global__ __launch_bounds__(256) void k_emd_primal(const float* __restrict__ ux
   block_reduce_store<1>(acc, m, partials);
 }
 
-// certificate partials: [sum phi f, max |grad phi|] (gradient in 1/h units)
+// certificate partials per instance (blockIdx.y): [sum phi f, max |grad phi|]
+// (gradient in 1/h units) -> partials[(inst * gridDim.x + blockIdx.x) * 2 + i]
 __global__ __launch_bounds__(256) void k_emd_cert(const double* __restrict__ phi, const float* __restrict__ f,
-                                                  int ny, int nx, double inv_h, int aniso,
+                                                  int nyi, int nx, double inv_h, int aniso,
                                                   double* __restrict__ partials) {
   double acc[2] = {0, 0};
-  const size_t n = size_t(ny) * nx;
+  const size_t n = size_t(nyi) * nx, base = size_t(blockIdx.y) * n;
   for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
     const int i = int(o / nx), j = int(o - size_t(i) * nx);
-    const double fc = phi[o];
-    const double gx = (j < nx - 1) ? (phi[o + 1] - fc) * inv_h : 0.0;
-    const double gy = (i < ny - 1) ? (phi[o + nx] - fc) * inv_h : 0.0;
-    acc[0] += fc * double(f[o]);
+    const double fc = phi[base + o];
+    const double gx = (j < nx - 1) ? (phi[base + o + 1] - fc) * inv_h : 0.0;
+    const double gy = (i < nyi - 1) ? (phi[base + o + nx] - fc) * inv_h : 0.0;
+    acc[0] += fc * double(f[base + o]);
     const double L = aniso ? fmax(fabs(gx), fabs(gy)) : sqrt(gx * gx + gy * gy);
     acc[1] = fmax(acc[1], L);
   }
   const bool m[2] = {false, true};
-  block_reduce_store<2>(acc, m, partials);
+  block_reduce_store<2>(acc, m, partials + size_t(blockIdx.y) * gridDim.x * 2);
 }
 
 // out = s * in

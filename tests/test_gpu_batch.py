@@ -1,0 +1,130 @@
+"""Batched solves (gp_batch_solve): every instance of a mixed batch must equal
+the matching single-instance solve bit for bit (the iteration of Algorithm 2 is
+per instance; stacking only changes which launch runs it), and instances are
+checked against the FP64 oracle through the single-instance parity."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import announce
+from oracle import emd as oemd
+from oracle import rof as orof
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dev(a):
+    import torch
+    return torch.tensor(np.asarray(a, dtype=np.float32), device="cuda")
+
+
+def host(t):
+    return t.cpu().double().numpy()
+
+
+def rof_problem(n, seed, lam, tau, h=1.0):
+    from paper_1805_09453_amd._lib import GP_KIND_ROF
+    return {"kind": GP_KIND_ROF, "I": dev(synth.rof_scene(n, seed)), "h": h, "lam": lam, "tau": tau}
+
+
+def emd_problem(n, seed, tau, k=4):
+    from paper_1805_09453_amd._lib import GP_KIND_EMD
+    r0, r1 = synth.emd_mixture_pair(n, seed, k=k)
+    return {"kind": GP_KIND_EMD, "rho0": dev(r0), "rho1": dev(r1), "h": 1.0 / n, "tau": tau}
+
+
+def single(ctx, q, opts):
+    from paper_1805_09453_amd._lib import GP_KIND_ROF
+    if q["kind"] == GP_KIND_ROF:
+        u, _, rep = ctx.rof_solve(q["I"], q["h"], q["lam"], opts)
+        return u, rep
+    m, _, rep = ctx.emd_solve(q["rho0"], q["rho1"], q["h"], opts, want_phi=False)
+    return m, rep
+
+
+def test_batch_mixed_equals_single_solves(gpctx):
+    """Two ROF sizes, two lambdas, two EMD sizes, interleaved: outputs, iteration
+    counts and gaps equal the single-instance solves exactly."""
+    from paper_1805_09453_amd import Options
+    probs = [rof_problem(128, 1, 8.0, 0.01), emd_problem(64, 2, 0.3), rof_problem(64, 3, 8.0, 0.01),
+             rof_problem(128, 4, 8.0, 0.01), rof_problem(64, 5, 4.0, 0.02), emd_problem(128, 6, 0.3),
+             emd_problem(64, 7, 0.3), rof_problem(64, 8, 8.0, 0.01)]
+    opts = Options(tau=1.0, tol=1e-4, max_iter=600, check_every=10)
+    announce(f"gp_batch_solve mixed batch of {len(probs)}")
+    outs, reps, rc = gpctx.batch_solve(probs, opts)
+    for i, q in enumerate(probs):
+        announce(f"single solve for batch instance {i}")
+        ref, rrep = single(gpctx, q, Options(tau=q["tau"], tol=opts.tol, max_iter=opts.max_iter, check_every=10))
+        print(i, reps[i]["iters"], rrep["iters"], reps[i]["rel_gap"], rrep["rel_gap"])
+        assert reps[i]["iters"] == rrep["iters"]
+        assert reps[i]["converged"] == rrep["converged"]
+        assert reps[i]["rel_gap"] == rrep["rel_gap"]
+        assert reps[i]["primal"] == rrep["primal"] and reps[i]["dual"] == rrep["dual"]
+        np.testing.assert_array_equal(host(outs[i]), host(ref))
+    # the instances did not all stop together (retirement was exercised)
+    assert len({r["iters"] for r in reps}) > 1
+
+
+def test_batch_rof_instance_matches_oracle_optimum(gpctx):
+    """The 64x64 config-0 scene inside a batch of 16: objective within 1e-5 of
+    the oracle's F*, and the batch's own gap is a valid certificate."""
+    from paper_1805_09453_amd import Options
+    from paper_1805_09453_amd._lib import GP_KIND_ROF
+    I0 = synth.rof_scene(64, synth.config_seed(0))
+    with open(os.path.join(GOLDEN, "oracle_references.json")) as fh:
+        Fstar = json.load(fh)["rof_c0"]["primal"]
+    probs = [{"kind": GP_KIND_ROF, "I": dev(I0), "h": 1.0, "lam": 8.0, "tau": 0.01}]
+    probs += [rof_problem(64, 100 + s, 8.0, 0.01) for s in range(15)]
+    announce("gp_batch_solve 16 x ROF 64x64")
+    outs, reps, rc = gpctx.batch_solve(probs, Options(tau=0.01, tol=1e-6, max_iter=20000, check_every=10))
+    assert all(r["converged"] for r in reps)
+    Fg = orof.primal(host(outs[0]), I0, 1.0, 8.0)
+    assert abs(Fg - Fstar) / Fstar <= 1e-5
+    for i, q in enumerate(probs):
+        P = orof.primal(host(outs[i]), host(q["I"]), 1.0, 8.0)
+        assert abs(reps[i]["primal"] - P) / P < 1e-6
+
+
+def test_batch_emd_translated_pairs_exact_values(gpctx):
+    """Translated Gaussians (exact EMD = shift / (1 + floor)) of two sizes in one batch."""
+    from paper_1805_09453_amd import Options
+    from paper_1805_09453_amd._lib import GP_KIND_EMD
+    probs, exact = [], []
+    for n in (64, 128, 128):
+        r0, r1, s = synth.translated_gaussian_pair(n)
+        probs.append({"kind": GP_KIND_EMD, "rho0": dev(r0), "rho1": dev(r1), "h": 1.0 / n, "tau": 0.25})
+        exact.append(s / (1 + synth.scenes.DENSITY_FLOOR))
+    announce("gp_batch_solve 3 x EMD translated pairs")
+    outs, reps, rc = gpctx.batch_solve(probs, Options(tau=0.25, tol=1e-4, max_iter=50000, check_every=50))
+    for i, q in enumerate(probs):
+        n = q["rho0"].shape[0]
+        f_ref, _ = oemd.setup(host(q["rho0"]), host(q["rho1"]), 1.0 / n)
+        val, _ = oemd.flux_value(host(outs[i])[0], host(outs[i])[1], f_ref, 1.0 / n)
+        print(n, reps[i], val, exact[i])
+        assert reps[i]["converged"]
+        assert reps[i]["dual"] <= exact[i] * (1 + 1e-6) <= reps[i]["primal"] * (1 + 2e-6)
+        assert abs(val - exact[i]) / exact[i] <= 2e-4
+
+
+def test_batch_max_iter_and_errors(gpctx):
+    from paper_1805_09453_amd import GPError, Options
+    from paper_1805_09453_amd._lib import GP_EMASS, GP_ENOTCONV, GP_EUNSUPPORTED, GP_KIND_EMD
+    probs = [rof_problem(64, 1, 8.0, 0.01), rof_problem(64, 2, 8.0, 0.01)]
+    announce("gp_batch_solve max_iter 20")
+    outs, reps, rc = gpctx.batch_solve(probs, Options(tau=0.01, tol=0.0, max_iter=20, check_every=10))
+    assert rc == GP_ENOTCONV and all(r["iters"] == 20 and not r["converged"] for r in reps)
+    bad = emd_problem(64, 3, 0.3)
+    bad["rho1"] = bad["rho1"] * 1.01
+    announce("gp_batch_solve mass mismatch")
+    with pytest.raises(GPError) as e:
+        gpctx.batch_solve([probs[0], bad], Options(tau=0.3))
+    assert e.value.code == GP_EMASS and "instance 1" in str(e.value)
+    odd = {"kind": GP_KIND_EMD, "rho0": dev(np.ones((96, 96))), "rho1": dev(np.ones((96, 96))), "h": 1.0,
+           "tau": 0.3}
+    with pytest.raises(GPError) as e:
+        gpctx.batch_solve([odd], Options(tau=0.3))
+    assert e.value.code == GP_EUNSUPPORTED
