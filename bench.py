@@ -6,7 +6,9 @@ evaluation (the solver's convergence check), on device-resident state.  The
 headline value is pixel-iterations per second of the ROF workload (noisy
 piecewise-constant 4096x4096 image, 50 shapes, sigma 0.1 noise, lambda 8 per
 pixel); the EMD workload (16-Gaussian mixtures, 4096x4096, h = 1/4096) is
-reported beside it.  Prints ONE JSON line.
+reported beside it, and so is a mixed batch of 512 ROF/EMD instances of sides
+64..1024 solved together (aggregate pixel-iterations/s over the solve loop and
+p50/p99 per-instance time to tolerance).  Prints ONE JSON line.
 """
 import argparse
 import hashlib
@@ -33,6 +35,10 @@ def parse():
     ap.add_argument("--no-emd", action="store_true")
     ap.add_argument("--solve", action="store_true", help="also time full solves to --tol")
     ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched mixed-instance leg")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-tol", type=float, default=1e-4)
+    ap.add_argument("--batch-max-iter", type=int, default=5000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
@@ -92,6 +98,50 @@ def cpu_baseline(n, iters_budget_s):
     return {"value": n * n * it / dt, "unit": "pixel-iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{it} ROF iterations of the FP64 NumPy/SciPy oracle on the same {n}x{n} image "
                       f"({dt:.1f} s; scipy.fft single-threaded, NumPy elementwise single-threaded)"}
+
+
+def batch_leg(ctx, dev, count, tol, max_iter):
+    """Mixed batch: `count` ROF/EMD instances (kind ~ Bernoulli(1/2), side 2^U[6,10]
+    snapped to a power of two), solved together by gp_batch_solve."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1805_09453_amd import Options
+    from paper_1805_09453_amd._lib import GP_KIND_EMD, GP_KIND_ROF
+    insts = synth.batch_instances(count)
+    probs = []
+    for q in insts:
+        x = synth.batch_instance_inputs(q)
+        if q["kind"] == "rof":
+            probs.append({"kind": GP_KIND_ROF, "I": torch.tensor(x["image"], dtype=torch.float32, device=dev),
+                          "h": 1.0, "lam": 8.0, "tau": 0.01})
+        else:
+            probs.append({"kind": GP_KIND_EMD, "rho0": torch.tensor(x["rho0"], dtype=torch.float32, device=dev),
+                          "rho1": torch.tensor(x["rho1"], dtype=torch.float32, device=dev), "h": 1.0 / q["n"],
+                          "tau": 0.3})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, reps, rc = ctx.batch_solve(probs, Options(tau=1.0, tol=tol, max_iter=max_iter, check_every=20))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    loop = max(r["seconds_loop"] for r in reps)
+    pxit = sum(q["n"] ** 2 * r["iters"] for q, r in zip(insts, reps))
+    tt = np.array([r["seconds_loop"] for r in reps])
+    per = {}
+    for kind in ("rof", "emd"):
+        for n in sorted({q["n"] for q in insts}):
+            sel = [r for q, r in zip(insts, reps) if q["kind"] == kind and q["n"] == n]
+            if sel:
+                per[f"{kind}_{n}"] = {"count": len(sel), "median_iters": int(np.median([r["iters"] for r in sel])),
+                                      "max_iters": max(r["iters"] for r in sel),
+                                      "converged": int(sum(r["converged"] for r in sel))}
+    return {"instances": len(insts), "pixels": int(sum(q["n"] ** 2 for q in insts)), "tol": tol,
+            "max_iter": max_iter, "check_every": 20, "pixel_iters_per_s": pxit / loop, "loop_s": loop,
+            "setup_s": reps[0]["seconds_setup"], "wall_s": wall,
+            "converged": int(sum(r["converged"] for r in reps)),
+            "time_to_tol_p50_s": float(np.percentile(tt, 50)), "time_to_tol_p99_s": float(np.percentile(tt, 99)),
+            "groups": per}
 
 
 def main():
@@ -189,6 +239,8 @@ def main():
                                                                 check_every=50), want_phi=False)
             torch.cuda.synchronize()
             extra["emd"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
+    if not args.no_batch:
+        extra["batch"] = batch_leg(ctx, dev, args.batch_count, args.batch_tol, args.batch_max_iter)
     ctx.close()
     cpu = None if args.no_cpu else cpu_baseline(n, args.cpu_seconds)
     out = {

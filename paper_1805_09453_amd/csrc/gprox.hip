@@ -8,6 +8,7 @@
 // through per-instance active flags.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -31,6 +32,7 @@ constexpr int kMinN = 64, kMaxN = 4096;
 constexpr int kRedBlocks = 1024;  // partial-sum blocks of the grid-stride reductions
 constexpr int kMaxK = 8;
 constexpr int kResult = 16;       // doubles in the finalized-result buffers
+constexpr int kSideStreams = 8;   // parallel branches of the batch graph
 
 bool is_pow2_in_range(int n) { return n >= kMinN && n <= kMaxN && (n & (n - 1)) == 0; }
 int ilog2i(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
@@ -47,6 +49,9 @@ struct Tables {  // per transform length N
 struct gp_ctx {
   hipStream_t stream = nullptr;   // the caller's stream
   hipStream_t bstream = nullptr;  // private stream of gp_batch_solve (graph capture and replay)
+  std::vector<hipStream_t> side;  // side streams of the batch graph's parallel branches
+  std::vector<hipEvent_t> side_ev;
+  hipEvent_t fork_ev = nullptr;
   int max_ny = 0, max_nx = 0;
   Tables tab[13];            // index log2 N
   float* work = nullptr;     // [max_n] FP32 tiled intermediate
@@ -822,6 +827,9 @@ int gp_destroy(gp_ctx* c) {
     (void)hipStreamSynchronize(c->bstream);
     (void)hipStreamDestroy(c->bstream);
   }
+  for (auto s : c->side) (void)hipStreamDestroy(s);
+  for (auto e : c->side_ev) (void)hipEventDestroy(e);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   for (auto& T : c->tab) {
     if (T.tw32) (void)hipFree(T.tw32);
     if (T.tw64) (void)hipFree(T.tw64);
@@ -1255,37 +1263,50 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     return r;
   };
   int rc = GP_OK;
-  for (size_t k = 0; k < G.size() && !rc; ++k) {
-    if (G[k].g.kind == GP_KIND_ROF) {
-      rc = rof_A(rp[k], 1, false);
-      if (!rc) rc = rof_CB(rp[k]);
-    } else {
-      rc = emd_A(ep[k], 1, false);
-      if (!rc) rc = emd_CB(ep[k]);
-    }
-  }
+  for (size_t k = 0; k < G.size() && !rc; ++k)
+    rc = G[k].g.kind == GP_KIND_ROF ? rof_A(rp[k], 1, false) : emd_A(ep[k], 1, false);
   if (rc) return restore(rc);
-  // chunk: C steady A's (the last one with gap partials) with the column pass and
-  // B between them, then the per-instance reductions; the column pass and B that
-  // follow the last A run outside the graph, after retirement
+  // side streams: independent groups form parallel branches of the graph
+  const int nside = int(std::min<size_t>(G.size(), size_t(kSideStreams))) - 1;
+  for (int s = int(c->side.size()); s < nside; ++s) {
+    hipStream_t st;
+    hipEvent_t ev;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      set_err(c, "side stream creation failed");
+      return restore(GP_EHIP);
+    }
+    c->side.push_back(st);
+    c->side_ev.push_back(ev);
+  }
+  if (!c->fork_ev && hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess) {
+    set_err(c, "event creation failed");
+    return restore(GP_EHIP);
+  }
+  // chunk, per group: C x (column pass + B, then A), the last A with gap partials,
+  // then the per-instance reductions (ROF: finalize; EMD: finalize + certificate)
   if (hipStreamBeginCapture(c->bstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     set_err(c, "hipStreamBeginCapture failed");
     return restore(GP_EHIP);
   }
-  for (int it = 0; it < C && !rc; ++it) {
-    const bool last = it + 1 == C;
-    for (size_t k = 0; k < G.size() && !rc; ++k) {
-      if (G[k].g.kind == GP_KIND_ROF) {
-        rc = rof_A(rp[k], 0, last);
-        if (!rc && !last) rc = rof_CB(rp[k]);
+  if (hipEventRecord(c->fork_ev, c->bstream) != hipSuccess) rc = GP_EHIP;
+  for (int s = 0; s < nside && !rc; ++s)
+    if (hipStreamWaitEvent(c->side[s], c->fork_ev, 0) != hipSuccess) rc = GP_EHIP;
+  if (rc) set_err(c, "fork inside the capture failed");
+  for (size_t k = 0; k < G.size() && !rc; ++k) {
+    c->stream = k == 0 || nside == 0 ? c->bstream : c->side[(k - 1) % nside];
+    const Group& g = G[k].g;
+    for (int it = 0; it < C && !rc; ++it) {
+      const bool last = it + 1 == C;
+      if (g.kind == GP_KIND_ROF) {
+        rc = rof_CB(rp[k]);
+        if (!rc) rc = rof_A(rp[k], 0, last);
       } else {
-        rc = emd_A(ep[k], 0, last);
-        if (!rc && !last) rc = emd_CB(ep[k]);
+        rc = emd_CB(ep[k]);
+        if (!rc) rc = emd_A(ep[k], 0, last);
       }
     }
-  }
-  for (size_t k = 0; k < G.size() && !rc; ++k) {
-    const Group& g = G[k].g;
+    if (rc) break;
     hipLaunchKernelGGL(k_finalize, dim3(g.m), dim3(256), 0, c->stream, g.gpart, g.nyi / 2,
                        g.kind == GP_KIND_ROF ? 4 : 1, 0u, G[k].gap_dev);
     if (hipGetLastError() != hipSuccess) {
@@ -1295,6 +1316,13 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     if (!rc && g.kind == GP_KIND_EMD) rc = emd_cert_enqueue(c, g, ep[k].X, G[k].cphi, G[k].ctmp, G[k].cpart,
                                                            G[k].cert_dev);
   }
+  c->stream = c->bstream;
+  for (int s = 0; s < nside && !rc; ++s)
+    if (hipEventRecord(c->side_ev[s], c->side[s]) != hipSuccess ||
+        hipStreamWaitEvent(c->bstream, c->side_ev[s], 0) != hipSuccess) {
+      set_err(c, "join inside the capture failed");
+      rc = GP_EHIP;
+    }
   const hipError_t ce = hipStreamEndCapture(c->bstream, &graph);
   if (rc || ce != hipSuccess) {
     if (!rc) set_err(c, "hipStreamEndCapture failed: %s", hipGetErrorString(ce));
@@ -1367,10 +1395,6 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
         return restore(GP_EHIP);
       }
     }
-    if (left == 0) break;
-    // the column pass and B after the chunk's last A, for the instances still running
-    for (size_t k = 0; k < G.size() && !rc; ++k) rc = G[k].g.kind == GP_KIND_ROF ? rof_CB(rp[k]) : emd_CB(ep[k]);
-    if (rc) return restore(rc);
   }
   // ---- outputs: ROF u_t (B never ran after an instance's last check); EMD flux
   // m_t = wt_{t-1} - grad phi_{t-1} (neither was touched after retirement)
