@@ -16,6 +16,9 @@ rof   : the ROF functional (section 3.1, eq. for F_lambda), its dual, and the
 emd   : the Beckmann/L1 EMD problem (section 3.2), the Hodge split, the
         G-prox PDHG iteration (updates of 3.2), the primal value and a dual
         certificate.
+unet  : the learned warm start's network (a U-Net predicting the dual
+        potential), its parameter gradients, loss, Adam step and the
+        resolution changes used at 4096^2.  Not part of the paper.
 
 Every function is FP64 NumPy/SciPy; scipy.fft's orthonormal DCT is used as a
 library primitive for the Laplace inversion (section 4 and appendix A: the
@@ -26,4 +29,4 @@ to something other than itself: adjointness, dense linear solves, BVLS, linear
 programs and network flow, closed forms and invariants.  No function here is
 "parity unpinned".
 """
-from . import grid, rof, emd  # noqa: F401
+from . import grid, rof, emd, unet  # noqa: F401
