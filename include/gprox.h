@@ -154,6 +154,7 @@ typedef struct {
   const float* in0;
   const float* in1;
   float* out;
+  float* phi; /* EMD, nullable: out [ny][nx] scaled certificate potential (as emd_solve) */
 } gp_instance;
 
 /* Solve count independent instances (each one the solve of rof_solve or
@@ -174,6 +175,75 @@ typedef struct {
  * when some reached max_iter (all outputs valid), or an error (GP_EMASS names
  * the first instance with unequal masses in gp_last_error). */
 int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opts* opts, gp_report* reps);
+
+/* ---------------------------------------------------------------- learned warm start
+ * Not part of the paper.  A U-Net predicts the dual potential phi0 of the EMD
+ * problem from (rho0, rho1); the iteration of section 3.2 then starts from
+ * p0 = proj(grad phi0), u0 = 0 and its duality gap still decides convergence.
+ *
+ * Network (widths 32/64/128/256): per encoder level two 3x3 convolutions with
+ * zero padding, each followed by ReLU, then 2x2 average pooling; bottleneck
+ * two 3x3 conv + ReLU; per decoder level a 2x2 stride-2 transposed
+ * convolution (no activation), concatenation [upsampled, encoder skip] and
+ * two 3x3 conv + ReLU; a 1x1 head gives phi.  Input channels (rho0 - 1,
+ * rho1 - 1).  BF16 weights and activations, FP32 accumulation (MFMA), FP32
+ * master weights and Adam moments.
+ *
+ * Parameter blob (FP32, ws_param_count() values): layers enc0a enc0b enc1a
+ * enc1b enc2a enc2b mid_a mid_b up2 dec2a dec2b up1 dec1a dec1b up0 dec0a dec0b
+ * head, each weights then bias.  3x3 conv weights [cout][3][3][cin] (tap
+ * (ky, kx) reads the input at offset (ky - 1, kx - 1)); transposed conv
+ * weights [cin][2][2][cout] (output pixel (2y + i, 2x + j) from input (y, x)
+ * through W[:, i, j, :]); head [1][32] and one bias.  (cin, cout): enc (2,32)
+ * (32,32) (32,64) (64,64) (64,128) (128,128); mid (128,256) (256,256);
+ * up2 (256,128); dec2 (256,128) (128,128); up1 (128,64); dec1 (128,64)
+ * (64,64); up0 (64,32); dec0 (64,32) (32,32); head (32,1).
+ *
+ * Loss for training: mean over the batch's pixels of |grad_h phi - grad_h
+ * phi*|^2 (forward differences as in the solver, h the targets' spacing). */
+typedef struct ws_net ws_net;
+typedef struct {
+  int used_warm;      /* 1 if the reported solve started from the prediction */
+  int fallback;       /* 1 if the warm start was rejected or missed max_iter and a plain solve ran */
+  int warm_iters;     /* iterations of the warm attempt (0 if not tried) */
+  double d0;          /* certificate value D(phi0) of the prediction */
+  double seconds_predict;  /* resampling + network + certificate */
+  double seconds_total;    /* whole call, including any fallback */
+} ws_report;
+
+long long ws_param_count(void);
+/* Network on ctx's stream for batches of up to max_batch inputs of ny x nx
+ * (multiples of 8, <= 4096; the native resolution).  Parameters start at 0. */
+int ws_create(gp_ctx* ctx, ws_net** net, int max_batch, int ny, int nx);
+int ws_destroy(ws_net* net);
+/* Copy the FP32 blob (device) in (resets the Adam state) or out. */
+int ws_set_params(gp_ctx* ctx, ws_net* net, const float* blob);
+int ws_get_params(gp_ctx* ctx, ws_net* net, float* blob);
+/* phi0 [batch][ny][nx] = net(rho0, rho1) at the native size (rho [batch][ny][nx]). */
+int ws_predict(gp_ctx* ctx, ws_net* net, const float* rho0, const float* rho1, int batch, float* phi0);
+/* Forward, loss against phi_star [batch][ny][nx] and parameter gradients
+ * (kept for ws_adam; copied to grad, nullable, as an FP32 blob).  h > 0 is the
+ * targets' grid spacing.  Synchronises; *loss receives the loss. */
+int ws_grads(gp_ctx* ctx, ws_net* net, const float* rho0, const float* rho1, const float* phi_star, int batch,
+             double h, float* grad, double* loss);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, bias-corrected) with learning
+ * rate lr on the gradients of the last ws_grads. */
+int ws_adam(gp_ctx* ctx, ws_net* net, double lr);
+/* The resolution changes of ws_emd_solve: f x f block mean ([ny][nx] ->
+ * [ny/f][nx/f], mass-preserving for densities) and bilinear interpolation
+ * between cell centres ([ny][nx] -> [f ny][f nx], constant beyond the
+ * outermost centres). */
+int ws_downsample(gp_ctx* ctx, const float* in, int ny, int nx, int f, float* out);
+int ws_upsample(gp_ctx* ctx, const float* in, int ny, int nx, int f, float* out);
+/* emd_solve with the learned start.  ny, nx must be f times the network's
+ * native size (f a power of two): the densities are block-averaged by f, the
+ * prediction is interpolated bilinearly back (a potential in unit-square
+ * units keeps its slope bound).  The start is rejected when D(phi0) <= 0;
+ * a warm run that reaches opts->max_iter is followed by a plain solve with
+ * the same opts (fallback).  m, phi, rep as emd_solve (phi nullable);
+ * wrep nullable. */
+int ws_emd_solve(gp_ctx* ctx, ws_net* net, const float* rho0, const float* rho1, float* m, float* phi, int ny,
+                 int nx, double h, const gp_opts* opts, gp_report* rep, ws_report* wrep);
 
 /* Per-kernel timing on the context's stream (HIP events around each kernel
  * launch; for measurement, not needed by the solvers).  gp_profile(ctx, 1)

@@ -166,71 +166,84 @@ def head_bwd(X, W, dphi):
 
 
 # ---------------------------------------------------------------- network
-def forward(P, rho0, rho1):
-    """rho0, rho1: (B, H, W) with H, W multiples of 8.  Returns (phi (B,H,W), cache)."""
-    x = np.stack([np.asarray(rho0, np.float64) - 1.0, np.asarray(rho1, np.float64) - 1.0], axis=-1)
+def _same(a):
+    return a
+
+
+def forward(P, rho0, rho1, rnd=None):
+    """rho0, rho1: (B, H, W) with H, W multiples of 8.  Returns (phi (B,H,W), cache).
+    rnd (optional) is applied to every stored activation (the input, each layer
+    output); it models a storage format such as BF16 and defaults to none."""
+    r = rnd or _same
+    x = r(np.stack([np.asarray(rho0, np.float64) - 1.0, np.asarray(rho1, np.float64) - 1.0], axis=-1))
     c = {"x": x}
     h = x
     skips = []
     for lvl, (a, bn) in enumerate((("enc0a", "enc0b"), ("enc1a", "enc1b"), ("enc2a", "enc2b"))):
         c[a + "_in"] = h
-        h = relu(conv3(h, *P[a]))
+        h = r(relu(conv3(h, *P[a])))
         c[a] = h
-        h = relu(conv3(h, *P[bn]))
+        h = r(relu(conv3(h, *P[bn])))
         c[bn] = h
         skips.append(h)
-        h = pool2(h)
+        h = r(pool2(h))
     c["mid_a_in"] = h
-    h = relu(conv3(h, *P["mid_a"]))
+    h = r(relu(conv3(h, *P["mid_a"])))
     c["mid_a"] = h
-    h = relu(conv3(h, *P["mid_b"]))
+    h = r(relu(conv3(h, *P["mid_b"])))
     c["mid_b"] = h
     for up, a, bn, skip in (("up2", "dec2a", "dec2b", skips[2]), ("up1", "dec1a", "dec1b", skips[1]),
                             ("up0", "dec0a", "dec0b", skips[0])):
         c[up + "_in"] = h
-        h = tconv2(h, *P[up])
+        h = r(tconv2(h, *P[up]))
         h = np.concatenate([h, skip], axis=-1)
         c[a + "_in"] = h
-        h = relu(conv3(h, *P[a]))
+        h = r(relu(conv3(h, *P[a])))
         c[a] = h
-        h = relu(conv3(h, *P[bn]))
+        h = r(relu(conv3(h, *P[bn])))
         c[bn] = h
     c["head_in"] = h
     return head(h, *P["head"]), c
 
 
-def backward(P, c, dphi):
-    """Parameter gradients {name: (dW, db)} of <dphi, forward(P, ...)>."""
+def backward(P, c, dphi, rnd=None):
+    """Parameter gradients {name: (dW, db)} of <dphi, forward(P, ...)>; rnd (optional)
+    is applied to every stored activation gradient."""
+    r = rnd or _same
     G = {}
     dh, dW, db = head_bwd(c["head_in"], P["head"][0], dphi)
     G["head"] = (dW, db)
+    dh = r(relu_bwd(c["head_in"], dh))
     dskips = {}
     for up, a, bn, lvl in (("up0", "dec0a", "dec0b", 0), ("up1", "dec1a", "dec1b", 1),
                            ("up2", "dec2a", "dec2b", 2)):
-        g = relu_bwd(c[bn], dh)
+        g = dh if lvl == 0 else relu_bwd(c[bn], dh)
         dh, dW, db = conv3_bwd(c[a], P[bn][0], g)
         G[bn] = (dW, db)
-        g = relu_bwd(c[a], dh)
+        g = relu_bwd(c[a], r(dh))
         dh, dW, db = conv3_bwd(c[a + "_in"], P[a][0], g)
         G[a] = (dW, db)
+        dh = r(dh)
         cu = P[up][0].shape[3]
         dskips[lvl] = dh[..., cu:]
         dh, dW, db = tconv2_bwd(c[up + "_in"], P[up][0], dh[..., :cu])
         G[up] = (dW, db)
+        dh = r(dh)
     g = relu_bwd(c["mid_b"], dh)
     dh, dW, db = conv3_bwd(c["mid_a"], P["mid_b"][0], g)
     G["mid_b"] = (dW, db)
-    g = relu_bwd(c["mid_a"], dh)
+    g = relu_bwd(c["mid_a"], r(dh))
     dh, dW, db = conv3_bwd(c["mid_a_in"], P["mid_a"][0], g)
     G["mid_a"] = (dW, db)
+    dh = r(dh)
     for lvl, (a, bn) in reversed(list(enumerate((("enc0a", "enc0b"), ("enc1a", "enc1b"), ("enc2a", "enc2b"))))):
-        dh = pool2_bwd(dh) + dskips[lvl]
-        g = relu_bwd(c[bn], dh)
+        g = r(relu_bwd(c[bn], pool2_bwd(dh) + dskips[lvl]))
         dh, dW, db = conv3_bwd(c[a], P[bn][0], g)
         G[bn] = (dW, db)
-        g = relu_bwd(c[a], dh)
+        g = relu_bwd(c[a], r(dh))
         dh, dW, db = conv3_bwd(c[a + "_in"], P[a][0], g)
         G[a] = (dW, db)
+        dh = r(dh)
     return G
 
 

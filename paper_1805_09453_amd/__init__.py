@@ -9,5 +9,8 @@ from .api import (  # noqa: F401
     GPError,
     Context,
     Options,
+    WarmStart,
     lib_path,
+    ws_downsample,
+    ws_upsample,
 )

@@ -34,7 +34,15 @@ class gp_state(ctypes.Structure):
 
 class gp_instance(ctypes.Structure):
     _fields_ = [("kind", c_int), ("ny", c_int), ("nx", c_int), ("h", c_double), ("lam", c_double),
-                ("tau", c_double), ("in0", c_void_p), ("in1", c_void_p), ("out", c_void_p)]
+                ("tau", c_double), ("in0", c_void_p), ("in1", c_void_p), ("out", c_void_p), ("phi", c_void_p)]
+
+
+class ws_report(ctypes.Structure):
+    _fields_ = [("used_warm", c_int), ("fallback", c_int), ("warm_iters", c_int), ("d0", c_double),
+                ("seconds_predict", c_double), ("seconds_total", c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class gp_kstat(ctypes.Structure):
@@ -58,6 +66,19 @@ _SIGS = {
     "pd_gap": (c_int, [c_void_p, ctypes.POINTER(gp_state), ctypes.POINTER(gp_report)]),
     "gp_batch_solve": (c_int, [c_void_p, ctypes.POINTER(gp_instance), c_int, ctypes.POINTER(gp_opts),
                                ctypes.POINTER(gp_report)]),
+    "ws_param_count": (c_longlong, []),
+    "ws_create": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_int, c_int, c_int]),
+    "ws_destroy": (c_int, [c_void_p]),
+    "ws_set_params": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "ws_get_params": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "ws_predict": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "ws_grads": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p,
+                         ctypes.POINTER(c_double)]),
+    "ws_adam": (c_int, [c_void_p, c_void_p, c_double]),
+    "ws_downsample": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+    "ws_upsample": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+    "ws_emd_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double,
+                             ctypes.POINTER(gp_opts), ctypes.POINTER(gp_report), ctypes.POINTER(ws_report)]),
     "gp_profile": (c_int, [c_void_p, c_int]),
     "gp_profile_read": (c_int, [c_void_p, ctypes.POINTER(gp_kstat), c_int, ctypes.POINTER(c_int)]),
 }

@@ -221,7 +221,9 @@ class Context:
 
         problems: sequence of dicts, ROF: {"kind": GP_KIND_ROF, "I": (ny, nx) tensor, "h", "lam", "tau"};
         EMD: {"kind": GP_KIND_EMD, "rho0", "rho1": (ny, nx) tensors, "h", "tau"}.
-        Returns (outs, reports, rc): outs[i] is u (ROF) or the flux m (EMD)."""
+        An EMD problem may carry "phi": an (ny, nx) tensor that receives the scaled
+        certificate potential.  Returns (outs, reports, rc): outs[i] is u (ROF) or
+        the flux m (EMD)."""
         torch = _torch()
         n = len(problems)
         arr = (L.gp_instance * n)()
@@ -237,8 +239,9 @@ class Context:
             in0 = _ptr(a, torch.float32, (ny, nx), f"problems[{i}] input")
             in1 = _ptr(q["rho1"], torch.float32, (ny, nx), f"problems[{i}].rho1") if kind == L.GP_KIND_EMD else None
             out = _ptr(outs[i], torch.float32, oshape, f"outs[{i}]")
+            phi = _ptr(q.get("phi"), torch.float32, (ny, nx), f"problems[{i}].phi") if kind == L.GP_KIND_EMD else None
             arr[i] = L.gp_instance(kind, ny, nx, float(q["h"]), float(q.get("lam", 0.0)), float(q["tau"]),
-                                   in0, in1, out)
+                                   in0, in1, out, phi)
             keep.append(a)
         reps = (L.gp_report * n)()
         rc = self._lib.gp_batch_solve(self._h, arr, n, ctypes.byref(opts.c()), reps)
@@ -249,3 +252,98 @@ class Context:
         rep = L.gp_report()
         self._check(self._lib.pd_gap(self._h, ctypes.byref(st.c), ctypes.byref(rep)))
         return rep.as_dict()
+
+
+class WarmStart:
+    """The learned warm-start network (ws_net) on a Context's stream."""
+
+    def __init__(self, ctx: Context, max_batch: int, ny: int, nx: int):
+        self.ctx, self.max_batch, self.ny, self.nx = ctx, max_batch, ny, nx
+        lib = ctx._lib
+        h = ctypes.c_void_p()
+        ctx._check(lib.ws_create(ctx._h, ctypes.byref(h), int(max_batch), int(ny), int(nx)))
+        self._h = h
+        self.n_params = int(lib.ws_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.ws_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, blob):
+        torch = _torch()
+        self.ctx._check(self.ctx._lib.ws_set_params(self.ctx._h, self._h,
+                                                    _ptr(blob, torch.float32, (self.n_params,), "blob")))
+
+    def get_params(self):
+        torch = _torch()
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self.ctx._check(self.ctx._lib.ws_get_params(self.ctx._h, self._h, _ptr(out, torch.float32, out.shape, "out")))
+        return out
+
+    def predict(self, rho0, rho1):
+        """rho0, rho1: (B, ny, nx) at the native size -> phi0 (B, ny, nx)."""
+        torch = _torch()
+        B = rho0.shape[0]
+        shp = (B, self.ny, self.nx)
+        phi = torch.empty(shp, dtype=torch.float32, device=rho0.device)
+        self.ctx._check(self.ctx._lib.ws_predict(self.ctx._h, self._h, _ptr(rho0, torch.float32, shp, "rho0"),
+                                                 _ptr(rho1, torch.float32, shp, "rho1"), int(B),
+                                                 _ptr(phi, torch.float32, shp, "phi")))
+        return phi
+
+    def grads(self, rho0, rho1, phi_star, h, want_grad=False):
+        """Loss (float) and, if asked, the FP32 gradient blob."""
+        torch = _torch()
+        B = rho0.shape[0]
+        shp = (B, self.ny, self.nx)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=rho0.device) if want_grad else None
+        loss = ctypes.c_double()
+        self.ctx._check(self.ctx._lib.ws_grads(self.ctx._h, self._h, _ptr(rho0, torch.float32, shp, "rho0"),
+                                               _ptr(rho1, torch.float32, shp, "rho1"),
+                                               _ptr(phi_star, torch.float32, shp, "phi_star"), int(B), float(h),
+                                               _ptr(g, torch.float32, (self.n_params,), "grad"),
+                                               ctypes.byref(loss)))
+        return (loss.value, g) if want_grad else loss.value
+
+    def adam(self, lr):
+        self.ctx._check(self.ctx._lib.ws_adam(self.ctx._h, self._h, float(lr)))
+
+    def emd_solve(self, rho0, rho1, h, opts: Options, want_phi=False):
+        """emd_solve from the learned start (with fallback); returns (m, phi, report, ws_report)."""
+        torch = _torch()
+        ny, nx = rho0.shape
+        m = torch.empty((2, ny, nx), device=rho0.device, dtype=torch.float32)
+        phi = torch.empty_like(rho0) if want_phi else None
+        rep, wrep = L.gp_report(), L.ws_report()
+        rc = self.ctx._lib.ws_emd_solve(self.ctx._h, self._h, _ptr(rho0, torch.float32, (ny, nx), "rho0"),
+                                        _ptr(rho1, torch.float32, (ny, nx), "rho1"),
+                                        _ptr(m, torch.float32, (2, ny, nx), "m"),
+                                        _ptr(phi, torch.float32, (ny, nx), "phi"), ny, nx, float(h),
+                                        ctypes.byref(opts.c()), ctypes.byref(rep), ctypes.byref(wrep))
+        self.ctx._check(rc, allow_notconv=True)
+        return m, phi, rep.as_dict(), wrep.as_dict()
+
+
+def ws_downsample(ctx: Context, x, f: int):
+    torch = _torch()
+    ny, nx = x.shape
+    out = torch.empty((ny // f, nx // f), dtype=torch.float32, device=x.device)
+    ctx._check(ctx._lib.ws_downsample(ctx._h, _ptr(x, torch.float32, (ny, nx), "x"), ny, nx, int(f),
+                                      _ptr(out, torch.float32, out.shape, "out")))
+    return out
+
+
+def ws_upsample(ctx: Context, x, f: int):
+    torch = _torch()
+    ny, nx = x.shape
+    out = torch.empty((ny * f, nx * f), dtype=torch.float32, device=x.device)
+    ctx._check(ctx._lib.ws_upsample(ctx._h, _ptr(x, torch.float32, (ny, nx), "x"), ny, nx, int(f),
+                                    _ptr(out, torch.float32, out.shape, "out")))
+    return out

@@ -6,12 +6,12 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libgprox.so")
-SOURCES = [os.path.join(PKG, "csrc", "gprox.hip")]
-DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp")] + [
-    os.path.join(ROOT, "include", "gprox.h")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("gprox.hip", "ws_unet.hip")]
+DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp",
+                                                         "ws_unet.hpp")] + [os.path.join(ROOT, "include", "gprox.h")]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
@@ -25,15 +25,33 @@ def hipcc():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile libgprox.so; always recompiles.  Returns the library path."""
+    """Compile libgprox.so; always recompiles (the translation units in parallel).
+    Returns the library path."""
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(PKG, "_build", os.path.basename(src) + ".o")
+        os.makedirs(os.path.dirname(obj), exist_ok=True)
+        cmd = [hipcc()] + HIPCC_FLAGS + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+        objs.append(obj)
+    failed = False
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed = True
+    if failed:
+        raise RuntimeError("hipcc failed building libgprox.so")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp] + SOURCES
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libgprox.so")
+        raise RuntimeError("linking libgprox.so failed")
     os.replace(tmp, LIB)
     return LIB
 

@@ -23,6 +23,7 @@
 #include "../../include/gprox.h"
 #include "gprox_fused.hpp"
 #include "gprox_kernels.hpp"
+#include "ws_unet.hpp"
 
 using namespace gp;
 
@@ -69,6 +70,9 @@ struct gp_ctx {
   // solver arena (grow-only)
   float* arena = nullptr;
   size_t arena_floats = 0;
+  // warm-start scratch (grow-only): coarse densities, coarse and fine potential
+  float* wsbuf = nullptr;
+  size_t wsbuf_floats = 0;
   // batch arena (grow-only)
   char* barena = nullptr;
   size_t barena_bytes = 0;
@@ -579,12 +583,13 @@ int emd_finish(EmdPipe& P, const float* wt, bool state, float* mout) {
 // EMD certificates of the dual iterates p of all m instances: phi_c = Delta^{-1} div p,
 // D = h^2 sum phi_c (rho0 - rho1) / max(1, max |grad phi_c|).  Enqueues only: per
 // instance [sum(-phi_c f), max |grad phi_c|] lands in out[2 i], out[2 i + 1].
-// phi, tmp: m n doubles (phi is left holding -phi_c); cpart: m * red_blocks(n) * 2.
+// phi, tmp: m n doubles (phi is left holding -phi_c; retired instances keep theirs);
+// cpart: m * red_blocks(n) * 2.
 int emd_cert_enqueue(gp_ctx* c, const Group& g, const float* p, double* phi, double* tmp, double* cpart, double* out) {
   const size_t n = size_t(g.nyi) * g.nx, nt = g.ntot();
   int ps = prof_begin(c, K_DIV64, 16.0 * double(nt));
   hipLaunchKernelGGL(k_div<double>, dim3(grid_for(nt)), dim3(256), 0, c->stream, p, p + nt, phi, g.nyi * g.m, g.nx,
-                     g.nyi, float(1.0 / g.h));
+                     g.nyi, float(1.0 / g.h), g.active);
   prof_end(c, ps);
   LAUNCHCHK(c);
   // Delta phi_c = div p  <=>  (0 I - Delta) phi_c = -div p: solving with div p gives -phi_c
@@ -843,6 +848,7 @@ int gp_destroy(gp_ctx* c) {
   for (double* p : db)
     if (p) (void)hipFree(p);
   if (c->barena) (void)hipFree(c->barena);
+  if (c->wsbuf) (void)hipFree(c->wsbuf);
   for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
   if (c->host_result) (void)hipHostFree(c->host_result);
   delete c;
@@ -1335,7 +1341,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
   // ---- replay until every instance has retired
   std::vector<char> retired(count, 0);
   std::vector<int> iters(count, 0);
-  std::vector<double> Pv(count, NAN), Dv(count, NAN), gv(count, NAN), tv(count, 0.0);
+  std::vector<double> Pv(count, NAN), Dv(count, NAN), gv(count, NAN), tv(count, 0.0), Lv(count, 0.0);
   int left = count, done = 0;
   const double t1 = now_s();
   std::vector<double> hbuf;
@@ -1376,6 +1382,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
         } else {
           P = g.h * g.h * hbuf[k];
           D = emd_dual_from(&hbuf[g.m + 2 * size_t(k)], g.h);
+          Lv[i] = hbuf[g.m + 2 * size_t(k) + 1];
         }
         const double gp = rel_gap(P, D);
         Pv[i] = P;
@@ -1397,27 +1404,38 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     }
   }
   // ---- outputs: ROF u_t (B never ran after an instance's last check); EMD flux
-  // m_t = wt_{t-1} - grad phi_{t-1} (neither was touched after retirement)
-  for (size_t k = 0; k < G.size(); ++k) {
+  // m_t = wt_{t-1} - grad phi_{t-1} (neither was touched after retirement) and,
+  // if asked, the scaled certificate potential phi_c / max(1, L) of p_t
+  bool ok = true;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    ok = ok && hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->bstream) == hipSuccess;
+  };
+  for (size_t k = 0; k < G.size() && ok; ++k) {
     const BatchGroup& bg = G[k];
     const Group& g = bg.g;
     const size_t n = size_t(g.nyi) * g.nx, nt = g.ntot();
     if (g.kind == GP_KIND_ROF) {
-      for (int q = 0; q < g.m; ++q)
-        HIPCHK(c, hipMemcpyAsync(inst[bg.idx[q]].out, g.u + q * n, n * sizeof(float), hipMemcpyDeviceToDevice,
-                                 c->bstream));
+      for (int q = 0; q < g.m; ++q) cp(inst[bg.idx[q]].out, g.u + q * n, n * sizeof(float));
     } else {
       rc = emd_finish(ep[k], ep[k].WY, false, bg.mflux);
       if (rc) return restore(rc);
       for (int q = 0; q < g.m; ++q) {
-        float* out = inst[bg.idx[q]].out;
-        HIPCHK(c, hipMemcpyAsync(out, bg.mflux + q * n, n * sizeof(float), hipMemcpyDeviceToDevice, c->bstream));
-        HIPCHK(c, hipMemcpyAsync(out + n, bg.mflux + nt + q * n, n * sizeof(float), hipMemcpyDeviceToDevice,
-                                 c->bstream));
+        const gp_instance& in = inst[bg.idx[q]];
+        cp(in.out, bg.mflux + q * n, n * sizeof(float));
+        cp(in.out + n, bg.mflux + nt + q * n, n * sizeof(float));
+        if (in.phi) {
+          const double L = Lv[bg.idx[q]];
+          hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->bstream, bg.cphi + q * n, in.phi, n,
+                             -1.0 / (L > 1.0 ? L : 1.0));
+          ok = ok && hipGetLastError() == hipSuccess;
+        }
       }
     }
   }
-  HIPCHK(c, hipStreamSynchronize(c->bstream));
+  if (!ok || hipStreamSynchronize(c->bstream) != hipSuccess) {
+    set_err(c, "batch output copies failed");
+    return restore(GP_EHIP);
+  }
   bool all_conv = true;
   for (int i = 0; i < count; ++i) {
     const bool conv = gv[i] <= o->tol;
@@ -1434,6 +1452,155 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     }
   }
   return restore(all_conv ? GP_OK : GP_ENOTCONV);
+}
+
+// ---------------------------------------------------------------- learned warm start
+long long ws_param_count(void) { return wsi::param_count(); }
+
+int ws_create(gp_ctx* c, ws_net** net, int max_batch, int ny, int nx) {
+  if (!c || !net) return GP_EINVAL;
+  return wsi::create(net, max_batch, ny, nx, c->err, sizeof(c->err));
+}
+
+int ws_destroy(ws_net* net) {
+  wsi::destroy(net);
+  return GP_OK;
+}
+
+#define WSCHK(c, net, expr)                                       \
+  do {                                                            \
+    const int rc_ = (expr);                                       \
+    if (rc_) {                                                    \
+      std::snprintf((c)->err, sizeof((c)->err), "%s", wsi::error(net)); \
+      return rc_;                                                 \
+    }                                                             \
+  } while (0)
+
+int ws_set_params(gp_ctx* c, ws_net* net, const float* blob) {
+  if (!c || !net || !blob) return GP_EINVAL;
+  WSCHK(c, net, wsi::set_params(net, c->stream, blob));
+  return GP_OK;
+}
+
+int ws_get_params(gp_ctx* c, ws_net* net, float* blob) {
+  if (!c || !net || !blob) return GP_EINVAL;
+  WSCHK(c, net, wsi::get_params(net, c->stream, blob));
+  return GP_OK;
+}
+
+int ws_predict(gp_ctx* c, ws_net* net, const float* rho0, const float* rho1, int batch, float* phi0) {
+  if (!c || !net || !rho0 || !rho1 || !phi0) return GP_EINVAL;
+  WSCHK(c, net, wsi::predict(net, c->stream, rho0, rho1, batch, phi0));
+  return GP_OK;
+}
+
+int ws_grads(gp_ctx* c, ws_net* net, const float* rho0, const float* rho1, const float* phi_star, int batch, double h,
+             float* grad, double* loss) {
+  if (!c || !net || !rho0 || !rho1 || !phi_star) return GP_EINVAL;
+  WSCHK(c, net, wsi::grads(net, c->stream, rho0, rho1, phi_star, batch, h, grad, loss));
+  return GP_OK;
+}
+
+int ws_adam(gp_ctx* c, ws_net* net, double lr) {
+  if (!c || !net || !(lr >= 0) || !std::isfinite(lr)) return GP_EINVAL;
+  WSCHK(c, net, wsi::adam(net, c->stream, lr));
+  return GP_OK;
+}
+
+int ws_downsample(gp_ctx* c, const float* in, int ny, int nx, int f, float* out) {
+  if (!c || !in || !out || f < 1 || ny < f || nx < f || ny % f || nx % f) return GP_EINVAL;
+  if (wsi::downsample(c->stream, in, ny, nx, f, out)) {
+    set_err(c, "downsample launch failed");
+    return GP_EHIP;
+  }
+  return GP_OK;
+}
+
+int ws_upsample(gp_ctx* c, const float* in, int ny, int nx, int f, float* out) {
+  if (!c || !in || !out || f < 1 || ny < 1 || nx < 1) return GP_EINVAL;
+  if (wsi::upsample(c->stream, in, ny, nx, f, out)) {
+    set_err(c, "upsample launch failed");
+    return GP_EHIP;
+  }
+  return GP_OK;
+}
+
+int ws_emd_solve(gp_ctx* c, ws_net* net, const float* rho0, const float* rho1, float* m, float* phi, int ny, int nx,
+                 double h, const gp_opts* o, gp_report* rep, ws_report* wrep) {
+  if (!c || !net) return GP_EINVAL;
+  const double t0 = now_s();
+  if (!rho0 || !rho1 || !m || !o) {
+    set_err(c, "NULL argument");
+    return GP_EINVAL;
+  }
+  RCHK(check_size(c, ny, nx, h));
+  int H, W, B;
+  wsi::native(net, &H, &W, &B);
+  const int f = ny / H;
+  if (ny % H || nx % W || nx / W != f || (f & (f - 1))) {
+    set_err(c, "grid %dx%d is not a power-of-two multiple of the network's %dx%d", ny, nx, H, W);
+    return GP_EUNSUPPORTED;
+  }
+  const size_t n = size_t(ny) * nx, nc = size_t(H) * W;
+  const size_t need = 3 * nc + n;
+  if (c->wsbuf_floats < need) {
+    if (c->wsbuf) (void)hipFree(c->wsbuf);
+    c->wsbuf = nullptr;
+    c->wsbuf_floats = 0;
+    if (hipMalloc(&c->wsbuf, need * sizeof(float)) != hipSuccess) {
+      set_err(c, "warm-start scratch allocation failed");
+      return GP_ENOMEM;
+    }
+    c->wsbuf_floats = need;
+  }
+  float* phi0 = phi ? phi : c->wsbuf + 3 * nc;
+  const float *c0 = rho0, *c1 = rho1;
+  float* cphi = f > 1 ? c->wsbuf + 2 * nc : phi0;
+  if (f > 1) {
+    if (wsi::downsample(c->stream, rho0, ny, nx, f, c->wsbuf) || wsi::downsample(c->stream, rho1, ny, nx, f,
+                                                                                 c->wsbuf + nc)) {
+      set_err(c, "downsample launch failed");
+      return GP_EHIP;
+    }
+    c0 = c->wsbuf;
+    c1 = c->wsbuf + nc;
+  }
+  WSCHK(c, net, wsi::predict(net, c->stream, c0, c1, 1, cphi));
+  if (f > 1 && wsi::upsample(c->stream, cphi, H, W, f, phi0)) {
+    set_err(c, "upsample launch failed");
+    return GP_EHIP;
+  }
+  // D(phi0): the certificate of the prediction itself
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL(k_phi_cert, dim3(nb), dim3(256), 0, c->stream, phi0, rho0, rho1, ny, nx, 1.0 / h, o->norm,
+                     c->partials);
+  LAUNCHCHK(c);
+  double r[2];
+  RCHK(finalize_read(c, c->partials, nb, 1, 2, 2u, r));
+  ws_report w{};
+  w.d0 = h * h * r[0] / (r[1] > 1.0 ? r[1] : 1.0);
+  w.seconds_predict = now_s() - t0;
+  gp_report r1{};
+  int rc = GP_ENOTCONV;
+  if (w.d0 > 0.0 && std::isfinite(w.d0)) {
+    gp_opts ow = *o;
+    ow.warm_start = 1;
+    rc = emd_solve(c, rho0, rho1, m, phi0, ny, nx, h, &ow, &r1);
+    if (rc != GP_OK && rc != GP_ENOTCONV) return rc;
+    w.warm_iters = r1.iters;
+    w.used_warm = rc == GP_OK;
+  }
+  if (!w.used_warm) {
+    gp_opts op = *o;
+    op.warm_start = 0;
+    w.fallback = 1;
+    rc = emd_solve(c, rho0, rho1, m, phi, ny, nx, h, &op, &r1);
+    if (rc != GP_OK && rc != GP_ENOTCONV) return rc;
+  }
+  w.seconds_total = now_s() - t0;
+  if (rep) *rep = r1;
+  if (wrep) *wrep = w;
+  return rc;
 }
 
 int gp_profile(gp_ctx* c, int enable) {

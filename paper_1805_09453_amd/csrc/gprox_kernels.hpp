@@ -326,10 +326,12 @@ __global__ __launch_bounds__(256) void k_rof_energy(const float* __restrict__ u,
 // r = s div v (s = +-1/h); T = float or double output
 template <class T>
 __global__ __launch_bounds__(256) void k_div(const float* __restrict__ vx, const float* __restrict__ vy,
-                                             T* __restrict__ r, int ny, int nx, int nyi, float s) {
+                                             T* __restrict__ r, int ny, int nx, int nyi, float s,
+                                             const int* __restrict__ active) {
   const size_t n = size_t(ny) * nx;
   for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
     const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    if (!inst_active(active, i / nyi)) continue;
     const int il = i % nyi;
     const float xr = (j < nx - 1) ? vx[o] : 0.f;
     const float xl = (j > 0) ? vx[o - 1] : 0.f;
@@ -368,6 +370,24 @@ __global__ __launch_bounds__(256) void k_emd_cert(const double* __restrict__ phi
   }
   const bool m[2] = {false, true};
   block_reduce_store<2>(acc, m, partials + size_t(blockIdx.y) * gridDim.x * 2);
+}
+
+// certificate of a given FP32 potential phi: [sum phi (rho0 - rho1), max |grad_h phi|]
+__global__ __launch_bounds__(256) void k_phi_cert(const float* __restrict__ phi, const float* __restrict__ r0,
+                                                  const float* __restrict__ r1, int ny, int nx, double inv_h,
+                                                  int aniso, double* __restrict__ partials) {
+  double acc[2] = {0, 0};
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const double fc = phi[o];
+    const double gx = (j < nx - 1) ? (double(phi[o + 1]) - fc) * inv_h : 0.0;
+    const double gy = (i < ny - 1) ? (double(phi[o + nx]) - fc) * inv_h : 0.0;
+    acc[0] += fc * (double(r0[o]) - double(r1[o]));
+    acc[1] = fmax(acc[1], aniso ? fmax(fabs(gx), fabs(gy)) : sqrt(gx * gx + gy * gy));
+  }
+  const bool m[2] = {false, true};
+  block_reduce_store<2>(acc, m, partials);
 }
 
 // out = s * in

@@ -22,7 +22,7 @@ def lib():
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?(?:long\s+long|\w+)\**\s+\**(\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -54,6 +54,15 @@ def test_strerror_and_null_arguments(lib):
     assert lib.pd_step(None, None, 1) == -1
     assert lib.pd_gap(None, None, None) == -1
     assert lib.rof_solve(None, None, None, None, 64, 64, 1.0, 8.0, None, None) == -1
+
+
+def test_warm_start_blob_size_matches_the_oracle_network(lib):
+    from oracle import unet
+    assert lib.ws_param_count() == unet.n_params() == 1925313
+    assert lib.ws_create(None, None, 1, 64, 64) == -1
+    assert lib.ws_destroy(None) == 0
+    assert lib.ws_emd_solve(None, None, None, None, None, None, 64, 64, 1.0, None, None, None) == -1
+    assert lib.gp_batch_solve(None, None, 1, None, None) == -1
 
 
 def test_unsupported_sizes_rejected_before_allocation(lib):

@@ -19,7 +19,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 def dev(a):
     import torch
-    return torch.tensor(np.asarray(a, dtype=np.float32), device="cuda")
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
 
 
 def host(t):
@@ -128,3 +128,22 @@ def test_batch_max_iter_and_errors(gpctx):
     with pytest.raises(GPError) as e:
         gpctx.batch_solve([odd], Options(tau=0.3))
     assert e.value.code == GP_EUNSUPPORTED
+
+
+def test_batch_emd_potential_output_equals_single_solve(gpctx):
+    """The optional per-instance potential (the scaled certificate of the final
+    dual) equals emd_solve's phi, also for instances that retire early while
+    others keep running."""
+    import torch
+    from paper_1805_09453_amd import Options
+    probs = [emd_problem(64, 21, 0.3), emd_problem(64, 22, 0.3, k=8), emd_problem(128, 23, 0.3)]
+    for q in probs:
+        q["phi"] = torch.empty_like(q["rho0"])
+    opts = Options(tau=0.3, tol=1e-4, max_iter=4000, check_every=20)
+    announce("gp_batch_solve EMD potentials")
+    outs, reps, _ = gpctx.batch_solve(probs, opts)
+    for i, q in enumerate(probs):
+        m, phi, rep = gpctx.emd_solve(q["rho0"], q["rho1"], q["h"], opts)
+        print(i, reps[i]["iters"], rep["iters"])
+        assert reps[i]["iters"] == rep["iters"]
+        assert torch.equal(outs[i], m) and torch.equal(q["phi"], phi)

@@ -22,7 +22,7 @@ def f32(a):
 
 def dev(a):
     import torch
-    return torch.tensor(np.asarray(a, dtype=np.float32), device="cuda")
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
 
 
 def host(t):
