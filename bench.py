@@ -8,7 +8,9 @@ piecewise-constant 4096x4096 image, 50 shapes, sigma 0.1 noise, lambda 8 per
 pixel); the EMD workload (16-Gaussian mixtures, 4096x4096, h = 1/4096) is
 reported beside it, and so is a mixed batch of 512 ROF/EMD instances of sides
 64..1024 solved together (aggregate pixel-iterations/s over the solve loop and
-p50/p99 per-instance time to tolerance).  Prints ONE JSON line.
+p50/p99 per-instance time to tolerance), and the EMD time to a 1e-5 relative gap
+at 4096x4096 from the zero start and from the learned warm start.  Prints ONE
+JSON line.
 """
 import argparse
 import hashlib
@@ -36,6 +38,9 @@ def parse():
     ap.add_argument("--solve", action="store_true", help="also time full solves to --tol")
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched mixed-instance leg")
+    ap.add_argument("--no-warm", action="store_true", help="skip the plain-vs-learned EMD time-to-tolerance leg")
+    ap.add_argument("--warm-tol", type=float, default=1e-5)
+    ap.add_argument("--warm-max-iter", type=int, default=60000)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-tol", type=float, default=1e-4)
     ap.add_argument("--batch-max-iter", type=int, default=5000)
@@ -144,6 +149,38 @@ def batch_leg(ctx, dev, count, tol, max_iter):
             "groups": per}
 
 
+def warm_leg(ctx, r0, r1, n, tol, max_iter):
+    """EMD time to `tol` on the same n x n pair: plain zero start vs the learned
+    warm start (8x block mean -> network at 512^2 -> bilinear potential, certificate
+    check, fallback), each timed whole."""
+    import numpy as np
+    import torch
+
+    from paper_1805_09453_amd import Options, WarmStart
+    wpath = os.path.join(ROOT, "paper_1805_09453_amd", "weights", "ws_unet_512.f32")
+    if not os.path.exists(wpath):
+        return {"skipped": "no trained weights"}
+    ws = WarmStart(ctx, 1, 512, 512)
+    ws.set_params(torch.tensor(np.fromfile(wpath, dtype="<f4"), device="cuda"))
+    opts = Options(tau=0.3, tol=tol, max_iter=max_iter, check_every=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, rp = ctx.emd_solve(r0, r1, 1.0 / n, opts, want_phi=False)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, rw, wr = ws.emd_solve(r0, r1, 1.0 / n, opts)
+    torch.cuda.synchronize()
+    tw = time.perf_counter() - t0
+    ws.close()
+    return {"grid": [n, n], "tol": tol, "plain": {"seconds": tp, "iters": rp["iters"], "rel_gap": rp["rel_gap"],
+                                                  "converged": bool(rp["converged"])},
+            "warm": {"seconds": tw, "iters": rw["iters"], "rel_gap": rw["rel_gap"], "converged": bool(rw["converged"]),
+                     "fallback": wr["fallback"], "warm_iters": wr["warm_iters"], "d0": wr["d0"],
+                     "seconds_predict": wr["seconds_predict"]},
+            "speedup": tp / tw if tw > 0 else None}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -239,6 +276,8 @@ def main():
                                                                 check_every=50), want_phi=False)
             torch.cuda.synchronize()
             extra["emd"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
+    if not args.no_warm and not args.no_emd:
+        extra["warm_start"] = warm_leg(ctx, r0, r1, n, args.warm_tol, args.warm_max_iter)
     if not args.no_batch:
         extra["batch"] = batch_leg(ctx, dev, args.batch_count, args.batch_tol, args.batch_max_iter)
     ctx.close()
