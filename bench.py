@@ -146,7 +146,9 @@ def batch_leg(ctx, dev, count, tol, max_iter):
             "setup_s": reps[0]["seconds_setup"], "wall_s": wall,
             "converged": int(sum(r["converged"] for r in reps)),
             "time_to_tol_p50_s": float(np.percentile(tt, 50)), "time_to_tol_p99_s": float(np.percentile(tt, 99)),
-            "groups": per}
+            "groups": per,
+            "tuned_shapes": {f"{'f64' if fp else 'f32'}_{n}": list(ctx.get_shape(fp, n))
+                             for fp in (False, True) for n in sorted({q["n"] for q in insts})}}
 
 
 def warm_leg(ctx, r0, r1, n, tol, max_iter):

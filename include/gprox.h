@@ -176,6 +176,20 @@ typedef struct {
  * the first instance with unequal masses in gp_last_error). */
 int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opts* opts, gp_report* reps);
 
+/* Launch shapes (a performance setting; results do not depend on it).  Each
+ * DCT pass runs FFT groups of N/32 threads, one per row pair (row passes) or
+ * column pair (column pass); these calls read or set how many groups share a
+ * workgroup for transforms of length n in FP32 (fp64 = 0: the ROF path and
+ * dct_poisson) or FP64 (fp64 = 1: the EMD path and dct_poisson_f64).  The
+ * column setting also fixes the strip width of the intermediate layout.
+ * gp_batch_solve measures the candidates on first use of a size and keeps the
+ * fastest (an autotuner); gp_set_shape fixes a choice (0 leaves a setting
+ * unchanged) and exempts it from tuning.  Row groups must be a multiple of
+ * max(1, 2048/n) (whole waves) with at most 256 threads; column groups a power
+ * of two within the LDS and 512-thread limits; GP_EINVAL otherwise. */
+int gp_get_shape(gp_ctx* ctx, int fp64, int n, int* row_groups, int* col_groups);
+int gp_set_shape(gp_ctx* ctx, int fp64, int n, int row_groups, int col_groups);
+
 /* ---------------------------------------------------------------- learned warm start
  * Not part of the paper.  A U-Net predicts the dual potential phi0 of the EMD
  * problem from (rho0, rho1); the iteration of section 3.2 then starts from

@@ -55,6 +55,11 @@ struct gp_ctx {
   hipEvent_t fork_ev = nullptr;
   int max_ny = 0, max_nx = 0;
   Tables tab[13];            // index log2 N
+  // launch shapes per [FP32, FP64][log2 N]: FFT groups per block of the row
+  // passes (row pairs) and of the column pass (column pairs = half the strip
+  // width of the tiled intermediate); defaults, or measured by the autotuner
+  int row_g[2][13] = {}, col_g[2][13] = {};
+  bool row_tuned[2][13] = {}, col_tuned[2][13] = {};
   float* work = nullptr;     // [max_n] FP32 tiled intermediate
   float* work2 = nullptr;    // [2 max_n] EMD stored field (ping)
   float* work3 = nullptr;    // [2 max_n] EMD stored field (pong)
@@ -249,15 +254,51 @@ int set_mu(gp_ctx* c, int ny, int nx, double h) {
 }
 
 // ---------------------------------------------------------------- launchers
-// log2 of the strip width of the tiled intermediate, fixed by the column pass over ny
-template <class C> int col_lgtw(int ny) {
-  switch (ny) {
-#define GP_TW(NN) case NN: return ilog2i(2 * ColShape<NN, C>::G);
-    GP_TW(64) GP_TW(128) GP_TW(256) GP_TW(512) GP_TW(1024) GP_TW(2048) GP_TW(4096)
-#undef GP_TW
+// shape limits per transform length and precision
+struct ShapeInfo {
+  int T = 0;                 // threads per FFT group
+  int row_def = 0, row_gm = 1, row_gmax = 0;
+  int col_def = 0, col_gmax = 0;
+  size_t group_lds = 0;      // LDS bytes per group
+};
+template <class C> ShapeInfo shape_info(int n) {
+  ShapeInfo i;
+  switch (n) {
+#define GP_SI(NN)                                                                                       \
+  case NN:                                                                                              \
+    i.T = Sched<NN>::T;                                                                                 \
+    i.row_def = RowShape<NN, C>::G;                                                                     \
+    i.row_gm = RowShape<NN, C>::GM;                                                                     \
+    i.row_gmax = RowShape<NN, C>::GMAX;                                                                 \
+    i.col_def = ColShape<NN, C>::G;                                                                     \
+    i.col_gmax = ColShape<NN, C>::MAXTHREADS / Sched<NN>::T;                                            \
+    i.group_lds = RowShape<NN, C>::GROUP_LDS;                                                           \
+    break;
+    GP_SI(64) GP_SI(128) GP_SI(256) GP_SI(512) GP_SI(1024) GP_SI(2048) GP_SI(4096)
+#undef GP_SI
   }
-  return 0;
+  return i;
 }
+template <class C> constexpr int prec() { return sizeof(C) == sizeof(double2) ? 1 : 0; }
+
+void init_shapes(gp_ctx* c) {
+  for (int ln = 6; ln <= 12; ++ln) {
+    const ShapeInfo a = shape_info<float2>(1 << ln), b = shape_info<double2>(1 << ln);
+    c->row_g[0][ln] = a.row_def;
+    c->col_g[0][ln] = a.col_def;
+    c->row_g[1][ln] = b.row_def;
+    c->col_g[1][ln] = b.col_def;
+  }
+}
+
+// column pairs per column-pass block for columns of length ny in a grid nx wide
+// (the strip width 2G may not exceed nx)
+template <class C> int col_groups(const gp_ctx* c, int ny, int nx) {
+  const int G = c->col_g[prec<C>()][ilog2i(ny)];
+  return 2 * G > nx ? nx / 2 : G;
+}
+// log2 of the strip width of the tiled intermediate, fixed by the column pass
+template <class C> int col_lgtw(const gp_ctx* c, int ny, int nx) { return ilog2i(2 * col_groups<C>(c, ny, nx)); }
 
 template <class C> const C* tw_of(const Tables& T);
 template <> const float2* tw_of<float2>(const Tables& T) { return T.tw32; }
@@ -282,27 +323,27 @@ template <class C> struct Pass {
   using Re = typename Cx<C>::R;
   template <int N> struct At {
     static void rows_fwd(gp_ctx* c, const Re* in, Re* out, int nyi, int m, const int* active) {
-      using SH = RowShape<N, C>;
-      const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
+      const int G = c->row_g[prec<C>()][ilog2i(N)];
+      const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
       const Tables& T = c->tab[ilog2i(N)];
-      hipLaunchKernelGGL((k_rows_fwd<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, in, out,
-                         ny, nyi, active, col_lgtw<C>(nyi), tw_of<C>(T), dw_of<C>(T));
+      hipLaunchKernelGGL((k_rows_fwd<N, C>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, C>::GROUP_LDS),
+                         c->stream, in, out, ny, nyi, active, col_lgtw<C>(c, nyi, N), tw_of<C>(T), dw_of<C>(T));
     }
     static void rows_inv(gp_ctx* c, const Re* in, Re* out, int nyi, int m, const int* active) {
-      using SH = RowShape<N, C>;
-      const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
+      const int G = c->row_g[prec<C>()][ilog2i(N)];
+      const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
       const Tables& T = c->tab[ilog2i(N)];
-      hipLaunchKernelGGL((k_rows_inv<N, C>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, in, out,
-                         ny, nyi, active, col_lgtw<C>(nyi), tw_of<C>(T), dw_of<C>(T));
+      hipLaunchKernelGGL((k_rows_inv<N, C>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, C>::GROUP_LDS),
+                         c->stream, in, out, ny, nyi, active, col_lgtw<C>(c, nyi, N), tw_of<C>(T), dw_of<C>(T));
     }
     // here N is the column length nyi
     static void cols(gp_ctx* c, Re* buf, int nx, int m, const int* active, const Re* mux, const Re* muy, Re alpha,
                      Re inv_nn) {
-      using SH = ColShape<N, C>;
-      const int blocks = (nx / 2 + SH::G - 1) / SH::G;
+      const int G = col_groups<C>(c, N, nx);
+      const int blocks = (nx / 2 + G - 1) / G;
       const Tables& T = c->tab[ilog2i(N)];
-      hipLaunchKernelGGL((k_cols_solve<N, C>), dim3(blocks, m), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, buf,
-                         nx, active, tw_of<C>(T), dw_of<C>(T), mux, muy, alpha, inv_nn);
+      hipLaunchKernelGGL((k_cols_solve<N, C>), dim3(blocks, m), dim3(G * Sched<N>::T), (G * ColShape<N, C>::GROUP_LDS),
+                         c->stream, buf, nx, active, tw_of<C>(T), dw_of<C>(T), mux, muy, alpha, inv_nn);
     }
   };
 };
@@ -313,29 +354,29 @@ template <int N> struct Fused {
   static void rof_A(gp_ctx* c, const float* u, const float* pin, float* pout, const float* I, float* rhat, int nyi,
                     int m, const int* active, float lt, float tau_h, float sig_h, int aniso, int mode,
                     double* partials) {
-    using SH = RowShape<N, float2>;
-    const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
+    const int G = c->row_g[0][ilog2i(N)];
+    const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_rof_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, u, pin, pout, I,
-                       rhat, ny, nyi, active, col_lgtw<float2>(nyi), lt, tau_h, sig_h, aniso, mode, partials, T.tw32,
-                       T.dw32);
+    hipLaunchKernelGGL((k_rof_A<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
+                       c->stream, u, pin, pout, I, rhat, ny, nyi, active, col_lgtw<float2>(c, nyi, N), lt, tau_h, sig_h,
+                       aniso, mode, partials, T.tw32, T.dw32);
   }
   static void rof_B(gp_ctx* c, const float* dhat, float* u, int nyi, int m, const int* active) {
-    using SH = RowShape<N, float2>;
-    const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
+    const int G = c->row_g[0][ilog2i(N)];
+    const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_rof_B<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, dhat, u, ny, nyi,
-                       active, col_lgtw<float2>(nyi), T.tw32, T.dw32);
+    hipLaunchKernelGGL((k_rof_B<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
+                       c->stream, dhat, u, ny, nyi, active, col_lgtw<float2>(c, nyi, N), T.tw32, T.dw32);
   }
   static void emd_A(gp_ctx* c, const float* wt_in, const double* phi, const float* pin, const float* gpsi,
                     const float* f, float* pout, float* wt_out, double* rhat, int nyi, int m, const int* active,
                     double inv_h, float tau, float sigma, int aniso, int mode, double* partials) {
-    using SH = RowShape<N, double2>;
-    const int ny = nyi * m, blocks = (ny / 2 + SH::G - 1) / SH::G;
+    const int G = c->row_g[1][ilog2i(N)];
+    const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_emd_A<N>), dim3(blocks), dim3(SH::THREADS), SH::LDS_BYTES, c->stream, wt_in, phi, pin,
-                       gpsi, f, pout, wt_out, rhat, ny, nyi, active, col_lgtw<double2>(nyi), inv_h, tau, sigma, aniso,
-                       mode, partials, T.tw64, T.dw64);
+    hipLaunchKernelGGL((k_emd_A<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, double2>::GROUP_LDS),
+                       c->stream, wt_in, phi, pin, gpsi, f, pout, wt_out, rhat, ny, nyi, active,
+                       col_lgtw<double2>(c, nyi, N), inv_h, tau, sigma, aniso, mode, partials, T.tw64, T.dw64);
   }
 };
 
@@ -708,6 +749,92 @@ int validate_state(gp_ctx* c, const gp_state* s) {
   return prepare(c, s->ny, s->nx, s->h);
 }
 
+// ---------------------------------------------------------------- autotuner
+// median time (ms) of `reps` runs of launch() on the context stream, after one warm-up
+template <class F> double time_ms(gp_ctx* c, F&& launch, int reps = 3) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return 1e30;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return 1e30;
+  }
+  launch();
+  std::vector<float> ts;
+  for (int r = 0; r < reps; ++r) {
+    float ms = 1e30f;
+    if (hipEventRecord(a, c->stream) == hipSuccess) {
+      launch();
+      if (hipEventRecord(b, c->stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess)
+        (void)hipEventElapsedTime(&ms, a, b);
+    }
+    ts.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::sort(ts.begin(), ts.end());
+  return (hipGetLastError() == hipSuccess) ? ts[ts.size() / 2] : 1e30;
+}
+
+// Chooses the launch shapes of one batch group's kernels by measurement: the
+// column pass over its own intermediate (column pairs per block, which also fixes
+// the strip width of the tiled layout) and the fused row pass (row pairs per
+// block) in its entry form, which reads the state and writes only scratch.
+// Results are cached per precision and transform length in the context.
+int tune_group(gp_ctx* c, const Group& g) {
+  const bool f64 = g.kind == GP_KIND_EMD;
+  const int di = f64 ? 1 : 0, ly = ilog2i(g.nyi), lx = ilog2i(g.nx);
+  const ShapeInfo sy = f64 ? shape_info<double2>(g.nyi) : shape_info<float2>(g.nyi);
+  const ShapeInfo sx = f64 ? shape_info<double2>(g.nx) : shape_info<float2>(g.nx);
+  const bool prof = c->prof_on;
+  c->prof_on = false;
+  if (!c->col_tuned[di][ly]) {
+    double best = 1e30;
+    int bestg = c->col_g[di][ly];
+    for (int G = 2; G <= sy.col_gmax && 2 * G <= g.nx; G *= 2) {
+      c->col_g[di][ly] = G;
+      const double t = time_ms(c, [&] {
+        if (f64) {
+          GP_DISPATCH_NM(g.nyi, P64, cols, c, g.rhat64, g.nx, g.m, nullptr, g.mux64, g.muy64, 0.0,
+                         1.0 / (double(g.nyi) * g.nx));
+        } else {
+          GP_DISPATCH_NM(g.nyi, P32, cols, c, g.rhat, g.nx, g.m, nullptr, g.mux32, g.muy32, float(g.lambda * g.tau),
+                         float(1.0 / (double(g.nyi) * g.nx)));
+        }
+      });
+      if (t < best) {
+        best = t;
+        bestg = G;
+      }
+    }
+    c->col_g[di][ly] = bestg;
+    c->col_tuned[di][ly] = true;
+  }
+  if (!c->row_tuned[di][lx]) {
+    double best = 1e30;
+    int bestg = c->row_g[di][lx];
+    for (int G = sx.row_gm; G <= sx.row_gmax; G *= 2) {
+      c->row_g[di][lx] = G;
+      const double t = time_ms(c, [&] {
+        if (f64) {
+          EmdPipe P{c, &g, g.p, g.pbar, g.w0, g.w1};
+          (void)emd_A(P, 1, false);
+        } else {
+          RofPipe P{c, &g, g.p, g.pbar};
+          (void)rof_A(P, 1, false);
+        }
+      });
+      if (t < best) {
+        best = t;
+        bestg = G;
+      }
+    }
+    c->row_g[di][lx] = bestg;
+    c->row_tuned[di][lx] = true;
+  }
+  c->prof_on = prof;
+  return hipGetLastError() == hipSuccess ? GP_OK : GP_EHIP;
+}
+
 // ---------------------------------------------------------------- batch
 struct BatchGroup {
   Group g;
@@ -796,6 +923,7 @@ int gp_create(gp_ctx** out, int max_ny, int max_nx, void* stream) {
   gp_ctx* c = new (std::nothrow) gp_ctx();
   if (!c) return GP_ENOMEM;
   c->stream = static_cast<hipStream_t>(stream);
+  init_shapes(c);
   c->max_ny = max_ny;
   c->max_nx = max_nx;
   const size_t n = size_t(max_ny) * max_nx;
@@ -1246,6 +1374,14 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     RCHK(fill_mu(c, bg.mu64, bg.mu32, bg.mu64 + g.nyi, bg.mu32 + g.nyi, g.nyi, g.nx, g.h));
     HIPCHK(c, hipStreamSynchronize(c->stream));  // `ones` leaves scope
   }
+  // ---- launch shapes: measured per precision and size on first use
+  for (auto& bg : G) {
+    if (tune_group(c, bg.g)) {
+      set_err(c, "autotuning launch failed");
+      return GP_EHIP;
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   // ---- pipelines: the entry step eagerly, then one captured chunk of C iterations
   std::vector<RofPipe> rp(G.size());
   std::vector<EmdPipe> ep(G.size());
@@ -1452,6 +1588,42 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     }
   }
   return restore(all_conv ? GP_OK : GP_ENOTCONV);
+}
+
+int gp_get_shape(gp_ctx* c, int fp64, int n, int* row_groups, int* col_groups) {
+  if (!c || !is_pow2_in_range(n)) return c ? GP_EUNSUPPORTED : GP_EINVAL;
+  const int di = fp64 ? 1 : 0, ln = ilog2i(n);
+  if (row_groups) *row_groups = c->row_g[di][ln];
+  if (col_groups) *col_groups = c->col_g[di][ln];
+  return GP_OK;
+}
+
+int gp_set_shape(gp_ctx* c, int fp64, int n, int row_groups, int col_groups) {
+  if (!c) return GP_EINVAL;
+  if (!is_pow2_in_range(n)) {
+    set_err(c, "n must be a power of two in [%d, %d]", kMinN, kMaxN);
+    return GP_EUNSUPPORTED;
+  }
+  const int di = fp64 ? 1 : 0, ln = ilog2i(n);
+  const ShapeInfo si = fp64 ? shape_info<double2>(n) : shape_info<float2>(n);
+  if (row_groups && (row_groups < si.row_gm || row_groups > si.row_gmax || row_groups % si.row_gm)) {
+    set_err(c, "row groups %d invalid for n=%d (multiples of %d up to %d)", row_groups, n, si.row_gm, si.row_gmax);
+    return GP_EINVAL;
+  }
+  if (col_groups && (col_groups < 1 || col_groups > si.col_gmax || (col_groups & (col_groups - 1)))) {
+    set_err(c, "column groups %d invalid for n=%d (powers of two up to %d)", col_groups, n, si.col_gmax);
+    return GP_EINVAL;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (row_groups) {
+    c->row_g[di][ln] = row_groups;
+    c->row_tuned[di][ln] = true;
+  }
+  if (col_groups) {
+    c->col_g[di][ln] = col_groups;
+    c->col_tuned[di][ln] = true;
+  }
+  return GP_OK;
 }
 
 // ---------------------------------------------------------------- learned warm start

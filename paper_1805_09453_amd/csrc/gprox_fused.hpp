@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
   float2* smem = reinterpret_cast<float2*>(smem_raw);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   float2* lds = smem + g * Sched<N>::LDS;
-  const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
+  const int a = 2 * (blockIdx.x * int(blockDim.x / T) + g), b = a + 1;
   const bool valid = a < ny && inst_active(active, a / nyi);  // nyi is even
   const size_t n = size_t(ny) * N;
   const float* pinx = pin;
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, f
   float2* smem = reinterpret_cast<float2*>(smem_raw);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   float2* lds = smem + g * Sched<N>::LDS;
-  const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
+  const int a = 2 * (blockIdx.x * int(blockDim.x / T) + g), b = a + 1;
   const bool valid = a < ny && inst_active(active, a / nyi);
   float* ua = u + size_t(valid ? a : 0) * N;
   float* ub = u + size_t(valid ? b : 0) * N;
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
   double2* smem = reinterpret_cast<double2*>(smem_raw);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   double2* lds = smem + g * Sched<N>::LDS;
-  const int a = 2 * (blockIdx.x * SH::G + g), b = a + 1;
+  const int a = 2 * (blockIdx.x * int(blockDim.x / T) + g), b = a + 1;
   const bool valid = a < ny && inst_active(active, a / nyi);
   const size_t n = size_t(ny) * N;
   double acc[1] = {0};

@@ -15,24 +15,35 @@
 namespace gp {
 
 // ------------------------------------------------------------ launch shapes
+// Launch shapes.  The number of FFT groups per block is a launch-time choice
+// (blockDim.x / T): the defaults below, or what the library's autotuner
+// measured best; the limits keep blocks within 256 threads (row passes, whole
+// waves) or 512 threads (column pass), and within the CU's 160 KB of LDS.
 template <int N, class C> struct RowShape {
   static constexpr int T = Sched<N>::T;
+  static constexpr size_t GROUP_LDS = size_t(Sched<N>::LDS) * sizeof(C);
   static constexpr int G1 = 256 / T;
-  static constexpr int G2 = int(147456 / (size_t(Sched<N>::LDS) * sizeof(C)));
+  static constexpr int G2 = int(147456 / GROUP_LDS);
   static constexpr int G3 = G1 < G2 ? G1 : G2;
   // whole 64-lane waves (the fused kernels reduce across waves)
   static constexpr int GM = T >= 64 ? 1 : 64 / T;
-  static constexpr int G = (G3 / GM) * GM;  // row pairs per block
+  static constexpr int G = (G3 / GM) * GM;  // default row pairs per block
+  static constexpr int GMAX = G;            // largest allowed (256 threads)
   static constexpr int THREADS = G * T;
   static_assert(G >= 1 && THREADS % 64 == 0 && THREADS <= 256, "row-pass shape");
-  static constexpr size_t LDS_BYTES = size_t(G) * Sched<N>::LDS * sizeof(C);
+  static constexpr size_t LDS_BYTES = size_t(G) * GROUP_LDS;
 };
 template <int N, class C> struct ColShape {
   static constexpr int T = Sched<N>::T;
-  static constexpr int G0 = int(147456 / (size_t(Sched<N>::LDS) * sizeof(C)));
-  static constexpr int G = G0 > 16 ? 16 : (G0 < 1 ? 1 : G0);  // column pairs per block
+  static constexpr size_t GROUP_LDS = size_t(Sched<N>::LDS) * sizeof(C);
+  static constexpr int G0 = int(147456 / GROUP_LDS);
+  static constexpr int G = G0 > 16 ? 16 : (G0 < 1 ? 1 : G0);  // default column pairs per block
+  static constexpr int GL = int(163840 / GROUP_LDS) < 512 / T ? int(163840 / GROUP_LDS) : 512 / T;
+  static constexpr int GL2 = GL > 64 ? 64 : GL;
+  static constexpr int GMAX = GL2 >= 64 ? 64 : GL2 >= 32 ? 32 : GL2 >= 16 ? 16 : GL2 >= 8 ? 8 : GL2 >= 4 ? 4 : GL2 >= 2 ? 2 : 1;
   static constexpr int THREADS = T * G;
-  static constexpr size_t LDS_BYTES = size_t(G) * Sched<N>::LDS * sizeof(C);
+  static constexpr int MAXTHREADS = T * (GMAX > G ? GMAX : G);
+  static constexpr size_t LDS_BYTES = size_t(G) * GROUP_LDS;
   // FP32: keep to 256 registers so two workgroups fit a CU; FP64 needs more
   static constexpr int MINW = sizeof(C) == 8 ? 2 : 1;
 };
@@ -68,7 +79,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, t
   C* smem = reinterpret_cast<C*>(smem_raw);
   const int g = threadIdx.x / SH::T, t = threadIdx.x % SH::T;
   C* lds = smem + g * Sched<N>::LDS;
-  const int ra = 2 * (blockIdx.x * SH::G + g), rb = ra + 1;
+  const int ra = 2 * (blockIdx.x * int(blockDim.x / SH::T) + g), rb = ra + 1;
   const bool va = ra < ny && inst_active(active, ra / nyi), vb = va && rb < ny;
   const Re* pa = in + size_t(va ? ra : 0) * ld;
   const Re* pb = in + size_t(vb ? rb : 0) * ld;
@@ -99,7 +110,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, t
   C* smem = reinterpret_cast<C*>(smem_raw);
   const int g = threadIdx.x / SH::T, t = threadIdx.x % SH::T;
   C* lds = smem + g * Sched<N>::LDS;
-  const int ra = 2 * (blockIdx.x * SH::G + g), rb = ra + 1;
+  const int ra = 2 * (blockIdx.x * int(blockDim.x / SH::T) + g), rb = ra + 1;
   const bool va = ra < ny && inst_active(active, ra / nyi), vb = va && rb < ny;
   C v[32];
 #pragma unroll
@@ -121,7 +132,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, t
 // columns per FFT group; consecutive lanes take consecutive column pairs so
 // every row access of a wave covers G*2 contiguous values.
 template <int N, class C>
-__global__ __launch_bounds__((ColShape<N, C>::THREADS), (ColShape<N, C>::MINW)) void k_cols_solve(
+__global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW)) void k_cols_solve(
     typename Cx<C>::R* buf, int nx, const int* __restrict__ active, const C* __restrict__ tw,
     const C* __restrict__ dctw, const typename Cx<C>::R* __restrict__ mux,
     const typename Cx<C>::R* __restrict__ muy, typename Cx<C>::R alpha, typename Cx<C>::R inv_nn) {
@@ -131,7 +142,8 @@ __global__ __launch_bounds__((ColShape<N, C>::THREADS), (ColShape<N, C>::MINW)) 
   buf += size_t(blockIdx.y) * N * nx;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* smem = reinterpret_cast<C*>(smem_raw);
-  const int g = threadIdx.x % SH::G, t = threadIdx.x / SH::G;
+  const int G = blockDim.x / SH::T;  // column pairs per block: strip width 2G
+  const int g = threadIdx.x % G, t = threadIdx.x / G;
   C* lds = smem + g * Sched<N>::LDS;
   // XCD-aware strip order: workgroups are dealt round-robin to the 8 XCDs, so
   // give each XCD a contiguous run of strips; strips that share cache lines
@@ -139,11 +151,11 @@ __global__ __launch_bounds__((ColShape<N, C>::THREADS), (ColShape<N, C>::MINW)) 
   const int nstrip = gridDim.x, b = blockIdx.x;
   const int strip = (nstrip % 8 == 0) ? (b % 8) * (nstrip / 8) + b / 8 : b;
   // this block's strip of TW = 2G columns is contiguous (tile_idx layout)
-  constexpr int TW = 2 * SH::G;
+  const int TW = 2 * G;
   const int c = strip * TW + 2 * g;
   const bool valid = c < nx;
   Re* col = buf + (valid ? size_t(strip) * N * TW + 2 * g : 0);
-  constexpr int ld = TW;
+  const int ld = TW;
   C v[32];
   dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
     if (valid) {

@@ -147,3 +147,36 @@ def test_batch_emd_potential_output_equals_single_solve(gpctx):
         print(i, reps[i]["iters"], rep["iters"])
         assert reps[i]["iters"] == rep["iters"]
         assert torch.equal(outs[i], m) and torch.equal(q["phi"], phi)
+
+
+def test_launch_shapes_do_not_change_results(gpctx):
+    """Every FFT group computes the same arithmetic whatever the number of groups
+    per workgroup: solves under other row / column shapes are bit-identical."""
+    from paper_1805_09453_amd import GPError, Options
+    I = dev(synth.rof_scene(256, 31))
+    r0, r1 = synth.emd_mixture_pair(128, 32, k=4)
+    r0, r1 = dev(r0), dev(r1)
+    o_rof = Options(tau=0.01, tol=0.0, max_iter=60, check_every=20)
+    o_emd = Options(tau=0.3, tol=0.0, max_iter=60, check_every=20)
+    saved = [gpctx.get_shape(False, 256), gpctx.get_shape(True, 128)]
+    announce("shape variants ROF 256x256 / EMD 128x128")
+    u0, p0, rep0 = gpctx.rof_solve(I, 1.0, 8.0, o_rof)
+    m0, phi0, rpe0 = gpctx.emd_solve(r0, r1, 1.0 / 128, o_emd)
+    try:
+        for rg, cg in ((8, 2), (32, 4), (16, 32)):
+            gpctx.set_shape(False, 256, rg, cg)
+            gpctx.set_shape(True, 128, 16, min(cg, 16))
+            print("shapes", gpctx.get_shape(False, 256), gpctx.get_shape(True, 128))
+            u, p, rep = gpctx.rof_solve(I, 1.0, 8.0, o_rof)
+            m, phi, rpe = gpctx.emd_solve(r0, r1, 1.0 / 128, o_emd)
+            assert rep["primal"] == rep0["primal"] and rep["dual"] == rep0["dual"]
+            np.testing.assert_array_equal(host(u), host(u0))
+            np.testing.assert_array_equal(host(m), host(m0))
+            np.testing.assert_array_equal(host(phi), host(phi0))
+        with pytest.raises(GPError):
+            gpctx.set_shape(False, 256, 3, 0)   # not a whole number of waves
+        with pytest.raises(GPError):
+            gpctx.set_shape(False, 256, 0, 3)   # not a power of two
+    finally:
+        gpctx.set_shape(False, 256, *saved[0])
+        gpctx.set_shape(True, 128, *saved[1])
