@@ -182,8 +182,9 @@ int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opt
  * workgroup for transforms of length n in FP32 (fp64 = 0: the ROF path and
  * dct_poisson) or FP64 (fp64 = 1: the EMD path and dct_poisson_f64).  The
  * column setting also fixes the strip width of the intermediate layout.
- * gp_batch_solve measures the candidates on first use of a size and keeps the
- * fastest (an autotuner); gp_set_shape fixes a choice (0 leaves a setting
+ * rof_solve, emd_solve and gp_batch_solve measure the candidates on first use
+ * of a size and keep the fastest (an autotuner; pd_step and dct_poisson use
+ * the current setting); gp_set_shape fixes a choice (0 leaves a setting
  * unchanged) and exempts it from tuning.  Row groups must be a multiple of
  * max(1, 2048/n) (whole waves) with at most 256 threads; column groups a power
  * of two within the LDS and 512-thread limits; GP_EINVAL otherwise. */

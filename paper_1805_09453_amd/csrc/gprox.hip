@@ -775,62 +775,61 @@ template <class F> double time_ms(gp_ctx* c, F&& launch, int reps = 3) {
   return (hipGetLastError() == hipSuccess) ? ts[ts.size() / 2] : 1e30;
 }
 
-// Chooses the launch shapes of one batch group's kernels by measurement: the
-// column pass over its own intermediate (column pairs per block, which also fixes
-// the strip width of the tiled layout) and the fused row pass (row pairs per
-// block) in its entry form, which reads the state and writes only scratch.
-// Results are cached per precision and transform length in the context.
+// Chooses the launch shapes of a group's kernels by measurement.  The column
+// setting also fixes the strip width of the tiled intermediate that the row
+// passes write and read, so the choice is joint: every (row groups, column
+// groups) pair is timed on one iteration's worth of transforms that touch only
+// scratch -- the fused row pass in its entry form (reads the state, writes the
+// intermediate), the column pass, and the row inverse in place on the
+// intermediate.  Results are cached per precision and transform length in the
+// context; shapes fixed with gp_set_shape are kept.
 int tune_group(gp_ctx* c, const Group& g) {
   const bool f64 = g.kind == GP_KIND_EMD;
   const int di = f64 ? 1 : 0, ly = ilog2i(g.nyi), lx = ilog2i(g.nx);
+  if (c->col_tuned[di][ly] && c->row_tuned[di][lx]) return GP_OK;
   const ShapeInfo sy = f64 ? shape_info<double2>(g.nyi) : shape_info<float2>(g.nyi);
   const ShapeInfo sx = f64 ? shape_info<double2>(g.nx) : shape_info<float2>(g.nx);
+  std::vector<int> cols, rows;
+  if (c->col_tuned[di][ly]) cols.push_back(c->col_g[di][ly]);
+  else
+    for (int G = 2; G <= sy.col_gmax && 2 * G <= g.nx; G *= 2) cols.push_back(G);
+  if (c->row_tuned[di][lx]) rows.push_back(c->row_g[di][lx]);
+  else
+    for (int G = sx.row_gm; G <= sx.row_gmax; G *= 2) rows.push_back(G);
+  if (cols.empty()) cols.push_back(c->col_g[di][ly]);
   const bool prof = c->prof_on;
   c->prof_on = false;
-  if (!c->col_tuned[di][ly]) {
-    double best = 1e30;
-    int bestg = c->col_g[di][ly];
-    for (int G = 2; G <= sy.col_gmax && 2 * G <= g.nx; G *= 2) {
-      c->col_g[di][ly] = G;
-      const double t = time_ms(c, [&] {
-        if (f64) {
-          GP_DISPATCH_NM(g.nyi, P64, cols, c, g.rhat64, g.nx, g.m, nullptr, g.mux64, g.muy64, 0.0,
-                         1.0 / (double(g.nyi) * g.nx));
-        } else {
-          GP_DISPATCH_NM(g.nyi, P32, cols, c, g.rhat, g.nx, g.m, nullptr, g.mux32, g.muy32, float(g.lambda * g.tau),
-                         float(1.0 / (double(g.nyi) * g.nx)));
-        }
-      });
-      if (t < best) {
-        best = t;
-        bestg = G;
-      }
-    }
-    c->col_g[di][ly] = bestg;
-    c->col_tuned[di][ly] = true;
-  }
-  if (!c->row_tuned[di][lx]) {
-    double best = 1e30;
-    int bestg = c->row_g[di][lx];
-    for (int G = sx.row_gm; G <= sx.row_gmax; G *= 2) {
-      c->row_g[di][lx] = G;
+  double best = 1e30;
+  int bc = c->col_g[di][ly], br = c->row_g[di][lx];
+  for (int cg : cols)
+    for (int rg : rows) {
+      c->col_g[di][ly] = cg;
+      c->row_g[di][lx] = rg;
       const double t = time_ms(c, [&] {
         if (f64) {
           EmdPipe P{c, &g, g.p, g.pbar, g.w0, g.w1};
           (void)emd_A(P, 1, false);
+          GP_DISPATCH_NM(g.nyi, P64, cols, c, g.rhat64, g.nx, g.m, nullptr, g.mux64, g.muy64, 0.0,
+                         1.0 / (double(g.nyi) * g.nx));
+          GP_DISPATCH_NM(g.nx, P64, rows_inv, c, g.rhat64, g.rhat64, g.nyi, g.m, nullptr);
         } else {
           RofPipe P{c, &g, g.p, g.pbar};
           (void)rof_A(P, 1, false);
+          GP_DISPATCH_NM(g.nyi, P32, cols, c, g.rhat, g.nx, g.m, nullptr, g.mux32, g.muy32, float(g.lambda * g.tau),
+                         float(1.0 / (double(g.nyi) * g.nx)));
+          GP_DISPATCH_NM(g.nx, P32, rows_inv, c, g.rhat, g.rhat, g.nyi, g.m, nullptr);
         }
       });
       if (t < best) {
         best = t;
-        bestg = G;
+        bc = cg;
+        br = rg;
       }
     }
-    c->row_g[di][lx] = bestg;
-    c->row_tuned[di][lx] = true;
-  }
+  c->col_g[di][ly] = bc;
+  c->row_g[di][lx] = br;
+  c->col_tuned[di][ly] = true;
+  c->row_tuned[di][lx] = true;
   c->prof_on = prof;
   return hipGetLastError() == hipSuccess ? GP_OK : GP_EHIP;
 }
@@ -1091,6 +1090,7 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
   HIPCHK(c, hipMemcpyAsync(P1, P0, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   const gp_state s{GP_KIND_ROF, ny, nx, o->norm, h, lambda, tau, sigma, I, nullptr, u, P0, P1, 0};
   const Group g = state_group(c, &s);
+  RCHK(tune_group(c, g));  // launch shapes, measured once per size (reads the state, writes scratch)
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t1 = now_s();
   double P = NAN, D = NAN, gap = NAN;
@@ -1212,6 +1212,7 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   HIPCHK(c, hipMemcpyAsync(P1, P0, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   const gp_state s{GP_KIND_EMD, ny, nx, o->norm, h, 0.0, tau, sigma, f, gpsi, u, P0, P1, 0};
   const Group g = state_group(c, &s);
+  RCHK(tune_group(c, g));  // launch shapes, measured once per size (reads the state, writes scratch)
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t1 = now_s();
   double P = NAN, D = NAN, gap = NAN, L = 0;

@@ -12,15 +12,18 @@
 // and for the inverse
 //     V_k = exp(+i pi k / 2N) (X_k - i X_{N-k}),   X_N = 0,   v = N * IFFT(V).
 //
-// FFT layout: a "group" of T = N/32 threads owns one complex sequence; each
-// thread holds 32 complex values in registers.  Passes are Stockham
-// (self-sorting, natural-order output) with radix 16, plus one leading
-// radix-2/4/8 pass when log2 N is not a multiple of 4.  Between passes the
-// group exchanges through its own LDS region.  Butterfly-to-thread assignment:
+// FFT layout: a "group" of T = N/E threads owns one complex sequence; each
+// thread holds E complex values in registers (E = 32 for N <= 512, E = 16 for
+// longer sequences, which doubles the threads -- and the waves a CU can keep in
+// flight -- for the same LDS).  Passes are Stockham (self-sorting,
+// natural-order output) with radix H = E/2 (16 or 8), plus one leading smaller
+// power-of-two pass when log2 N is not a multiple of log2 H.  Between passes
+// the group exchanges through its own LDS region.  Butterfly-to-thread
+// assignment:
 //   * first forward pass: butterflies (b, N/R-1-b) on one thread, so the
 //     Makhoul reordering is done by the global loads themselves (one float2
 //     load gives x_{2m}, x_{2m+1} = v_m, v_{N-1-m});
-//   * last forward pass: butterflies (b, N/R-b), so each thread holds both
+//   * last forward pass (radix H): butterflies (b, N/H-b), so each thread holds both
 //     Z_k and Z_{N-k} for the real/imaginary split and the DCT twiddle, and
 //     the inverse's first pass (same radix, same indices) needs no exchange;
 //   * last inverse pass: (b, N/R-1-b) again, so stores are float2 pairs.
@@ -138,13 +141,19 @@ constexpr double kCS32[16][2] = {
     {0.19509032201612833135, -0.98078528040323043058}, {0.09801714032956077016, -0.99518472667219681771}};
 constexpr double kE64[2] = {0.99879545620517239271, -0.04906767432741801425};
 
-template <class C> __device__ __forceinline__ C cs32(int s) {
+// exp(-i pi s / 2H) for s < H (H = 16 or 8): the ratio of DCT twiddles N/H apart
+template <int H, class C> __device__ __forceinline__ C csh(int s) {
   using Re = typename Cx<C>::R;
-  return mk<C>(Re(kCS32[s][0]), Re(kCS32[s][1]));
+  return mk<C>(Re(kCS32[s * (16 / H)][0]), Re(kCS32[s * (16 / H)][1]));
 }
-// DCT twiddle w_k = exp(-i pi k / 2N) for k = b + s N/16 from w_b; and the
+// exp(-i pi / 4H): the DCT twiddle of index N/2H
+template <int H, class C> __device__ __forceinline__ C ceh() {
+  using Re = typename Cx<C>::R;
+  return H == 16 ? mk<C>(Re(kE64[0]), Re(kE64[1])) : mk<C>(Re(kCS32[16 / (2 * H)][0]), Re(kCS32[16 / (2 * H)][1]));
+}
+// DCT twiddle w_k = exp(-i pi k / 2N) for k = b + s N/H from w_b; and the
 // partner w_{N-k} = -i conj(w_k)
-template <class C> __device__ __forceinline__ C dcw(C wb, int s) { return cmul(wb, cs32<C>(s)); }
+template <int H, class C> __device__ __forceinline__ C dcw(C wb, int s) { return cmul(wb, csh<H, C>(s)); }
 template <class C> __device__ __forceinline__ C dcw_partner(C w) { return mk<C>(-w.y, -w.x); }
 
 // Stockham twiddles W^{j r}, r = 1..R-1, from W^j (w1) and, for R = 16, W^{4j}
@@ -186,15 +195,20 @@ template <int R, class C> __device__ __forceinline__ void apply_tw(C* x, C w1, C
 // ---------------------------------------------------------------- schedule
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
+// complex values per thread for sequences of length N
+constexpr int kE16MinN = 1024;
 template <int N> struct Sched {
   static_assert(N >= 64 && N <= 4096 && (N & (N - 1)) == 0, "power-of-two N in [64, 4096]");
-  static constexpr int E = 32;          // complex values per thread
-  static constexpr int T = N / E;       // threads per sequence
+  static constexpr int E = N >= kE16MinN ? 16 : 32;  // complex values per thread
+  static constexpr int H = E / 2;                    // main radix, values per output slot
+  static constexpr int LH = ilog2c(H);
+  static constexpr int T = N / E;                    // threads per sequence
   static constexpr int L2 = ilog2c(N);
-  static constexpr int REM = L2 % 4;
-  static constexpr int NP = L2 / 4 + (REM ? 1 : 0);
+  static constexpr int REM = L2 % LH;
+  static constexpr int NP = L2 / LH + (REM ? 1 : 0);
+  static_assert(NP >= 2, "at least two passes");
   // forward radix of pass p; the inverse runs the sequence reversed
-  static constexpr int rad(int p) { return (REM && p == 0) ? (1 << REM) : 16; }
+  static constexpr int rad(int p) { return (REM && p == 0) ? (1 << REM) : H; }
   static constexpr int irad(int p) { return rad(NP - 1 - p); }
   static constexpr int ls(int p) { int l = 1; for (int i = 0; i < p; ++i) l *= rad(i); return l; }
   static constexpr int ils(int p) { int l = 1; for (int i = 0; i < p; ++i) l *= irad(i); return l; }
@@ -209,6 +223,8 @@ template <int N> struct Sched {
   // interleaved lane-by-lane (the column pass) start on different banks
   static constexpr int LDS = ((N + N / 16 + 31) / 32) * 32 + 8;
 };
+// register array of one thread's values
+template <int N, class C> using Vals = C[Sched<N>::E];
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
@@ -216,9 +232,9 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 //   inputs of butterfly b:  x[b + r N/R], twiddled by W_{LS R}^{(b mod LS) r}
 //   outputs:                 y[(b/LS) LS R + (b mod LS) + s LS]
 template <int N, int R, int LS, bool INV, bool FROM_LDS, bool TO_LDS, class C>
-__device__ __forceinline__ void stockham_pass(C (&v)[32], const int (&bi)[32 / R], C* lds,
+__device__ __forceinline__ void stockham_pass(Vals<N, C>& v, const int (&bi)[Sched<N>::E / R], C* lds,
                                               const C* __restrict__ tw) {
-  constexpr int NB = 32 / R;
+  constexpr int NB = Sched<N>::E / R;
   // twiddle bases are loaded before the LDS exchange so their latency overlaps it
   C w1[NB], w4[NB];
   if constexpr (LS > 1) {
@@ -254,23 +270,23 @@ __device__ __forceinline__ void stockham_pass(C (&v)[32], const int (&bi)[32 / R
 }
 
 // butterfly index lists
-template <int N, int R> __device__ __forceinline__ void bidx_seq(int t, int (&bi)[32 / R]) {
-  constexpr int T = N / 32;
+template <int N, int R> __device__ __forceinline__ void bidx_seq(int t, int (&bi)[Sched<N>::E / R]) {
+  constexpr int T = Sched<N>::T;
 #pragma unroll
-  for (int q = 0; q < 32 / R; ++q) bi[q] = t + q * T;
+  for (int q = 0; q < Sched<N>::E / R; ++q) bi[q] = t + q * T;
 }
-template <int N, int R> __device__ __forceinline__ void bidx_mk(int t, int (&bi)[32 / R]) {
-  constexpr int T = N / 32;
+template <int N, int R> __device__ __forceinline__ void bidx_mk(int t, int (&bi)[Sched<N>::E / R]) {
+  constexpr int T = Sched<N>::T;
 #pragma unroll
-  for (int q = 0; q < 16 / R; ++q) {
+  for (int q = 0; q < Sched<N>::H / R; ++q) {
     bi[2 * q] = t + q * T;
     bi[2 * q + 1] = N / R - 1 - (t + q * T);
   }
 }
-template <int N, int R> __device__ __forceinline__ void bidx_dc(int t, int (&bi)[32 / R]) {
-  constexpr int T = N / 32;
+template <int N, int R> __device__ __forceinline__ void bidx_dc(int t, int (&bi)[Sched<N>::E / R]) {
+  constexpr int T = Sched<N>::T;
 #pragma unroll
-  for (int q = 0; q < 16 / R; ++q) {
+  for (int q = 0; q < Sched<N>::H / R; ++q) {
     const int b = t + q * T;
     bi[2 * q] = b;
     bi[2 * q + 1] = (b == 0) ? N / (2 * R) : N / R - b;
@@ -279,13 +295,13 @@ template <int N, int R> __device__ __forceinline__ void bidx_dc(int t, int (&bi)
 
 // Middle passes p in [P, PEND) of the forward (INV=false) or inverse FFT.
 template <int N, bool INV, int P, int PEND, class C>
-__device__ __forceinline__ void middle_passes(int t, C (&v)[32], C* lds, const C* __restrict__ tw) {
+__device__ __forceinline__ void middle_passes(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw) {
   if constexpr (P < PEND) {
     using S = Sched<N>;
     constexpr int R = INV ? S::irad(P) : S::rad(P);
     constexpr int LS = INV ? S::ils(P) : S::ls(P);
     constexpr int OFF = INV ? S::itoff(P) : S::toff(P);
-    int bi[32 / R];
+    int bi[S::E / R];
     bidx_seq<N, R>(t, bi);
     stockham_pass<N, R, LS, INV, true, true>(v, bi, lds, tw + OFF);
     middle_passes<N, INV, P + 1, PEND, C>(t, v, lds, tw);
@@ -294,22 +310,24 @@ __device__ __forceinline__ void middle_passes(int t, C (&v)[32], C* lds, const C
 
 // Forward DCT-II of two real sequences a, b of length N.
 // ld(m, A, B) must return A = (a_{2m}, a_{2m+1}), B = (b_{2m}, b_{2m+1}) for m < N/2.
-// On return, spec[slot*16 + s] = (A_k, B_k) with k = dc_index(slot, s), the
+// On return, spec[slot*H + s] = (A_k, B_k) with k = dc_index(slot, s), the
 // unnormalised DCT-II X_k = sum_j x_j cos(pi k (2j+1) / 2N).
+template <int N, class C>
+__device__ __forceinline__ void dct_split_fwd(int t, Vals<N, C>& v, C wt);
+
 template <int N, class C, class Loader>
-__device__ __forceinline__ void dct2_fwd(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+__device__ __forceinline__ void dct2_fwd(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw,
                                          const C* __restrict__ dctw, Loader&& ld) {
-  using Re = typename Cx<C>::R;
   using S = Sched<N>;
-  constexpr int T = S::T;
+  constexpr int T = S::T, H = S::H, E = S::E;
   constexpr int R0 = S::rad(0);
   const C wt = dctw[t];  // exp(-i pi t / 2N), base of this thread's DCT twiddles
   // ---- pass 0 with the Makhoul reordering done by the loads
   {
-    int bi[32 / R0];
+    int bi[E / R0];
     bidx_mk<N, R0>(t, bi);
 #pragma unroll
-    for (int q = 0; q < 16 / R0; ++q) {
+    for (int q = 0; q < H / R0; ++q) {
       const int b = t + q * T;
       const int bp = N / R0 - 1 - b;
 #pragma unroll
@@ -328,102 +346,110 @@ __device__ __forceinline__ void dct2_fwd(int t, C (&v)[32], C* lds, const C* __r
   }
   // ---- middle passes
   middle_passes<N, false, 1, S::NP - 1, C>(t, v, lds, tw);
-  // ---- last pass (radix 16), pairs (b, N/16 - b): outputs stay in registers
+  // ---- last pass (radix H), pairs (b, N/H - b): outputs stay in registers
   {
     constexpr int PL = S::NP - 1;
     int bi[2];
-    bidx_dc<N, 16>(t, bi);
-    stockham_pass<N, 16, S::ls(PL), false, true, false>(v, bi, lds, tw + S::toff(PL));
+    bidx_dc<N, H>(t, bi);
+    stockham_pass<N, H, S::ls(PL), false, true, false>(v, bi, lds, tw + S::toff(PL));
   }
-  // ---- split the two real transforms and apply exp(-i pi k / 2N).  Output s
-  // of butterfly b is index b + s N/16; Z_{N-k} sits at (slot1, 15 - s).
-  const int b = t;
-  if (b != 0) {
+  dct_split_fwd<N>(t, v, wt);
+}
+
+// Split the two real transforms held in a forward FFT's last-pass registers and
+// apply exp(-i pi k / 2N).  Output s of butterfly b is index b + s N/H; Z_{N-k}
+// sits at (slot1, H - 1 - s).
+template <int N, class C>
+__device__ __forceinline__ void dct_split_fwd(int t, Vals<N, C>& v, C wt) {
+  using Re = typename Cx<C>::R;
+  constexpr int H = Sched<N>::H;
+  if (t != 0) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      // k0 = b + s N/16 and its partner k1 = N - k0 = (N/16 - b) + (15 - s) N/16
-      C z0 = v[s], z1 = v[16 + 15 - s];
-      C w0 = dcw(wt, s), w1 = dcw_partner(w0);
-      C a0 = cmul(w0, z0), c0 = cmul(w0, mk<C>(z1.x, -z1.y));
-      C a1 = cmul(w1, z1), c1 = cmul(w1, mk<C>(z0.x, -z0.y));
+    for (int s = 0; s < H; ++s) {
+      // k0 = t + s N/H and its partner k1 = N - k0 = (N/H - t) + (H - 1 - s) N/H
+      C z0 = v[s], z1 = v[H + H - 1 - s];
+      C w0 = dcw<H>(wt, s), w1 = dcw_partner(w0);
+      C a0 = cmul(w0, z0), c0 = cmul(w0, conjc(z1));
+      C a1 = cmul(w1, z1), c1 = cmul(w1, conjc(z0));
       v[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
-      v[16 + 15 - s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
+      v[H + H - 1 - s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
     }
   } else {
-    // thread 0: slot 0 holds k = s N/16 (pairs s <-> 16 - s, s = 0 and 8 self),
-    //           slot 1 holds k = N/32 + s N/16 (pairs s <-> 15 - s)
-    C o[32];
+    // thread 0: slot 0 holds k = s N/H (pairs s <-> H - s, s = 0 and H/2 self),
+    //           slot 1 holds k = N/2H + s N/H (pairs s <-> H - 1 - s)
+    C o[2 * H];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      C z0 = v[s], zp = v[(16 - s) & 15];
-      C w0 = cs32<C>(s);
-      C a0 = cmul(w0, z0), c0 = cmul(w0, mk<C>(zp.x, -zp.y));
+    for (int s = 0; s < H; ++s) {
+      C z0 = v[s], zp = v[(H - s) & (H - 1)];
+      C w0 = csh<H, C>(s);
+      C a0 = cmul(w0, z0), c0 = cmul(w0, conjc(zp));
       o[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
-      C z1 = v[16 + s], zq = v[16 + 15 - s];
-      C w1 = dcw(mk<C>(Re(kE64[0]), Re(kE64[1])), s);
-      C a1 = cmul(w1, z1), c1 = cmul(w1, mk<C>(zq.x, -zq.y));
-      o[16 + s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
+      C z1 = v[H + s], zq = v[H + H - 1 - s];
+      C w1 = dcw<H>(ceh<H, C>(), s);
+      C a1 = cmul(w1, z1), c1 = cmul(w1, conjc(zq));
+      o[H + s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
     }
 #pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = o[i];
+    for (int i = 0; i < 2 * H; ++i) v[i] = o[i];
   }
 }
 
-// DCT index held in spec slot (slot in {0,1}, s in [0,16)) by thread t.
+// DCT index held in spec slot (slot in {0,1}, s in [0,H)) by thread t.
 template <int N> __device__ __forceinline__ int dc_index(int t, int slot, int s) {
-  const int b = (slot == 0) ? t : ((t == 0) ? N / 32 : N / 16 - t);
-  return b + s * (N / 16);
+  constexpr int H = Sched<N>::H;
+  const int b = (slot == 0) ? t : ((t == 0) ? N / (2 * H) : N / H - t);
+  return b + s * (N / H);
 }
 
 // Inverse of the unnormalised DCT-II, times N, for two real spectra held as
-// spec[slot*16+s] = (A_k, B_k) (layout of dct2_fwd).  st(m, A, B) receives
+// spec[slot*H+s] = (A_k, B_k) (layout of dct2_fwd).  st(m, A, B) receives
 // A = N (a_{2m}, a_{2m+1}), B = N (b_{2m}, b_{2m+1}).
 template <int N, class C, class Hook>
-__device__ __forceinline__ void dct2_inv_core(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+__device__ __forceinline__ void dct2_inv_core(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw,
                                               const C* __restrict__ dctw, Hook&& before_last) {
   using Re = typename Cx<C>::R;
   using S = Sched<N>;
-  constexpr int T = S::T;
+  constexpr int H = S::H, E = S::E;
   const C wt = dctw[t];  // exp(-i pi t / 2N); the inverse uses conjugates
   // ---- V_k = conj(w_k) (X_k - i X_{N-k}) for both spectra, Z_k = V^a_k + i V^b_k
   if (t != 0) {
-    // pairs (slot0, s) <-> (slot1, 15 - s), s in [0, 16)
+    // pairs (slot0, s) <-> (slot1, H - 1 - s), s in [0, H)
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      C y0 = v[s], y1 = v[16 + 15 - s];
-      C c0 = dcw(wt, s), c1 = dcw_partner(c0);
+    for (int s = 0; s < H; ++s) {
+      C y0 = v[s], y1 = v[H + H - 1 - s];
+      C c0 = dcw<H>(wt, s), c1 = dcw_partner(c0);
       c0.y = -c0.y;
       c1.y = -c1.y;
       C va0 = cmul(c0, mk<C>(y0.x, -y1.x)), vb0 = cmul(c0, mk<C>(y0.y, -y1.y));
       C va1 = cmul(c1, mk<C>(y1.x, -y0.x)), vb1 = cmul(c1, mk<C>(y1.y, -y0.y));
       v[s] = mk<C>(va0.x - vb0.y, va0.y + vb0.x);
-      v[16 + 15 - s] = mk<C>(va1.x - vb1.y, va1.y + vb1.x);
+      v[H + H - 1 - s] = mk<C>(va1.x - vb1.y, va1.y + vb1.x);
     }
   } else {
-    C o[32];
+    C o[E];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < H; ++s) {
       C y0 = v[s];
-      C yp = (s == 0) ? mk<C>(Re(0), Re(0)) : v[(16 - s) & 15];  // X_N = 0
-      C c0 = cs32<C>(s);
+      C yp = (s == 0) ? mk<C>(Re(0), Re(0)) : v[(H - s) & (H - 1)];  // X_N = 0
+      C c0 = csh<H, C>(s);
       c0.y = -c0.y;
       C va = cmul(c0, mk<C>(y0.x, -yp.x)), vb = cmul(c0, mk<C>(y0.y, -yp.y));
       o[s] = mk<C>(va.x - vb.y, va.y + vb.x);
-      C y1 = v[16 + s], yq = v[16 + 15 - s];
-      C c1 = dcw(mk<C>(Re(kE64[0]), Re(kE64[1])), s);
+      C y1 = v[H + s], yq = v[H + H - 1 - s];
+      C c1 = dcw<H>(ceh<H, C>(), s);
       c1.y = -c1.y;
       C va1 = cmul(c1, mk<C>(y1.x, -yq.x)), vb1 = cmul(c1, mk<C>(y1.y, -yq.y));
-      o[16 + s] = mk<C>(va1.x - vb1.y, va1.y + vb1.x);
+      o[H + s] = mk<C>(va1.x - vb1.y, va1.y + vb1.x);
     }
 #pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = o[i];
+    for (int i = 0; i < E; ++i) v[i] = o[i];
   }
-  // ---- inverse pass 0 (radix 16) directly on the registers: butterfly b's
-  // inputs b + r N/16 are exactly what this thread holds
+  // ---- inverse pass 0 (radix H) directly on the registers: butterfly b's
+  // inputs b + r N/H are exactly what this thread holds
   {
     int bi[2];
-    bidx_dc<N, 16>(t, bi);
-    stockham_pass<N, 16, 1, true, false, true>(v, bi, lds, tw + S::itoff(0));
+    bidx_dc<N, H>(t, bi);
+    stockham_pass<N, H, 1, true, false, true>(v, bi, lds, tw + S::itoff(0));
   }
   middle_passes<N, true, 1, S::NP - 1, C>(t, v, lds, tw);
   before_last();
@@ -431,25 +457,25 @@ __device__ __forceinline__ void dct2_inv_core(int t, C (&v)[32], C* lds, const C
   {
     constexpr int PL = S::NP - 1;
     constexpr int RL = S::irad(PL);
-    int bi[32 / RL];
+    int bi[E / RL];
     bidx_mk<N, RL>(t, bi);
     stockham_pass<N, RL, S::ils(PL), true, true, false>(v, bi, lds, tw + S::itoff(PL));
   }
 }
 
-// Positions held after dct2_inv_core: for q < 16/RL and s < RL/2 the thread holds
-// output pairs (x_{2m}, x_{2m+1}) for m = inv_m<N>(t, 2q, s) and m = inv_m<N>(t, 2q+1, s):
-//   slot 2q:   x_{2m} = v[2q RL + s],     x_{2m+1} = v[(2q+1) RL + RL-1-s],  m = b + s N/RL
-//   slot 2q+1: x_{2m} = v[(2q+1) RL + s], x_{2m+1} = v[2q RL + RL-1-s],      m = bp + s N/RL
+// Positions held after dct2_inv_core: for q < H/RL and s < RL/2 the thread holds
+// output pairs (x_{2m}, x_{2m+1}) for m = InvOut::m(t, q, half, s):
+//   half 0: x_{2m} = v[2q RL + s],     x_{2m+1} = v[(2q+1) RL + RL-1-s],  m = b + s N/RL
+//   half 1: x_{2m} = v[(2q+1) RL + s], x_{2m+1} = v[2q RL + RL-1-s],      m = bp + s N/RL
 template <int N> struct InvOut {
   static constexpr int RL = Sched<N>::irad(Sched<N>::NP - 1);
-  static constexpr int NQ = 16 / RL;   // butterfly pairs per thread
-  static constexpr int NS = RL / 2;    // outputs per butterfly
+  static constexpr int NQ = Sched<N>::H / RL;  // butterfly pairs per thread
+  static constexpr int NS = RL / 2;            // outputs per butterfly
   __device__ __forceinline__ static int m(int t, int q, int half, int s) {
     const int b = t + q * Sched<N>::T;
     return (half ? N / RL - 1 - b : b) + s * (N / RL);
   }
-  template <class C> __device__ __forceinline__ static void get(const C (&v)[32], int q, int half, int s, C& x0,
+  template <class C> __device__ __forceinline__ static void get(const Vals<N, C>& v, int q, int half, int s, C& x0,
                                                                  C& x1) {
     x0 = v[(2 * q + half) * RL + s];
     x1 = v[(2 * q + 1 - half) * RL + (RL - 1 - s)];
@@ -457,7 +483,7 @@ template <int N> struct InvOut {
 };
 
 template <int N, class C, class Storer>
-__device__ __forceinline__ void dct2_inv(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+__device__ __forceinline__ void dct2_inv(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw,
                                          const C* __restrict__ dctw, Storer&& st) {
   using S = Sched<N>;
   constexpr int T = S::T;
@@ -465,7 +491,7 @@ __device__ __forceinline__ void dct2_inv(int t, C (&v)[32], C* lds, const C* __r
   {
     constexpr int RL = S::irad(S::NP - 1);
 #pragma unroll
-    for (int q = 0; q < 16 / RL; ++q) {
+    for (int q = 0; q < S::H / RL; ++q) {
       const int b = t + q * T;
       const int bp = N / RL - 1 - b;
 #pragma unroll

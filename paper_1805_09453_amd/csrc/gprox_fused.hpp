@@ -39,14 +39,13 @@ namespace gp {
 // Forward DCT-II of two real sequences already in LDS in Makhoul order
 // (lds[lpad(m)] = (a, b)-packed v_m).  Layout of the result as dct2_fwd.
 template <int N, class C>
-__device__ __forceinline__ void dct2_fwd_lds(int t, C (&v)[32], C* lds, const C* __restrict__ tw,
+__device__ __forceinline__ void dct2_fwd_lds(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw,
                                              const C* __restrict__ dctw) {
   using S = Sched<N>;
-  using Re = typename Cx<C>::R;
-  constexpr int R0 = S::rad(0);
+  constexpr int R0 = S::rad(0), H = S::H;
   const C wt = dctw[t];  // exp(-i pi t / 2N), base of this thread's DCT twiddles
   {
-    int bi[32 / R0];
+    int bi[S::E / R0];
     bidx_seq<N, R0>(t, bi);
     stockham_pass<N, R0, 1, false, true, true>(v, bi, lds, tw + S::toff(0));
   }
@@ -54,35 +53,10 @@ __device__ __forceinline__ void dct2_fwd_lds(int t, C (&v)[32], C* lds, const C*
   {
     constexpr int PL = S::NP - 1;
     int bi[2];
-    bidx_dc<N, 16>(t, bi);
-    stockham_pass<N, 16, S::ls(PL), false, true, false>(v, bi, lds, tw + S::toff(PL));
+    bidx_dc<N, H>(t, bi);
+    stockham_pass<N, H, S::ls(PL), false, true, false>(v, bi, lds, tw + S::toff(PL));
   }
-  if (t != 0) {
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      C z0 = v[s], z1 = v[16 + 15 - s];
-      C w0 = dcw(wt, s), w1 = dcw_partner(w0);
-      C a0 = cmul(w0, z0), c0 = cmul(w0, conjc(z1));
-      C a1 = cmul(w1, z1), c1 = cmul(w1, conjc(z0));
-      v[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
-      v[16 + 15 - s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
-    }
-  } else {
-    C o[32];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      C z0 = v[s], zp = v[(16 - s) & 15];
-      C w0 = cs32<C>(s);
-      C a0 = cmul(w0, z0), c0 = cmul(w0, conjc(zp));
-      o[s] = mk<C>(Re(0.5) * (a0.x + c0.x), Re(0.5) * (a0.y - c0.y));
-      C z1 = v[16 + s], zq = v[16 + 15 - s];
-      C w1 = dcw(mk<C>(Re(kE64[0]), Re(kE64[1])), s);
-      C a1 = cmul(w1, z1), c1 = cmul(w1, conjc(zq));
-      o[16 + s] = mk<C>(Re(0.5) * (a1.x + c1.x), Re(0.5) * (a1.y - c1.y));
-    }
-#pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = o[i];
-  }
+  dct_split_fwd<N>(t, v, wt);
 }
 
 // store (ra, rb) of column j (natural order) into the Makhoul-ordered LDS sequence
@@ -110,7 +84,7 @@ __device__ __forceinline__ void rof_dual_pt(float px, float py, float gx, float 
 // Gap partials (mode 0, partials != nullptr): [sum|grad u|, sum (u-I)^2,
 // sum I div p_n, sum (div p_n)^2] in 1/h units.
 template <int N>
-__global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, const float* __restrict__ pin,
+__global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::MINW)) void k_rof_A(const float* __restrict__ u, const float* __restrict__ pin,
                                                float* __restrict__ pout, const float* __restrict__ I,
                                                float* __restrict__ rhat, int ny, int nyi, const int* __restrict__ active,
                                                int lgtw, float lt, float tau_h, float sig_h, int aniso, int mode,
@@ -132,7 +106,7 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
     const bool has_up = (a % nyi) > 0, has_dn = ((a + 2) % nyi) != 0;
     const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
 #pragma unroll 2
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < Sched<N>::E / 4; ++k) {
       const int c = 4 * (t + T * k);
       const bool has_l = c > 0, has_r = c + 4 < N;
       float ra[4], rb[4];
@@ -253,16 +227,16 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
   // gap partials per row pair (so that each instance of a batch has its own)
   if (partials) group_reduce_store<4, T>(acc, valid ? partials + size_t(a / 2) * 4 : nullptr, t);
   __syncthreads();
-  float2 v[32];
+  Vals<N, float2> v;
   dct2_fwd_lds<N>(t, v, lds, tw, dctw);
   if (valid) {
 #pragma unroll
     for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
+      for (int s = 0; s < Sched<N>::H; ++s) {
         const int k = dc_index<N>(t, slot, s);
-        rhat[btile(a, k, nyi, N, lgtw)] = v[slot * 16 + s].x;
-        rhat[btile(b, k, nyi, N, lgtw)] = v[slot * 16 + s].y;
+        rhat[btile(a, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].x;
+        rhat[btile(b, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].y;
       }
   }
 }
@@ -270,7 +244,7 @@ __global__ __launch_bounds__(256) void k_rof_A(const float* __restrict__ u, cons
 // ---------------------------------------------------------------- ROF B
 // u += inverse row DCT of the column-solved field
 template <int N>
-__global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, float* __restrict__ u, int ny,
+__global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::MINW)) void k_rof_B(const float* __restrict__ dhat, float* __restrict__ u, int ny,
                                                int nyi, const int* __restrict__ active, int lgtw,
                                                const float2* __restrict__ tw, const float2* __restrict__ dctw) {
   using SH = RowShape<N, float2>;
@@ -284,13 +258,13 @@ __global__ __launch_bounds__(256) void k_rof_B(const float* __restrict__ dhat, f
   const bool valid = a < ny && inst_active(active, a / nyi);
   float* ua = u + size_t(valid ? a : 0) * N;
   float* ub = u + size_t(valid ? b : 0) * N;
-  float2 v[32];
+  Vals<N, float2> v;
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < Sched<N>::H; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      v[slot * 16 + s] = valid ? make_float2(dhat[btile(a, k, nyi, N, lgtw)], dhat[btile(b, k, nyi, N, lgtw)])
+      v[slot * Sched<N>::H + s] = valid ? make_float2(dhat[btile(a, k, nyi, N, lgtw)], dhat[btile(b, k, nyi, N, lgtw)])
                                : make_float2(0, 0);
     }
   // u at this thread's output positions, loaded before the last pass so the
@@ -350,7 +324,7 @@ __global__ __launch_bounds__(256) void k_rof_finish(const float* __restrict__ u,
 //                  partials (nullable): [sum |m_{n+1}|].
 // mode 1 (entry):  u = u_n (in wt_in's place), p_in = pbar_n, gpsi = grad psi -> wt_out = wt_n.
 template <int N>
-__global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, const double* __restrict__ phi,
+__global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>::MINW)) void k_emd_A(const float* __restrict__ wt_in, const double* __restrict__ phi,
                                                const float* __restrict__ pin, const float* __restrict__ gpsi,
                                                const float* __restrict__ f, float* __restrict__ pout,
                                                float* __restrict__ wt_out, double* __restrict__ rhat, int ny,
@@ -372,7 +346,7 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
     const bool has_up = (a % nyi) > 0, has_dn = ((a + 2) % nyi) != 0;
     const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
 #pragma unroll 2
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < Sched<N>::E / 4; ++k) {
       const int c = 4 * (t + T * k);
       const bool has_l = c > 0, has_r = c + 4 < N;
       // new wt at (a-1, c..c+3) [y only], (a, c-1..c+3), (b, c-1..c+3)
@@ -501,16 +475,16 @@ __global__ __launch_bounds__(256) void k_emd_A(const float* __restrict__ wt_in, 
   }
   if (partials) group_reduce_store<1, T>(acc, valid ? partials + size_t(a / 2) : nullptr, t);
   __syncthreads();
-  double2 v[32];
+  Vals<N, double2> v;
   dct2_fwd_lds<N>(t, v, lds, tw, dctw);
   if (valid) {
 #pragma unroll
     for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
+      for (int s = 0; s < Sched<N>::H; ++s) {
         const int k = dc_index<N>(t, slot, s);
-        rhat[btile(a, k, nyi, N, lgtw)] = v[slot * 16 + s].x;
-        rhat[btile(b, k, nyi, N, lgtw)] = v[slot * 16 + s].y;
+        rhat[btile(a, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].x;
+        rhat[btile(b, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].y;
       }
   }
 }

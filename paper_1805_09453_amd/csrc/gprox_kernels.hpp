@@ -21,31 +21,38 @@ namespace gp {
 // waves) or 512 threads (column pass), and within the CU's 160 KB of LDS.
 template <int N, class C> struct RowShape {
   static constexpr int T = Sched<N>::T;
+  static constexpr int MAXT = Sched<N>::E == 16 ? 512 : 256;  // threads per block
+  // waves per SIMD the registers must allow: two 512-thread FP32 blocks per CU
+  // (their LDS fits); FP64 blocks fill the LDS alone
+  static constexpr int MINW = Sched<N>::E == 16 ? (sizeof(C) == 16 ? 2 : 4) : 1;
   static constexpr size_t GROUP_LDS = size_t(Sched<N>::LDS) * sizeof(C);
-  static constexpr int G1 = 256 / T;
+  static constexpr int G1 = MAXT / T;
   static constexpr int G2 = int(147456 / GROUP_LDS);
   static constexpr int G3 = G1 < G2 ? G1 : G2;
   // whole 64-lane waves (the fused kernels reduce across waves)
   static constexpr int GM = T >= 64 ? 1 : 64 / T;
   static constexpr int G = (G3 / GM) * GM;  // default row pairs per block
-  static constexpr int GMAX = G;            // largest allowed (256 threads)
+  static constexpr int GMAX = G;            // largest allowed
   static constexpr int THREADS = G * T;
-  static_assert(G >= 1 && THREADS % 64 == 0 && THREADS <= 256, "row-pass shape");
+  static_assert(G >= 1 && THREADS % 64 == 0 && THREADS <= MAXT, "row-pass shape");
   static constexpr size_t LDS_BYTES = size_t(G) * GROUP_LDS;
 };
 template <int N, class C> struct ColShape {
   static constexpr int T = Sched<N>::T;
+  static constexpr int MAXT = Sched<N>::E == 16 ? 1024 : 512;
   static constexpr size_t GROUP_LDS = size_t(Sched<N>::LDS) * sizeof(C);
   static constexpr int G0 = int(147456 / GROUP_LDS);
   static constexpr int G = G0 > 16 ? 16 : (G0 < 1 ? 1 : G0);  // default column pairs per block
-  static constexpr int GL = int(163840 / GROUP_LDS) < 512 / T ? int(163840 / GROUP_LDS) : 512 / T;
+  static constexpr int GL = int(163840 / GROUP_LDS) < MAXT / T ? int(163840 / GROUP_LDS) : MAXT / T;
   static constexpr int GL2 = GL > 64 ? 64 : GL;
   static constexpr int GMAX = GL2 >= 64 ? 64 : GL2 >= 32 ? 32 : GL2 >= 16 ? 16 : GL2 >= 8 ? 8 : GL2 >= 4 ? 4 : GL2 >= 2 ? 2 : 1;
   static constexpr int THREADS = T * G;
   static constexpr int MAXTHREADS = T * (GMAX > G ? GMAX : G);
+  static_assert(MAXTHREADS <= 1024, "column-pass shape");
   static constexpr size_t LDS_BYTES = size_t(G) * GROUP_LDS;
-  // FP32: keep to 256 registers so two workgroups fit a CU; FP64 needs more
-  static constexpr int MINW = sizeof(C) == 8 ? 2 : 1;
+  // waves per SIMD the register budget must allow
+  static constexpr int MINW0 = MAXTHREADS / 256;
+  static constexpr int MINW = Sched<N>::E == 16 ? (MINW0 < 1 ? 1 : MINW0) : (sizeof(C) == 8 ? 2 : 1);
 };
 
 // Layout of the row-transformed intermediate (the field between the row and
@@ -69,7 +76,7 @@ __device__ __forceinline__ bool inst_active(const int* active, int inst) { retur
 // ------------------------------------------------------------ DCT passes
 // Forward DCT-II along rows, two rows per FFT group.  out may alias in.
 template <int N, class C>
-__global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
+__global__ __launch_bounds__((RowShape<N, C>::MAXT), (RowShape<N, C>::MINW)) void k_rows_fwd(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
                                                   int nyi, const int* __restrict__ active, int lgtw,
                                                   const C* __restrict__ tw, const C* __restrict__ dctw) {
   constexpr int ld = N;
@@ -83,7 +90,7 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, t
   const bool va = ra < ny && inst_active(active, ra / nyi), vb = va && rb < ny;
   const Re* pa = in + size_t(va ? ra : 0) * ld;
   const Re* pb = in + size_t(vb ? rb : 0) * ld;
-  C v[32];
+  Vals<N, C> v;
   dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
     A = va ? *reinterpret_cast<const C*>(pa + 2 * m) : mk<C>(Re(0), Re(0));
     B = vb ? *reinterpret_cast<const C*>(pb + 2 * m) : mk<C>(Re(0), Re(0));
@@ -91,16 +98,16 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const typename Cx<C>::R* in, t
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < Sched<N>::H; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      if (va) out[btile(ra, k, nyi, N, lgtw)] = v[slot * 16 + s].x;
-      if (vb) out[btile(rb, k, nyi, N, lgtw)] = v[slot * 16 + s].y;
+      if (va) out[btile(ra, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].x;
+      if (vb) out[btile(rb, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].y;
     }
 }
 
 // Inverse of the (unnormalised) DCT-II along rows times N.  out may alias in.
 template <int N, class C>
-__global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
+__global__ __launch_bounds__((RowShape<N, C>::MAXT), (RowShape<N, C>::MINW)) void k_rows_inv(const typename Cx<C>::R* in, typename Cx<C>::R* out, int ny,
                                                   int nyi, const int* __restrict__ active, int lgtw,
                                                   const C* __restrict__ tw, const C* __restrict__ dctw) {
   constexpr int ld = N;
@@ -112,13 +119,13 @@ __global__ __launch_bounds__(256) void k_rows_inv(const typename Cx<C>::R* in, t
   C* lds = smem + g * Sched<N>::LDS;
   const int ra = 2 * (blockIdx.x * int(blockDim.x / SH::T) + g), rb = ra + 1;
   const bool va = ra < ny && inst_active(active, ra / nyi), vb = va && rb < ny;
-  C v[32];
+  Vals<N, C> v;
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < Sched<N>::H; ++s) {
       const int k = dc_index<N>(t, slot, s);
-      v[slot * 16 + s] = mk<C>(va ? in[btile(ra, k, nyi, N, lgtw)] : Re(0), vb ? in[btile(rb, k, nyi, N, lgtw)] : Re(0));
+      v[slot * Sched<N>::H + s] = mk<C>(va ? in[btile(ra, k, nyi, N, lgtw)] : Re(0), vb ? in[btile(rb, k, nyi, N, lgtw)] : Re(0));
     }
   dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
     if (va) *reinterpret_cast<C*>(out + size_t(ra) * ld + 2 * m) = A;
@@ -156,7 +163,7 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
   const bool valid = c < nx;
   Re* col = buf + (valid ? size_t(strip) * N * TW + 2 * g : 0);
   const int ld = TW;
-  C v[32];
+  Vals<N, C> v;
   dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
     if (valid) {
       C L0 = *reinterpret_cast<const C*>(col + size_t(2 * m) * ld);
@@ -172,10 +179,10 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < Sched<N>::H; ++s) {
       const int k = dc_index<N>(t, slot, s);
       const Re da = alpha + muy[k] + mxa, db = alpha + muy[k] + mxb;
-      C& z = v[slot * 16 + s];
+      C& z = v[slot * Sched<N>::H + s];
       z.x = da > Re(0) ? z.x * (inv_nn / da) : Re(0);
       z.y = db > Re(0) ? z.y * (inv_nn / db) : Re(0);
     }
@@ -235,7 +242,7 @@ __device__ __forceinline__ void group_reduce_store(double (&acc)[K], double* out
     }
   } else {
     constexpr int WPG = T / 64;  // waves per group
-    __shared__ double red[4][K];
+    __shared__ double red[8][K];  // blocks of up to 512 threads
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
