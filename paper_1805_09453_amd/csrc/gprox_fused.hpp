@@ -254,7 +254,7 @@ __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::
   float2* smem = reinterpret_cast<float2*>(smem_raw);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   float2* lds = smem + g * Sched<N>::LDS;
-  const int a = 2 * (blockIdx.x * int(blockDim.x / T) + g), b = a + 1;
+  const int a = 2 * (xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x / T) + g), b = a + 1;
   const bool valid = a < ny && inst_active(active, a / nyi);
   float* ua = u + size_t(valid ? a : 0) * N;
   float* ub = u + size_t(valid ? b : 0) * N;

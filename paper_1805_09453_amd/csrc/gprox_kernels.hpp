@@ -73,6 +73,15 @@ __device__ __forceinline__ size_t btile(int a, int k, int nyi, int nx, int lgtw)
 }
 __device__ __forceinline__ bool inst_active(const int* active, int inst) { return !active || active[inst] != 0; }
 
+// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8).
+// Renumbering them so that each XCD takes a contiguous range of the work keeps
+// neighbouring row groups -- which share halo rows and the cache lines of the
+// tiled intermediate -- under one L2.  A permutation of [0, nb) for any nb.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // ------------------------------------------------------------ DCT passes
 // Forward DCT-II along rows, two rows per FFT group.  out may alias in.
 template <int N, class C>
@@ -117,7 +126,7 @@ __global__ __launch_bounds__((RowShape<N, C>::MAXT), (RowShape<N, C>::MINW)) voi
   C* smem = reinterpret_cast<C*>(smem_raw);
   const int g = threadIdx.x / SH::T, t = threadIdx.x % SH::T;
   C* lds = smem + g * Sched<N>::LDS;
-  const int ra = 2 * (blockIdx.x * int(blockDim.x / SH::T) + g), rb = ra + 1;
+  const int ra = 2 * (xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x / SH::T) + g), rb = ra + 1;
   const bool va = ra < ny && inst_active(active, ra / nyi), vb = va && rb < ny;
   Vals<N, C> v;
 #pragma unroll
@@ -152,11 +161,8 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
   const int G = blockDim.x / SH::T;  // column pairs per block: strip width 2G
   const int g = threadIdx.x % G, t = threadIdx.x / G;
   C* lds = smem + g * Sched<N>::LDS;
-  // XCD-aware strip order: workgroups are dealt round-robin to the 8 XCDs, so
-  // give each XCD a contiguous run of strips; strips that share cache lines
-  // then run together under one L2.
-  const int nstrip = gridDim.x, b = blockIdx.x;
-  const int strip = (nstrip % 8 == 0) ? (b % 8) * (nstrip / 8) + b / 8 : b;
+  // XCD-aware strip order: strips that share cache lines run under one L2
+  const int strip = xcd_block(blockIdx.x, gridDim.x);
   // this block's strip of TW = 2G columns is contiguous (tile_idx layout)
   const int TW = 2 * G;
   const int c = strip * TW + 2 * g;
