@@ -158,16 +158,18 @@ def batch_leg(ctx, dev, count, tol, max_iter):
 
 def warm_leg(ctx, r0, r1, n, tol, max_iter):
     """EMD time to `tol` on the same n x n pair: plain zero start vs the learned
-    warm start (8x block mean -> network at 512^2 -> bilinear potential, certificate
-    check, fallback), each timed whole."""
+    warm start (block mean to the network's native size -> prediction -> bilinear
+    potential, certificate check, fallback), each timed whole."""
     import numpy as np
     import torch
 
     from paper_1805_09453_amd import Options, WarmStart
-    wpath = os.path.join(ROOT, "paper_1805_09453_amd", "weights", "ws_unet_512.f32")
+    wpath = os.path.join(ROOT, "paper_1805_09453_amd", "weights", "ws_unet.f32")
     if not os.path.exists(wpath):
         return {"skipped": "no trained weights"}
-    ws = WarmStart(ctx, 1, 512, 512)
+    with open(wpath.replace(".f32", ".json")) as fh:
+        native = json.load(fh)["native"]
+    ws = WarmStart(ctx, 1, native, native)
     ws.set_params(torch.tensor(np.fromfile(wpath, dtype="<f4"), device="cuda"))
     opts = Options(tau=0.3, tol=tol, max_iter=max_iter, check_every=50)
     torch.cuda.synchronize()
@@ -180,7 +182,7 @@ def warm_leg(ctx, r0, r1, n, tol, max_iter):
     torch.cuda.synchronize()
     tw = time.perf_counter() - t0
     ws.close()
-    return {"grid": [n, n], "tol": tol, "plain": {"seconds": tp, "iters": rp["iters"], "rel_gap": rp["rel_gap"],
+    return {"grid": [n, n], "network_native": native, "tol": tol, "plain": {"seconds": tp, "iters": rp["iters"], "rel_gap": rp["rel_gap"],
                                                   "converged": bool(rp["converged"])},
             "warm": {"seconds": tw, "iters": rw["iters"], "rel_gap": rw["rel_gap"], "converged": bool(rw["converged"]),
                      "fallback": wr["fallback"], "warm_iters": wr["warm_iters"], "d0": wr["d0"],

@@ -1,7 +1,7 @@
 """Train the warm-start network on solutions of the EMD iteration itself.
 
-    python -m paper_1805_09453_amd.warmstart_train --pairs 2048 --epochs 6 \
-        --out paper_1805_09453_amd/weights/ws_unet_512.f32 --summary summary.json
+    python -m paper_1805_09453_amd.warmstart_train --pairs 4096 --epochs 30 --native 128 \
+        --out paper_1805_09453_amd/weights/ws_unet.f32 --summary paper_1805_09453_amd/weights/ws_unet.json
 
 Steps (everything numerical runs in libgprox on the GPU; this module only
 moves tensors and loops):
@@ -9,9 +9,13 @@ moves tensors and loops):
      Gaussians (synth.emd_mixture_pair, seed = config_seed(4, i));
   2. target potentials phi*: gp_batch_solve (the plain zero-start iteration of
      section 3.2) to --target-tol, returning the scaled certificate potential;
-  3. training with ws_grads / ws_adam (mean squared gradient error, Adam with a
+  3. the network runs at --native (a divisor of 512): densities and targets are
+     block-averaged to it with ws_downsample (a coarser native size widens the
+     network's receptive field relative to the domain; the potential is smooth);
+     training with ws_grads / ws_adam (mean squared gradient error, Adam with a
      cosine learning-rate decay), a held-out slice monitored for the loss;
-  4. evaluation on held-out pairs: plain emd_solve vs ws_emd_solve (prediction,
+  4. evaluation on held-out 512^2 pairs: plain emd_solve vs ws_emd_solve
+     (block mean to the native size, prediction, bilinear interpolation,
      certificate check and any fallback included) to --eval-tol;
   5. the FP32 parameter blob is written to --out (raw little-endian floats).
 """
@@ -152,6 +156,7 @@ def main(argv=None):
     ap.add_argument("--eval-tol", type=float, default=1e-5)
     ap.add_argument("--eval-max-iter", type=int, default=40000)
     ap.add_argument("--init-seed", type=int, default=1)
+    ap.add_argument("--native", type=int, default=128, help="network resolution (divides 512)")
     ap.add_argument("--out", required=True)
     ap.add_argument("--summary")
     a = ap.parse_args(argv)
@@ -168,7 +173,15 @@ def main(argv=None):
     ctx = Context(n, n)
     log("solving targets")
     PHI, titers = targets(ctx, R0, R1, a.target_tol, a.target_max_iter)
-    ws = WarmStart(ctx, a.batch, n, n)
+    nn = a.native
+    f = n // nn
+    if f > 1:
+        from . import ws_downsample
+        log(f"block-averaging inputs and targets {n} -> {nn}")
+        down = lambda X: torch.stack([ws_downsample(ctx, X[i], f) for i in range(X.shape[0])])
+        R0, R1, PHI = down(R0), down(R1), down(PHI)
+        torch.cuda.synchronize()
+    ws = WarmStart(ctx, a.batch, nn, nn)
     # He-normal initial weights (fan-in), zero biases, seeded; the 1x1 head starts at zero
     # so the first prediction is phi = 0 (loss = mean |grad phi*|^2) instead of noise
     rng = np.random.default_rng(a.init_seed)
@@ -191,7 +204,7 @@ def main(argv=None):
     del R0, R1, PHI
     torch.cuda.empty_cache()
     ev = evaluate(ctx, ws, E0, E1, a.eval_tol, a.eval_max_iter) if a.eval_pairs else None
-    summary = {"pairs": a.pairs, "native": n, "epochs": a.epochs, "batch": a.batch, "lr": a.lr,
+    summary = {"pairs": a.pairs, "native": nn, "solve_grid": n, "epochs": a.epochs, "batch": a.batch, "lr": a.lr,
                "target_tol": a.target_tol, "target_iters_median": int(np.median(titers)),
                "history": hist, "eval": ev, "seconds": time.time() - t_all}
     if a.summary:
