@@ -231,13 +231,14 @@ __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::
   dct2_fwd_lds<N>(t, v, lds, tw, dctw);
   if (valid) {
 #pragma unroll
-    for (int slot = 0; slot < 2; ++slot)
+    for (int slot = 0; slot < 2; ++slot) {
+      const SlotTile<N> ta(a, t, slot, nyi, lgtw), tb(b, t, slot, nyi, lgtw);
 #pragma unroll
       for (int s = 0; s < Sched<N>::H; ++s) {
-        const int k = dc_index<N>(t, slot, s);
-        rhat[btile(a, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].x;
-        rhat[btile(b, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].y;
+        rhat[ta.at(s)] = v[slot * Sched<N>::H + s].x;
+        rhat[tb.at(s)] = v[slot * Sched<N>::H + s].y;
       }
+    }
   }
 }
 
@@ -260,13 +261,12 @@ __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::
   float* ub = u + size_t(valid ? b : 0) * N;
   Vals<N, float2> v;
 #pragma unroll
-  for (int slot = 0; slot < 2; ++slot)
+  for (int slot = 0; slot < 2; ++slot) {
+    const SlotTile<N> ta(a, t, slot, nyi, lgtw), tb(b, t, slot, nyi, lgtw);
 #pragma unroll
-    for (int s = 0; s < Sched<N>::H; ++s) {
-      const int k = dc_index<N>(t, slot, s);
-      v[slot * Sched<N>::H + s] = valid ? make_float2(dhat[btile(a, k, nyi, N, lgtw)], dhat[btile(b, k, nyi, N, lgtw)])
-                               : make_float2(0, 0);
-    }
+    for (int s = 0; s < Sched<N>::H; ++s)
+      v[slot * Sched<N>::H + s] = valid ? make_float2(dhat[ta.at(s)], dhat[tb.at(s)]) : make_float2(0, 0);
+  }
   // u at this thread's output positions, loaded before the last pass so the
   // latency overlaps it
   float2 oa[IO::NQ][2][IO::NS], ob[IO::NQ][2][IO::NS];
@@ -479,13 +479,14 @@ __global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>
   dct2_fwd_lds<N>(t, v, lds, tw, dctw);
   if (valid) {
 #pragma unroll
-    for (int slot = 0; slot < 2; ++slot)
+    for (int slot = 0; slot < 2; ++slot) {
+      const SlotTile<N> ta(a, t, slot, nyi, lgtw), tb(b, t, slot, nyi, lgtw);
 #pragma unroll
       for (int s = 0; s < Sched<N>::H; ++s) {
-        const int k = dc_index<N>(t, slot, s);
-        rhat[btile(a, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].x;
-        rhat[btile(b, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].y;
+        rhat[ta.at(s)] = v[slot * Sched<N>::H + s].x;
+        rhat[tb.at(s)] = v[slot * Sched<N>::H + s].y;
       }
+    }
   }
 }
 

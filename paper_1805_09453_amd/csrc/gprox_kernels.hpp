@@ -73,6 +73,24 @@ __device__ __forceinline__ size_t btile(int a, int k, int nyi, int nx, int lgtw)
 }
 __device__ __forceinline__ bool inst_active(const int* active, int inst) { return !active || active[inst] != 0; }
 
+// Offset of spectrum value (slot, s) of row a in the tiled intermediate.  The
+// H values of a slot are the indices b + s N/H; when N/H is a multiple of the
+// strip width (always for E = 16: N/H >= 128 >= the widest strip) they sit
+// at a constant stride (N/H) nyi from the first one.
+template <int N> struct SlotTile {
+  size_t base;
+  int nyi, lgtw, a, b0;
+  __device__ __forceinline__ SlotTile(int a_, int t, int slot, int nyi_, int lgtw_)
+      : nyi(nyi_), lgtw(lgtw_), a(a_), b0(0) {
+    b0 = slot == 0 ? t : ((t == 0) ? N / (2 * Sched<N>::H) : N / Sched<N>::H - t);
+    base = btile(a, b0, nyi, N, lgtw);
+  }
+  __device__ __forceinline__ size_t at(int s) const {
+    if constexpr (Sched<N>::E == 16) return base + size_t(s) * (size_t(N / Sched<N>::H) * nyi);
+    else return btile(a, b0 + s * (N / Sched<N>::H), nyi, N, lgtw);
+  }
+};
+
 // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8).
 // Renumbering them so that each XCD takes a contiguous range of the work keeps
 // neighbouring row groups -- which share halo rows and the cache lines of the
@@ -105,13 +123,14 @@ __global__ __launch_bounds__((RowShape<N, C>::MAXT), (RowShape<N, C>::MINW)) voi
     B = vb ? *reinterpret_cast<const C*>(pb + 2 * m) : mk<C>(Re(0), Re(0));
   });
 #pragma unroll
-  for (int slot = 0; slot < 2; ++slot)
+  for (int slot = 0; slot < 2; ++slot) {
+    const SlotTile<N> ta(ra, t, slot, nyi, lgtw), tb(rb, t, slot, nyi, lgtw);
 #pragma unroll
     for (int s = 0; s < Sched<N>::H; ++s) {
-      const int k = dc_index<N>(t, slot, s);
-      if (va) out[btile(ra, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].x;
-      if (vb) out[btile(rb, k, nyi, N, lgtw)] = v[slot * Sched<N>::H + s].y;
+      if (va) out[ta.at(s)] = v[slot * Sched<N>::H + s].x;
+      if (vb) out[tb.at(s)] = v[slot * Sched<N>::H + s].y;
     }
+  }
 }
 
 // Inverse of the (unnormalised) DCT-II along rows times N.  out may alias in.
@@ -130,17 +149,21 @@ __global__ __launch_bounds__((RowShape<N, C>::MAXT), (RowShape<N, C>::MINW)) voi
   const bool va = ra < ny && inst_active(active, ra / nyi), vb = va && rb < ny;
   Vals<N, C> v;
 #pragma unroll
-  for (int slot = 0; slot < 2; ++slot)
+  for (int slot = 0; slot < 2; ++slot) {
+    const SlotTile<N> ta(ra, t, slot, nyi, lgtw), tb(rb, t, slot, nyi, lgtw);
 #pragma unroll
-    for (int s = 0; s < Sched<N>::H; ++s) {
-      const int k = dc_index<N>(t, slot, s);
-      v[slot * Sched<N>::H + s] = mk<C>(va ? in[btile(ra, k, nyi, N, lgtw)] : Re(0), vb ? in[btile(rb, k, nyi, N, lgtw)] : Re(0));
-    }
+    for (int s = 0; s < Sched<N>::H; ++s)
+      v[slot * Sched<N>::H + s] = mk<C>(va ? in[ta.at(s)] : Re(0), vb ? in[tb.at(s)] : Re(0));
+  }
   dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
     if (va) *reinterpret_cast<C*>(out + size_t(ra) * ld + 2 * m) = A;
     if (vb) *reinterpret_cast<C*>(out + size_t(rb) * ld + 2 * m) = B;
   });
 }
+
+// 1/x: the hardware reciprocal in FP32 (1 ulp), exact division in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Column pass of the screened Poisson solve, in place on the row-transformed
 // field: DCT-II along y, scale by 1/(nx ny (alpha + mu_y[k] + mu_x[l])) (the
@@ -189,8 +212,8 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
       const int k = dc_index<N>(t, slot, s);
       const Re da = alpha + muy[k] + mxa, db = alpha + muy[k] + mxb;
       C& z = v[slot * Sched<N>::H + s];
-      z.x = da > Re(0) ? z.x * (inv_nn / da) : Re(0);
-      z.y = db > Re(0) ? z.y * (inv_nn / db) : Re(0);
+      z.x = da > Re(0) ? z.x * (inv_nn * recip(da)) : Re(0);
+      z.y = db > Re(0) ? z.y * (inv_nn * recip(db)) : Re(0);
     }
   dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
     if (valid) {
