@@ -323,16 +323,18 @@ __device__ __forceinline__ void proj_ball(float& qx, float& qy, int aniso) {
     qx = fminf(1.f, fmaxf(-1.f, qx));
     qy = fminf(1.f, fmaxf(-1.f, qy));
   } else {
-    const float n = sqrtf(qx * qx + qy * qy);
-    if (n > 1.f) {
-      const float s = 1.f / n;
-      qx *= s;
-      qy *= s;
-    }
+    // scale by 1/|q| outside the unit disc; the hardware reciprocal square root
+    // (1 ulp) replaces a correctly rounded sqrt and divide, which cost about
+    // twenty instructions per cell on this path
+    const float n2 = qx * qx + qy * qy;
+    const float s = n2 > 1.f ? __builtin_amdgcn_rsqf(n2) : 1.f;
+    qx *= s;
+    qy *= s;
   }
 }
 __device__ __forceinline__ float pnorm(float x, float y, int aniso) {
-  return aniso ? fabsf(x) + fabsf(y) : sqrtf(x * x + y * y);
+  const float n2 = x * x + y * y;
+  return aniso ? fabsf(x) + fabsf(y) : (n2 > 0.f ? __builtin_amdgcn_sqrtf(n2) : 0.f);
 }
 
 // divergence of a planar vector field at (i, j), far-face components treated as 0
