@@ -177,19 +177,25 @@ typedef struct {
 int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opts* opts, gp_report* reps);
 
 /* Launch shapes (a performance setting; results do not depend on it).  Each
- * DCT pass runs FFT groups of N/32 threads, one per row pair (row passes) or
- * column pair (column pass); these calls read or set how many groups share a
- * workgroup for transforms of length n in FP32 (fp64 = 0: the ROF path and
- * dct_poisson) or FP64 (fp64 = 1: the EMD path and dct_poisson_f64).  The
- * column setting also fixes the strip width of the intermediate layout.
+ * DCT pass runs FFT groups of n/32 threads (n <= 512) or n/16 threads
+ * (n >= 1024), one per row pair (row passes) or column pair (column pass).
+ * For transforms of length n in FP32 (fp64 = 0: the ROF path and dct_poisson)
+ * or FP64 (fp64 = 1: the EMD path and dct_poisson_f64) these calls read or set
+ *   row_groups  FFT groups per row-pass workgroup (rows of length n);
+ *   col_groups  FFT groups per column-pass workgroup (columns of length n);
+ *   tile_width  strip width of the column-tiled intermediate between the row
+ *               and column passes of columns of length n (used clamped to
+ *               [2 col_groups, grid width]).
  * rof_solve, emd_solve and gp_batch_solve measure the candidates on first use
  * of a size and keep the fastest (an autotuner; pd_step and dct_poisson use
  * the current setting); gp_set_shape fixes a choice (0 leaves a setting
- * unchanged) and exempts it from tuning.  Row groups must be a multiple of
- * max(1, 2048/n) (whole waves) with at most 256 threads; column groups a power
- * of two within the LDS and 512-thread limits; GP_EINVAL otherwise. */
-int gp_get_shape(gp_ctx* ctx, int fp64, int n, int* row_groups, int* col_groups);
-int gp_set_shape(gp_ctx* ctx, int fp64, int n, int row_groups, int col_groups);
+ * unchanged; a column setting fixes both column values) and exempts it from
+ * tuning.  Row groups must fill whole 64-lane waves within the 256-thread
+ * (512 for n >= 1024) and LDS limits; column groups must be a power of two
+ * within the LDS and 512-thread (1024 for n >= 1024) limits; the tile width a
+ * power of two in [2, 64]; GP_EINVAL otherwise.  Out pointers may be NULL. */
+int gp_get_shape(gp_ctx* ctx, int fp64, int n, int* row_groups, int* col_groups, int* tile_width);
+int gp_set_shape(gp_ctx* ctx, int fp64, int n, int row_groups, int col_groups, int tile_width);
 
 /* ---------------------------------------------------------------- learned warm start
  * Not part of the paper.  A U-Net predicts the dual potential phi0 of the EMD

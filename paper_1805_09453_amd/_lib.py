@@ -66,8 +66,9 @@ _SIGS = {
     "pd_gap": (c_int, [c_void_p, ctypes.POINTER(gp_state), ctypes.POINTER(gp_report)]),
     "gp_batch_solve": (c_int, [c_void_p, ctypes.POINTER(gp_instance), c_int, ctypes.POINTER(gp_opts),
                                ctypes.POINTER(gp_report)]),
-    "gp_get_shape": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
-    "gp_set_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
+    "gp_get_shape": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                             ctypes.POINTER(c_int)]),
+    "gp_set_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "ws_param_count": (c_longlong, []),
     "ws_create": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_int, c_int, c_int]),
     "ws_destroy": (c_int, [c_void_p]),

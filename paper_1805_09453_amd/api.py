@@ -249,13 +249,15 @@ class Context:
         return outs, [r.as_dict() for r in reps], rc
 
     def get_shape(self, fp64: bool, n: int):
-        """(row groups, column groups) per workgroup for length-n transforms."""
-        r, c = ctypes.c_int(), ctypes.c_int()
-        self._check(self._lib.gp_get_shape(self._h, int(bool(fp64)), int(n), ctypes.byref(r), ctypes.byref(c)))
-        return r.value, c.value
+        """(row groups, column groups, tile width) for length-n transforms."""
+        r, c, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(self._lib.gp_get_shape(self._h, int(bool(fp64)), int(n), ctypes.byref(r), ctypes.byref(c),
+                                           ctypes.byref(w)))
+        return r.value, c.value, w.value
 
-    def set_shape(self, fp64: bool, n: int, row_groups: int = 0, col_groups: int = 0):
-        self._check(self._lib.gp_set_shape(self._h, int(bool(fp64)), int(n), int(row_groups), int(col_groups)))
+    def set_shape(self, fp64: bool, n: int, row_groups: int = 0, col_groups: int = 0, tile_width: int = 0):
+        self._check(self._lib.gp_set_shape(self._h, int(bool(fp64)), int(n), int(row_groups), int(col_groups),
+                                           int(tile_width)))
 
     def pd_gap(self, st: State):
         rep = L.gp_report()

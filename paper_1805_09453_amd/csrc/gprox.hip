@@ -30,6 +30,10 @@ using namespace gp;
 namespace {
 
 constexpr int kMinN = 64, kMaxN = 4096;
+// default log2 tile width of the intermediate per precision (FP32, FP64): row
+// segments of 64 bytes in both; and the widest tile the tuner tries
+constexpr int kTileLgDefault[2] = {4, 3};
+constexpr int kTileLgMax = 5;
 constexpr int kRedBlocks = 1024;  // partial-sum blocks of the grid-stride reductions
 constexpr int kMaxK = 8;
 constexpr int kResult = 16;       // doubles in the finalized-result buffers
@@ -59,6 +63,7 @@ struct gp_ctx {
   // passes (row pairs) and of the column pass (column pairs = half the strip
   // width of the tiled intermediate); defaults, or measured by the autotuner
   int row_g[2][13] = {}, col_g[2][13] = {};
+  int col_lw[2][13] = {};  // log2 of the tile width of the intermediate, per column length
   bool row_tuned[2][13] = {}, col_tuned[2][13] = {};
   float* work = nullptr;     // [max_n] FP32 tiled intermediate
   float* work2 = nullptr;    // [2 max_n] EMD stored field (ping)
@@ -286,6 +291,8 @@ void init_shapes(gp_ctx* c) {
     const ShapeInfo a = shape_info<float2>(1 << ln), b = shape_info<double2>(1 << ln);
     c->row_g[0][ln] = a.row_def;
     c->col_g[0][ln] = a.col_def;
+    c->col_lw[0][ln] = kTileLgDefault[0];
+    c->col_lw[1][ln] = kTileLgDefault[1];
     c->row_g[1][ln] = b.row_def;
     c->col_g[1][ln] = b.col_def;
   }
@@ -297,8 +304,14 @@ template <class C> int col_groups(const gp_ctx* c, int ny, int nx) {
   const int G = c->col_g[prec<C>()][ilog2i(ny)];
   return 2 * G > nx ? nx / 2 : G;
 }
-// log2 of the strip width of the tiled intermediate, fixed by the column pass
-template <class C> int col_lgtw(const gp_ctx* c, int ny, int nx) { return ilog2i(2 * col_groups<C>(c, ny, nx)); }
+// log2 of the strip width TW of the tiled intermediate: the stored width, at
+// least one column-pass block (2G columns) and at most the grid width.  Row
+// kernels store 2 TW-wide segments per row pair and strip, so a wider tile
+// gives longer contiguous stores; a column block covers 2G of the TW columns.
+template <class C> int col_lgtw(const gp_ctx* c, int ny, int nx) {
+  const int lo = ilog2i(2 * col_groups<C>(c, ny, nx)), hi = ilog2i(nx);
+  return std::max(lo, std::min(c->col_lw[prec<C>()][ilog2i(ny)], hi));
+}
 
 template <class C> const C* tw_of(const Tables& T);
 template <> const float2* tw_of<float2>(const Tables& T) { return T.tw32; }
@@ -343,7 +356,8 @@ template <class C> struct Pass {
       const int blocks = (nx / 2 + G - 1) / G;
       const Tables& T = c->tab[ilog2i(N)];
       hipLaunchKernelGGL((k_cols_solve<N, C>), dim3(blocks, m), dim3(G * Sched<N>::T), (G * ColShape<N, C>::GROUP_LDS),
-                         c->stream, buf, nx, active, tw_of<C>(T), dw_of<C>(T), mux, muy, alpha, inv_nn);
+                         c->stream, buf, nx, active, tw_of<C>(T), dw_of<C>(T), mux, muy, alpha, inv_nn,
+                         col_lgtw<C>(c, N, nx));
     }
   };
 };
@@ -783,16 +797,30 @@ template <class F> double time_ms(gp_ctx* c, F&& launch, int reps = 3) {
 // intermediate), the column pass, and the row inverse in place on the
 // intermediate.  Results are cached per precision and transform length in the
 // context; shapes fixed with gp_set_shape are kept.
-int tune_group(gp_ctx* c, const Group& g) {
-  const bool f64 = g.kind == GP_KIND_EMD;
-  const int di = f64 ? 1 : 0, ly = ilog2i(g.nyi), lx = ilog2i(g.nx);
+int tune_group(gp_ctx* c, const Group& g0) {
+  const bool f64 = g0.kind == GP_KIND_EMD;
+  const int di = f64 ? 1 : 0, ly = ilog2i(g0.nyi), lx = ilog2i(g0.nx);
   if (c->col_tuned[di][ly] && c->row_tuned[di][lx]) return GP_OK;
+  // time a prefix of the stack of at most 16M cells: one steady iteration per
+  // candidate (A in its steady mode, the column pass, the row inverse), reading
+  // the state and writing only a scratch allocation and the intermediate
+  Group g = g0;
+  g.m = std::max(1, std::min(g0.m, (1 << 24) / (g0.nyi * g0.nx)));
+  const size_t nt = g.ntot();
+  float* scr = nullptr;
+  if (hipMalloc(&scr, (f64 ? 4 : 2) * nt * sizeof(float)) != hipSuccess) {
+    set_err(c, "tuning scratch allocation of %zu bytes failed", (f64 ? 4 : 2) * nt * sizeof(float));
+    return GP_ENOMEM;
+  }
   const ShapeInfo sy = f64 ? shape_info<double2>(g.nyi) : shape_info<float2>(g.nyi);
   const ShapeInfo sx = f64 ? shape_info<double2>(g.nx) : shape_info<float2>(g.nx);
-  std::vector<int> cols, rows;
+  std::vector<int> cols, rows, tiles;
   if (c->col_tuned[di][ly]) cols.push_back(c->col_g[di][ly]);
   else
     for (int G = 2; G <= sy.col_gmax && 2 * G <= g.nx; G *= 2) cols.push_back(G);
+  if (c->col_tuned[di][ly]) tiles.push_back(c->col_lw[di][ly]);
+  else
+    for (int l = 2; l <= kTileLgMax && (1 << l) <= g.nx; ++l) tiles.push_back(l);
   if (c->row_tuned[di][lx]) rows.push_back(c->row_g[di][lx]);
   else
     for (int G = sx.row_gm; G <= sx.row_gmax; G *= 2) rows.push_back(G);
@@ -800,38 +828,75 @@ int tune_group(gp_ctx* c, const Group& g) {
   const bool prof = c->prof_on;
   c->prof_on = false;
   double best = 1e30;
-  int bc = c->col_g[di][ly], br = c->row_g[di][lx];
-  for (int cg : cols)
-    for (int rg : rows) {
-      c->col_g[di][ly] = cg;
-      c->row_g[di][lx] = rg;
-      const double t = time_ms(c, [&] {
-        if (f64) {
-          EmdPipe P{c, &g, g.p, g.pbar, g.w0, g.w1};
-          (void)emd_A(P, 1, false);
-          GP_DISPATCH_NM(g.nyi, P64, cols, c, g.rhat64, g.nx, g.m, nullptr, g.mux64, g.muy64, 0.0,
-                         1.0 / (double(g.nyi) * g.nx));
-          GP_DISPATCH_NM(g.nx, P64, rows_inv, c, g.rhat64, g.rhat64, g.nyi, g.m, nullptr);
-        } else {
-          RofPipe P{c, &g, g.p, g.pbar};
-          (void)rof_A(P, 1, false);
-          GP_DISPATCH_NM(g.nyi, P32, cols, c, g.rhat, g.nx, g.m, nullptr, g.mux32, g.muy32, float(g.lambda * g.tau),
-                         float(1.0 / (double(g.nyi) * g.nx)));
-          GP_DISPATCH_NM(g.nx, P32, rows_inv, c, g.rhat, g.rhat, g.nyi, g.m, nullptr);
-        }
-      });
-      if (t < best) {
-        best = t;
-        bc = cg;
-        br = rg;
-      }
+  int bc = c->col_g[di][ly], br = c->row_g[di][lx], bl = c->col_lw[di][ly];
+  const int dc = bc, dr = br, dl = bl;  // the setting before tuning (the defaults)
+  double t_def = 1e30, t_dl = 1e30;       // the defaults; the best at the default tile width
+  int dl_c = bc, dl_r = br;
+  for (int cg : cols) {
+    std::vector<int> lws;  // tile widths below 2G are the same as 2G
+    for (int l : tiles) {
+      const int e = std::max(l, ilog2i(2 * cg));
+      if (lws.empty() || lws.back() != e) lws.push_back(e);
     }
+    for (int lw : lws)
+      for (int rg : rows) {
+        c->col_g[di][ly] = cg;
+        c->col_lw[di][ly] = lw;
+        c->row_g[di][lx] = rg;
+        const double t = time_ms(c, [&] {
+          if (f64) {
+            // dual and stored field to scratch; the potential's row inverse to scratch
+            EmdPipe P{c, &g, g.p, scr, g.w0, scr + 2 * nt};
+            (void)emd_A(P, 0, false);
+            GP_DISPATCH_NM(g.nyi, P64, cols, c, g.rhat64, g.nx, g.m, g.active, g.mux64, g.muy64, 0.0,
+                           1.0 / (double(g.nyi) * g.nx));
+            GP_DISPATCH_NM(g.nx, P64, rows_inv, c, g.rhat64, reinterpret_cast<double*>(scr), g.nyi, g.m, g.active);
+          } else {
+            // dual to scratch; the update is applied to a scratch copy of u
+            RofPipe P{c, &g, g.p, scr};
+            (void)rof_A(P, 0, false);
+            GP_DISPATCH_NM(g.nyi, P32, cols, c, g.rhat, g.nx, g.m, g.active, g.mux32, g.muy32, float(g.lambda * g.tau),
+                           float(1.0 / (double(g.nyi) * g.nx)));
+            GP_DISPATCH_NM(g.nx, Fused, rof_B, c, g.rhat, scr, g.nyi, g.m, g.active);
+          }
+        }, 7);
+        if (lw == std::max(dl, ilog2i(2 * cg))) {
+          if (cg == dc && rg == dr) t_def = t;
+          if (t < t_dl) {
+            t_dl = t;
+            dl_c = cg;
+            dl_r = rg;
+          }
+        }
+        if (t < best) {
+          best = t;
+          bc = cg;
+          br = rg;
+          bl = lw;
+        }
+      }
+  }
+  // keep the default tile width, and then the default groups, unless another
+  // choice is clearly (1%) faster: near-ties are timing noise, and a stable
+  // choice keeps runs comparable
+  if (t_def <= 1.01 * best) {
+    bc = dc;
+    br = dr;
+    bl = dl;
+  } else if (t_dl <= 1.01 * best) {
+    bc = dl_c;
+    br = dl_r;
+    bl = dl;
+  }
   c->col_g[di][ly] = bc;
+  c->col_lw[di][ly] = bl;
   c->row_g[di][lx] = br;
   c->col_tuned[di][ly] = true;
   c->row_tuned[di][lx] = true;
   c->prof_on = prof;
-  return hipGetLastError() == hipSuccess ? GP_OK : GP_EHIP;
+  const bool ok = hipGetLastError() == hipSuccess;
+  HIPCHK(c, hipFree(scr));
+  return ok ? GP_OK : GP_EHIP;
 }
 
 // ---------------------------------------------------------------- batch
@@ -1591,15 +1656,16 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
   return restore(all_conv ? GP_OK : GP_ENOTCONV);
 }
 
-int gp_get_shape(gp_ctx* c, int fp64, int n, int* row_groups, int* col_groups) {
+int gp_get_shape(gp_ctx* c, int fp64, int n, int* row_groups, int* col_groups, int* tile_width) {
   if (!c || !is_pow2_in_range(n)) return c ? GP_EUNSUPPORTED : GP_EINVAL;
   const int di = fp64 ? 1 : 0, ln = ilog2i(n);
   if (row_groups) *row_groups = c->row_g[di][ln];
   if (col_groups) *col_groups = c->col_g[di][ln];
+  if (tile_width) *tile_width = 1 << c->col_lw[di][ln];
   return GP_OK;
 }
 
-int gp_set_shape(gp_ctx* c, int fp64, int n, int row_groups, int col_groups) {
+int gp_set_shape(gp_ctx* c, int fp64, int n, int row_groups, int col_groups, int tile_width) {
   if (!c) return GP_EINVAL;
   if (!is_pow2_in_range(n)) {
     set_err(c, "n must be a power of two in [%d, %d]", kMinN, kMaxN);
@@ -1615,15 +1681,18 @@ int gp_set_shape(gp_ctx* c, int fp64, int n, int row_groups, int col_groups) {
     set_err(c, "column groups %d invalid for n=%d (powers of two up to %d)", col_groups, n, si.col_gmax);
     return GP_EINVAL;
   }
+  if (tile_width && (tile_width < 2 || tile_width > 64 || (tile_width & (tile_width - 1)))) {
+    set_err(c, "tile width %d invalid (powers of two in [2, 64])", tile_width);
+    return GP_EINVAL;
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (row_groups) {
     c->row_g[di][ln] = row_groups;
     c->row_tuned[di][ln] = true;
   }
-  if (col_groups) {
-    c->col_g[di][ln] = col_groups;
-    c->col_tuned[di][ln] = true;
-  }
+  if (col_groups) c->col_g[di][ln] = col_groups;
+  if (tile_width) c->col_lw[di][ln] = ilog2i(tile_width);
+  if (col_groups || tile_width) c->col_tuned[di][ln] = true;
   return GP_OK;
 }
 

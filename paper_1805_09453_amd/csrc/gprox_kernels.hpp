@@ -174,7 +174,7 @@ template <int N, class C>
 __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW)) void k_cols_solve(
     typename Cx<C>::R* buf, int nx, const int* __restrict__ active, const C* __restrict__ tw,
     const C* __restrict__ dctw, const typename Cx<C>::R* __restrict__ mux,
-    const typename Cx<C>::R* __restrict__ muy, typename Cx<C>::R alpha, typename Cx<C>::R inv_nn) {
+    const typename Cx<C>::R* __restrict__ muy, typename Cx<C>::R alpha, typename Cx<C>::R inv_nn, int lgtw) {
   using Re = typename Cx<C>::R;
   using SH = ColShape<N, C>;
   if (!inst_active(active, blockIdx.y)) return;  // whole workgroup: instance retired
@@ -185,12 +185,14 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
   const int g = threadIdx.x % G, t = threadIdx.x / G;
   C* lds = smem + g * Sched<N>::LDS;
   // XCD-aware strip order: strips that share cache lines run under one L2
-  const int strip = xcd_block(blockIdx.x, gridDim.x);
-  // this block's strip of TW = 2G columns is contiguous (tile_idx layout)
-  const int TW = 2 * G;
-  const int c = strip * TW + 2 * g;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  // strips of TW = 2^lgtw columns are contiguous (tile_idx layout); a block
+  // takes 2G of them (TW / 2G blocks per strip)
+  const int TW = 1 << lgtw, per = TW / (2 * G);
+  const int strip = blk / per, sub = blk - strip * per;
+  const int c = strip * TW + 2 * (sub * G + g);
   const bool valid = c < nx;
-  Re* col = buf + (valid ? size_t(strip) * N * TW + 2 * g : 0);
+  Re* col = buf + (valid ? size_t(strip) * N * TW + 2 * (sub * G + g) : 0);
   const int ld = TW;
   Vals<N, C> v;
   dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {

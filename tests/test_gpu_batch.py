@@ -151,7 +151,8 @@ def test_batch_emd_potential_output_equals_single_solve(gpctx):
 
 def test_launch_shapes_do_not_change_results(gpctx):
     """Every FFT group computes the same arithmetic whatever the number of groups
-    per workgroup: solves under other row / column shapes are bit-identical."""
+    per workgroup or the tile width of the intermediate: solves under other
+    row / column / tile shapes are bit-identical."""
     from paper_1805_09453_amd import GPError, Options
     I = dev(synth.rof_scene(256, 31))
     r0, r1 = synth.emd_mixture_pair(128, 32, k=4)
@@ -163,9 +164,9 @@ def test_launch_shapes_do_not_change_results(gpctx):
     u0, p0, rep0 = gpctx.rof_solve(I, 1.0, 8.0, o_rof)
     m0, phi0, rpe0 = gpctx.emd_solve(r0, r1, 1.0 / 128, o_emd)
     try:
-        for rg, cg in ((8, 2), (32, 4), (16, 32)):
-            gpctx.set_shape(False, 256, rg, cg)
-            gpctx.set_shape(True, 128, 16, min(cg, 16))
+        for rg, cg, tw in ((8, 2, 4), (32, 4, 64), (16, 32, 2), (16, 1, 32)):
+            gpctx.set_shape(False, 256, rg, cg, tw)
+            gpctx.set_shape(True, 128, 16, min(cg, 16), tw)
             print("shapes", gpctx.get_shape(False, 256), gpctx.get_shape(True, 128))
             u, p, rep = gpctx.rof_solve(I, 1.0, 8.0, o_rof)
             m, phi, rpe = gpctx.emd_solve(r0, r1, 1.0 / 128, o_emd)
@@ -177,6 +178,8 @@ def test_launch_shapes_do_not_change_results(gpctx):
             gpctx.set_shape(False, 256, 3, 0)   # not a whole number of waves
         with pytest.raises(GPError):
             gpctx.set_shape(False, 256, 0, 3)   # not a power of two
+        with pytest.raises(GPError):
+            gpctx.set_shape(False, 256, 0, 0, 12)  # tile width not a power of two
     finally:
         gpctx.set_shape(False, 256, *saved[0])
         gpctx.set_shape(True, 128, *saved[1])
