@@ -643,15 +643,16 @@ int emd_finish(EmdPipe& P, const float* wt, bool state, float* mout) {
 int emd_cert_enqueue(gp_ctx* c, const Group& g, const float* p, double* phi, double* tmp, double* cpart, double* out) {
   const size_t n = size_t(g.nyi) * g.nx, nt = g.ntot();
   int ps = prof_begin(c, K_DIV64, 16.0 * double(nt));
-  hipLaunchKernelGGL(k_div<double>, dim3(grid_for(nt)), dim3(256), 0, c->stream, p, p + nt, phi, g.nyi * g.m, g.nx,
-                     g.nyi, float(1.0 / g.h), g.active);
+  const int bx = std::min(256, g.nx);  // the grid widths are powers of two >= 64
+  hipLaunchKernelGGL(k_div<double>, dim3(g.nx / bx, std::min(g.nyi * g.m, 65535)), dim3(bx), 0, c->stream, p, p + nt,
+                     phi, g.nyi * g.m, g.nx, g.nyi, float(1.0 / g.h), g.active);
   prof_end(c, ps);
   LAUNCHCHK(c);
   // Delta phi_c = div p  <=>  (0 I - Delta) phi_c = -div p: solving with div p gives -phi_c
   RCHK(poisson_f64(c, phi, phi, g.nyi, g.nx, g.m, g.active, g.mux64, g.muy64, 0.0, tmp));
-  const int nbc = red_blocks(n);
+  const int nbc = std::min(red_blocks(n), g.nyi);  // row-strided blocks
   ps = prof_begin(c, K_REDUCE, 12.0 * double(nt));
-  hipLaunchKernelGGL(k_emd_cert, dim3(nbc, g.m), dim3(256), 0, c->stream, phi, g.f, g.nyi, g.nx, 1.0 / g.h, g.norm,
+  hipLaunchKernelGGL(k_emd_cert, dim3(nbc, g.m), dim3(bx), 0, c->stream, phi, g.f, g.nyi, g.nx, 1.0 / g.h, g.norm,
                      cpart);
   prof_end(c, ps);
   LAUNCHCHK(c);
@@ -1813,9 +1814,9 @@ int ws_emd_solve(gp_ctx* c, ws_net* net, const float* rho0, const float* rho1, f
     return GP_EHIP;
   }
   // D(phi0): the certificate of the prediction itself
-  const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_phi_cert, dim3(nb), dim3(256), 0, c->stream, phi0, rho0, rho1, ny, nx, 1.0 / h, o->norm,
-                     c->partials);
+  const int nb = std::min(red_blocks(n), ny);  // row-strided blocks of min(256, nx) threads
+  hipLaunchKernelGGL(k_phi_cert, dim3(nb), dim3(std::min(256, nx)), 0, c->stream, phi0, rho0, rho1, ny, nx, 1.0 / h,
+                     o->norm, c->partials);
   LAUNCHCHK(c);
   double r[2];
   RCHK(finalize_read(c, c->partials, nb, 1, 2, 2u, r));

@@ -69,6 +69,12 @@ __device__ __forceinline__ void mk_put(C* lds, int j, typename Cx<C>::R ra, type
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
 __device__ __forceinline__ float f4(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+// Loads of halo cells that may not exist are issued unconditionally from an
+// in-bounds address and the value is masked afterwards: a load under a branch
+// makes the compiler wait for the loads before it, serialising the memory
+// round trips of a row pair.
+__device__ __forceinline__ float4 sel4(bool c, float4 v) { return c ? v : make_float4(0.f, 0.f, 0.f, 0.f); }
+template <class T> __device__ __forceinline__ T sel(bool c, T v) { return c ? v : T(0); }
 
 // pointwise ROF dual step at one cell: p_new = proj(p + s grad u)
 __device__ __forceinline__ void rof_dual_pt(float px, float py, float gx, float gy, float s, int aniso, float& ox,
@@ -109,23 +115,25 @@ __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::
     for (int k = 0; k < Sched<N>::E / 4; ++k) {
       const int c = 4 * (t + T * k);
       const bool has_l = c > 0, has_r = c + 4 < N;
+      const int cl = has_l ? c - 1 : c, cr = has_r ? c + 4 : c;  // in-bounds halo columns
       float ra[4], rb[4];
       if (mode == 0) {
-        // u at rows a-1, a, b, b+1 (columns c-1 .. c+4 where needed)
-        const float4 uU = has_up ? ld4(u + ou + c) : make_float4(0, 0, 0, 0);
+        // u at rows a-1, a, b, b+1 (columns c-1 .. c+4 where needed); without a
+        // row below, od = ob and uD = uB (the y-difference at b is masked below)
+        const float4 uU = sel4(has_up, ld4(u + ou + c));
         const float4 uA = ld4(u + oa + c), uB = ld4(u + ob + c);
-        const float4 uD = has_dn ? ld4(u + od + c) : uB;
-        const float uU4 = (has_up && has_r) ? u[ou + c + 4] : 0.f;
-        const float uA4 = has_r ? u[oa + c + 4] : 0.f, uB4 = has_r ? u[ob + c + 4] : 0.f;
-        const float uAl = has_l ? u[oa + c - 1] : 0.f, uBl = has_l ? u[ob + c - 1] : 0.f;
-        const float uDl = has_l ? (has_dn ? u[od + c - 1] : uBl) : 0.f;
+        const float4 uD = ld4(u + od + c);
+        const float uU4 = sel(has_up && has_r, u[ou + cr]);
+        const float uA4 = sel(has_r, u[oa + cr]), uB4 = sel(has_r, u[ob + cr]);
+        const float uAl = sel(has_l, u[oa + cl]), uBl = sel(has_l, u[ob + cl]);
+        const float uDl = sel(has_l, u[od + cl]);
         // p_{n-1}
-        const float4 pxU = has_up ? ld4(pinx + ou + c) : make_float4(0, 0, 0, 0);
-        const float4 pyU = has_up ? ld4(piny + ou + c) : make_float4(0, 0, 0, 0);
+        const float4 pxU = sel4(has_up, ld4(pinx + ou + c));
+        const float4 pyU = sel4(has_up, ld4(piny + ou + c));
         const float4 pxA = ld4(pinx + oa + c), pyA = ld4(piny + oa + c);
         const float4 pxB = ld4(pinx + ob + c), pyB = ld4(piny + ob + c);
-        const float pxAl = has_l ? pinx[oa + c - 1] : 0.f, pyAl = has_l ? piny[oa + c - 1] : 0.f;
-        const float pxBl = has_l ? pinx[ob + c - 1] : 0.f, pyBl = has_l ? piny[ob + c - 1] : 0.f;
+        const float pxAl = sel(has_l, pinx[oa + cl]), pyAl = sel(has_l, piny[oa + cl]);
+        const float pxBl = sel(has_l, pinx[ob + cl]), pyBl = sel(has_l, piny[ob + cl]);
         const float4 IA = ld4(I + oa + c), IB = ld4(I + ob + c);
         // p_n and pbar_n at (a-1, c..c+3), (a, c-1..c+3), (b, c-1..c+3); index e = -1..3
         float nxA[5], nyA[5], nxB[5], nyB[5], byU[4], bxA[5], byA[5], bxB[5], byB[5];
@@ -202,8 +210,8 @@ __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::
         const float4 IA = ld4(I + oa + c), IB = ld4(I + ob + c);
         const float4 xA = ld4(pinx + oa + c), yA = ld4(piny + oa + c);
         const float4 xB = ld4(pinx + ob + c), yB = ld4(piny + ob + c);
-        const float4 yU = has_up ? ld4(piny + ou + c) : make_float4(0, 0, 0, 0);
-        const float xAl = has_l ? pinx[oa + c - 1] : 0.f, xBl = has_l ? pinx[ob + c - 1] : 0.f;
+        const float4 yU = sel4(has_up, ld4(piny + ou + c));
+        const float xAl = sel(has_l, pinx[oa + cl]), xBl = sel(has_l, pinx[ob + cl]);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int j = c + e;
@@ -349,6 +357,7 @@ __global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>
     for (int k = 0; k < Sched<N>::E / 4; ++k) {
       const int c = 4 * (t + T * k);
       const bool has_l = c > 0, has_r = c + 4 < N;
+      const int cl = has_l ? c - 1 : c, cr = has_r ? c + 4 : c;  // in-bounds halo columns
       // new wt at (a-1, c..c+3) [y only], (a, c-1..c+3), (b, c-1..c+3)
       float wxA[5], wyA[5], wxB[5], wyB[5], wyU[4];
       if (mode == 0) {
@@ -360,39 +369,32 @@ __global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>
           double2 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
           fA[1] = a0.x; fA[2] = a0.y; fA[3] = a1.x; fA[4] = a1.y;
           fB[1] = b0.x; fB[2] = b0.y; fB[3] = b1.x; fB[4] = b1.y;
-          fA[0] = has_l ? phi[oa + c - 1] : 0.0;
-          fB[0] = has_l ? phi[ob + c - 1] : 0.0;
-          fA[5] = has_r ? phi[oa + c + 4] : 0.0;
-          fB[5] = has_r ? phi[ob + c + 4] : 0.0;
-          if (has_up) {
-            const double2* pu = reinterpret_cast<const double2*>(phi + ou + c);
-            double2 u0 = pu[0], u1 = pu[1];
-            fU[0] = u0.x; fU[1] = u0.y; fU[2] = u1.x; fU[3] = u1.y;
-            fU[4] = has_r ? phi[ou + c + 4] : 0.0;
-          } else {
-            fU[0] = fU[1] = fU[2] = fU[3] = fU[4] = 0.0;
-          }
-          if (has_dn) {
-            const double2* pd = reinterpret_cast<const double2*>(phi + od + c);
-            double2 d0 = pd[0], d1 = pd[1];
-            fD[1] = d0.x; fD[2] = d0.y; fD[3] = d1.x; fD[4] = d1.y;
-            fD[0] = has_l ? phi[od + c - 1] : 0.0;
-          } else {
-            fD[0] = fD[1] = fD[2] = fD[3] = fD[4] = 0.0;
-          }
+          fA[0] = sel(has_l, phi[oa + cl]);
+          fB[0] = sel(has_l, phi[ob + cl]);
+          fA[5] = sel(has_r, phi[oa + cr]);
+          fB[5] = sel(has_r, phi[ob + cr]);
+          // rows a-1 and b+1 (ou = oa, od = ob where they do not exist)
+          const double2* pu = reinterpret_cast<const double2*>(phi + ou + c);
+          const double2* pd = reinterpret_cast<const double2*>(phi + od + c);
+          const double2 u0 = pu[0], u1 = pu[1], d0 = pd[0], d1 = pd[1];
+          const double fu4 = phi[ou + cr], fdl = phi[od + cl];
+          fU[0] = sel(has_up, u0.x); fU[1] = sel(has_up, u0.y); fU[2] = sel(has_up, u1.x); fU[3] = sel(has_up, u1.y);
+          fU[4] = sel(has_up && has_r, fu4);
+          fD[1] = sel(has_dn, d0.x); fD[2] = sel(has_dn, d0.y); fD[3] = sel(has_dn, d1.x); fD[4] = sel(has_dn, d1.y);
+          fD[0] = sel(has_dn && has_l, fdl);
         }
         const float4 wxa = ld4(wt_in + oa + c), wya = ld4(wt_in + n + oa + c);
         const float4 wxb = ld4(wt_in + ob + c), wyb = ld4(wt_in + n + ob + c);
-        const float4 wyu = has_up ? ld4(wt_in + n + ou + c) : make_float4(0, 0, 0, 0);
-        const float4 wxu = has_up ? ld4(wt_in + ou + c) : make_float4(0, 0, 0, 0);
-        const float wxal = has_l ? wt_in[oa + c - 1] : 0.f, wyal = has_l ? wt_in[n + oa + c - 1] : 0.f;
-        const float wxbl = has_l ? wt_in[ob + c - 1] : 0.f, wybl = has_l ? wt_in[n + ob + c - 1] : 0.f;
+        const float4 wyu = sel4(has_up, ld4(wt_in + n + ou + c));
+        const float4 wxu = sel4(has_up, ld4(wt_in + ou + c));
+        const float wxal = sel(has_l, wt_in[oa + cl]), wyal = sel(has_l, wt_in[n + oa + cl]);
+        const float wxbl = sel(has_l, wt_in[ob + cl]), wybl = sel(has_l, wt_in[n + ob + cl]);
         const float4 pxa = ld4(pin + oa + c), pya = ld4(pin + n + oa + c);
         const float4 pxb = ld4(pin + ob + c), pyb = ld4(pin + n + ob + c);
-        const float4 pxu = has_up ? ld4(pin + ou + c) : make_float4(0, 0, 0, 0);
-        const float4 pyu = has_up ? ld4(pin + n + ou + c) : make_float4(0, 0, 0, 0);
-        const float pxal = has_l ? pin[oa + c - 1] : 0.f, pyal = has_l ? pin[n + oa + c - 1] : 0.f;
-        const float pxbl = has_l ? pin[ob + c - 1] : 0.f, pybl = has_l ? pin[n + ob + c - 1] : 0.f;
+        const float4 pxu = sel4(has_up, ld4(pin + ou + c));
+        const float4 pyu = sel4(has_up, ld4(pin + n + ou + c));
+        const float pxal = sel(has_l, pin[oa + cl]), pyal = sel(has_l, pin[n + oa + cl]);
+        const float pxbl = sel(has_l, pin[ob + cl]), pybl = sel(has_l, pin[n + ob + cl]);
         float nxA[4], nyA[4], nxB[4], nyB[4];
 #pragma unroll
         for (int e = -1; e < 4; ++e) {

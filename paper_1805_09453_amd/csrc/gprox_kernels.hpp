@@ -375,20 +375,26 @@ __global__ __launch_bounds__(256) void k_rof_energy(const float* __restrict__ u,
   block_reduce_store<4>(acc, mx, partials);
 }
 
-// r = s div v (s = +-1/h); T = float or double output
+// r = s div v (s = +-1/h); T = float or double output.  Columns over
+// blockIdx.x * blockDim.x + threadIdx.x (nx a multiple of blockDim.x), rows
+// over blockIdx.y with stride gridDim.y.
 template <class T>
 __global__ __launch_bounds__(256) void k_div(const float* __restrict__ vx, const float* __restrict__ vy,
                                              T* __restrict__ r, int ny, int nx, int nyi, float s,
                                              const int* __restrict__ active) {
-  const size_t n = size_t(ny) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
-    const int i = int(o / nx), j = int(o - size_t(i) * nx);
-    if (!inst_active(active, i / nyi)) continue;
-    const int il = i % nyi;
-    const float xr = (j < nx - 1) ? vx[o] : 0.f;
-    const float xl = (j > 0) ? vx[o - 1] : 0.f;
-    const float yu = (il < nyi - 1) ? vy[o] : 0.f;
-    const float yd = (il > 0) ? vy[o - nx] : 0.f;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int i = blockIdx.y; i < ny; i += gridDim.y) {
+    const int inst = i / nyi, il = i - inst * nyi;
+    if (!inst_active(active, inst)) continue;
+    const size_t o = size_t(i) * nx + j;
+    float vxo = vx[o], vyo = vy[o], vxl = vx[o - (j > 0 ? 1 : 0)], vyd = vy[o - (il > 0 ? nx : 0)];
+    // all four loads are in flight before any is masked (keeps the compiler
+    // from moving a load under the mask's branch)
+    asm volatile("" : "+v"(vxo), "+v"(vyo), "+v"(vxl), "+v"(vyd));
+    const float xr = (j < nx - 1) ? vxo : 0.f;
+    const float xl = (j > 0) ? vxl : 0.f;
+    const float yu = (il < nyi - 1) ? vyo : 0.f;
+    const float yd = (il > 0) ? vyd : 0.f;
     r[o] = T((xr - xl) + (yu - yd)) * T(s);
   }
 }
@@ -405,39 +411,57 @@ __global__ __launch_bounds__(256) void k_emd_primal(const float* __restrict__ ux
 }
 
 // certificate partials per instance (blockIdx.y): [sum phi f, max |grad phi|]
-// (gradient in 1/h units) -> partials[(inst * gridDim.x + blockIdx.x) * 2 + i]
+// (gradient in 1/h units) -> partials[(inst * gridDim.x + blockIdx.x) * 2 + i].
+// Rows are strided over the blocks and a row's cells over the threads; nx must
+// be a multiple of blockDim.x.  A missing neighbour is read as the cell itself,
+// so its difference is exactly 0 and every load is unconditional (loads under a
+// branch would serialise the memory round trips); the isotropic maximum is
+// taken over |g|^2 and rooted once per thread.
 __global__ __launch_bounds__(256) void k_emd_cert(const double* __restrict__ phi, const float* __restrict__ f,
                                                   int nyi, int nx, double inv_h, int aniso,
                                                   double* __restrict__ partials) {
   double acc[2] = {0, 0};
-  const size_t n = size_t(nyi) * nx, base = size_t(blockIdx.y) * n;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
-    const int i = int(o / nx), j = int(o - size_t(i) * nx);
-    const double fc = phi[base + o];
-    const double gx = (j < nx - 1) ? (phi[base + o + 1] - fc) * inv_h : 0.0;
-    const double gy = (i < nyi - 1) ? (phi[base + o + nx] - fc) * inv_h : 0.0;
-    acc[0] += fc * double(f[base + o]);
-    const double L = aniso ? fmax(fabs(gx), fabs(gy)) : sqrt(gx * gx + gy * gy);
-    acc[1] = fmax(acc[1], L);
+  const size_t base = size_t(blockIdx.y) * nyi * nx;
+  const int kn = nx / int(blockDim.x);
+  for (int i = blockIdx.x; i < nyi; i += gridDim.x) {
+    const double* pr = phi + base + size_t(i) * nx;
+    const float* fr_ = f + base + size_t(i) * nx;
+    const int dn = i < nyi - 1 ? nx : 0;
+#pragma unroll 4
+    for (int k = 0; k < kn; ++k) {
+      const int j = threadIdx.x + k * int(blockDim.x);
+      const double fc = pr[j], fr = pr[j + (j < nx - 1 ? 1 : 0)], fu = pr[j + dn];
+      const double gx = (fr - fc) * inv_h, gy = (fu - fc) * inv_h;
+      acc[0] += fc * double(fr_[j]);
+      acc[1] = fmax(acc[1], aniso ? fmax(fabs(gx), fabs(gy)) : gx * gx + gy * gy);
+    }
   }
+  if (!aniso) acc[1] = sqrt(acc[1]);
   const bool m[2] = {false, true};
   block_reduce_store<2>(acc, m, partials + size_t(blockIdx.y) * gridDim.x * 2);
 }
 
 // certificate of a given FP32 potential phi: [sum phi (rho0 - rho1), max |grad_h phi|]
+// (same walk as k_emd_cert; nx a multiple of blockDim.x)
 __global__ __launch_bounds__(256) void k_phi_cert(const float* __restrict__ phi, const float* __restrict__ r0,
                                                   const float* __restrict__ r1, int ny, int nx, double inv_h,
                                                   int aniso, double* __restrict__ partials) {
   double acc[2] = {0, 0};
-  const size_t n = size_t(ny) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
-    const int i = int(o / nx), j = int(o - size_t(i) * nx);
-    const double fc = phi[o];
-    const double gx = (j < nx - 1) ? (double(phi[o + 1]) - fc) * inv_h : 0.0;
-    const double gy = (i < ny - 1) ? (double(phi[o + nx]) - fc) * inv_h : 0.0;
-    acc[0] += fc * (double(r0[o]) - double(r1[o]));
-    acc[1] = fmax(acc[1], aniso ? fmax(fabs(gx), fabs(gy)) : sqrt(gx * gx + gy * gy));
+  const int kn = nx / int(blockDim.x);
+  for (int i = blockIdx.x; i < ny; i += gridDim.x) {
+    const size_t row = size_t(i) * nx;
+    const int dn = i < ny - 1 ? nx : 0;
+#pragma unroll 4
+    for (int k = 0; k < kn; ++k) {
+      const size_t o = row + threadIdx.x + size_t(k) * blockDim.x;
+      const int j = int(o - row);
+      const double fc = phi[o], fr = phi[o + (j < nx - 1 ? 1 : 0)], fu = phi[o + dn];
+      const double gx = (fr - fc) * inv_h, gy = (fu - fc) * inv_h;
+      acc[0] += fc * (double(r0[o]) - double(r1[o]));
+      acc[1] = fmax(acc[1], aniso ? fmax(fabs(gx), fabs(gy)) : gx * gx + gy * gy);
+    }
   }
+  if (!aniso) acc[1] = sqrt(acc[1]);
   const bool m[2] = {false, true};
   block_reduce_store<2>(acc, m, partials);
 }
