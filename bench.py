@@ -287,8 +287,9 @@ def main():
         extra["rof"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
         if not args.no_emd:
             t0 = time.perf_counter()
-            _, _, rep = ctx.emd_solve(r0, r1, 1.0 / n, Options(tau=args.emd_tau, tol=args.tol, max_iter=20000,
-                                                                check_every=50), want_phi=False)
+            _, _, rep = ctx.emd_solve(r0, r1, 1.0 / n, Options(tau=args.emd_tau, tol=args.tol,
+                                                                max_iter=args.warm_max_iter, check_every=50),
+                                      want_phi=False)
             torch.cuda.synchronize()
             extra["emd"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
     if not args.no_warm and not args.no_emd:
