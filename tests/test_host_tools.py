@@ -1,0 +1,28 @@
+"""Host-side logic that needs no GPU: the rocprofv3 summariser's kernel-name
+shortening and its steady-state counter figure."""
+from paper_1805_09453_amd import profsum
+
+
+def test_short_names():
+    assert profsum.short("void gp::k_rof_A<4096>(float const*, float*)") == "k_rof_A<4096>"
+    assert profsum.short("void gp::k_cols_solve<4096, HIP_vector_type<double, 2u> >(double*, int)") == \
+        "k_cols_solve<4096, f64>"
+
+
+def test_counter_figure_is_the_late_median():
+    """Early dispatches (tuner launches in their entry mode, fewer stores) must not
+    pull the figure down: the median over the later half of the dispatches is used,
+    and the copy calibration is the largest copy dispatch."""
+    rows = []
+    did = 0
+    for v in [70000.0, 69000.0, 90000.0, 71000.0, 209000.0, 208000.0, 210000.0, 77000.0, 209500.0, 208500.0]:
+        did += 1
+        rows.append({"Kernel_Name": "void gp::k_rof_A<4096>(float const*)", "Counter_Value": str(v),
+                     "Dispatch_Id": str(did)})
+    for v in [12.0, 262144.0, 40.0]:
+        did += 1
+        rows.append({"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Value": str(v), "Dispatch_Id": str(did)})
+    per, copy = profsum.counter_means(rows)
+    assert copy == 262144.0
+    # later half: 208000, 210000, 77000, 209500, 208500 -> median 208500
+    assert per["k_rof_A<4096>"] == 208500.0
