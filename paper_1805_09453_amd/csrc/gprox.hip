@@ -6,6 +6,7 @@
 // instances by kind, size, h, lambda and tau, captures chunks of iterations of
 // all groups in one hipGraph and retires converged instances between replays
 // through per-instance active flags.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,6 +89,7 @@ struct gp_ctx {
   size_t barena_bytes = 0;
   // per-kernel timing (gp_profile)
   bool prof_on = false;
+  int prof_arm = -1;  // profiling slot the next GP_LAUNCH times (-1: none)
   std::vector<hipEvent_t> prof_ev;  // 2 per recorded launch
   std::vector<int> prof_id;
   std::vector<double> prof_bytes;
@@ -110,6 +112,10 @@ const char* kKName[K_COUNT] = {"rows_fwd_dct2", "cols_solve", "rows_inv_dct2", "
 constexpr int kProfPool = 16384;
 
 // records a start event for a launch of kind id moving `bytes`; returns the slot or -1
+// Per-launch timing: prof_begin arms a slot and the next GP_LAUNCH passes the
+// slot's two events to hipExtLaunchKernelGGL, which binds them to that kernel's
+// own dispatch (start and end timestamps of the kernel, no extra packets in the
+// stream: event records between launches would add dispatch gaps to the loop).
 int prof_begin(gp_ctx* c, int id, double bytes) {
   if (!c->prof_on) return -1;
   if (c->prof_used >= kProfPool) {
@@ -119,12 +125,27 @@ int prof_begin(gp_ctx* c, int id, double bytes) {
   const int s = c->prof_used++;
   c->prof_id[s] = id;
   c->prof_bytes[s] = bytes;
-  (void)hipEventRecord(c->prof_ev[2 * s], c->stream);
+  c->prof_arm = s;
   return s;
 }
 void prof_end(gp_ctx* c, int s) {
-  if (s >= 0) (void)hipEventRecord(c->prof_ev[2 * s + 1], c->stream);
+  if (s >= 0 && c->prof_arm == s) {  // no launch took the slot: drop it
+    c->prof_arm = -1;
+    c->prof_id[s] = -1;
+  }
 }
+
+#define GP_LAUNCH(ctx, kernel, grid, block, shmem, stream, ...)                                            \
+  do {                                                                                                     \
+    if ((ctx)->prof_arm >= 0) {                                                                            \
+      const int a_ = (ctx)->prof_arm;                                                                      \
+      (ctx)->prof_arm = -1;                                                                                \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, (ctx)->prof_ev[2 * a_],                   \
+                            (ctx)->prof_ev[2 * a_ + 1], 0, __VA_ARGS__);                                   \
+    } else {                                                                                               \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                                 \
+    }                                                                                                      \
+  } while (0)
 
 void set_err(gp_ctx* c, const char* fmt, ...) {
   if (!c) return;
@@ -242,9 +263,9 @@ __global__ void k_mu(double* __restrict__ m64, float* __restrict__ m32, int n, d
 }
 
 int fill_mu(gp_ctx* c, double* y64, float* y32, double* x64, float* x32, int ny, int nx, double h) {
-  hipLaunchKernelGGL(k_mu, dim3((ny + 255) / 256), dim3(256), 0, c->stream, y64, y32, ny, h);
+  GP_LAUNCH(c, k_mu, dim3((ny + 255) / 256), dim3(256), 0, c->stream, y64, y32, ny, h);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL(k_mu, dim3((nx + 255) / 256), dim3(256), 0, c->stream, x64, x32, nx, h);
+  GP_LAUNCH(c, k_mu, dim3((nx + 255) / 256), dim3(256), 0, c->stream, x64, x32, nx, h);
   LAUNCHCHK(c);
   return GP_OK;
 }
@@ -339,14 +360,14 @@ template <class C> struct Pass {
       const int G = c->row_g[prec<C>()][ilog2i(N)];
       const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
       const Tables& T = c->tab[ilog2i(N)];
-      hipLaunchKernelGGL((k_rows_fwd<N, C>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, C>::GROUP_LDS),
+      GP_LAUNCH(c, (k_rows_fwd<N, C>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, C>::GROUP_LDS),
                          c->stream, in, out, ny, nyi, active, col_lgtw<C>(c, nyi, N), tw_of<C>(T), dw_of<C>(T));
     }
     static void rows_inv(gp_ctx* c, const Re* in, Re* out, int nyi, int m, const int* active) {
       const int G = c->row_g[prec<C>()][ilog2i(N)];
       const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
       const Tables& T = c->tab[ilog2i(N)];
-      hipLaunchKernelGGL((k_rows_inv<N, C>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, C>::GROUP_LDS),
+      GP_LAUNCH(c, (k_rows_inv<N, C>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, C>::GROUP_LDS),
                          c->stream, in, out, ny, nyi, active, col_lgtw<C>(c, nyi, N), tw_of<C>(T), dw_of<C>(T));
     }
     // here N is the column length nyi
@@ -355,7 +376,7 @@ template <class C> struct Pass {
       const int G = col_groups<C>(c, N, nx);
       const int blocks = (nx / 2 + G - 1) / G;
       const Tables& T = c->tab[ilog2i(N)];
-      hipLaunchKernelGGL((k_cols_solve<N, C>), dim3(blocks, m), dim3(G * Sched<N>::T), (G * ColShape<N, C>::GROUP_LDS),
+      GP_LAUNCH(c, (k_cols_solve<N, C>), dim3(blocks, m), dim3(G * Sched<N>::T), (G * ColShape<N, C>::GROUP_LDS),
                          c->stream, buf, nx, active, tw_of<C>(T), dw_of<C>(T), mux, muy, alpha, inv_nn,
                          col_lgtw<C>(c, N, nx));
     }
@@ -371,7 +392,7 @@ template <int N> struct Fused {
     const int G = c->row_g[0][ilog2i(N)];
     const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_rof_A<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
+    GP_LAUNCH(c, (k_rof_A<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
                        c->stream, u, pin, pout, I, rhat, ny, nyi, active, col_lgtw<float2>(c, nyi, N), lt, tau_h, sig_h,
                        aniso, mode, partials, T.tw32, T.dw32);
   }
@@ -379,7 +400,7 @@ template <int N> struct Fused {
     const int G = c->row_g[0][ilog2i(N)];
     const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_rof_B<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
+    GP_LAUNCH(c, (k_rof_B<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
                        c->stream, dhat, u, ny, nyi, active, col_lgtw<float2>(c, nyi, N), T.tw32, T.dw32);
   }
   static void emd_A(gp_ctx* c, const float* wt_in, const double* phi, const float* pin, const float* gpsi,
@@ -388,7 +409,7 @@ template <int N> struct Fused {
     const int G = c->row_g[1][ilog2i(N)];
     const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
-    hipLaunchKernelGGL((k_emd_A<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, double2>::GROUP_LDS),
+    GP_LAUNCH(c, (k_emd_A<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, double2>::GROUP_LDS),
                        c->stream, wt_in, phi, pin, gpsi, f, pout, wt_out, rhat, ny, nyi, active,
                        col_lgtw<double2>(c, nyi, N), inv_h, tau, sigma, aniso, mode, partials, T.tw64, T.dw64);
   }
@@ -455,7 +476,7 @@ int prepare(gp_ctx* c, int ny, int nx, double h) {
 // finalizes m segments of seg partials (K values each) into c->result and copies
 // them to out (synchronises); m * K <= kResult
 int finalize_read(gp_ctx* c, const double* partials, int seg, int m, int K, unsigned max_mask, double* out) {
-  hipLaunchKernelGGL(k_finalize, dim3(m), dim3(256), 0, c->stream, partials, seg, K, max_mask, c->result);
+  GP_LAUNCH(c, k_finalize, dim3(m), dim3(256), 0, c->stream, partials, seg, K, max_mask, c->result);
   LAUNCHCHK(c);
   HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, size_t(m) * K * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
@@ -466,7 +487,7 @@ int finalize_read(gp_ctx* c, const double* partials, int seg, int m, int K, unsi
 
 int count_nonfinite(gp_ctx* c, const float* x, size_t n, double* cnt) {
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_nonfinite, dim3(nb), dim3(256), 0, c->stream, x, n, c->partials);
+  GP_LAUNCH(c, k_nonfinite, dim3(nb), dim3(256), 0, c->stream, x, n, c->partials);
   LAUNCHCHK(c);
   return finalize_read(c, c->partials, nb, 1, 1, 0u, cnt);
 }
@@ -575,7 +596,7 @@ int rof_finish(RofPipe& P) {
   gp_ctx* c = P.c;
   const Group& g = *P.g;
   const int ps = prof_begin(c, K_ROF_FINISH, 28.0 * double(g.ntot()));
-  hipLaunchKernelGGL(k_rof_finish, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, g.u, P.X, g.p, g.pbar,
+  GP_LAUNCH(c, k_rof_finish, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, g.u, P.X, g.p, g.pbar,
                      g.nyi * g.m, g.nx, g.nyi, float(g.sigma / g.h), g.norm);
   prof_end(c, ps);
   LAUNCHCHK(c);
@@ -627,7 +648,7 @@ int emd_finish(EmdPipe& P, const float* wt, bool state, float* mout) {
   gp_ctx* c = P.c;
   const Group& g = *P.g;
   const int ps = prof_begin(c, K_EMD_FINISH, (state ? 56.0 : 24.0) * double(g.ntot()));
-  hipLaunchKernelGGL(k_emd_finish, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, wt, g.phi, P.X, g.gpsi,
+  GP_LAUNCH(c, k_emd_finish, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, wt, g.phi, P.X, g.gpsi,
                      state ? g.p : nullptr, g.pbar, state ? g.u : nullptr, mout, g.nyi * g.m, g.nx, g.nyi, 1.0 / g.h,
                      float(g.sigma), g.norm);
   prof_end(c, ps);
@@ -644,7 +665,7 @@ int emd_cert_enqueue(gp_ctx* c, const Group& g, const float* p, double* phi, dou
   const size_t n = size_t(g.nyi) * g.nx, nt = g.ntot();
   int ps = prof_begin(c, K_DIV64, 16.0 * double(nt));
   const int bx = std::min(256, g.nx);  // the grid widths are powers of two >= 64
-  hipLaunchKernelGGL(k_div<double>, dim3(g.nx / bx, std::min(g.nyi * g.m, 65535)), dim3(bx), 0, c->stream, p, p + nt,
+  GP_LAUNCH(c, k_div<double>, dim3(g.nx / bx, std::min(g.nyi * g.m, 65535)), dim3(bx), 0, c->stream, p, p + nt,
                      phi, g.nyi * g.m, g.nx, g.nyi, float(1.0 / g.h), g.active);
   prof_end(c, ps);
   LAUNCHCHK(c);
@@ -652,11 +673,11 @@ int emd_cert_enqueue(gp_ctx* c, const Group& g, const float* p, double* phi, dou
   RCHK(poisson_f64(c, phi, phi, g.nyi, g.nx, g.m, g.active, g.mux64, g.muy64, 0.0, tmp));
   const int nbc = std::min(red_blocks(n), g.nyi);  // row-strided blocks
   ps = prof_begin(c, K_REDUCE, 12.0 * double(nt));
-  hipLaunchKernelGGL(k_emd_cert, dim3(nbc, g.m), dim3(bx), 0, c->stream, phi, g.f, g.nyi, g.nx, 1.0 / g.h, g.norm,
+  GP_LAUNCH(c, k_emd_cert, dim3(nbc, g.m), dim3(bx), 0, c->stream, phi, g.f, g.nyi, g.nx, 1.0 / g.h, g.norm,
                      cpart);
   prof_end(c, ps);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL(k_finalize, dim3(g.m), dim3(256), 0, c->stream, cpart, nbc, 2, 2u, out);
+  GP_LAUNCH(c, k_finalize, dim3(g.m), dim3(256), 0, c->stream, cpart, nbc, 2, 2u, out);
   LAUNCHCHK(c);
   return GP_OK;
 }
@@ -719,7 +740,7 @@ int rof_gap_state(gp_ctx* c, const gp_state* s, double* P, double* D) {
   const size_t n = size_t(s->ny) * s->nx;
   const int nb = red_blocks(n);
   const int ps = prof_begin(c, K_REDUCE, 16.0 * n);
-  hipLaunchKernelGGL(k_rof_energy, dim3(nb), dim3(256), 0, c->stream, s->u, s->p, s->p + n, s->f, s->ny, s->nx,
+  GP_LAUNCH(c, k_rof_energy, dim3(nb), dim3(256), 0, c->stream, s->u, s->p, s->p + n, s->f, s->ny, s->nx,
                      float(1.0 / s->h), s->norm, c->partials);
   prof_end(c, ps);
   LAUNCHCHK(c);
@@ -734,7 +755,7 @@ int rof_gap_state(gp_ctx* c, const gp_state* s, double* P, double* D) {
 int emd_primal_state(gp_ctx* c, const gp_state* s, double* P) {
   const size_t n = size_t(s->ny) * s->nx;
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_emd_primal, dim3(nb), dim3(256), 0, c->stream, s->u, s->u + n, s->gpsi, s->gpsi + n, n,
+  GP_LAUNCH(c, k_emd_primal, dim3(nb), dim3(256), 0, c->stream, s->u, s->u + n, s->gpsi, s->gpsi + n, n,
                      s->norm, c->partials);
   LAUNCHCHK(c);
   double r[1];
@@ -1211,7 +1232,7 @@ int emd_setup(gp_ctx* c, const float* rho0, const float* rho1, float* f, float* 
   RCHK(prepare(c, ny, nx, h));
   const size_t n = size_t(ny) * nx;
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_mass, dim3(nb), dim3(256), 0, c->stream, rho0, rho1, n, c->partials);
+  GP_LAUNCH(c, k_mass, dim3(nb), dim3(256), 0, c->stream, rho0, rho1, n, c->partials);
   LAUNCHCHK(c);
   double r[3];
   RCHK(finalize_read(c, c->partials, nb, 1, 3, 0u, r));
@@ -1228,11 +1249,11 @@ int emd_setup(gp_ctx* c, const float* rho0, const float* rho1, float* f, float* 
   double* f64 = c->work64;
   double* psi = c->work64;  // the solve consumes f64 before writing psi over it
   double* tmp = c->work64 + n;
-  hipLaunchKernelGGL(k_f64_diff, dim3(grid_for(n)), dim3(256), 0, c->stream, rho0, rho1, c->result,
+  GP_LAUNCH(c, k_f64_diff, dim3(grid_for(n)), dim3(256), 0, c->stream, rho0, rho1, c->result,
                      1.0 / double(n), n, f64, f);
   LAUNCHCHK(c);
   RCHK(poisson_f64(c, f64, psi, ny, nx, 1, nullptr, c->mux64, c->muy64, 0.0, tmp));
-  hipLaunchKernelGGL(k_grad_f64, dim3(grid_for(n)), dim3(256), 0, c->stream, psi, gpsi, gpsi + n, ny, nx, 1.0 / h);
+  GP_LAUNCH(c, k_grad_f64, dim3(grid_for(n)), dim3(256), 0, c->stream, psi, gpsi, gpsi + n, ny, nx, 1.0 / h);
   LAUNCHCHK(c);
   return GP_OK;
 }
@@ -1271,7 +1292,7 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   HIPCHK(c, hipMemsetAsync(P0, 0, 2 * n * sizeof(float), c->stream));
   if (o->warm_start) {
     // p0 = proj(grad phi0): the ROF dual step with u = phi0, p = 0, sigma/h = 1/h
-    hipLaunchKernelGGL(k_rof_finish, dim3(grid_for(n)), dim3(256), 0, c->stream, phi, P0, P0, P1, ny, nx, ny,
+    GP_LAUNCH(c, k_rof_finish, dim3(grid_for(n)), dim3(256), 0, c->stream, phi, P0, P0, P1, ny, nx, ny,
                        float(1.0 / h), o->norm);
     LAUNCHCHK(c);
   }
@@ -1295,7 +1316,7 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
     ++it;
     if (chk) {
       RCHK(emd_cert_enqueue(c, g, pipe.X, cphi, ctmp, cpart, c->result + 8));
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, g.gpart, ny / 2, 1, 0u, c->result);
+      GP_LAUNCH(c, k_finalize, dim3(1), dim3(256), 0, c->stream, g.gpart, ny / 2, 1, 0u, c->result);
       LAUNCHCHK(c);
       HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1317,7 +1338,7 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   RCHK(emd_finish(pipe, pipe.WY, false, m));
   if (phi) {
     // cphi holds -phi_c from the last certificate; phi~ = phi_c / max(1, L)
-    hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, cphi, phi, n,
+    GP_LAUNCH(c, k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, cphi, phi, n,
                        -1.0 / (L > 1.0 ? L : 1.0));
     LAUNCHCHK(c);
   }
@@ -1516,7 +1537,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
       }
     }
     if (rc) break;
-    hipLaunchKernelGGL(k_finalize, dim3(g.m), dim3(256), 0, c->stream, g.gpart, g.nyi / 2,
+    GP_LAUNCH(c, k_finalize, dim3(g.m), dim3(256), 0, c->stream, g.gpart, g.nyi / 2,
                        g.kind == GP_KIND_ROF ? 4 : 1, 0u, G[k].gap_dev);
     if (hipGetLastError() != hipSuccess) {
       set_err(c, "k_finalize launch failed during capture");
@@ -1628,7 +1649,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
         cp(in.out + n, bg.mflux + nt + q * n, n * sizeof(float));
         if (in.phi) {
           const double L = Lv[bg.idx[q]];
-          hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->bstream, bg.cphi + q * n, in.phi, n,
+          GP_LAUNCH(c, k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->bstream, bg.cphi + q * n, in.phi, n,
                              -1.0 / (L > 1.0 ? L : 1.0));
           ok = ok && hipGetLastError() == hipSuccess;
         }
@@ -1815,7 +1836,7 @@ int ws_emd_solve(gp_ctx* c, ws_net* net, const float* rho0, const float* rho1, f
   }
   // D(phi0): the certificate of the prediction itself
   const int nb = std::min(red_blocks(n), ny);  // row-strided blocks of min(256, nx) threads
-  hipLaunchKernelGGL(k_phi_cert, dim3(nb), dim3(std::min(256, nx)), 0, c->stream, phi0, rho0, rho1, ny, nx, 1.0 / h,
+  GP_LAUNCH(c, k_phi_cert, dim3(nb), dim3(std::min(256, nx)), 0, c->stream, phi0, rho0, rho1, ny, nx, 1.0 / h,
                      o->norm, c->partials);
   LAUNCHCHK(c);
   double r[2];
@@ -1868,6 +1889,7 @@ int gp_profile_read(gp_ctx* c, gp_kstat* out, int max, int* n_out) {
   double ms[K_COUNT] = {0}, by[K_COUNT] = {0};
   long long cnt[K_COUNT] = {0};
   for (int s = 0; s < c->prof_used; ++s) {
+    if (c->prof_id[s] < 0) continue;
     float t = 0.f;
     HIPCHK(c, hipEventElapsedTime(&t, c->prof_ev[2 * s], c->prof_ev[2 * s + 1]));
     ms[c->prof_id[s]] += t;

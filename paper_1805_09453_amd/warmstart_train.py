@@ -1,6 +1,6 @@
 """Train the warm-start network on solutions of the EMD iteration itself.
 
-    python -m paper_1805_09453_amd.warmstart_train --pairs 4096 --epochs 30 --native 128 \
+    python -m paper_1805_09453_amd.warmstart_train --pairs 20000 --epochs 30 --batch 32 --native 128 \
         --out paper_1805_09453_amd/weights/ws_unet.f32 --summary paper_1805_09453_amd/weights/ws_unet.json
 
 Steps (everything numerical runs in libgprox on the GPU; this module only
@@ -146,9 +146,9 @@ def evaluate(ctx, ws, E0, E1, tol, max_iter, n=N_NATIVE):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--pairs", type=int, default=2048)
-    ap.add_argument("--epochs", type=int, default=6)
-    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--pairs", type=int, default=20000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--target-tol", type=float, default=1e-4)
     ap.add_argument("--target-max-iter", type=int, default=8000)
