@@ -34,7 +34,20 @@ def emd_c1_mixture():
                 tau=0.3, iters=r.iters, primal=r.primal, dual=r.dual, rel_gap=r.rel_gap)
 
 
-JOBS = {"rof_c0": rof_c0, "emd_c1_mixture": emd_c1_mixture}
+def emd_aniso_64():
+    import numpy as np
+
+    from oracle import grid
+    n = 64
+    rho0, rho1 = synth.emd_mixture_pair(n, 17, k=2)
+    # the densities as the GPU receives them (FP32)
+    rho0, rho1 = (np.asarray(a, np.float32).astype(np.float64) for a in (rho0, rho1))
+    r = emd.solve(rho0, rho1, 1.0 / n, tau=0.3, tol=1e-7, max_iter=400000, check_every=50, norm=grid.ANISO)
+    return dict(workload="EMD 64x64, 2-Gaussian mixtures (seed 17) rounded to FP32, l1 grid norm, h=1/64",
+                tau=0.3, iters=r.iters, primal=r.primal, dual=r.dual, rel_gap=r.rel_gap)
+
+
+JOBS = {"rof_c0": rof_c0, "emd_c1_mixture": emd_c1_mixture, "emd_aniso_64": emd_aniso_64}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(JOBS)
