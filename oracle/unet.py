@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The warm start is not part of the paper.  It predicts an initial dual
 potential phi0 from the two densities; the EMD iteration of section 3.2
-(Algorithm 2) then starts from p0 = proj(grad phi0), u0 = 0 and remains the
-judge through its duality gap.  At a saddle point of that iteration the dual
+(Algorithm 2) then starts from p0 = proj(grad phi0), u0 = 0, and its duality
+gap still decides when the solve is done.  At a saddle point of that iteration the dual
 p is a gradient field (its divergence-free part vanishes) bounded by 1, i.e.
 the gradient of a 1-Lipschitz Kantorovich potential, which is what the
 network is trained to approximate.

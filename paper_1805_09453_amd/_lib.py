@@ -94,8 +94,7 @@ def load():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            raise ImportError(f"libgprox.so not found at {LIB}: run paper_1805_09453_amd.build.build() "
-                              "(or __graft_entry__.build()) first")
+            raise ImportError(f"libgprox.so not found at {LIB}: run paper_1805_09453_amd.build.build() first")
         lib = ctypes.CDLL(LIB)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)
