@@ -84,7 +84,24 @@ def targets(ctx, R0, R1, tol, max_iter, chunk=256):
     return PHI, iters
 
 
-def train(ws, R0, R1, PHI, epochs, batch, lr, val=32, seed=0):
+def symmetry(a, c, t, code):
+    """One of the 16 symmetries of a pair on the square: the 8 rotations and
+    reflections of the grid (the potential moves with the densities) and the
+    exchange of the two densities (the potential changes sign).  Index
+    permutations and a sign only."""
+    import torch
+    if code & 1:
+        a, c, t = (torch.flip(x, dims=(-1,)) for x in (a, c, t))
+    if code & 2:
+        a, c, t = (torch.flip(x, dims=(-2,)) for x in (a, c, t))
+    if code & 4:
+        a, c, t = (x.transpose(-1, -2) for x in (a, c, t))
+    if code & 8:
+        a, c, t = c, a, -t
+    return a.contiguous(), c.contiguous(), t.contiguous()
+
+
+def train(ws, R0, R1, PHI, epochs, batch, lr, val=32, seed=0, augment=True):
     import torch
     N, n = R0.shape[0], R0.shape[1]
     ntr = N - val
@@ -97,6 +114,8 @@ def train(ws, R0, R1, PHI, epochs, batch, lr, val=32, seed=0):
         for b in range(ntr // batch):
             idx = torch.tensor(perm[b * batch:(b + 1) * batch], device=R0.device)
             a, c, t = R0.index_select(0, idx), R1.index_select(0, idx), PHI.index_select(0, idx)
+            if augment:
+                a, c, t = symmetry(a, c, t, int(rng.integers(16)))
             tr.append(ws.grads(a, c, t, 1.0 / n))
             cur = lr * 0.5 * (1 + math.cos(math.pi * step / steps))
             ws.adam(cur)
@@ -157,6 +176,7 @@ def main(argv=None):
     ap.add_argument("--eval-max-iter", type=int, default=40000)
     ap.add_argument("--init-seed", type=int, default=1)
     ap.add_argument("--native", type=int, default=128, help="network resolution (divides 512)")
+    ap.add_argument("--no-augment", action="store_true", help="train without the 16 grid/exchange symmetries")
     ap.add_argument("--out", required=True)
     ap.add_argument("--summary")
     a = ap.parse_args(argv)
@@ -196,7 +216,7 @@ def main(argv=None):
     assert o == ws.n_params
     ws.set_params(torch.tensor(blob, device="cuda"))
     log("training")
-    hist = train(ws, R0, R1, PHI, a.epochs, a.batch, a.lr)
+    hist = train(ws, R0, R1, PHI, a.epochs, a.batch, a.lr, augment=not a.no_augment)
     params = ws.get_params().cpu().numpy()
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     params.astype("<f4").tofile(a.out)
@@ -205,6 +225,7 @@ def main(argv=None):
     torch.cuda.empty_cache()
     ev = evaluate(ctx, ws, E0, E1, a.eval_tol, a.eval_max_iter) if a.eval_pairs else None
     summary = {"pairs": a.pairs, "native": nn, "solve_grid": n, "epochs": a.epochs, "batch": a.batch, "lr": a.lr,
+               "augment": not a.no_augment,
                "target_tol": a.target_tol, "target_iters_median": int(np.median(titers)),
                "history": hist, "eval": ev, "seconds": time.time() - t_all}
     if a.summary:

@@ -26,3 +26,23 @@ def test_counter_figure_is_the_late_median():
     assert copy == 262144.0
     # later half: 208000, 210000, 77000, 209500, 208500 -> median 208500
     assert per["k_rof_A<4096>"] == 208500.0
+
+
+def test_training_symmetries():
+    """The 16 training symmetries: distinct on a generic pair, reflections are
+    involutions, and the density exchange negates the potential."""
+    import torch
+
+    from paper_1805_09453_amd.warmstart_train import symmetry
+    g = torch.Generator().manual_seed(0)
+    a, c, t = (torch.rand((2, 8, 8), generator=g) for _ in range(3))
+    seen = set()
+    for code in range(16):
+        x = symmetry(a, c, t, code)
+        seen.add(tuple(round(float(v), 6) for v in torch.cat([y.flatten() for y in x])[:24]))
+    assert len(seen) == 16
+    for code in (1, 2, 4, 8):
+        x = symmetry(*symmetry(a, c, t, code), code)
+        assert all(torch.equal(p, q) for p, q in zip(x, (a, c, t)))
+    sa, sc, st = symmetry(a, c, t, 8)
+    assert torch.equal(sa, c) and torch.equal(sc, a) and torch.equal(st, -t)
