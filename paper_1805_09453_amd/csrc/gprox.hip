@@ -392,9 +392,15 @@ template <int N> struct Fused {
     const int G = c->row_g[0][ilog2i(N)];
     const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
-    GP_LAUNCH(c, (k_rof_A<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
-                       c->stream, u, pin, pout, I, rhat, ny, nyi, active, col_lgtw<float2>(c, nyi, N), lt, tau_h, sig_h,
-                       aniso, mode, partials, T.tw32, T.dw32);
+    // the gap partials are a compile-time variant: without them the accumulators free registers
+    if (partials)
+      GP_LAUNCH(c, (k_rof_A<N, true>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
+                c->stream, u, pin, pout, I, rhat, ny, nyi, active, col_lgtw<float2>(c, nyi, N), lt, tau_h, sig_h,
+                aniso, mode, partials, T.tw32, T.dw32);
+    else
+      GP_LAUNCH(c, (k_rof_A<N, false>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
+                c->stream, u, pin, pout, I, rhat, ny, nyi, active, col_lgtw<float2>(c, nyi, N), lt, tau_h, sig_h,
+                aniso, mode, partials, T.tw32, T.dw32);
   }
   static void rof_B(gp_ctx* c, const float* dhat, float* u, int nyi, int m, const int* active) {
     const int G = c->row_g[0][ilog2i(N)];
@@ -409,9 +415,14 @@ template <int N> struct Fused {
     const int G = c->row_g[1][ilog2i(N)];
     const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
-    GP_LAUNCH(c, (k_emd_A<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, double2>::GROUP_LDS),
-                       c->stream, wt_in, phi, pin, gpsi, f, pout, wt_out, rhat, ny, nyi, active,
-                       col_lgtw<double2>(c, nyi, N), inv_h, tau, sigma, aniso, mode, partials, T.tw64, T.dw64);
+    if (partials)
+      GP_LAUNCH(c, (k_emd_A<N, true>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, double2>::GROUP_LDS),
+                c->stream, wt_in, phi, pin, gpsi, f, pout, wt_out, rhat, ny, nyi, active, col_lgtw<double2>(c, nyi, N),
+                inv_h, tau, sigma, aniso, mode, partials, T.tw64, T.dw64);
+    else
+      GP_LAUNCH(c, (k_emd_A<N, false>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, double2>::GROUP_LDS),
+                c->stream, wt_in, phi, pin, gpsi, f, pout, wt_out, rhat, ny, nyi, active, col_lgtw<double2>(c, nyi, N),
+                inv_h, tau, sigma, aniso, mode, partials, T.tw64, T.dw64);
   }
 };
 

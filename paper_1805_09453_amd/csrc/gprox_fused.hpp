@@ -87,9 +87,9 @@ __device__ __forceinline__ void rof_dual_pt(float px, float py, float gx, float 
 // ---------------------------------------------------------------- ROF A
 // mode 0 (steady): p_in = p_{n-1}; computes p_n (written to p_out) and pbar_n.
 // mode 1 (entry):  p_in = pbar_n given by the caller; p_out unused.
-// Gap partials (mode 0, partials != nullptr): [sum|grad u|, sum (u-I)^2,
+// Gap partials (PART, mode 0; partials non-null): [sum|grad u|, sum (u-I)^2,
 // sum I div p_n, sum (div p_n)^2] in 1/h units.
-template <int N>
+template <int N, bool PART>
 __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::MINW)) void k_rof_A(const float* __restrict__ u, const float* __restrict__ pin,
                                                float* __restrict__ pout, const float* __restrict__ I,
                                                float* __restrict__ rhat, int ny, int nyi, const int* __restrict__ active,
@@ -173,7 +173,7 @@ __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::
             rof_dual_pt(f4(pxU, e), f4(pyU, e), gxu, gyu, sig_h, aniso, ox, oy);
             byU[e] = has_up ? 2.f * oy - f4(pyU, e) : 0.f;
             // gap partials of (u_n, p_n) at rows a, b
-            if (partials) {
+            if constexpr (PART) {
               acc[0] += double(pnorm(gxa, gya, aniso)) + double(pnorm(gxb, gyb, aniso));
               const float ea = f4(uA, e) - f4(IA, e), eb = f4(uB, e) - f4(IB, e);
               acc[1] += double(ea) * ea + double(eb) * eb;
@@ -233,7 +233,7 @@ __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::
     for (int m = t; m < N; m += T) lds[lpad(m)] = make_float2(0.f, 0.f);
   }
   // gap partials per row pair (so that each instance of a batch has its own)
-  if (partials) group_reduce_store<4, T>(acc, valid ? partials + size_t(a / 2) * 4 : nullptr, t);
+  if constexpr (PART) group_reduce_store<4, T>(acc, valid ? partials + size_t(a / 2) * 4 : nullptr, t);
   __syncthreads();
   Vals<N, float2> v;
   dct2_fwd_lds<N>(t, v, lds, tw, dctw);
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_rof_finish(const float* __restrict__ u,
 // mode 0 (steady): wt_in = wt_n, phi = phi_n, p_in = p_n -> p_out = p_{n+1}, wt_out = wt_{n+1};
 //                  partials (nullable): [sum |m_{n+1}|].
 // mode 1 (entry):  u = u_n (in wt_in's place), p_in = pbar_n, gpsi = grad psi -> wt_out = wt_n.
-template <int N>
+template <int N, bool PART>
 __global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>::MINW)) void k_emd_A(const float* __restrict__ wt_in, const double* __restrict__ phi,
                                                const float* __restrict__ pin, const float* __restrict__ gpsi,
                                                const float* __restrict__ f, float* __restrict__ pout,
@@ -422,7 +422,7 @@ __global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>
             nyA[e] = qya;
             nxB[e] = xin ? qxb : 0.f;
             nyB[e] = has_dn ? qyb : 0.f;
-            if (partials) acc[0] += double(pnorm(mxa, mya, aniso)) + double(pnorm(mxb, myb, aniso));
+            if constexpr (PART) acc[0] += double(pnorm(mxa, mya, aniso)) + double(pnorm(mxb, myb, aniso));
             // row a-1: y component of the new wt
             if (has_up) {
               const float mxu = xin ? f4(wxu, e) - float((fU[e + 1] - fU[e]) * inv_h) : 0.f;
@@ -475,7 +475,7 @@ __global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>
 #pragma unroll 1
     for (int m = t; m < N; m += T) lds[lpad(m)] = make_double2(0.0, 0.0);
   }
-  if (partials) group_reduce_store<1, T>(acc, valid ? partials + size_t(a / 2) : nullptr, t);
+  if constexpr (PART) group_reduce_store<1, T>(acc, valid ? partials + size_t(a / 2) : nullptr, t);
   __syncthreads();
   Vals<N, double2> v;
   dct2_fwd_lds<N>(t, v, lds, tw, dctw);
