@@ -266,8 +266,10 @@ int ws_upsample(gp_ctx* ctx, const float* in, int ny, int nx, int f, float* out)
 int ws_emd_solve(gp_ctx* ctx, ws_net* net, const float* rho0, const float* rho1, float* m, float* phi, int ny,
                  int nx, double h, const gp_opts* opts, gp_report* rep, ws_report* wrep);
 
-/* Per-kernel timing on the context's stream (HIP events around each kernel
- * launch; for measurement, not needed by the solvers).  gp_profile(ctx, 1)
+/* Per-kernel timing on the context's stream (a start and a stop HIP event
+ * bound to each kernel's own dispatch, i.e. the kernel's execution interval;
+ * for measurement, not needed by the solvers; recording is suspended inside
+ * the captured graphs of gp_batch_solve).  gp_profile(ctx, 1)
  * clears and starts recording (allocates the event pool), gp_profile(ctx, 0)
  * stops.  gp_profile_read synchronises the stream and fills up to max entries
  * (one per kernel kind that ran): total elapsed ms, launch count, and the
