@@ -910,13 +910,14 @@ int tune_group(gp_ctx* c, const Group& g0) {
       }
   }
   // keep the default tile width, and then the default groups, unless another
-  // choice is clearly (1%) faster: near-ties are timing noise, and a stable
-  // choice keeps runs comparable
-  if (t_def <= 1.01 * best) {
+  // choice is clearly (3%) faster: single-iteration timings of near-equal
+  // shapes differ by a few percent from box to box, and a stable choice keeps
+  // runs comparable
+  if (t_def <= 1.03 * best) {
     bc = dc;
     br = dr;
     bl = dl;
-  } else if (t_dl <= 1.01 * best) {
+  } else if (t_dl <= 1.03 * best) {
     bc = dl_c;
     br = dl_r;
     bl = dl;
