@@ -474,13 +474,6 @@ __global__ __launch_bounds__(256) void k_scale(const T* __restrict__ in, float* 
     out[o] = float(s * in[o]);
 }
 
-// m = u + grad psi
-__global__ __launch_bounds__(256) void k_add2(const float* __restrict__ a, const float* __restrict__ b,
-                                              float* __restrict__ out, size_t n) {
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
-    out[o] = a[o] + b[o];
-}
-
 // ------------------------------------------------------------ set-up (FP64)
 // partials: [sum rho0, sum rho1, count(rho0 < 0 or rho1 < 0 or non-finite)]
 __global__ __launch_bounds__(256) void k_mass(const float* __restrict__ r0, const float* __restrict__ r1, size_t n,
