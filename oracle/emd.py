@@ -103,9 +103,11 @@ def rel_gap(P, D):
 
 
 def solve(rho0, rho1, h, tau=1.0, sigma=None, tol=1e-5, max_iter=100000, check_every=10,
-          phi0=None, norm=ISO, callback=None):
+          phi0=None, norm=ISO, callback=None, ergodic=False):
     """Iterate until (P - D)/|P| <= tol on the last iterate or max_iter.
-    Returns a Result whose ``m`` attribute is the flux u + grad psi."""
+    Returns a Result whose ``m`` attribute is the flux u + grad psi.
+    ergodic: evaluate the gap on, and return, the averages u^N, p^N of the
+    iterates n = 1..N (the iterates the section-2 theorems bound)."""
     if sigma is None:
         sigma = 1.0 / tau
     f, psi = setup(rho0, rho1, h)
@@ -122,12 +124,17 @@ def solve(rho0, rho1, h, tau=1.0, sigma=None, tol=1e-5, max_iter=100000, check_e
     it = 0
     P = D = g = np.nan
     conv = False
+    sums = [np.zeros_like(f) for _ in range(4)]
     while it < max_iter:
         ux, uy, px, py, pbx, pby = step(ux, uy, px, py, pbx, pby, gpx, gpy, h, tau, sigma, norm)
         it += 1
+        if ergodic:
+            for acc, x in zip(sums, (ux, uy, px, py)):
+                acc += x
         if it % check_every == 0 or it == max_iter:
-            P = primal(ux, uy, gpx, gpy, h, norm)
-            D = certificate(px, py, f, h, norm)[0]
+            eux, euy, epx, epy = [a / it for a in sums] if ergodic else (ux, uy, px, py)
+            P = primal(eux, euy, gpx, gpy, h, norm)
+            D = certificate(epx, epy, f, h, norm)[0]
             g = rel_gap(P, D)
             hist.append((it, P, D, g))
             if callback is not None:
@@ -135,6 +142,8 @@ def solve(rho0, rho1, h, tau=1.0, sigma=None, tol=1e-5, max_iter=100000, check_e
             if g <= tol:
                 conv = True
                 break
+    if ergodic:
+        ux, uy, px, py = [a / it for a in sums]
     res = Result(ux, uy, px, py, psi, f, it, P, D, g, conv, hist)
     res.m = (ux + gpx, uy + gpy)
     return res

@@ -70,10 +70,12 @@ def rel_gap(P: float, D: float) -> float:
 
 
 def solve(I, h, lam, tau, sigma=None, tol=1e-8, max_iter=100000, check_every=10,
-          u0=None, p0=None, norm=ISO, callback=None) -> Result:
+          u0=None, p0=None, norm=ISO, callback=None, ergodic=False) -> Result:
     """Iterate until the relative gap (P - D)/|P| of the last iterate is <= tol
     (checked every ``check_every`` iterations) or ``max_iter`` is reached.
-    sigma defaults to 1/tau, the choice of every step rule in the paper."""
+    sigma defaults to 1/tau, the choice of every step rule in the paper.
+    ergodic: evaluate the gap on, and return, the averages u^N = (1/N) sum u_n,
+    p^N = (1/N) sum p_n over n = 1..N (the iterates the section-2 theorems bound)."""
     I = np.asarray(I, dtype=np.float64)
     if sigma is None:
         sigma = 1.0 / tau
@@ -88,12 +90,18 @@ def solve(I, h, lam, tau, sigma=None, tol=1e-8, max_iter=100000, check_every=10,
     it = 0
     P = D = g = np.nan
     conv = False
+    su, sx, sy = np.zeros_like(I), np.zeros_like(I), np.zeros_like(I)
     while it < max_iter:
         u, px, py, pbx, pby = step(u, px, py, pbx, pby, I, h, lam, tau, sigma, norm)
         it += 1
+        if ergodic:
+            su += u
+            sx += px
+            sy += py
         if it % check_every == 0 or it == max_iter:
-            P = primal(u, I, h, lam, norm)
-            D = dual(px, py, I, h, lam)
+            eu, ex, ey = (su / it, sx / it, sy / it) if ergodic else (u, px, py)
+            P = primal(eu, I, h, lam, norm)
+            D = dual(ex, ey, I, h, lam)
             g = rel_gap(P, D)
             hist.append((it, P, D, g))
             if callback is not None:
@@ -101,6 +109,8 @@ def solve(I, h, lam, tau, sigma=None, tol=1e-8, max_iter=100000, check_every=10,
             if g <= tol:
                 conv = True
                 break
+    if ergodic:
+        u, px, py = su / it, sx / it, sy / it
     return Result(u, px, py, it, P, D, g, conv, hist)
 
 

@@ -154,3 +154,28 @@ def test_disc_converges_to_corrected_closed_form():
         assert abs(r.u.mean() - I.mean()) < 1e-12
     assert errs[2][0] < errs[0][0] and errs[2][1] < errs[0][1]
     assert errs[2][0] < 0.01 and errs[2][1] < 0.005
+
+
+def test_ergodic_average_is_the_mean_of_the_iterates_and_brackets_the_optimum():
+    """ergodic=True returns (1/N) sum_{n=1..N} (u_n, p_n), checked against a
+    separate loop over rof.step; the averages are feasible (|p| <= 1 is convex),
+    so weak duality D(p^N) <= F* <= P(u^N) holds; the averaged gap closes."""
+    I = synth.rof_scene(16, 3)
+    h, lam, tau = 1.0, 8.0, 0.05
+    K = 7
+    st = (np.zeros_like(I),) + tuple(np.zeros_like(I) for _ in range(4))
+    acc = [np.zeros_like(I) for _ in range(3)]
+    for _ in range(K):
+        st = rof.step(*st, I, h, lam, tau, 1.0 / tau)
+        for a, x in zip(acc, st[:3]):
+            a += x
+    r = rof.solve(I, h, lam, tau, tol=0.0, max_iter=K, check_every=K, ergodic=True)
+    for got, a in zip((r.u, r.px, r.py), acc):
+        np.testing.assert_allclose(got, a / K, rtol=0, atol=1e-14)
+    assert abs(r.primal - rof.primal(acc[0] / K, I, h, lam)) < 1e-12
+    assert abs(r.dual - rof.dual(acc[1] / K, acc[2] / K, I, h, lam)) < 1e-12
+    fstar = rof.solve(I, h, lam, tau, tol=1e-11, max_iter=200000, check_every=100).primal
+    long = rof.solve(I, h, lam, tau, tol=0.0, max_iter=3000, check_every=3000, ergodic=True)
+    for res in (r, long):
+        assert res.dual <= fstar * (1 + 1e-12) and fstar <= res.primal * (1 + 1e-12)
+    assert long.rel_gap < 1e-2 < r.rel_gap
