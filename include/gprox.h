@@ -64,10 +64,17 @@ typedef struct gp_ctx gp_ctx; /* opaque: stream, twiddle tables, workspace */
  * check_every: evaluate the gap every this many iterations (>= 1).
  * norm: GP_NORM_ISO or GP_NORM_ANISO.
  * warm_start: nonzero uses the caller's u/p (ROF) or phi (EMD) as the start.
+ * ergodic: nonzero evaluates the gap on, and returns, the averages
+ *   u^N = (1/N) sum u_n and p^N = (1/N) sum p_n over the iterates n = 1..N of
+ *   this call (the ergodic iterates that the convergence rates of section 2
+ *   are stated for; EMD averages the flux m_n = u_n + grad psi).  The sums are
+ *   FP64 in the context's workspace (ROF 9, EMD 10 more floats of workspace
+ *   per cell) and cost one more pass over them per iteration.  rof_solve and
+ *   emd_solve only; gp_batch_solve rejects it (GP_EUNSUPPORTED).
  */
 typedef struct {
   double tau, sigma, tol;
-  int max_iter, check_every, norm, warm_start;
+  int max_iter, check_every, norm, warm_start, ergodic;
 } gp_opts;
 
 /* Filled by the solvers and by pd_gap. primal/dual are P(u) and D(p)

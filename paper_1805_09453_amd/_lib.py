@@ -13,7 +13,7 @@ GP_NORM_ISO, GP_NORM_ANISO = 0, 1
 
 class gp_opts(ctypes.Structure):
     _fields_ = [("tau", c_double), ("sigma", c_double), ("tol", c_double), ("max_iter", c_int),
-                ("check_every", c_int), ("norm", c_int), ("warm_start", c_int)]
+                ("check_every", c_int), ("norm", c_int), ("warm_start", c_int), ("ergodic", c_int)]
 
 
 class gp_report(ctypes.Structure):

@@ -32,10 +32,11 @@ class Options:
     check_every: int = 10
     norm: int = L.GP_NORM_ISO
     warm_start: bool = False
+    ergodic: bool = False
 
     def c(self) -> L.gp_opts:
         return L.gp_opts(float(self.tau), float(self.sigma), float(self.tol), int(self.max_iter),
-                         int(self.check_every), int(self.norm), int(bool(self.warm_start)))
+                         int(self.check_every), int(self.norm), int(bool(self.warm_start)), int(bool(self.ergodic)))
 
 
 def _torch():

@@ -1172,14 +1172,19 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
     set_err(c, "image has %.0f non-finite values", bad);
     return GP_EINVAL;
   }
-  float* ar = arena(c, 4 * n);
+  // arena: P0, P1 (2 n floats each); ergodic: sums of u and p (3 n doubles), averages (3 n floats)
+  const bool erg = o->ergodic != 0;
+  const size_t nar = (erg ? 13 : 4) * n;
+  float* ar = arena(c, nar);
   if (!ar) {
-    set_err(c, "arena allocation of %zu floats failed", 4 * n);
+    set_err(c, "arena allocation of %zu floats failed", nar);
     return GP_ENOMEM;
   }
   // dual buffers: P0 holds p_0, P1 pbar_0
   float* P0 = ar;
   float* P1 = ar + 2 * n;
+  double* esum = reinterpret_cast<double*>(ar + 4 * n);  // [u | px | py] sums
+  float* eavg = ar + 10 * n;                             // [u | px | py] averages
   if (o->warm_start && p) {
     HIPCHK(c, hipMemcpyAsync(P0, p, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   } else {
@@ -1202,12 +1207,29 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
     ++it;
     const bool chk = (it % o->check_every == 0) || (it == o->max_iter);
     // A computes p_it from (u_it, p_{it-1}) and, on checks, the gap partials of (u_it, p_it)
-    RCHK(rof_A(pipe, 0, chk));
-    if (chk) {
+    RCHK(rof_A(pipe, 0, chk && !erg));
+    if (erg) {
+      // sums of u_1..u_it and p_1..p_it; on checks the gap of their averages
+      GP_LAUNCH(c, k_ergodic_add, dim3(grid_for(n / 4)), dim3(256), 0, c->stream,
+                reinterpret_cast<const float4*>(g.u), reinterpret_cast<double2*>(esum), n / 4, int(it == 1));
+      LAUNCHCHK(c);
+      GP_LAUNCH(c, k_ergodic_add, dim3(grid_for(n / 2)), dim3(256), 0, c->stream,
+                reinterpret_cast<const float4*>(pipe.X), reinterpret_cast<double2*>(esum + n), n / 2, int(it == 1));
+      LAUNCHCHK(c);
+    }
+    if (chk && erg) {
+      GP_LAUNCH(c, k_scale<double>, dim3(grid_for(3 * n)), dim3(256), 0, c->stream, esum, eavg, 3 * n,
+                1.0 / double(it));
+      LAUNCHCHK(c);
+      const gp_state sa{GP_KIND_ROF, ny, nx, o->norm, h, lambda, tau, sigma, I, nullptr, eavg, eavg + n, eavg + n, 0};
+      RCHK(rof_gap_state(c, &sa, &P, &D));
+    } else if (chk) {
       double r[4];
       RCHK(finalize_read(c, g.gpart, ny / 2, 1, 4, 0u, r));
       P = h * r[0] + 0.5 * lambda * h * h * r[1];
       D = -h * r[2] - r[3] / (2.0 * lambda);
+    }
+    if (chk) {
       gap = rel_gap(P, D);
       if (!std::isfinite(gap)) {
         set_err(c, "duality gap became non-finite at iteration %d", it);
@@ -1219,7 +1241,13 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
       }
     }
   }
-  if (p) HIPCHK(c, hipMemcpyAsync(p, pipe.X, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  if (erg) {
+    // the loop ends on a check, so eavg holds the averages over all it iterates
+    HIPCHK(c, hipMemcpyAsync(u, eavg, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    if (p) HIPCHK(c, hipMemcpyAsync(p, eavg + n, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  } else if (p) {
+    HIPCHK(c, hipMemcpyAsync(p, pipe.X, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const double t2 = now_s();
   if (rep) {
@@ -1286,10 +1314,13 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   }
   RCHK(prepare(c, ny, nx, h));
   const size_t n = size_t(ny) * nx;
-  // arena: f, grad psi, u, P0, P1, certificate potential and its intermediate (n doubles each)
-  float* ar = arena(c, 13 * n);
+  // arena: f, grad psi, u, P0, P1, certificate potential and its intermediate (n doubles each);
+  // ergodic: sums of m and p (4 n doubles) and the averaged dual (2 n floats)
+  const bool erg = o->ergodic != 0;
+  const size_t nar = (erg ? 23 : 13) * n;
+  float* ar = arena(c, nar);
   if (!ar) {
-    set_err(c, "arena allocation of %zu floats failed", 13 * n);
+    set_err(c, "arena allocation of %zu floats failed", nar);
     return GP_ENOMEM;
   }
   float* f = ar;
@@ -1299,6 +1330,8 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   float* P1 = ar + 7 * n;
   double* cphi = reinterpret_cast<double*>(ar + 9 * n);
   double* ctmp = reinterpret_cast<double*>(ar + 11 * n);
+  double* esum = reinterpret_cast<double*>(ar + 13 * n);  // [mx | my | px | py] sums
+  float* epavg = ar + 21 * n;                              // [px | py] averages
   RCHK(emd_setup(c, rho0, rho1, f, gpsi, ny, nx, h));
   HIPCHK(c, hipMemsetAsync(u, 0, 2 * n * sizeof(float), c->stream));
   HIPCHK(c, hipMemsetAsync(P0, 0, 2 * n * sizeof(float), c->stream));
@@ -1324,12 +1357,38 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   while (it < o->max_iter) {
     RCHK(emd_CB(pipe));  // phi_it
     const bool chk = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter);
-    RCHK(emd_A(pipe, 0, chk));  // u_{it+1}, p_{it+1}
+    RCHK(emd_A(pipe, 0, chk && !erg));  // u_{it+1}, p_{it+1}
     ++it;
-    if (chk) {
-      RCHK(emd_cert_enqueue(c, g, pipe.X, cphi, ctmp, cpart, c->result + 8));
-      GP_LAUNCH(c, k_finalize, dim3(1), dim3(256), 0, c->stream, g.gpart, ny / 2, 1, 0u, c->result);
+    if (erg) {
+      // sums of m_1..m_it (m_it = the field A read minus grad phi, now in WY) and p_1..p_it
+      GP_LAUNCH(c, k_emd_ergodic_flux, dim3(grid_for(n)), dim3(256), 0, c->stream, pipe.WY, g.phi, esum, ny, nx,
+                1.0 / h, int(it == 1));
       LAUNCHCHK(c);
+      GP_LAUNCH(c, k_ergodic_add, dim3(grid_for(n / 2)), dim3(256), 0, c->stream,
+                reinterpret_cast<const float4*>(pipe.X), reinterpret_cast<double2*>(esum + 2 * n), n / 2,
+                int(it == 1));
+      LAUNCHCHK(c);
+    }
+    if (chk) {
+      const float* pc = pipe.X;
+      if (erg) {
+        // averaged flux into the caller's m with its primal partials, averaged dual for the certificate
+        const int nb = red_blocks(n);
+        GP_LAUNCH(c, k_emd_ergodic_primal, dim3(nb), dim3(256), 0, c->stream, esum, 1.0 / double(it), n, o->norm,
+                  m, c->partials);
+        LAUNCHCHK(c);
+        GP_LAUNCH(c, k_finalize, dim3(1), dim3(256), 0, c->stream, c->partials, nb, 1, 0u, c->result);
+        LAUNCHCHK(c);
+        GP_LAUNCH(c, k_scale<double>, dim3(grid_for(2 * n)), dim3(256), 0, c->stream, esum + 2 * n, epavg, 2 * n,
+                  1.0 / double(it));
+        LAUNCHCHK(c);
+        pc = epavg;
+      } else {
+        GP_LAUNCH(c, k_finalize, dim3(1), dim3(256), 0, c->stream, g.gpart, ny / 2, 1, 0u, c->result);
+        LAUNCHCHK(c);
+      }
+      // (stream order: the certificate's partials overwrite c->partials only after the finalize above)
+      RCHK(emd_cert_enqueue(c, g, pc, cphi, ctmp, cpart, c->result + 8));
       HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
       P = h * h * c->host_result[0];
@@ -1347,7 +1406,8 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
     }
   }
   // flux m_it = wt_{it-1} - grad phi_{it-1}: the stored field the last A read, now in WY
-  RCHK(emd_finish(pipe, pipe.WY, false, m));
+  // (ergodic: the loop ended on a check, which wrote the averaged flux into m)
+  if (!erg) RCHK(emd_finish(pipe, pipe.WY, false, m));
   if (phi) {
     // cphi holds -phi_c from the last certificate; phi~ = phi_c / max(1, L)
     GP_LAUNCH(c, k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, cphi, phi, n,
@@ -1380,6 +1440,10 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
       (o->norm != GP_NORM_ISO && o->norm != GP_NORM_ANISO)) {
     set_err(c, "max_iter and check_every must be >= 1, tol >= 0 and norm valid");
     return GP_EINVAL;
+  }
+  if (o->ergodic) {
+    set_err(c, "ergodic averages are not supported by the batch solver");
+    return GP_EUNSUPPORTED;
   }
   // the chunk between checks has an even length, so the ping-pong buffers hold
   // the same roles at every check

@@ -482,6 +482,62 @@ __global__ __launch_bounds__(256) void k_scale(const T* __restrict__ in, float* 
     out[o] = float(s * in[o]);
 }
 
+// ------------------------------------------------------------ ergodic averages
+// Running FP64 sums of the iterates for the averages x^N = (1/N) sum_{n<=N} x_n
+// that the convergence theorems of section 2 bound.  The sums are FP64 so that
+// the average of N FP32 iterates keeps FP32 accuracy at any N.  n4 = n / 4
+// float4 groups (grid sides are powers of two >= 64, so n is a multiple of 4);
+// first != 0 starts the sum (s = a) instead of adding.
+__global__ __launch_bounds__(256) void k_ergodic_add(const float4* __restrict__ a, double2* __restrict__ s,
+                                                     size_t n4, int first) {
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n4; o += size_t(gridDim.x) * blockDim.x) {
+    const float4 v = a[o];
+    double2 lo = make_double2(v.x, v.y), hi = make_double2(v.z, v.w);
+    if (!first) {
+      const double2 s0 = s[2 * o], s1 = s[2 * o + 1];
+      lo.x += s0.x;
+      lo.y += s0.y;
+      hi.x += s1.x;
+      hi.y += s1.y;
+    }
+    s[2 * o] = lo;
+    s[2 * o + 1] = hi;
+  }
+}
+
+// EMD: the flux m_n = wt - grad phi of the latest iterate (the field the last
+// fused step read and the potential it read, as k_emd_finish forms it, here in
+// FP64) into sm [2][ny][nx].  One instance.
+__global__ __launch_bounds__(256) void k_emd_ergodic_flux(const float* __restrict__ wt,
+                                                          const double* __restrict__ phi, double* __restrict__ sm,
+                                                          int ny, int nx, double inv_h, int first) {
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const double fc = phi[o];
+    const double mx = (j < nx - 1) ? double(wt[o]) - (phi[o + 1] - fc) * inv_h : 0.0;
+    const double my = (i < ny - 1) ? double(wt[o + n]) - (phi[o + nx] - fc) * inv_h : 0.0;
+    sm[o] = first ? mx : sm[o] + mx;
+    sm[o + n] = first ? my : sm[o + n] + my;
+  }
+}
+
+// EMD: the averaged flux m^N = inv sm (written FP32 to mout [2][n]) and the
+// partial sums of its grid norm |m^N| (primal value h^2 sum |m^N|).
+__global__ __launch_bounds__(256) void k_emd_ergodic_primal(const double* __restrict__ sm, double inv, size_t n,
+                                                            int aniso, float* __restrict__ mout,
+                                                            double* __restrict__ partials) {
+  double acc[1] = {0};
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const float mx = float(inv * sm[o]), my = float(inv * sm[o + n]);
+    mout[o] = mx;
+    mout[o + n] = my;
+    acc[0] += double(pnorm(mx, my, aniso));
+  }
+  const bool m[1] = {false};
+  block_reduce_store<1>(acc, m, partials);
+}
+
 // ------------------------------------------------------------ set-up (FP64)
 // partials: [sum rho0, sum rho1, count(rho0 < 0 or rho1 < 0 or non-finite)]
 __global__ __launch_bounds__(256) void k_mass(const float* __restrict__ r0, const float* __restrict__ r1, size_t n,
