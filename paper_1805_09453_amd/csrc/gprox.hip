@@ -1990,3 +1990,7 @@ int gp_profile_read(gp_ctx* c, gp_kstat* out, int max, int* n_out) {
 }
 
 }  // extern "C"
+
+// 3-D grids: orchestration and entry points of the d = 3 solvers, built on the
+// context, tables and launch helpers above
+#include "gprox3d.inc"
