@@ -16,6 +16,8 @@ rof   : the ROF functional (section 3.1, eq. for F_lambda), its dual, and the
 emd   : the Beckmann/L1 EMD problem (section 3.2), the Hodge split, the
         G-prox PDHG iteration (updates of 3.2), the primal value and a dual
         certificate.
+grid3 : the d = 3 case: operators on nz x ny x nx grids (7-point Laplacian,
+        3-D DCT-II), the ROF and EMD iterations, values and certificates.
 unet  : the learned warm start's network (a U-Net predicting the dual
         potential), its parameter gradients, loss, Adam step and the
         resolution changes used at 4096^2.  Not part of the paper.

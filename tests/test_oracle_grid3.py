@@ -1,0 +1,164 @@
+"""Pins of the 3-D oracle (oracle/grid3.py) against things other than itself:
+the adjoint identity, a dense linear solve of the assembled 7-point operator,
+exact reduction to the pinned 2-D oracle for data constant along one axis
+(each axis in turn, both norms), the 1-D closed form of the EMD for
+densities that vary along z only, and the ROF invariants (mean preservation,
+maximum principle, weak duality)."""
+import numpy as np
+import pytest
+
+from oracle import emd as oemd
+from oracle import grid
+from oracle import grid3 as g3
+from oracle import rof as orof
+
+RNG = np.random.default_rng(20260303)
+
+
+def test_adjointness():
+    h = 0.37
+    u = RNG.standard_normal((5, 6, 7))
+    p = tuple(RNG.standard_normal((5, 6, 7)) for _ in range(3))
+    # far-face components of p are structurally zero
+    p[0][:, :, -1] = 0
+    p[1][:, -1, :] = 0
+    p[2][-1, :, :] = 0
+    lhs = h ** 3 * sum(float(np.sum(a * b)) for a, b in zip(g3.grad(u, h), p))
+    rhs = -h ** 3 * float(np.sum(u * g3.div(*p, h)))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("alpha", [0.7, 0.0])
+def test_poisson_against_dense_solve(alpha):
+    nz, ny, nx, h = 3, 4, 5, 0.5
+    n = nz * ny * nx
+    A = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        A[:, k] = alpha * e - g3.laplacian(e.reshape(nz, ny, nx), h).ravel()
+    b = RNG.standard_normal((nz, ny, nx))
+    x = g3.poisson_solve(b, h, alpha)
+    if alpha > 0:
+        ref = np.linalg.solve(A, b.ravel())
+    else:
+        ref = np.linalg.lstsq(A, (b - b.mean()).ravel(), rcond=None)[0]
+        ref -= ref.mean()
+    assert np.abs(x.ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _embed(a2, axis, n):
+    """a 2-D field repeated n times along the given 3-D axis"""
+    return np.repeat(np.expand_dims(a2, axis), n, axis=axis)
+
+
+# for data constant along `axis`, the 3-D components that map to the 2-D (x, y) ones
+# (the 2-D array's last axis is its x): axis 0 (z): (x, y); axis 1 (y): (x, z); axis 2 (x): (y, z)
+COMP = {0: (0, 1), 1: (0, 2), 2: (1, 2)}
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("norm", [grid.ISO, grid.ANISO])
+def test_rof_reduces_to_2d(axis, norm):
+    J = RNG.random((12, 10))
+    I = _embed(J, axis, 6)
+    h, lam, tau = 0.9, 8.0, 0.05
+    u3 = np.zeros_like(I)
+    p3 = tuple(np.zeros_like(I) for _ in range(3))
+    pb3 = tuple(a.copy() for a in p3)
+    z = np.zeros_like(J)
+    s2 = (z, z.copy(), z.copy(), z.copy(), z.copy())
+    cx, cy = COMP[axis]
+    for _ in range(5):
+        u3, p3, pb3 = g3.rof_step(u3, p3, pb3, I, h, lam, tau, 1 / tau, norm)
+        s2 = orof.step(*s2, J, h, lam, tau, 1 / tau, norm)
+    assert np.abs(u3 - _embed(s2[0], axis, 6)).max() <= 1e-12
+    assert np.abs(p3[cx] - _embed(s2[1], axis, 6)).max() <= 1e-12
+    assert np.abs(p3[cy] - _embed(s2[2], axis, 6)).max() <= 1e-12
+    assert np.abs(p3[axis_component(axis)]).max() == 0.0
+    # values: h^3 sums over 6 slices = 6 h times the 2-D h^2 sums
+    P3, P2 = g3.rof_primal(u3, I, h, lam, norm), orof.primal(s2[0], J, h, lam, norm)
+    D3, D2 = g3.rof_dual(*p3, I, h, lam), orof.dual(s2[1], s2[2], J, h, lam)
+    assert abs(P3 - 6 * h * P2) <= 1e-12 * abs(P3)
+    assert abs(D3 - 6 * h * D2) <= 1e-12 * abs(P3)
+
+
+def axis_component(axis):
+    """the gradient component along the constant axis (x is component 0)"""
+    return {0: 2, 1: 1, 2: 0}[axis]
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_emd_reduces_to_2d(axis):
+    n2 = 16
+    h = 1.0 / n2
+    a = RNG.random((n2, n2)) + 0.5
+    b = RNG.random((n2, n2)) + 0.5
+    b *= a.sum() / b.sum()
+    r0, r1 = _embed(a, axis, 4), _embed(b, axis, 4)
+    f3, psi3 = g3.emd_setup(r0, r1, h)
+    f2, psi2 = oemd.setup(a, b, h)
+    assert np.abs(psi3 - _embed(psi2, axis, 4)).max() <= 1e-12 * np.abs(psi2).max()
+    gp3 = g3.grad(psi3, h)
+    gp2 = grid.grad(psi2, h)
+    tau = 0.3
+    u3 = tuple(np.zeros_like(f3) for _ in range(3))
+    p3 = tuple(np.zeros_like(f3) for _ in range(3))
+    pb3 = tuple(x.copy() for x in p3)
+    z = np.zeros_like(f2)
+    s2 = (z, z.copy(), z.copy(), z.copy(), z.copy(), z.copy())
+    cx, cy = COMP[axis]
+    for _ in range(6):
+        u3, p3, pb3 = g3.emd_step(u3, p3, pb3, gp3, h, tau, 1 / tau)
+        s2 = oemd.step(*s2, gp2[0], gp2[1], h, tau, 1 / tau)
+    scale = np.abs(s2[0]).max() + np.abs(s2[2]).max()
+    assert np.abs(u3[cx] - _embed(s2[0], axis, 4)).max() <= 1e-11 * scale
+    assert np.abs(u3[cy] - _embed(s2[1], axis, 4)).max() <= 1e-11 * scale
+    assert np.abs(p3[cx] - _embed(s2[2], axis, 4)).max() <= 1e-11 * scale
+    assert np.abs(p3[cy] - _embed(s2[3], axis, 4)).max() <= 1e-11 * scale
+    P3, P2 = g3.emd_primal(u3, gp3, h), oemd.primal(s2[0], s2[1], gp2[0], gp2[1], h)
+    D3, D2 = g3.emd_certificate(p3, f3, h)[0], oemd.certificate(s2[2], s2[3], f2, h)[0]
+    assert abs(P3 - 4 * h * P2) <= 1e-10 * P3 and abs(D3 - 4 * h * D2) <= 1e-10 * P3
+
+
+def test_emd_z_only_closed_form():
+    """Densities varying along z only: EMD = (area of a z-slice) x the 1-D value
+    h sum_k |C_k|, C_k = h sum_{j<=k} (rho1_j - rho0_j); the starting flux
+    grad psi is already optimal and the certificate stays below it."""
+    nz, ny, nx = 32, 4, 4
+    h = 1.0 / nz
+    z = (np.arange(nz) + 0.5) * h
+    a = np.exp(-((z - 0.3) / 0.08) ** 2) + 1e-3
+    b = np.exp(-((z - 0.6) / 0.1) ** 2) + 1e-3
+    b *= a.sum() / b.sum()
+    C = h * np.cumsum(b - a)
+    exact = (nx * h) * (ny * h) * h * float(np.sum(np.abs(C)))
+    r0 = np.broadcast_to(a[:, None, None], (nz, ny, nx)).copy()
+    r1 = np.broadcast_to(b[:, None, None], (nz, ny, nx)).copy()
+    f, psi = g3.emd_setup(r0, r1, h)
+    gp = g3.grad(psi, h)
+    P0 = g3.emd_primal(tuple(np.zeros_like(f) for _ in range(3)), gp, h)
+    assert abs(P0 - exact) <= 1e-12 * exact
+    res = g3.emd_solve(r0, r1, h, tau=0.3, tol=0.0, max_iter=300, check_every=300)
+    assert res.dual <= exact * (1 + 1e-12) and abs(res.primal - exact) <= 1e-6 * exact
+    assert res.rel_gap < 0.05
+
+
+def test_rof_converges_with_invariants():
+    I = np.zeros((16, 16, 16))
+    I[3:9, 4:12, 2:7] = 1.0
+    I[8:14, 1:6, 9:15] = 0.5
+    I += 0.1 * np.random.default_rng(7).standard_normal(I.shape)
+    h, lam = 1.0, 8.0
+    res = g3.rof_solve(I, h, lam, 0.01, tol=1e-6, max_iter=20000, check_every=20)
+    assert res.converged and res.dual <= res.primal
+    assert abs(res.u.sum() - I.sum()) <= 1e-9 * np.abs(I).sum()
+    assert res.u.min() >= I.min() - 1e-6 and res.u.max() <= I.max() + 1e-6
+    # field bound of the strongly convex problem, ||u - u*||^2 <= 2 gap / lambda (h^3 norm),
+    # against a tighter solve (its own distance to u* bounded the same way)
+    ref = g3.rof_solve(I, h, lam, 0.01, tol=2e-8, max_iter=40000, check_every=20)
+    assert ref.converged and ref.rel_gap < 0.05 * res.rel_gap
+    dist = np.sqrt(h ** 3 * float(np.sum((res.u - ref.u) ** 2)))
+    bound = np.sqrt(2 * (res.primal - res.dual) / lam) + np.sqrt(2 * (ref.primal - ref.dual) / lam)
+    assert dist <= bound
+    assert dist >= 1e-3 * bound  # (the bound is not vacuous: the two solves differ)
