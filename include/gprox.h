@@ -149,6 +149,39 @@ int pd_step(gp_ctx* ctx, gp_state* st, int n_iter);
  * synchronises the stream once. */
 int pd_gap(gp_ctx* ctx, gp_state* st, gp_report* rep);
 
+/* ---- 3-D grids: the d = 3 case of section 3 (the theory of sections 2-3 is
+ * stated for general d).  Grids nz x ny x nx, each side a power of two in
+ * [64, 4096], at most 2^27 cells; scalar fields float[nz][ny][nx] (x
+ * fastest), vector fields planar float[3][nz][ny][nx] (x, y, z components).
+ * Operators: forward-difference gradient (zero on the far faces), divergence
+ * its negative adjoint, the 7-point Neumann Laplacian, h^3 sums; pointwise
+ * norms |p| = sqrt(px^2 + py^2 + pz^2) (GP_NORM_ISO) or |px| + |py| + |pz|
+ * (GP_NORM_ANISO).  Workspace: the context's arena (grown on demand: ROF
+ * about 40, EMD about 76 bytes per cell); all buffers caller-owned device
+ * memory; errors as the 2-D calls (GP_EUNSUPPORTED for other sizes). */
+
+/* (alpha I - Delta) x = b, Neumann, by the 3-D DCT-II (the linear solves of
+ * sections 3.1 and 3.2 in d = 3); alpha = 0 drops the zero mode (x has mean
+ * zero).  b and x may alias.  FP32 and FP64 variants. */
+int dct_poisson3(gp_ctx* ctx, const float* b, float* x, int nz, int ny, int nx, double h, double alpha);
+int dct_poisson3_f64(gp_ctx* ctx, const double* b, double* x, int nz, int ny, int nx, double h, double alpha);
+
+/* ROF denoising of the volume I (section 3.1 updates in d = 3) from u = 0,
+ * p = 0, or from the caller's u and p with opts->warm_start.  u: in/out
+ * [nz][ny][nx]; p: nullable in/out [3][nz][ny][nx].  Gap, stopping rule and
+ * report as rof_solve (P and D with h^3 sums).  opts->ergodic is not
+ * supported (GP_EUNSUPPORTED). */
+int rof3_solve(gp_ctx* ctx, const float* I, float* u, float* p, int nz, int ny, int nx, double h, double lambda,
+               const gp_opts* opts, gp_report* rep);
+
+/* EMD between volumes rho0, rho1 >= 0 of equal mass (section 3.2 updates in
+ * d = 3, projected form, FP64 potentials) from the zero start.  m: out flux
+ * u + grad psi [3][nz][ny][nx]; phi: nullable out [nz][ny][nx], the scaled
+ * certificate potential.  rep->primal = h^3 sum |m|, rep->dual the
+ * certificate's lower bound.  warm_start and ergodic are not supported. */
+int emd3_solve(gp_ctx* ctx, const float* rho0, const float* rho1, float* m, float* phi, int nz, int ny, int nx,
+               double h, const gp_opts* opts, gp_report* rep);
+
 /* One problem of a batch.
  *   GP_KIND_ROF: in0 = image I [ny][nx]; out = u [ny][nx]; lambda > 0.
  *   GP_KIND_EMD: in0 = rho0, in1 = rho1 [ny][nx] (equal mass); out = flux m

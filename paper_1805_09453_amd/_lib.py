@@ -61,6 +61,12 @@ _SIGS = {
                           ctypes.POINTER(gp_opts), ctypes.POINTER(gp_report)]),
     "emd_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double,
                           ctypes.POINTER(gp_opts), ctypes.POINTER(gp_report)]),
+    "dct_poisson3": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double, c_double]),
+    "dct_poisson3_f64": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double, c_double]),
+    "rof3_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double, c_double,
+                           ctypes.POINTER(gp_opts), ctypes.POINTER(gp_report)]),
+    "emd3_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double,
+                           ctypes.POINTER(gp_opts), ctypes.POINTER(gp_report)]),
     "emd_setup": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double]),
     "pd_step": (c_int, [c_void_p, ctypes.POINTER(gp_state), c_int]),
     "pd_gap": (c_int, [c_void_p, ctypes.POINTER(gp_state), ctypes.POINTER(gp_report)]),

@@ -170,6 +170,44 @@ class Context:
         self._check(rc, allow_notconv=True)
         return m, phi, rep.as_dict()
 
+    # -- 3-D grids
+    def dct_poisson3(self, b, x=None, h=1.0, alpha=0.0):
+        torch = _torch()
+        nz, ny, nx = b.shape
+        x = torch.empty_like(b) if x is None else x
+        fn, dt = (self._lib.dct_poisson3_f64, torch.float64) if b.dtype == torch.float64 else \
+            (self._lib.dct_poisson3, torch.float32)
+        self._check(fn(self._h, _ptr(b, dt, (nz, ny, nx), "b"), _ptr(x, dt, (nz, ny, nx), "x"), nz, ny, nx,
+                       float(h), float(alpha)))
+        return x
+
+    def rof3_solve(self, I, h, lam, opts: Options, u=None, p=None):
+        torch = _torch()
+        nz, ny, nx = I.shape
+        u = torch.empty_like(I) if u is None else u
+        p = torch.empty((3, nz, ny, nx), device=I.device, dtype=I.dtype) if p is None else p
+        rep = L.gp_report()
+        rc = self._lib.rof3_solve(self._h, _ptr(I, torch.float32, (nz, ny, nx), "I"),
+                                  _ptr(u, torch.float32, (nz, ny, nx), "u"),
+                                  _ptr(p, torch.float32, (3, nz, ny, nx), "p"), nz, ny, nx, float(h), float(lam),
+                                  ctypes.byref(opts.c()), ctypes.byref(rep))
+        self._check(rc, allow_notconv=True)
+        return u, p, rep.as_dict()
+
+    def emd3_solve(self, rho0, rho1, h, opts: Options, want_phi=True):
+        torch = _torch()
+        nz, ny, nx = rho0.shape
+        m = torch.empty((3, nz, ny, nx), device=rho0.device, dtype=rho0.dtype)
+        phi = torch.empty_like(rho0) if want_phi else None
+        rep = L.gp_report()
+        rc = self._lib.emd3_solve(self._h, _ptr(rho0, torch.float32, (nz, ny, nx), "rho0"),
+                                  _ptr(rho1, torch.float32, (nz, ny, nx), "rho1"),
+                                  _ptr(m, torch.float32, (3, nz, ny, nx), "m"),
+                                  _ptr(phi, torch.float32, (nz, ny, nx), "phi"), nz, ny, nx, float(h),
+                                  ctypes.byref(opts.c()), ctypes.byref(rep))
+        self._check(rc, allow_notconv=True)
+        return m, phi, rep.as_dict()
+
     def emd_setup(self, rho0, rho1, h):
         torch = _torch()
         ny, nx = rho0.shape

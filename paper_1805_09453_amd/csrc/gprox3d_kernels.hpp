@@ -1,2 +1,316 @@
-// 3-D grid kernels (the d = 3 case of the method of section 3).
+// 3-D grid kernels: the d = 3 case of the method of section 3 (the theory of
+// sections 2-3 holds for any dimension; the 2-D kernels' discretisation with
+// a third axis).
+//
+// Layout: scalar fields [nz][ny][nx] row-major (x fastest), vector fields
+// planar [3][nz][ny][nx] (components x, y, z).  Gradient: forward differences,
+// zero on the far faces; divergence: its negative adjoint (backward
+// differences).  The screened Poisson solve (alpha I - Delta)^{-1} is a 3-D
+// DCT-II in five passes over the field:
+//   x forward   k_rows_fwd  (rows of the [nz ny][nx] view, written to the
+//                            strip-tiled intermediate of each z-plane)
+//   y forward   k3_cols_dct<.., false> (columns of each z-plane's tiles)
+//   z solve     k_cols_solve over the [nz][ny nx] view: DCT-II along z,
+//               scale by 1/(nx ny nz (alpha + mu_z + mu_y + mu_x)), inverse
+//               (the y, x eigenvalue sum comes from a table laid out like the
+//               plane's tiled intermediate)
+//   y inverse   k3_cols_dct<.., true>
+//   x inverse   k_rows_inv (back to row-major)
 #pragma once
+#include <hip/hip_runtime.h>
+
+#include "gprox_fft.hpp"
+#include "gprox_kernels.hpp"
+
+namespace gp {
+
+// One direction of the y-axis DCT-II over the strip-tiled intermediate of a
+// stack of z-planes (blockIdx.y = plane): forward leaves the spectrum in
+// natural frequency order along the column, inverse (times N) takes it from
+// there.  Column addressing as in k_cols_solve: two adjacent columns per FFT
+// group, strips of TW = 2^lgtw columns stored row-major and contiguous.
+template <int N, class C, bool INV>
+__global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW)) void k3_cols_dct(
+    typename Cx<C>::R* buf, int nx, const C* __restrict__ tw, const C* __restrict__ dctw, int lgtw) {
+  using Re = typename Cx<C>::R;
+  using SH = ColShape<N, C>;
+  buf += size_t(blockIdx.y) * N * nx;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* smem = reinterpret_cast<C*>(smem_raw);
+  const int G = blockDim.x / SH::T;
+  const int g = threadIdx.x % G, t = threadIdx.x / G;
+  C* lds = smem + g * Sched<N>::LDS;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int TW = 1 << lgtw, per = TW / (2 * G);
+  const int strip = blk / per, sub = blk - strip * per;
+  const int c = strip * TW + 2 * (sub * G + g);
+  const bool valid = c < nx;
+  Re* col = buf + (valid ? size_t(strip) * N * TW + 2 * (sub * G + g) : 0);
+  const int ld = TW;
+  Vals<N, C> v;
+  if constexpr (!INV) {
+    dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
+      if (valid) {
+        const C L0 = *reinterpret_cast<const C*>(col + size_t(2 * m) * ld);
+        const C L1 = *reinterpret_cast<const C*>(col + size_t(2 * m + 1) * ld);
+        A = mk<C>(L0.x, L1.x);
+        B = mk<C>(L0.y, L1.y);
+      } else {
+        A = mk<C>(Re(0), Re(0));
+        B = A;
+      }
+    });
+    if (valid) {
+#pragma unroll
+      for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+        for (int s = 0; s < Sched<N>::H; ++s)
+          *reinterpret_cast<C*>(col + size_t(dc_index<N>(t, slot, s)) * ld) = v[slot * Sched<N>::H + s];
+    }
+  } else {
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+      for (int s = 0; s < Sched<N>::H; ++s)
+        v[slot * Sched<N>::H + s] =
+            valid ? *reinterpret_cast<const C*>(col + size_t(dc_index<N>(t, slot, s)) * ld) : mk<C>(Re(0), Re(0));
+    dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
+      if (valid) {
+        *reinterpret_cast<C*>(col + size_t(2 * m) * ld) = mk<C>(A.x, B.x);
+        *reinterpret_cast<C*>(col + size_t(2 * m + 1) * ld) = mk<C>(A.y, B.y);
+      }
+    });
+  }
+}
+
+// Eigenvalue sums mu_y[ky] + mu_x[kx] of one z-plane, laid out like the
+// plane's strip-tiled intermediate (the z pass reads them per column).
+__global__ __launch_bounds__(256) void k3_mu_plane(const double* __restrict__ muy, const double* __restrict__ mux,
+                                                   double* __restrict__ o64, float* __restrict__ o32, int ny, int nx,
+                                                   int lgtw) {
+  const size_t P = size_t(ny) * nx;
+  for (size_t q = size_t(blockIdx.x) * blockDim.x + threadIdx.x; q < P; q += size_t(gridDim.x) * blockDim.x) {
+    const size_t TW = size_t(1) << lgtw;
+    const size_t strip = q / (size_t(ny) * TW), r = q - strip * size_t(ny) * TW;
+    const int ky = int(r / TW), kx = int(strip * TW + (r - size_t(ky) * TW));
+    const double v = muy[ky] + mux[kx];
+    o64[q] = v;
+    o32[q] = float(v);
+  }
+}
+
+// cell (j, i, k) of a 3-D launch: x over blockIdx.x * blockDim.x + threadIdx.x
+// (nx a multiple of blockDim.x), y over blockIdx.y, z over blockIdx.z
+struct Cell3 {
+  int j, i, k;
+  size_t o;
+  __device__ __forceinline__ Cell3(int ny, int nx) {
+    j = blockIdx.x * blockDim.x + threadIdx.x;
+    i = blockIdx.y;
+    k = blockIdx.z;
+    o = (size_t(k) * ny + i) * nx + j;
+  }
+};
+
+// divergence (backward differences, far-face components read as zero) of
+// the planar field v at cell c, in grid units (times 1/h by the caller)
+__device__ __forceinline__ float div3_at(const float* __restrict__ v, size_t n, const Cell3& c, int nz, int ny,
+                                         int nx) {
+  const size_t P = size_t(ny) * nx;
+  const float* vx = v;
+  const float* vy = v + n;
+  const float* vz = v + 2 * n;
+  float d = 0.f;
+  d += (c.j < nx - 1 ? vx[c.o] : 0.f) - (c.j > 0 ? vx[c.o - 1] : 0.f);
+  d += (c.i < ny - 1 ? vy[c.o] : 0.f) - (c.i > 0 ? vy[c.o - nx] : 0.f);
+  d += (c.k < nz - 1 ? vz[c.o] : 0.f) - (c.k > 0 ? vz[c.o - P] : 0.f);
+  return d;
+}
+
+__device__ __forceinline__ void proj_ball3(float& x, float& y, float& z, int aniso) {
+  if (aniso) {
+    x = fminf(1.f, fmaxf(-1.f, x));
+    y = fminf(1.f, fmaxf(-1.f, y));
+    z = fminf(1.f, fmaxf(-1.f, z));
+  } else {
+    const float n2 = x * x + y * y + z * z;
+    const float s = n2 > 1.f ? __builtin_amdgcn_rsqf(n2) : 1.f;
+    x *= s;
+    y *= s;
+    z *= s;
+  }
+}
+
+__device__ __forceinline__ float pnorm3(float x, float y, float z, int aniso) {
+  const float n2 = x * x + y * y + z * z;
+  return aniso ? fabsf(x) + fabsf(y) + fabsf(z) : (n2 > 0.f ? __builtin_amdgcn_sqrtf(n2) : 0.f);
+}
+
+// ---------------------------------------------------------------- ROF (section 3.1 updates)
+// right-hand side of the incremental u-step: r = lambda tau (I - u) + tau div pbar
+__global__ __launch_bounds__(256) void k3_rof_rhs(const float* __restrict__ u, const float* __restrict__ pbar,
+                                                  const float* __restrict__ I, float* __restrict__ r, int nz, int ny,
+                                                  int nx, float lt, float tau_h) {
+  const Cell3 c(ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
+  r[c.o] = lt * (I[c.o] - u[c.o]) + tau_h * div3_at(pbar, n, c, nz, ny, nx);
+}
+
+// u+ = u + delta, then the dual step p+ = proj(p + sigma grad u+), pbar+ = 2 p+ - p
+// (u+ at the three forward neighbours formed from their own u and delta).
+// u_out must not alias u_in; p and pbar are updated in place.
+__global__ __launch_bounds__(256) void k3_rof_update(const float* __restrict__ u_in, const float* __restrict__ d,
+                                                     float* __restrict__ p, float* __restrict__ pbar,
+                                                     float* __restrict__ u_out, int nz, int ny, int nx, float sig_h,
+                                                     int aniso) {
+  const Cell3 c(ny, nx);
+  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  const float uc = u_in[c.o] + d[c.o];
+  const float gx = c.j < nx - 1 ? (u_in[c.o + 1] + d[c.o + 1]) - uc : 0.f;
+  const float gy = c.i < ny - 1 ? (u_in[c.o + nx] + d[c.o + nx]) - uc : 0.f;
+  const float gz = c.k < nz - 1 ? (u_in[c.o + P] + d[c.o + P]) - uc : 0.f;
+  const float ox = p[c.o], oy = p[c.o + n], oz = p[c.o + 2 * n];
+  float qx = ox + sig_h * gx, qy = oy + sig_h * gy, qz = oz + sig_h * gz;
+  proj_ball3(qx, qy, qz, aniso);
+  p[c.o] = qx;
+  p[c.o + n] = qy;
+  p[c.o + 2 * n] = qz;
+  pbar[c.o] = 2.f * qx - ox;
+  pbar[c.o + n] = 2.f * qy - oy;
+  pbar[c.o + 2 * n] = 2.f * qz - oz;
+  u_out[c.o] = uc;
+}
+
+// ROF gap partials [sum |grad u|, sum (u - I)^2, sum I div p, sum (div p)^2]
+// (differences in grid units); grid-stride over the cells, lgx = log2 nx,
+// lgy = log2 ny.
+__global__ __launch_bounds__(256) void k3_rof_energy(const float* __restrict__ u, const float* __restrict__ p,
+                                                     const float* __restrict__ I, int nz, int ny, int nx, int lgx,
+                                                     int lgy, int aniso, double* __restrict__ partials) {
+  double acc[4] = {0, 0, 0, 0};
+  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(o & size_t(nx - 1)), i = int((o >> lgx) & size_t(ny - 1)), k = int(o >> (lgx + lgy));
+    const float uc = u[o];
+    const float gx = j < nx - 1 ? u[o + 1] - uc : 0.f;
+    const float gy = i < ny - 1 ? u[o + nx] - uc : 0.f;
+    const float gz = k < nz - 1 ? u[o + P] - uc : 0.f;
+    float d = 0.f;
+    d += (j < nx - 1 ? p[o] : 0.f) - (j > 0 ? p[o - 1] : 0.f);
+    d += (i < ny - 1 ? p[n + o] : 0.f) - (i > 0 ? p[n + o - nx] : 0.f);
+    d += (k < nz - 1 ? p[2 * n + o] : 0.f) - (k > 0 ? p[2 * n + o - P] : 0.f);
+    const float e = uc - I[o];
+    acc[0] += double(pnorm3(gx, gy, gz, aniso));
+    acc[1] += double(e) * double(e);
+    acc[2] += double(I[o]) * double(d);
+    acc[3] += double(d) * double(d);
+  }
+  const bool mx[4] = {false, false, false, false};
+  block_reduce_store<4>(acc, mx, partials);
+}
+
+// ---------------------------------------------------------------- EMD (section 3.2 updates, projected form)
+// b = -div(u - tau pbar) / h in FP64: (0 I - Delta) phi = b gives Delta phi = div(u - tau pbar)
+__global__ __launch_bounds__(256) void k3_emd_rhs(const float* __restrict__ u, const float* __restrict__ pbar,
+                                                  double* __restrict__ b, int nz, int ny, int nx, float tau,
+                                                  double inv_h) {
+  const Cell3 c(ny, nx);
+  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  auto w = [&](int comp, size_t o) { return u[comp * n + o] - tau * pbar[comp * n + o]; };
+  double d = 0.0;
+  d += double(c.j < nx - 1 ? w(0, c.o) : 0.f) - double(c.j > 0 ? w(0, c.o - 1) : 0.f);
+  d += double(c.i < ny - 1 ? w(1, c.o) : 0.f) - double(c.i > 0 ? w(1, c.o - nx) : 0.f);
+  d += double(c.k < nz - 1 ? w(2, c.o) : 0.f) - double(c.k > 0 ? w(2, c.o - P) : 0.f);
+  b[c.o] = -d * inv_h;
+}
+
+// u+ = (u - tau pbar) - grad phi, p+ = proj(p + sigma (u+ + grad psi)),
+// pbar+ = 2 p+ - p; pointwise in u, p, pbar (updated in place), phi read at
+// the forward neighbours (FP64).
+__global__ __launch_bounds__(256) void k3_emd_update(float* __restrict__ u, float* __restrict__ p,
+                                                     float* __restrict__ pbar, const double* __restrict__ phi,
+                                                     const float* __restrict__ gpsi, int nz, int ny, int nx, float tau,
+                                                     float sigma, double inv_h, int aniso) {
+  const Cell3 c(ny, nx);
+  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  const double fc = phi[c.o];
+  const bool hx = c.j < nx - 1, hy = c.i < ny - 1, hz = c.k < nz - 1;
+  const float ux = hx ? (u[c.o] - tau * pbar[c.o]) - float((phi[c.o + 1] - fc) * inv_h) : 0.f;
+  const float uy = hy ? (u[n + c.o] - tau * pbar[n + c.o]) - float((phi[c.o + nx] - fc) * inv_h) : 0.f;
+  const float uz = hz ? (u[2 * n + c.o] - tau * pbar[2 * n + c.o]) - float((phi[c.o + P] - fc) * inv_h) : 0.f;
+  const float ox = p[c.o], oy = p[n + c.o], oz = p[2 * n + c.o];
+  float qx = ox + sigma * (ux + gpsi[c.o]), qy = oy + sigma * (uy + gpsi[n + c.o]),
+        qz = oz + sigma * (uz + gpsi[2 * n + c.o]);
+  proj_ball3(qx, qy, qz, aniso);
+  u[c.o] = ux;
+  u[n + c.o] = uy;
+  u[2 * n + c.o] = uz;
+  p[c.o] = qx;
+  p[n + c.o] = qy;
+  p[2 * n + c.o] = qz;
+  pbar[c.o] = 2.f * qx - ox;
+  pbar[n + c.o] = 2.f * qy - oy;
+  pbar[2 * n + c.o] = 2.f * qz - oz;
+}
+
+// b = -div p / h (FP64): the certificate potential phi_c with Delta phi_c = div p
+__global__ __launch_bounds__(256) void k3_div_f64(const float* __restrict__ p, double* __restrict__ b, int nz,
+                                                  int ny, int nx, double inv_h) {
+  const Cell3 c(ny, nx);
+  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  double d = 0.0;
+  d += double(c.j < nx - 1 ? p[c.o] : 0.f) - double(c.j > 0 ? p[c.o - 1] : 0.f);
+  d += double(c.i < ny - 1 ? p[n + c.o] : 0.f) - double(c.i > 0 ? p[n + c.o - nx] : 0.f);
+  d += double(c.k < nz - 1 ? p[2 * n + c.o] : 0.f) - double(c.k > 0 ? p[2 * n + c.o - P] : 0.f);
+  b[c.o] = -d * inv_h;
+}
+
+// grad psi from the FP64 potential, stored FP32 (planar, 3 components)
+__global__ __launch_bounds__(256) void k3_grad_f64(const double* __restrict__ psi, float* __restrict__ g, int nz,
+                                                   int ny, int nx, double inv_h) {
+  const Cell3 c(ny, nx);
+  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  const double fc = psi[c.o];
+  g[c.o] = c.j < nx - 1 ? float((psi[c.o + 1] - fc) * inv_h) : 0.f;
+  g[n + c.o] = c.i < ny - 1 ? float((psi[c.o + nx] - fc) * inv_h) : 0.f;
+  g[2 * n + c.o] = c.k < nz - 1 ? float((psi[c.o + P] - fc) * inv_h) : 0.f;
+}
+
+// EMD primal partials: sum |u + grad psi| (grid-stride over the cells)
+__global__ __launch_bounds__(256) void k3_emd_primal(const float* __restrict__ u, const float* __restrict__ gpsi,
+                                                     size_t n, int aniso, double* __restrict__ partials) {
+  double acc[1] = {0};
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
+    acc[0] += double(pnorm3(u[o] + gpsi[o], u[n + o] + gpsi[n + o], u[2 * n + o] + gpsi[2 * n + o], aniso));
+  const bool m[1] = {false};
+  block_reduce_store<1>(acc, m, partials);
+}
+
+// certificate partials [sum phi f, max |grad phi| (dual norm, 1/h units)]
+__global__ __launch_bounds__(256) void k3_emd_cert(const double* __restrict__ phi, const float* __restrict__ f,
+                                                   int nz, int ny, int nx, int lgx, int lgy, double inv_h, int aniso,
+                                                   double* __restrict__ partials) {
+  double acc[2] = {0, 0};
+  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(o & size_t(nx - 1)), i = int((o >> lgx) & size_t(ny - 1)), k = int(o >> (lgx + lgy));
+    const double fc = phi[o];
+    const double gx = j < nx - 1 ? (phi[o + 1] - fc) * inv_h : 0.0;
+    const double gy = i < ny - 1 ? (phi[o + nx] - fc) * inv_h : 0.0;
+    const double gz = k < nz - 1 ? (phi[o + P] - fc) * inv_h : 0.0;
+    acc[0] += fc * double(f[o]);
+    acc[1] = fmax(acc[1], aniso ? fmax(fmax(fabs(gx), fabs(gy)), fabs(gz)) : gx * gx + gy * gy + gz * gz);
+  }
+  if (!aniso) acc[1] = sqrt(acc[1]);
+  const bool m[2] = {false, true};
+  block_reduce_store<2>(acc, m, partials);
+}
+
+// out = a + b over n values (the flux m = u + grad psi)
+__global__ __launch_bounds__(256) void k3_add(const float* __restrict__ a, const float* __restrict__ b,
+                                              float* __restrict__ out, size_t n) {
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
+    out[o] = a[o] + b[o];
+}
+
+}  // namespace gp

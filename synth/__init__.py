@@ -25,3 +25,4 @@ from .scenes import (  # noqa: F401
     batch_instance_inputs,
     smooth_size,
 )
+from .volumes import cell_centres3, emd_volume_pair, rof_volume  # noqa: F401

@@ -54,6 +54,10 @@ def test_strerror_and_null_arguments(lib):
     assert lib.pd_step(None, None, 1) == -1
     assert lib.pd_gap(None, None, None) == -1
     assert lib.rof_solve(None, None, None, None, 64, 64, 1.0, 8.0, None, None) == -1
+    assert lib.dct_poisson3(None, None, None, 64, 64, 64, 1.0, 0.0) == -1
+    assert lib.dct_poisson3_f64(None, None, None, 64, 64, 64, 1.0, 0.0) == -1
+    assert lib.rof3_solve(None, None, None, None, 64, 64, 64, 1.0, 8.0, None, None) == -1
+    assert lib.emd3_solve(None, None, None, None, None, 64, 64, 64, 1.0, None, None) == -1
 
 
 def test_warm_start_blob_size_matches_the_oracle_network(lib):

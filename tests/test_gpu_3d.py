@@ -1,0 +1,173 @@
+"""3-D grids on the GPU (the d = 3 case of section 3) against the FP64 3-D
+oracle: the 3-D screened Poisson solve (FP32 and FP64), ROF and EMD
+iterations field by field with their gap values (cubic and non-cubic grids,
+both norms, and the 256^3 size the benchmark times), a converged ROF solve
+certified in FP64, the z-only EMD closed form, and the error paths."""
+import numpy as np
+import pytest
+
+import synth
+from conftest import announce
+from oracle import grid3 as g3
+
+pytestmark = pytest.mark.gpu
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def dev(a, dtype=np.float32):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a, dtype=dtype), device="cuda")
+
+
+def host(t):
+    return t.cpu().double().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+@pytest.mark.parametrize("shape,h,alpha", [((64, 64, 64), 1 / 64, 0.5), ((64, 128, 256), 1.0, 0.0),
+                                           ((128, 64, 64), 0.5, 2.0)])
+def test_dct_poisson3_matches_oracle(gpctx, shape, h, alpha):
+    import torch
+    b = np.random.default_rng(11).standard_normal(shape)
+    announce(f"dct_poisson3 {shape} h={h} alpha={alpha}")
+    x32 = gpctx.dct_poisson3(dev(b), h=h, alpha=alpha)
+    x64 = gpctx.dct_poisson3(dev(b, np.float64), h=h, alpha=alpha)
+    assert x64.dtype == torch.float64
+    ref32 = g3.poisson_solve(f32(b), h, alpha)
+    ref64 = g3.poisson_solve(b, h, alpha)
+    e32, e64 = rel(host(x32), ref32), rel(host(x64), ref64)
+    print(f"rel err fp32 {e32:.2e} fp64 {e64:.2e}")
+    assert e32 <= 2e-6 and e64 <= 1e-12
+
+
+@pytest.mark.parametrize("shape,norm,tau", [((64, 64, 64), 0, 0.05), ((64, 128, 64), 1, 0.2)])
+def test_rof3_iterations_match_oracle(gpctx, shape, norm, tau):
+    from paper_1805_09453_amd import Options
+    I = f32(synth.rof_volume(shape, 5))
+    lam, h, K = 8.0, 1.0, 6
+    announce(f"rof3_solve {shape} norm={norm}, {K} iterations")
+    u, p, rep = gpctx.rof3_solve(dev(I), h, lam, Options(tau=tau, tol=0.0, max_iter=K, check_every=3, norm=norm))
+    ref = g3.rof_solve(I, h, lam, tau, tol=0.0, max_iter=K, check_every=3, norm=norm)
+    pg = host(p)
+    errs = [rel(host(u), ref.u)] + [rel(pg[i], ref.p[i]) for i in range(3)]
+    print("rel err u, px, py, pz:", ["%.2e" % e for e in errs], "P", rep["primal"], ref.primal, "D", rep["dual"],
+          ref.dual)
+    assert rep["iters"] == K
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - ref.primal) <= 1e-6 * abs(ref.primal)
+    assert abs(rep["dual"] - ref.dual) <= 1e-6 * abs(ref.primal)
+
+
+@pytest.mark.parametrize("shape,norm,tau", [((64, 64, 64), 0, 0.3), ((128, 64, 64), 1, 1.0)])
+def test_emd3_iterations_match_oracle(gpctx, shape, norm, tau):
+    from paper_1805_09453_amd import Options
+    r0, r1 = (f32(a) for a in synth.emd_volume_pair(shape, 6))
+    h, K = 1.0 / max(shape), 5
+    announce(f"emd3_solve {shape} norm={norm}, {K} iterations")
+    m, phi, rep = gpctx.emd3_solve(dev(r0), dev(r1), h, Options(tau=tau, tol=0.0, max_iter=K, check_every=K,
+                                                                norm=norm))
+    ref = g3.emd_solve(r0, r1, h, tau=tau, tol=0.0, max_iter=K, check_every=K, norm=norm)
+    D, L, phit = g3.emd_certificate(ref.p, ref.f, h, norm)
+    mg = host(m)
+    errs = {"mx": rel(mg[0], ref.m[0]), "my": rel(mg[1], ref.m[1]), "mz": rel(mg[2], ref.m[2]),
+            "phi": rel(host(phi), phit)}
+    print("rel err:", {k: "%.2e" % v for k, v in errs.items()}, "P", rep["primal"], ref.primal, "D", rep["dual"], D)
+    assert rep["iters"] == K
+    assert max(errs.values()) <= 1e-5
+    assert abs(rep["primal"] - ref.primal) <= 1e-6 * ref.primal
+    assert abs(rep["dual"] - D) <= 2e-6 * ref.primal
+
+
+def test_rof3_converges_and_certifies(gpctx):
+    """A solve to a relative gap of 1e-5; P and D recomputed in FP64 from the
+    returned u and p agree with the reported ones (the gap certifies u)."""
+    from paper_1805_09453_amd import Options
+    I = f32(synth.rof_volume((64, 64, 64), 7))
+    announce("rof3_solve 64^3 to tol 1e-5")
+    u, p, rep = gpctx.rof3_solve(dev(I), 1.0, 8.0, Options(tau=0.05, tol=1e-5, max_iter=20000, check_every=10))
+    print(rep)
+    assert rep["converged"] and rep["rel_gap"] <= 1e-5
+    pg = host(p)
+    P = g3.rof_primal(host(u), I, 1.0, 8.0)
+    D = g3.rof_dual(pg[0], pg[1], pg[2], I, 1.0, 8.0)
+    assert abs(rep["primal"] - P) <= 1e-6 * P and abs(rep["dual"] - D) <= 1e-6 * P
+    assert (P - D) / P <= 1.1e-5
+
+
+def test_emd3_z_only_closed_form(gpctx):
+    """Densities varying along z only: EMD = (slice area) x h sum |C_k| with
+    C_k = h sum_{j<=k}(rho1_j - rho0_j); the GPU's primal value matches it and
+    its certificate stays below it."""
+    from paper_1805_09453_amd import Options
+    n = 64
+    h = 1.0 / n
+    z = (np.arange(n) + 0.5) * h
+    a = np.exp(-((z - 0.3) / 0.08) ** 2) + 1e-3
+    b = np.exp(-((z - 0.6) / 0.1) ** 2) + 1e-3
+    b *= a.sum() / b.sum()
+    a32, b32 = f32(a), f32(b)
+    f = b32 - a32
+    C = h * np.cumsum(f - f.mean())  # (the FP32 profiles' masses differ by rounding; the mean is removed)
+    exact = h * float(np.sum(np.abs(C)))  # slice area (n h)^2 = 1
+    r0 = np.broadcast_to(a32[:, None, None], (n, n, n))
+    r1 = np.broadcast_to(b32[:, None, None], (n, n, n))
+    announce("emd3_solve z-only densities 64^3")
+    m, phi, rep = gpctx.emd3_solve(dev(r0), dev(r1), h, Options(tau=0.3, tol=0.0, max_iter=200, check_every=100))
+    print(rep, exact)
+    assert abs(rep["primal"] - exact) <= 1e-5 * exact
+    assert rep["dual"] <= exact * (1 + 1e-5) and rep["rel_gap"] < 0.05
+
+
+def test_3d_full_size_256(gpctx):
+    """256^3 (as many cells as the 4096^2 workloads), two iterations of ROF and
+    of EMD against the oracle."""
+    from paper_1805_09453_amd import Options
+    shape, K = (256, 256, 256), 2
+    I = f32(synth.rof_volume(shape, 8, n_shapes=40, size_range=(0.03, 0.15)))
+    announce("rof3_solve 256^3, 2 iterations")
+    u, p, rep = gpctx.rof3_solve(dev(I), 1.0, 8.0, Options(tau=0.01, tol=0.0, max_iter=K, check_every=K))
+    ref = g3.rof_solve(I, 1.0, 8.0, 0.01, tol=0.0, max_iter=K, check_every=K)
+    pg = host(p)
+    errs = [rel(host(u), ref.u)] + [rel(pg[i], ref.p[i]) for i in range(3)]
+    print("rof rel err:", ["%.2e" % e for e in errs], rep["primal"], ref.primal, rep["dual"], ref.dual)
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - ref.primal) <= 1e-6 * abs(ref.primal)
+    assert abs(rep["dual"] - ref.dual) <= 1e-6 * abs(ref.primal)
+    del u, p, ref, I
+    r0, r1 = (f32(a) for a in synth.emd_volume_pair(shape, 9, k=8))
+    h = 1.0 / 256
+    announce("emd3_solve 256^3, 2 iterations")
+    m, phi, rep = gpctx.emd3_solve(dev(r0), dev(r1), h, Options(tau=0.3, tol=0.0, max_iter=K, check_every=K))
+    ref = g3.emd_solve(r0, r1, h, tau=0.3, tol=0.0, max_iter=K, check_every=K)
+    D, L, phit = g3.emd_certificate(ref.p, ref.f, h)
+    mg = host(m)
+    errs = [rel(mg[i], ref.m[i]) for i in range(3)] + [rel(host(phi), phit)]
+    print("emd rel err:", ["%.2e" % e for e in errs], rep["primal"], ref.primal, rep["dual"], D)
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - ref.primal) <= 1e-6 * ref.primal
+    assert abs(rep["dual"] - D) <= 2e-6 * ref.primal
+
+
+def test_3d_errors(gpctx):
+    from paper_1805_09453_amd import GPError, Options
+    from paper_1805_09453_amd._lib import GP_EMASS, GP_EUNSUPPORTED
+    ok = dev(np.ones((64, 64, 64)))
+    with pytest.raises(GPError) as e:
+        gpctx.rof3_solve(dev(np.ones((32, 64, 64))), 1.0, 8.0, Options(tau=0.1))
+    assert e.value.code == GP_EUNSUPPORTED
+    with pytest.raises(GPError) as e:
+        gpctx.rof3_solve(ok, 1.0, 8.0, Options(tau=0.1, ergodic=True))
+    assert e.value.code == GP_EUNSUPPORTED
+    with pytest.raises(GPError) as e:
+        gpctx.emd3_solve(ok, ok, 1 / 64, Options(tau=0.1, warm_start=True))
+    assert e.value.code == GP_EUNSUPPORTED
+    with pytest.raises(GPError) as e:
+        gpctx.emd3_solve(ok, dev(1.01 * np.ones((64, 64, 64))), 1 / 64, Options(tau=0.1))
+    assert e.value.code == GP_EMASS
