@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-tol", type=float, default=1e-4)
     ap.add_argument("--batch-max-iter", type=int, default=5000)
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D grid leg")
+    ap.add_argument("--n3", type=int, default=256, help="side of the 3-D grid leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--calib-copy", action="store_true",
@@ -192,6 +194,47 @@ def warm_leg(ctx, r0, r1, n, tol, max_iter):
             "speedup": tp / tw if tw > 0 else None}
 
 
+# HBM bytes per cell and iteration that the 3-D loops stream (FP32 state; EMD potential FP64):
+# ROF  rhs (u, pbar, I -> r) 24 + five transform passes 5 x 8 + update (u, delta, p -> u, p, pbar) 48
+# EMD  rhs (u, pbar -> b) 32 + five FP64 passes 5 x 16 + update (u, p, pbar, phi, grad psi -> u, p, pbar) 92
+GRID3_BYTES = {"rof3": 112.0, "emd3": 204.0}
+
+
+def grid3_leg(ctx, dev, n3, C, K, W):
+    """ROF and EMD on an n3^3 grid: W warm-up steps, then K timed steps of C
+    iterations each (one solver call, the gap checked every C iterations)."""
+    import torch
+
+    import synth
+    from paper_1805_09453_amd import Options
+    shape = (n3, n3, n3)
+    I = torch.tensor(synth.rof_volume(shape, synth.config_seed(5), n_shapes=40, size_range=(0.03, 0.15)),
+                     dtype=torch.float32, device=dev)
+    r0, r1 = (torch.tensor(a, dtype=torch.float32, device=dev)
+              for a in synth.emd_volume_pair(shape, synth.config_seed(5, 1), k=8))
+    cells = float(n3) ** 3
+    out = {"grid": list(shape),
+           "workload": "ROF: 40 balls/boxes (radii 0.03-0.15), sigma 0.1 noise, lambda 8, h 1, tau 0.01; "
+                       "EMD: 8-Gaussian mixtures on [0,1]^3, h 1/n, tau 0.3"}
+    for name, call in (("rof3", lambda it: ctx.rof3_solve(I, 1.0, 8.0, Options(tau=0.01, tol=0.0, max_iter=it,
+                                                                                   check_every=C))),
+                       ("emd3", lambda it: ctx.emd3_solve(r0, r1, 1.0 / n3, Options(tau=0.3, tol=0.0, max_iter=it,
+                                                                                     check_every=C),
+                                                          want_phi=False))):
+        call(C * W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = call(C * K)[2]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rate = cells * C * K / dt
+        out[name] = {"cell_iters_per_s": rate, "ms_per_iter": 1e3 * dt / (C * K), "last_rel_gap": rep["rel_gap"],
+                     "algorithmic_bytes_per_cell_iter": GRID3_BYTES[name],
+                     "hbm_frac": GRID3_BYTES[name] * rate / 1e9 / HBM_PEAK_GBPS}
+    del I, r0, r1
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -310,6 +353,8 @@ def main():
         extra["warm_start"] = warm_leg(ctx, r0, r1, n, args.warm_tol, args.warm_max_iter)
     if not args.no_batch:
         extra["batch"] = batch_leg(ctx, dev, args.batch_count, args.batch_tol, args.batch_max_iter)
+    if not args.no_3d:
+        extra["grid3d"] = grid3_leg(ctx, dev, args.n3, C, K, W)
     ctx.close()
     cpu = None if args.no_cpu else cpu_baseline(n, args.cpu_seconds)
     out = {
