@@ -196,8 +196,9 @@ def warm_leg(ctx, r0, r1, n, tol, max_iter):
 
 # HBM bytes per cell and iteration that the 3-D loops stream (FP32 state; EMD potential FP64):
 # ROF  rhs (u, pbar, I -> r) 24 + five transform passes 5 x 8 + update (u, delta, p -> u, p, pbar) 48
-# EMD  rhs (u, pbar -> b) 32 + five FP64 passes 5 x 16 + update (u, p, pbar, phi, grad psi -> u, p, pbar) 92
-GRID3_BYTES = {"rof3": 112.0, "emd3": 204.0}
+# EMD  rhs (w -> b) 20 + five FP64 passes 5 x 16 + update (w, p, phi, grad psi -> w, p) 68
+#      (w = u - tau pbar, the stored field)
+GRID3_BYTES = {"rof3": 112.0, "emd3": 168.0}
 
 
 def grid3_leg(ctx, dev, n3, C, K, W):

@@ -157,7 +157,7 @@ int pd_gap(gp_ctx* ctx, gp_state* st, gp_report* rep);
  * its negative adjoint, the 7-point Neumann Laplacian, h^3 sums; pointwise
  * norms |p| = sqrt(px^2 + py^2 + pz^2) (GP_NORM_ISO) or |px| + |py| + |pz|
  * (GP_NORM_ANISO).  Workspace: the context's arena (grown on demand: ROF
- * about 40, EMD about 76 bytes per cell); all buffers caller-owned device
+ * about 40, EMD about 64 bytes per cell); all buffers caller-owned device
  * memory; errors as the 2-D calls (GP_EUNSUPPORTED for other sizes). */
 
 /* (alpha I - Delta) x = b, Neumann, by the 3-D DCT-II (the linear solves of

@@ -210,47 +210,51 @@ __global__ __launch_bounds__(256) void k3_rof_energy(const float* __restrict__ u
 }
 
 // ---------------------------------------------------------------- EMD (section 3.2 updates, projected form)
-// b = -div(u - tau pbar) / h in FP64: (0 I - Delta) phi = b gives Delta phi = div(u - tau pbar)
-__global__ __launch_bounds__(256) void k3_emd_rhs(const float* __restrict__ u, const float* __restrict__ pbar,
-                                                  double* __restrict__ b, int nz, int ny, int nx, float tau,
-                                                  double inv_h) {
+// The state between iterations is (w, p) with the stored field w = u - tau pbar
+// (u the divergence-free part of the flux): the next projection needs only
+// div w, and the next update only w at the cell itself.
+// b = -div w / h in FP64: (0 I - Delta) phi = b gives Delta phi = div w
+__global__ __launch_bounds__(256) void k3_emd_rhs(const float* __restrict__ w, double* __restrict__ b, int nz,
+                                                  int ny, int nx, double inv_h) {
   const Cell3 c(ny, nx);
   const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
-  auto w = [&](int comp, size_t o) { return u[comp * n + o] - tau * pbar[comp * n + o]; };
   double d = 0.0;
-  d += double(c.j < nx - 1 ? w(0, c.o) : 0.f) - double(c.j > 0 ? w(0, c.o - 1) : 0.f);
-  d += double(c.i < ny - 1 ? w(1, c.o) : 0.f) - double(c.i > 0 ? w(1, c.o - nx) : 0.f);
-  d += double(c.k < nz - 1 ? w(2, c.o) : 0.f) - double(c.k > 0 ? w(2, c.o - P) : 0.f);
+  d += double(c.j < nx - 1 ? w[c.o] : 0.f) - double(c.j > 0 ? w[c.o - 1] : 0.f);
+  d += double(c.i < ny - 1 ? w[n + c.o] : 0.f) - double(c.i > 0 ? w[n + c.o - nx] : 0.f);
+  d += double(c.k < nz - 1 ? w[2 * n + c.o] : 0.f) - double(c.k > 0 ? w[2 * n + c.o - P] : 0.f);
   b[c.o] = -d * inv_h;
 }
 
-// u+ = (u - tau pbar) - grad phi, p+ = proj(p + sigma (u+ + grad psi)),
-// pbar+ = 2 p+ - p; pointwise in u, p, pbar (updated in place), phi read at
-// the forward neighbours (FP64).
-__global__ __launch_bounds__(256) void k3_emd_update(float* __restrict__ u, float* __restrict__ p,
-                                                     float* __restrict__ pbar, const double* __restrict__ phi,
-                                                     const float* __restrict__ gpsi, int nz, int ny, int nx, float tau,
+// u+ = w - grad phi (the Leray projection of u - tau pbar), p+ = proj(p + sigma
+// (u+ + grad psi)), pbar+ = 2 p+ - p, and the next stored field w+ = u+ - tau pbar+.
+// Pointwise in w and p (updated in place); phi read at the forward neighbours
+// (FP64).  mout (nullable): the flux m = u+ + grad psi [3][n].
+__global__ __launch_bounds__(256) void k3_emd_update(float* __restrict__ w, float* __restrict__ p,
+                                                     const double* __restrict__ phi, const float* __restrict__ gpsi,
+                                                     float* __restrict__ mout, int nz, int ny, int nx, float tau,
                                                      float sigma, double inv_h, int aniso) {
   const Cell3 c(ny, nx);
   const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
   const double fc = phi[c.o];
   const bool hx = c.j < nx - 1, hy = c.i < ny - 1, hz = c.k < nz - 1;
-  const float ux = hx ? (u[c.o] - tau * pbar[c.o]) - float((phi[c.o + 1] - fc) * inv_h) : 0.f;
-  const float uy = hy ? (u[n + c.o] - tau * pbar[n + c.o]) - float((phi[c.o + nx] - fc) * inv_h) : 0.f;
-  const float uz = hz ? (u[2 * n + c.o] - tau * pbar[2 * n + c.o]) - float((phi[c.o + P] - fc) * inv_h) : 0.f;
+  const float ux = hx ? w[c.o] - float((phi[c.o + 1] - fc) * inv_h) : 0.f;
+  const float uy = hy ? w[n + c.o] - float((phi[c.o + nx] - fc) * inv_h) : 0.f;
+  const float uz = hz ? w[2 * n + c.o] - float((phi[c.o + P] - fc) * inv_h) : 0.f;
+  const float mx = ux + gpsi[c.o], my = uy + gpsi[n + c.o], mz = uz + gpsi[2 * n + c.o];
   const float ox = p[c.o], oy = p[n + c.o], oz = p[2 * n + c.o];
-  float qx = ox + sigma * (ux + gpsi[c.o]), qy = oy + sigma * (uy + gpsi[n + c.o]),
-        qz = oz + sigma * (uz + gpsi[2 * n + c.o]);
+  float qx = ox + sigma * mx, qy = oy + sigma * my, qz = oz + sigma * mz;
   proj_ball3(qx, qy, qz, aniso);
-  u[c.o] = ux;
-  u[n + c.o] = uy;
-  u[2 * n + c.o] = uz;
   p[c.o] = qx;
   p[n + c.o] = qy;
   p[2 * n + c.o] = qz;
-  pbar[c.o] = 2.f * qx - ox;
-  pbar[n + c.o] = 2.f * qy - oy;
-  pbar[2 * n + c.o] = 2.f * qz - oz;
+  w[c.o] = ux - tau * (2.f * qx - ox);
+  w[n + c.o] = uy - tau * (2.f * qy - oy);
+  w[2 * n + c.o] = uz - tau * (2.f * qz - oz);
+  if (mout) {
+    mout[c.o] = mx;
+    mout[n + c.o] = my;
+    mout[2 * n + c.o] = mz;
+  }
 }
 
 // b = -div p / h (FP64): the certificate potential phi_c with Delta phi_c = div p
@@ -276,14 +280,14 @@ __global__ __launch_bounds__(256) void k3_grad_f64(const double* __restrict__ ps
   g[2 * n + c.o] = c.k < nz - 1 ? float((psi[c.o + P] - fc) * inv_h) : 0.f;
 }
 
-// EMD primal partials: sum |u + grad psi| (grid-stride over the cells)
-__global__ __launch_bounds__(256) void k3_emd_primal(const float* __restrict__ u, const float* __restrict__ gpsi,
-                                                     size_t n, int aniso, double* __restrict__ partials) {
+// EMD primal partials: sum |m| over the flux m [3][n] (grid-stride over the cells)
+__global__ __launch_bounds__(256) void k3_emd_primal(const float* __restrict__ m, size_t n, int aniso,
+                                                     double* __restrict__ partials) {
   double acc[1] = {0};
   for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
-    acc[0] += double(pnorm3(u[o] + gpsi[o], u[n + o] + gpsi[n + o], u[2 * n + o] + gpsi[2 * n + o], aniso));
-  const bool m[1] = {false};
-  block_reduce_store<1>(acc, m, partials);
+    acc[0] += double(pnorm3(m[o], m[n + o], m[2 * n + o], aniso));
+  const bool mm[1] = {false};
+  block_reduce_store<1>(acc, mm, partials);
 }
 
 // certificate partials [sum phi f, max |grad phi| (dual norm, 1/h units)]
@@ -304,13 +308,6 @@ __global__ __launch_bounds__(256) void k3_emd_cert(const double* __restrict__ ph
   if (!aniso) acc[1] = sqrt(acc[1]);
   const bool m[2] = {false, true};
   block_reduce_store<2>(acc, m, partials);
-}
-
-// out = a + b over n values (the flux m = u + grad psi)
-__global__ __launch_bounds__(256) void k3_add(const float* __restrict__ a, const float* __restrict__ b,
-                                              float* __restrict__ out, size_t n) {
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x)
-    out[o] = a[o] + b[o];
 }
 
 }  // namespace gp
