@@ -101,6 +101,20 @@ def test_rof3_converges_and_certifies(gpctx):
     assert (P - D) / P <= 1.1e-5
 
 
+def test_rof3_warm_start_from_a_solution(gpctx):
+    """Started from a solve's own (u, p) the warm solve meets the same tolerance
+    within a few iterations; the cold solve needs hundreds."""
+    from paper_1805_09453_amd import Options
+    I = f32(synth.rof_volume((64, 64, 64), 12))
+    announce("rof3_solve warm start 64^3")
+    u, p, rep = gpctx.rof3_solve(dev(I), 1.0, 8.0, Options(tau=0.05, tol=1e-4, max_iter=20000, check_every=10))
+    assert rep["converged"] and rep["iters"] >= 100
+    u2, p2, rep2 = gpctx.rof3_solve(dev(I), 1.0, 8.0, Options(tau=0.05, tol=2e-4, max_iter=1000, check_every=1,
+                                                              warm_start=True), u=u.clone(), p=p.clone())
+    print(rep["iters"], rep2)
+    assert rep2["converged"] and rep2["iters"] <= 10
+
+
 def test_emd3_z_only_closed_form(gpctx):
     """Densities varying along z only: EMD = (slice area) x h sum |C_k| with
     C_k = h sum_{j<=k}(rho1_j - rho0_j); the GPU's primal value matches it and
