@@ -100,30 +100,50 @@ __global__ __launch_bounds__(256) void k3_mu_plane(const double* __restrict__ mu
 }
 
 // cell (j, i, k) of a 3-D launch: x over blockIdx.x * blockDim.x + threadIdx.x
-// (nx a multiple of blockDim.x), y over blockIdx.y, z over blockIdx.z
+// (nx a multiple of blockDim.x), y over blockIdx.y, z over blockIdx.z.
+// Neighbour offsets: a neighbour that does not exist is replaced by the cell
+// itself, so every halo load is issued unconditionally from an in-bounds
+// address and masked afterwards (a load under a branch makes the compiler wait
+// for the loads before it); a forward difference with the cell itself is
+// exactly zero.
 struct Cell3 {
   int j, i, k;
   size_t o;
-  __device__ __forceinline__ Cell3(int ny, int nx) {
+  bool hx, hy, hz, lx, ly, lz;  // forward / backward neighbour exists along x, y, z
+  size_t fx, fy, fz, bx, by, bz;  // offsets to them (0 where they do not exist)
+  __device__ __forceinline__ Cell3(int nz, int ny, int nx) {
     j = blockIdx.x * blockDim.x + threadIdx.x;
     i = blockIdx.y;
     k = blockIdx.z;
     o = (size_t(k) * ny + i) * nx + j;
+    const size_t P = size_t(ny) * nx;
+    hx = j < nx - 1;
+    hy = i < ny - 1;
+    hz = k < nz - 1;
+    lx = j > 0;
+    ly = i > 0;
+    lz = k > 0;
+    fx = hx ? 1 : 0;
+    fy = hy ? size_t(nx) : 0;
+    fz = hz ? P : 0;
+    bx = lx ? 1 : 0;
+    by = ly ? size_t(nx) : 0;
+    bz = lz ? P : 0;
   }
 };
 
 // divergence (backward differences, far-face components read as zero) of
 // the planar field v at cell c, in grid units (times 1/h by the caller)
-__device__ __forceinline__ float div3_at(const float* __restrict__ v, size_t n, const Cell3& c, int nz, int ny,
-                                         int nx) {
-  const size_t P = size_t(ny) * nx;
+__device__ __forceinline__ float div3_at(const float* __restrict__ v, size_t n, const Cell3& c) {
   const float* vx = v;
   const float* vy = v + n;
   const float* vz = v + 2 * n;
+  const float ax = vx[c.o], ax0 = vx[c.o - c.bx], ay = vy[c.o], ay0 = vy[c.o - c.by], az = vz[c.o],
+              az0 = vz[c.o - c.bz];
   float d = 0.f;
-  d += (c.j < nx - 1 ? vx[c.o] : 0.f) - (c.j > 0 ? vx[c.o - 1] : 0.f);
-  d += (c.i < ny - 1 ? vy[c.o] : 0.f) - (c.i > 0 ? vy[c.o - nx] : 0.f);
-  d += (c.k < nz - 1 ? vz[c.o] : 0.f) - (c.k > 0 ? vz[c.o - P] : 0.f);
+  d += (c.hx ? ax : 0.f) - (c.lx ? ax0 : 0.f);
+  d += (c.hy ? ay : 0.f) - (c.ly ? ay0 : 0.f);
+  d += (c.hz ? az : 0.f) - (c.lz ? az0 : 0.f);
   return d;
 }
 
@@ -151,9 +171,9 @@ __device__ __forceinline__ float pnorm3(float x, float y, float z, int aniso) {
 __global__ __launch_bounds__(256) void k3_rof_rhs(const float* __restrict__ u, const float* __restrict__ pbar,
                                                   const float* __restrict__ I, float* __restrict__ r, int nz, int ny,
                                                   int nx, float lt, float tau_h) {
-  const Cell3 c(ny, nx);
+  const Cell3 c(nz, ny, nx);
   const size_t n = size_t(nz) * ny * nx;
-  r[c.o] = lt * (I[c.o] - u[c.o]) + tau_h * div3_at(pbar, n, c, nz, ny, nx);
+  r[c.o] = lt * (I[c.o] - u[c.o]) + tau_h * div3_at(pbar, n, c);
 }
 
 // u+ = u + delta, then the dual step p+ = proj(p + sigma grad u+), pbar+ = 2 p+ - p
@@ -163,12 +183,14 @@ __global__ __launch_bounds__(256) void k3_rof_update(const float* __restrict__ u
                                                      float* __restrict__ p, float* __restrict__ pbar,
                                                      float* __restrict__ u_out, int nz, int ny, int nx, float sig_h,
                                                      int aniso) {
-  const Cell3 c(ny, nx);
-  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  const Cell3 c(nz, ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
   const float uc = u_in[c.o] + d[c.o];
-  const float gx = c.j < nx - 1 ? (u_in[c.o + 1] + d[c.o + 1]) - uc : 0.f;
-  const float gy = c.i < ny - 1 ? (u_in[c.o + nx] + d[c.o + nx]) - uc : 0.f;
-  const float gz = c.k < nz - 1 ? (u_in[c.o + P] + d[c.o + P]) - uc : 0.f;
+  const float ux = u_in[c.o + c.fx] + d[c.o + c.fx], uy = u_in[c.o + c.fy] + d[c.o + c.fy],
+              uz = u_in[c.o + c.fz] + d[c.o + c.fz];
+  const float gx = c.hx ? ux - uc : 0.f;
+  const float gy = c.hy ? uy - uc : 0.f;
+  const float gz = c.hz ? uz - uc : 0.f;
   const float ox = p[c.o], oy = p[c.o + n], oz = p[c.o + 2 * n];
   float qx = ox + sig_h * gx, qy = oy + sig_h * gy, qz = oz + sig_h * gz;
   proj_ball3(qx, qy, qz, aniso);
@@ -216,12 +238,14 @@ __global__ __launch_bounds__(256) void k3_rof_energy(const float* __restrict__ u
 // b = -div w / h in FP64: (0 I - Delta) phi = b gives Delta phi = div w
 __global__ __launch_bounds__(256) void k3_emd_rhs(const float* __restrict__ w, double* __restrict__ b, int nz,
                                                   int ny, int nx, double inv_h) {
-  const Cell3 c(ny, nx);
-  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  const Cell3 c(nz, ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
+  const float ax = w[c.o], ax0 = w[c.o - c.bx], ay = w[n + c.o], ay0 = w[n + c.o - c.by], az = w[2 * n + c.o],
+              az0 = w[2 * n + c.o - c.bz];
   double d = 0.0;
-  d += double(c.j < nx - 1 ? w[c.o] : 0.f) - double(c.j > 0 ? w[c.o - 1] : 0.f);
-  d += double(c.i < ny - 1 ? w[n + c.o] : 0.f) - double(c.i > 0 ? w[n + c.o - nx] : 0.f);
-  d += double(c.k < nz - 1 ? w[2 * n + c.o] : 0.f) - double(c.k > 0 ? w[2 * n + c.o - P] : 0.f);
+  d += double(c.hx ? ax : 0.f) - double(c.lx ? ax0 : 0.f);
+  d += double(c.hy ? ay : 0.f) - double(c.ly ? ay0 : 0.f);
+  d += double(c.hz ? az : 0.f) - double(c.lz ? az0 : 0.f);
   b[c.o] = -d * inv_h;
 }
 
@@ -233,13 +257,13 @@ __global__ __launch_bounds__(256) void k3_emd_update(float* __restrict__ w, floa
                                                      const double* __restrict__ phi, const float* __restrict__ gpsi,
                                                      float* __restrict__ mout, int nz, int ny, int nx, float tau,
                                                      float sigma, double inv_h, int aniso) {
-  const Cell3 c(ny, nx);
-  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
-  const double fc = phi[c.o];
-  const bool hx = c.j < nx - 1, hy = c.i < ny - 1, hz = c.k < nz - 1;
-  const float ux = hx ? w[c.o] - float((phi[c.o + 1] - fc) * inv_h) : 0.f;
-  const float uy = hy ? w[n + c.o] - float((phi[c.o + nx] - fc) * inv_h) : 0.f;
-  const float uz = hz ? w[2 * n + c.o] - float((phi[c.o + P] - fc) * inv_h) : 0.f;
+  const Cell3 c(nz, ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
+  const double fc = phi[c.o], fx = phi[c.o + c.fx], fy = phi[c.o + c.fy], fz = phi[c.o + c.fz];
+  const float wx = w[c.o], wy = w[n + c.o], wz = w[2 * n + c.o];
+  const float ux = c.hx ? wx - float((fx - fc) * inv_h) : 0.f;
+  const float uy = c.hy ? wy - float((fy - fc) * inv_h) : 0.f;
+  const float uz = c.hz ? wz - float((fz - fc) * inv_h) : 0.f;
   const float mx = ux + gpsi[c.o], my = uy + gpsi[n + c.o], mz = uz + gpsi[2 * n + c.o];
   const float ox = p[c.o], oy = p[n + c.o], oz = p[2 * n + c.o];
   float qx = ox + sigma * mx, qy = oy + sigma * my, qz = oz + sigma * mz;
@@ -260,24 +284,26 @@ __global__ __launch_bounds__(256) void k3_emd_update(float* __restrict__ w, floa
 // b = -div p / h (FP64): the certificate potential phi_c with Delta phi_c = div p
 __global__ __launch_bounds__(256) void k3_div_f64(const float* __restrict__ p, double* __restrict__ b, int nz,
                                                   int ny, int nx, double inv_h) {
-  const Cell3 c(ny, nx);
-  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  const Cell3 c(nz, ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
+  const float ax = p[c.o], ax0 = p[c.o - c.bx], ay = p[n + c.o], ay0 = p[n + c.o - c.by], az = p[2 * n + c.o],
+              az0 = p[2 * n + c.o - c.bz];
   double d = 0.0;
-  d += double(c.j < nx - 1 ? p[c.o] : 0.f) - double(c.j > 0 ? p[c.o - 1] : 0.f);
-  d += double(c.i < ny - 1 ? p[n + c.o] : 0.f) - double(c.i > 0 ? p[n + c.o - nx] : 0.f);
-  d += double(c.k < nz - 1 ? p[2 * n + c.o] : 0.f) - double(c.k > 0 ? p[2 * n + c.o - P] : 0.f);
+  d += double(c.hx ? ax : 0.f) - double(c.lx ? ax0 : 0.f);
+  d += double(c.hy ? ay : 0.f) - double(c.ly ? ay0 : 0.f);
+  d += double(c.hz ? az : 0.f) - double(c.lz ? az0 : 0.f);
   b[c.o] = -d * inv_h;
 }
 
 // grad psi from the FP64 potential, stored FP32 (planar, 3 components)
 __global__ __launch_bounds__(256) void k3_grad_f64(const double* __restrict__ psi, float* __restrict__ g, int nz,
                                                    int ny, int nx, double inv_h) {
-  const Cell3 c(ny, nx);
-  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
-  const double fc = psi[c.o];
-  g[c.o] = c.j < nx - 1 ? float((psi[c.o + 1] - fc) * inv_h) : 0.f;
-  g[n + c.o] = c.i < ny - 1 ? float((psi[c.o + nx] - fc) * inv_h) : 0.f;
-  g[2 * n + c.o] = c.k < nz - 1 ? float((psi[c.o + P] - fc) * inv_h) : 0.f;
+  const Cell3 c(nz, ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
+  const double fc = psi[c.o], fx = psi[c.o + c.fx], fy = psi[c.o + c.fy], fz = psi[c.o + c.fz];
+  g[c.o] = c.hx ? float((fx - fc) * inv_h) : 0.f;
+  g[n + c.o] = c.hy ? float((fy - fc) * inv_h) : 0.f;
+  g[2 * n + c.o] = c.hz ? float((fz - fc) * inv_h) : 0.f;
 }
 
 // EMD primal partials: sum |m| over the flux m [3][n] (grid-stride over the cells)
