@@ -8,7 +8,9 @@
 // differences).  The screened Poisson solve (alpha I - Delta)^{-1} is a 3-D
 // DCT-II in five passes over the field:
 //   x forward   k_rows_fwd  (rows of the [nz ny][nx] view, written to the
-//                            strip-tiled intermediate of each z-plane)
+//                            strip-tiled intermediate of each z-plane); in the
+//                            solvers k3_rows_fwd_rhs, which forms the
+//                            right-hand side in its loads
 //   y forward   k3_cols_dct<.., false> (columns of each z-plane's tiles)
 //   z solve     k_cols_solve over the [nz][ny nx] view: DCT-II along z,
 //               scale by 1/(nx ny nz (alpha + mu_z + mu_y + mu_x)), inverse
@@ -83,6 +85,91 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
   }
 }
 
+// x-forward DCT-II pass fused with the right-hand side it transforms, formed
+// in the loads of the FFT's first pass (Makhoul pairs (2m, 2m+1) of each row
+// pair) and never stored:
+//   ROF (C = float2):  r = lambda tau (I - u) + tau div pbar
+//   EMD (C = double2): b = -div w / h in FP64 (w the stored field)
+// V is the planar vector field whose divergence is taken (pbar or w; backward
+// differences, far-face components read as zero, every halo load issued
+// unconditionally from an in-bounds address and masked); rows of the
+// [nz ny][N] view, output to each plane's strip-tiled intermediate as
+// k_rows_fwd.  (0 I - Delta) phi = b then gives Delta phi = div w.
+template <int N, class C, bool EMD>
+__global__ __launch_bounds__((RowShape<N, C>::MAXT), (RowShape<N, C>::MINW)) void k3_rows_fwd_rhs(
+    const float* __restrict__ u, const float* __restrict__ V, const float* __restrict__ I,
+    typename Cx<C>::R* __restrict__ out, int nz, int ny, int lgtw, float lt, float tau_h, double inv_h,
+    const C* __restrict__ tw, const C* __restrict__ dctw) {
+  using Re = typename Cx<C>::R;
+  using SH = RowShape<N, C>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* smem = reinterpret_cast<C*>(smem_raw);
+  const int g = threadIdx.x / SH::T, t = threadIdx.x % SH::T;
+  C* lds = smem + g * Sched<N>::LDS;
+  const int rows = nz * ny;
+  const int ra = 2 * (blockIdx.x * int(blockDim.x / SH::T) + g), rb = ra + 1;
+  const bool va = ra < rows;  // rows is even: rb exists with ra
+  const size_t n = size_t(rows) * N, P = size_t(ny) * N;
+  const float* vx = V;
+  const float* vy = V + n;
+  const float* vz = V + 2 * n;
+  // right-hand side at (row, 2m) and (row, 2m + 1); an out-of-range row pair reads row 0 and is not stored
+  auto rhs2 = [&](int row, int m, Re& r0, Re& r1) {
+    const int i = row % ny, k = row / ny;
+    const bool hy = i < ny - 1, ly = i > 0, hz = k < nz - 1, lz = k > 0, lx0 = m > 0, hx1 = 2 * m + 1 < N - 1;
+    const size_t base = size_t(row) * N + 2 * m;
+    const float2 X = *reinterpret_cast<const float2*>(vx + base);
+    const float Xl = vx[base - (lx0 ? 1 : 0)];
+    const float2 Y = *reinterpret_cast<const float2*>(vy + base);
+    const float2 Ym = *reinterpret_cast<const float2*>(vy + base - (ly ? size_t(N) : 0));
+    const float2 Z = *reinterpret_cast<const float2*>(vz + base);
+    const float2 Zm = *reinterpret_cast<const float2*>(vz + base - (lz ? P : 0));
+    if constexpr (!EMD) {
+      const float2 U = *reinterpret_cast<const float2*>(u + base);
+      const float2 J = *reinterpret_cast<const float2*>(I + base);
+      float d0 = 0.f, d1 = 0.f;
+      d0 += X.x - (lx0 ? Xl : 0.f);
+      d0 += (hy ? Y.x : 0.f) - (ly ? Ym.x : 0.f);
+      d0 += (hz ? Z.x : 0.f) - (lz ? Zm.x : 0.f);
+      d1 += (hx1 ? X.y : 0.f) - X.x;
+      d1 += (hy ? Y.y : 0.f) - (ly ? Ym.y : 0.f);
+      d1 += (hz ? Z.y : 0.f) - (lz ? Zm.y : 0.f);
+      r0 = lt * (J.x - U.x) + tau_h * d0;
+      r1 = lt * (J.y - U.y) + tau_h * d1;
+    } else {
+      double d0 = 0.0, d1 = 0.0;
+      d0 += double(X.x) - double(lx0 ? Xl : 0.f);
+      d0 += double(hy ? Y.x : 0.f) - double(ly ? Ym.x : 0.f);
+      d0 += double(hz ? Z.x : 0.f) - double(lz ? Zm.x : 0.f);
+      d1 += double(hx1 ? X.y : 0.f) - double(X.x);
+      d1 += double(hy ? Y.y : 0.f) - double(ly ? Ym.y : 0.f);
+      d1 += double(hz ? Z.y : 0.f) - double(lz ? Zm.y : 0.f);
+      r0 = -d0 * inv_h;
+      r1 = -d1 * inv_h;
+    }
+  };
+  const int la = va ? ra : 0, lb = va ? rb : 1;
+  Vals<N, C> v;
+  dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
+    Re a0, a1, b0, b1;
+    rhs2(la, m, a0, a1);
+    rhs2(lb, m, b0, b1);
+    A = mk<C>(a0, a1);
+    B = mk<C>(b0, b1);
+  });
+  if (va) {
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const SlotTile<N> ta(ra, t, slot, ny, lgtw), tb(rb, t, slot, ny, lgtw);
+#pragma unroll
+      for (int s = 0; s < Sched<N>::H; ++s) {
+        out[ta.at(s)] = v[slot * Sched<N>::H + s].x;
+        out[tb.at(s)] = v[slot * Sched<N>::H + s].y;
+      }
+    }
+  }
+}
+
 // Eigenvalue sums mu_y[ky] + mu_x[kx] of one z-plane, laid out like the
 // plane's strip-tiled intermediate (the z pass reads them per column).
 __global__ __launch_bounds__(256) void k3_mu_plane(const double* __restrict__ muy, const double* __restrict__ mux,
@@ -132,21 +219,6 @@ struct Cell3 {
   }
 };
 
-// divergence (backward differences, far-face components read as zero) of
-// the planar field v at cell c, in grid units (times 1/h by the caller)
-__device__ __forceinline__ float div3_at(const float* __restrict__ v, size_t n, const Cell3& c) {
-  const float* vx = v;
-  const float* vy = v + n;
-  const float* vz = v + 2 * n;
-  const float ax = vx[c.o], ax0 = vx[c.o - c.bx], ay = vy[c.o], ay0 = vy[c.o - c.by], az = vz[c.o],
-              az0 = vz[c.o - c.bz];
-  float d = 0.f;
-  d += (c.hx ? ax : 0.f) - (c.lx ? ax0 : 0.f);
-  d += (c.hy ? ay : 0.f) - (c.ly ? ay0 : 0.f);
-  d += (c.hz ? az : 0.f) - (c.lz ? az0 : 0.f);
-  return d;
-}
-
 __device__ __forceinline__ void proj_ball3(float& x, float& y, float& z, int aniso) {
   if (aniso) {
     x = fminf(1.f, fmaxf(-1.f, x));
@@ -167,15 +239,6 @@ __device__ __forceinline__ float pnorm3(float x, float y, float z, int aniso) {
 }
 
 // ---------------------------------------------------------------- ROF (section 3.1 updates)
-// right-hand side of the incremental u-step: r = lambda tau (I - u) + tau div pbar
-__global__ __launch_bounds__(256) void k3_rof_rhs(const float* __restrict__ u, const float* __restrict__ pbar,
-                                                  const float* __restrict__ I, float* __restrict__ r, int nz, int ny,
-                                                  int nx, float lt, float tau_h) {
-  const Cell3 c(nz, ny, nx);
-  const size_t n = size_t(nz) * ny * nx;
-  r[c.o] = lt * (I[c.o] - u[c.o]) + tau_h * div3_at(pbar, n, c);
-}
-
 // u+ = u + delta, then the dual step p+ = proj(p + sigma grad u+), pbar+ = 2 p+ - p
 // (u+ at the three forward neighbours formed from their own u and delta).
 // u_out must not alias u_in; p and pbar are updated in place.
@@ -234,21 +297,7 @@ __global__ __launch_bounds__(256) void k3_rof_energy(const float* __restrict__ u
 // ---------------------------------------------------------------- EMD (section 3.2 updates, projected form)
 // The state between iterations is (w, p) with the stored field w = u - tau pbar
 // (u the divergence-free part of the flux): the next projection needs only
-// div w, and the next update only w at the cell itself.
-// b = -div w / h in FP64: (0 I - Delta) phi = b gives Delta phi = div w
-__global__ __launch_bounds__(256) void k3_emd_rhs(const float* __restrict__ w, double* __restrict__ b, int nz,
-                                                  int ny, int nx, double inv_h) {
-  const Cell3 c(nz, ny, nx);
-  const size_t n = size_t(nz) * ny * nx;
-  const float ax = w[c.o], ax0 = w[c.o - c.bx], ay = w[n + c.o], ay0 = w[n + c.o - c.by], az = w[2 * n + c.o],
-              az0 = w[2 * n + c.o - c.bz];
-  double d = 0.0;
-  d += double(c.hx ? ax : 0.f) - double(c.lx ? ax0 : 0.f);
-  d += double(c.hy ? ay : 0.f) - double(c.ly ? ay0 : 0.f);
-  d += double(c.hz ? az : 0.f) - double(c.lz ? az0 : 0.f);
-  b[c.o] = -d * inv_h;
-}
-
+// div w (formed in k3_rows_fwd_rhs), and the next update only w at the cell.
 // u+ = w - grad phi (the Leray projection of u - tau pbar), p+ = proj(p + sigma
 // (u+ + grad psi)), pbar+ = 2 p+ - p, and the next stored field w+ = u+ - tau pbar+.
 // Pointwise in w and p (updated in place); phi read at the forward neighbours
