@@ -47,7 +47,24 @@ def test_dct_poisson3_matches_oracle(gpctx, shape, h, alpha):
     assert e32 <= 2e-6 and e64 <= 1e-12
 
 
-@pytest.mark.parametrize("shape,norm,tau", [((64, 64, 64), 0, 0.05), ((64, 128, 64), 1, 0.2)])
+@pytest.mark.parametrize("shape", [(64, 64, 4096), (64, 4096, 64), (4096, 64, 64)])
+def test_dct_poisson3_long_axes(gpctx, shape):
+    """Each axis at the longest transform (4096, the radix-16 schedule) with the
+    other two at the shortest: x rows, y columns and z columns of every length
+    class."""
+    b = np.random.default_rng(13).standard_normal(shape)
+    announce(f"dct_poisson3 {shape}")
+    x32 = gpctx.dct_poisson3(dev(b), h=1.0 / 64, alpha=0.0)
+    x64 = gpctx.dct_poisson3(dev(b, np.float64), h=1.0 / 64, alpha=0.0)
+    ref32 = g3.poisson_solve(f32(b), 1.0 / 64, 0.0)
+    ref64 = g3.poisson_solve(b, 1.0 / 64, 0.0)
+    e32, e64 = rel(host(x32), ref32), rel(host(x64), ref64)
+    print(f"rel err fp32 {e32:.2e} fp64 {e64:.2e}")
+    assert e32 <= 5e-6 and e64 <= 1e-12
+
+
+@pytest.mark.parametrize("shape,norm,tau", [((64, 64, 64), 0, 0.05), ((64, 128, 64), 1, 0.2),
+                                            ((64, 64, 1024), 0, 0.05)])
 def test_rof3_iterations_match_oracle(gpctx, shape, norm, tau):
     from paper_1805_09453_amd import Options
     I = f32(synth.rof_volume(shape, 5))
@@ -65,7 +82,8 @@ def test_rof3_iterations_match_oracle(gpctx, shape, norm, tau):
     assert abs(rep["dual"] - ref.dual) <= 1e-6 * abs(ref.primal)
 
 
-@pytest.mark.parametrize("shape,norm,tau", [((64, 64, 64), 0, 0.3), ((128, 64, 64), 1, 1.0)])
+@pytest.mark.parametrize("shape,norm,tau", [((64, 64, 64), 0, 0.3), ((128, 64, 64), 1, 1.0),
+                                            ((1024, 64, 64), 0, 0.3)])
 def test_emd3_iterations_match_oracle(gpctx, shape, norm, tau):
     from paper_1805_09453_amd import Options
     r0, r1 = (f32(a) for a in synth.emd_volume_pair(shape, 6))
