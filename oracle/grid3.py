@@ -252,3 +252,36 @@ def emd_solve(rho0, rho1, h, tau=1.0, sigma=None, tol=1e-5, max_iter=100000, che
                 break
     m = tuple(a + b for a, b in zip(u, gpsi))
     return EmdResult(u, p, f, psi, m, it, P, D, g, conv, hist)
+
+
+# ---------------------------------------------------------------- single-variable form (sigma tau = 1)
+# With sigma = 1/tau the two-variable iteration above depends on (u_n, p_n, pbar_n)
+# only through y_n = p_{n-1} + sigma grad u_n (ROF) or y_n = p_{n-1} + sigma (u_n +
+# grad psi) (EMD), with p_n = proj(y_n): the boundary case tau sigma = 1 that
+# section 2 relates to Douglas-Rachford splitting.  Writing R(y) = 2 proj(y) - y:
+#   ROF  u_{n+1} = (lambda tau - Delta)^{-1} (lambda tau I + tau div R(y_n)),
+#        y_{n+1} = proj(y_n) + sigma grad u_{n+1}
+#   EMD  y_{n+1} = y_n - proj(y_n) + grad Delta^{-1} div R(y_n) + sigma grad psi,
+#        u_{n+1} = -tau (R(y_n) - grad Delta^{-1} div R(y_n))
+# (the EMD u-update is the projection P applied to u_n - tau pbar_n = -tau R(y_n)
+# - grad psi, P grad psi = 0).  The zero start u_0 = 0, p_0 = pbar_0 = 0 is y_0 = 0
+# in both.  Derived here from the updates of sections 3.1 and 3.2.
+def reflect(y, norm=ISO):
+    q = project_unit_ball(*y, norm)
+    return q, tuple(2.0 * a - b for a, b in zip(q, y))
+
+
+def rof_drs_step(y, I, h, lam, tau, norm=ISO):
+    """One single-variable ROF step (sigma = 1/tau): returns (u_{n+1}, y_{n+1})."""
+    q, R = reflect(y, norm)
+    u1 = poisson_solve(lam * tau * I + tau * div(*R, h), h, lam * tau)
+    g = grad(u1, h)
+    return u1, tuple(a + b / tau for a, b in zip(q, g))
+
+
+def emd_drs_step(y, gpsi, h, tau, norm=ISO):
+    """One single-variable EMD step (sigma = 1/tau): returns (u_{n+1}, y_{n+1})."""
+    q, R = reflect(y, norm)
+    gphi = grad(inv_laplacian(div(*R, h), h), h)
+    u1 = tuple(-tau * (r - g) for r, g in zip(R, gphi))
+    return u1, tuple(a - b + g + c / tau for a, b, g, c in zip(y, q, gphi, gpsi))

@@ -162,3 +162,44 @@ def test_rof_converges_with_invariants():
     bound = np.sqrt(2 * (res.primal - res.dual) / lam) + np.sqrt(2 * (ref.primal - ref.dual) / lam)
     assert dist <= bound
     assert dist >= 1e-3 * bound  # (the bound is not vacuous: the two solves differ)
+
+
+@pytest.mark.parametrize("norm", [grid.ISO, grid.ANISO])
+def test_single_variable_rof_equals_the_two_variable_iteration(norm):
+    """sigma = 1/tau: from y_0 = 0 the single-variable iteration reproduces the
+    iterates of rof_step from the zero start, u_n and p_n = proj(y_n)."""
+    rng = np.random.default_rng(31)
+    I = rng.random((6, 8, 10))
+    h, lam, tau = 0.7, 8.0, 0.3
+    u = np.zeros_like(I)
+    p = tuple(np.zeros_like(I) for _ in range(3))
+    pb = tuple(a.copy() for a in p)
+    y = tuple(np.zeros_like(I) for _ in range(3))
+    for _ in range(12):
+        u, p, pb = g3.rof_step(u, p, pb, I, h, lam, tau, 1 / tau, norm)
+        u2, y = g3.rof_drs_step(y, I, h, lam, tau, norm)
+        q = g3.project_unit_ball(*y, norm)
+        assert np.abs(u2 - u).max() <= 1e-12 * np.abs(u).max()
+        assert max(np.abs(a - b).max() for a, b in zip(q, p)) <= 1e-12
+
+
+@pytest.mark.parametrize("norm", [grid.ISO, grid.ANISO])
+def test_single_variable_emd_equals_the_two_variable_iteration(norm):
+    rng = np.random.default_rng(32)
+    a = rng.random((8, 8, 8)) + 0.5
+    b = rng.random((8, 8, 8)) + 0.5
+    b *= a.sum() / b.sum()
+    h, tau = 1.0 / 8, 0.4
+    f, psi = g3.emd_setup(a, b, h)
+    gp = g3.grad(psi, h)
+    u = tuple(np.zeros_like(f) for _ in range(3))
+    p = tuple(np.zeros_like(f) for _ in range(3))
+    pb = tuple(x.copy() for x in p)
+    y = tuple(np.zeros_like(f) for _ in range(3))
+    for _ in range(12):
+        u, p, pb = g3.emd_step(u, p, pb, gp, h, tau, 1 / tau, norm)
+        u2, y = g3.emd_drs_step(y, gp, h, tau, norm)
+        q = g3.project_unit_ball(*y, norm)
+        scale = max(np.abs(x).max() for x in u) + 1.0
+        assert max(np.abs(x - z).max() for x, z in zip(u2, u)) <= 1e-12 * scale
+        assert max(np.abs(x - z).max() for x, z in zip(q, p)) <= 1e-12
