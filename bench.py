@@ -197,9 +197,9 @@ def warm_leg(ctx, r0, r1, n, tol, max_iter):
 # HBM bytes per cell and iteration that the 3-D loops stream (FP32 state; EMD potential FP64):
 # ROF  x-forward pass with the right-hand side (u, pbar, I -> tiles) 24 + four more passes 4 x 8
 #      + update (u, delta, p -> u, p, pbar) 48
-# EMD  x-forward pass with div w (w -> tiles) 20 + four more FP64 passes 4 x 16
-#      + update (w, p, phi, grad psi -> w, p) 68   (w = u - tau pbar, the stored field)
-GRID3_BYTES = {"rof3": 104.0, "emd3": 152.0}
+# EMD  (sigma tau = 1: the single-variable form, state y = p_prev + sigma (u + grad psi))
+#      rhs (y -> b = div R(y)) 20 + five FP64 passes 5 x 16 + update (y, phi, grad psi -> y) 44
+GRID3_BYTES = {"rof3": 104.0, "emd3": 144.0}
 
 
 def grid3_leg(ctx, dev, n3, C, K, W):

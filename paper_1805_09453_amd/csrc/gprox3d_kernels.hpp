@@ -385,4 +385,80 @@ __global__ __launch_bounds__(256) void k3_emd_cert(const double* __restrict__ ph
   block_reduce_store<2>(acc, m, partials);
 }
 
+// ---------------------------------------------------------------- single-variable form (sigma tau = 1)
+// With sigma = 1/tau the EMD iteration depends on (u, p, pbar) only through
+// y_n = p_{n-1} + sigma (u_n + grad psi), with p_n = proj(y_n) and
+// R(y) = 2 proj(y) - y (the Douglas-Rachford case of section 2):
+//   phi = Delta^{-1} div R(y_n), u_{n+1} = -tau (R(y_n) - grad phi),
+//   y_{n+1} = y_n - proj(y_n) + grad phi + sigma grad psi
+// One 3-component field is the whole state; the zero start is y_0 = 0.  (The
+// ROF iteration has the same form, but it forms u afresh each iteration, which
+// costs FP32 accuracy; ROF keeps the incremental two-variable form.)
+
+// R(y) = 2 proj(y) - y at offset o (all three components: the projection couples them)
+__device__ __forceinline__ void refl3(const float* __restrict__ y, size_t n, size_t o, int aniso, float& rx,
+                                      float& ry, float& rz) {
+  const float yx = y[o], yy = y[n + o], yz = y[2 * n + o];
+  float qx = yx, qy = yy, qz = yz;
+  proj_ball3(qx, qy, qz, aniso);
+  rx = 2.f * qx - yx;
+  ry = 2.f * qy - yy;
+  rz = 2.f * qz - yz;
+}
+
+// EMD: b = -div R(y) / h in FP64: (0 I - Delta) phi = b gives Delta phi = div R(y)
+__global__ __launch_bounds__(256) void k3_drs_emd_rhs(const float* __restrict__ y, double* __restrict__ b, int nz,
+                                                      int ny, int nx, double inv_h, int aniso) {
+  const Cell3 c(nz, ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
+  float Rx, Ry, Rz, Ax, Ay, Az, Bx, By, Bz, Cx, Cy, Cz;
+  refl3(y, n, c.o, aniso, Rx, Ry, Rz);
+  refl3(y, n, c.o - c.bx, aniso, Ax, Ay, Az);
+  refl3(y, n, c.o - c.by, aniso, Bx, By, Bz);
+  refl3(y, n, c.o - c.bz, aniso, Cx, Cy, Cz);
+  double d = 0.0;
+  d += double(c.hx ? Rx : 0.f) - double(c.lx ? Ax : 0.f);
+  d += double(c.hy ? Ry : 0.f) - double(c.ly ? By : 0.f);
+  d += double(c.hz ? Rz : 0.f) - double(c.lz ? Cz : 0.f);
+  b[c.o] = -d * inv_h;
+}
+
+// EMD: y <- y - proj(y) + grad phi + sigma grad psi (in place); mout (nullable):
+// the flux of the new iterate, m = u + grad psi = -tau (R(y) - grad phi) + grad psi
+__global__ __launch_bounds__(256) void k3_drs_emd_update(float* __restrict__ y, const double* __restrict__ phi,
+                                                         const float* __restrict__ gpsi, float* __restrict__ mout,
+                                                         int nz, int ny, int nx, float tau, float sigma, double inv_h,
+                                                         int aniso) {
+  const Cell3 c(nz, ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
+  const double fc = phi[c.o], fx = phi[c.o + c.fx], fy = phi[c.o + c.fy], fz = phi[c.o + c.fz];
+  const float gx = c.hx ? float((fx - fc) * inv_h) : 0.f;
+  const float gy = c.hy ? float((fy - fc) * inv_h) : 0.f;
+  const float gz = c.hz ? float((fz - fc) * inv_h) : 0.f;
+  const float yx = y[c.o], yy = y[n + c.o], yz = y[2 * n + c.o];
+  const float sx = gpsi[c.o], sy = gpsi[n + c.o], sz = gpsi[2 * n + c.o];
+  float qx = yx, qy = yy, qz = yz;
+  proj_ball3(qx, qy, qz, aniso);
+  y[c.o] = (yx - qx) + gx + sigma * sx;
+  y[n + c.o] = (yy - qy) + gy + sigma * sy;
+  y[2 * n + c.o] = (yz - qz) + gz + sigma * sz;
+  if (mout) {
+    mout[c.o] = -tau * ((2.f * qx - yx) - gx) + sx;
+    mout[n + c.o] = -tau * ((2.f * qy - yy) - gy) + sy;
+    mout[2 * n + c.o] = -tau * ((2.f * qz - yz) - gz) + sz;
+  }
+}
+
+// p = proj(y), pointwise over n cells (the dual iterate of the single-variable form)
+__global__ __launch_bounds__(256) void k3_proj3(const float* __restrict__ y, float* __restrict__ p, size_t n,
+                                                int aniso) {
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    float qx = y[o], qy = y[n + o], qz = y[2 * n + o];
+    proj_ball3(qx, qy, qz, aniso);
+    p[o] = qx;
+    p[n + o] = qy;
+    p[2 * n + o] = qz;
+  }
+}
+
 }  // namespace gp

@@ -103,6 +103,38 @@ def test_emd3_iterations_match_oracle(gpctx, shape, norm, tau):
     assert abs(rep["dual"] - D) <= 2e-6 * ref.primal
 
 
+@pytest.mark.parametrize("kind", ["rof", "emd"])
+def test_3d_two_variable_form_matches_oracle(gpctx, kind):
+    """sigma tau < 1 runs the two-variable iteration (sigma tau = 1 from the zero
+    start runs the single-variable form, which the other parity tests cover)."""
+    from paper_1805_09453_amd import Options
+    shape, K = (64, 64, 64), 6
+    if kind == "rof":
+        I = f32(synth.rof_volume(shape, 14))
+        tau, sigma = 0.05, 0.5 / 0.05
+        announce("rof3_solve sigma tau = 1/2")
+        u, p, rep = gpctx.rof3_solve(dev(I), 1.0, 8.0, Options(tau=tau, sigma=sigma, tol=0.0, max_iter=K,
+                                                               check_every=K))
+        ref = g3.rof_solve(I, 1.0, 8.0, tau, sigma=sigma, tol=0.0, max_iter=K, check_every=K)
+        pg = host(p)
+        errs = [rel(host(u), ref.u)] + [rel(pg[i], ref.p[i]) for i in range(3)]
+        P, D = ref.primal, ref.dual
+    else:
+        r0, r1 = (f32(a) for a in synth.emd_volume_pair(shape, 15))
+        h, tau, sigma = 1.0 / 64, 0.3, 0.5 / 0.3
+        announce("emd3_solve sigma tau = 1/2")
+        m, phi, rep = gpctx.emd3_solve(dev(r0), dev(r1), h, Options(tau=tau, sigma=sigma, tol=0.0, max_iter=K,
+                                                                    check_every=K))
+        ref = g3.emd_solve(r0, r1, h, tau=tau, sigma=sigma, tol=0.0, max_iter=K, check_every=K)
+        D, L, phit = g3.emd_certificate(ref.p, ref.f, h)
+        mg = host(m)
+        errs = [rel(mg[i], ref.m[i]) for i in range(3)] + [rel(host(phi), phit)]
+        P = ref.primal
+    print(kind, ["%.2e" % e for e in errs], rep["primal"], P, rep["dual"], D)
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - P) <= 1e-6 * abs(P) and abs(rep["dual"] - D) <= 2e-6 * abs(P)
+
+
 def test_rof3_converges_and_certifies(gpctx):
     """A solve to a relative gap of 1e-5; P and D recomputed in FP64 from the
     returned u and p agree with the reported ones (the gap certifies u)."""
