@@ -178,7 +178,11 @@ int rof3_solve(gp_ctx* ctx, const float* I, float* u, float* p, int nz, int ny, 
  * d = 3, projected form, FP64 potentials) from the zero start.  m: out flux
  * u + grad psi [3][nz][ny][nx]; phi: nullable out [nz][ny][nx], the scaled
  * certificate potential.  rep->primal = h^3 sum |m|, rep->dual the
- * certificate's lower bound.  warm_start and ergodic are not supported. */
+ * certificate's lower bound.  warm_start and ergodic are not supported.
+ * With sigma tau = 1 (the default sigma) the same iterates are formed in the
+ * equivalent single-variable form (state y = p_prev + sigma (u + grad psi),
+ * p = proj(y); the Douglas-Rachford case of section 2), which stores one
+ * vector field instead of two. */
 int emd3_solve(gp_ctx* ctx, const float* rho0, const float* rho1, float* m, float* phi, int nz, int ny, int nx,
                double h, const gp_opts* opts, gp_report* rep);
 
