@@ -406,21 +406,52 @@ __device__ __forceinline__ void refl3(const float* __restrict__ y, size_t n, siz
   rz = 2.f * qz - yz;
 }
 
-// EMD: b = -div R(y) / h in FP64: (0 I - Delta) phi = b gives Delta phi = div R(y)
-__global__ __launch_bounds__(256) void k3_drs_emd_rhs(const float* __restrict__ y, double* __restrict__ b, int nz,
-                                                      int ny, int nx, double inv_h, int aniso) {
-  const Cell3 c(nz, ny, nx);
-  const size_t n = size_t(nz) * ny * nx;
-  float Rx, Ry, Rz, Ax, Ay, Az, Bx, By, Bz, Cx, Cy, Cz;
-  refl3(y, n, c.o, aniso, Rx, Ry, Rz);
-  refl3(y, n, c.o - c.bx, aniso, Ax, Ay, Az);
-  refl3(y, n, c.o - c.by, aniso, Bx, By, Bz);
-  refl3(y, n, c.o - c.bz, aniso, Cx, Cy, Cz);
-  double d = 0.0;
-  d += double(c.hx ? Rx : 0.f) - double(c.lx ? Ax : 0.f);
-  d += double(c.hy ? Ry : 0.f) - double(c.ly ? By : 0.f);
-  d += double(c.hz ? Rz : 0.f) - double(c.lz ? Cz : 0.f);
-  b[c.o] = -d * inv_h;
+// EMD: b = -div R(y) / h in FP64: (0 I - Delta) phi = b gives Delta phi = div R(y).
+// R couples the three components of y at a cell, so each cell's R is formed
+// once and shared: a block is a tile of TX x TY cells of one plane (the x and
+// y backward neighbours' R from LDS, the tile's edge threads forming the
+// halo's) and marches ZB planes along z, keeping R_z of the previous plane in
+// a register.  Launch: block (TX, TY), grid (nx / TX, ny / TY, nz / ZB).
+template <int TX, int TY, int ZB>
+__global__ __launch_bounds__(TX* TY) void k3_drs_emd_rhs(const float* __restrict__ y, double* __restrict__ b, int nz,
+                                                          int ny, int nx, double inv_h, int aniso) {
+  __shared__ float sx[TY][TX + 1];  // R_x, column 0: the x halo
+  __shared__ float sy[TY + 1][TX];  // R_y, row 0: the y halo
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int j = blockIdx.x * TX + tx, i = blockIdx.y * TY + ty, k0 = blockIdx.z * ZB;
+  const size_t n = size_t(nz) * ny * nx, P = size_t(ny) * nx;
+  const bool hx = j < nx - 1, lx = j > 0, hy = i < ny - 1, ly = i > 0;
+  size_t o = (size_t(k0) * ny + i) * nx + j;
+  float Rx, Ry, Rz, t0, t1, rzm = 0.f;
+  if (k0 > 0) refl3(y, n, o - P, aniso, t0, t1, rzm);  // R_z of the plane below the first
+#pragma unroll 1
+  for (int kk = 0; kk < ZB; ++kk) {
+    const int k = k0 + kk;
+    refl3(y, n, o, aniso, Rx, Ry, Rz);
+    sx[ty][tx + 1] = Rx;
+    sy[ty + 1][tx] = Ry;
+    if (tx == 0) {  // x halo: R_x at j - 1 (the cell itself, masked, at j = 0)
+      float hxv, a1, a2;
+      refl3(y, n, o - (lx ? 1 : 0), aniso, hxv, a1, a2);
+      sx[ty][0] = hxv;
+    }
+    if (ty == 0) {  // y halo: R_y at i - 1
+      float a0, hyv, a2;
+      refl3(y, n, o - (ly ? size_t(nx) : 0), aniso, a0, hyv, a2);
+      sy[0][tx] = hyv;
+    }
+    __syncthreads();
+    const float Ax = sx[ty][tx], By = sy[ty][tx];
+    const bool hz = k < nz - 1, lz = k > 0;
+    double d = 0.0;
+    d += double(hx ? Rx : 0.f) - double(lx ? Ax : 0.f);
+    d += double(hy ? Ry : 0.f) - double(ly ? By : 0.f);
+    d += double(hz ? Rz : 0.f) - double(lz ? rzm : 0.f);
+    b[o] = -d * inv_h;
+    rzm = Rz;
+    o += P;
+    __syncthreads();  // the next plane overwrites the tile
+  }
 }
 
 // EMD: y <- y - proj(y) + grad phi + sigma grad psi (in place); mout (nullable):
