@@ -219,6 +219,27 @@ def test_3d_full_size_256(gpctx):
     assert abs(rep["dual"] - D) <= 2e-6 * ref.primal
 
 
+def test_3d_degenerate_problems(gpctx):
+    """rho0 = rho1: f = 0, psi = 0, the zero flux is optimal and P = D = 0 at the
+    first check; I = c: u* = c, p* = 0, F* = 0."""
+    import torch
+    from paper_1805_09453_amd import Options
+    rho, _ = synth.emd_volume_pair((64, 64, 64), 16)
+    announce("emd3_solve identical densities")
+    m, phi, rep = gpctx.emd3_solve(dev(rho), dev(rho), 1.0 / 64, Options(tau=0.3, tol=1e-6, max_iter=100,
+                                                                        check_every=5))
+    print(rep)
+    assert rep["converged"] and rep["iters"] == 5 and rep["primal"] == 0.0 and rep["dual"] == 0.0
+    assert torch.count_nonzero(m).item() == 0
+    c = 0.3
+    announce("rof3_solve constant volume")
+    u, p, rep = gpctx.rof3_solve(dev(np.full((64, 64, 64), c)), 1.0, 8.0, Options(tau=0.01, tol=1e-7, max_iter=20000,
+                                                                                  check_every=10))
+    print(rep, float((u - c).abs().max()))
+    assert float((u - c).abs().max()) <= 1e-5
+    assert rep["primal"] <= 1e-6 * 0.5 * 8.0 * c * c * 64 ** 3  # 1e-6 of the zero start's objective
+
+
 def test_3d_errors(gpctx):
     from paper_1805_09453_amd import GPError, Options
     from paper_1805_09453_amd._lib import GP_EMASS, GP_EUNSUPPORTED
