@@ -150,25 +150,34 @@ class RofResult:
     history: list = field(default_factory=list)
 
 
-def rof_solve(I, h, lam, tau, sigma=None, tol=1e-8, max_iter=100000, check_every=10, norm=ISO):
+def rof_solve(I, h, lam, tau, sigma=None, tol=1e-8, max_iter=100000, check_every=10, norm=ISO, ergodic=False):
     """From u0 = 0, p0 = 0: iterate until the relative gap of the last iterate
-    is <= tol (checked every check_every iterations) or max_iter."""
+    is <= tol (checked every check_every iterations) or max_iter.  ergodic:
+    evaluate the gap on, and return, the averages of the iterates n = 1..N."""
     I = np.asarray(I, np.float64)
     sigma = 1.0 / tau if sigma is None else sigma
     u = np.zeros_like(I)
     p = tuple(np.zeros_like(I) for _ in range(3))
     pbar = tuple(a.copy() for a in p)
+    sums = [np.zeros_like(I) for _ in range(4)]
     it, P, D, g, conv, hist = 0, np.nan, np.nan, np.nan, False, []
     while it < max_iter:
         u, p, pbar = rof_step(u, p, pbar, I, h, lam, tau, sigma, norm)
         it += 1
+        if ergodic:
+            for acc, x in zip(sums, (u,) + p):
+                acc += x
         if it % check_every == 0 or it == max_iter:
-            P, D = rof_primal(u, I, h, lam, norm), rof_dual(*p, I, h, lam)
+            eu, *ep = [a / it for a in sums] if ergodic else (u,) + p
+            P, D = rof_primal(eu, I, h, lam, norm), rof_dual(*ep, I, h, lam)
             g = rel_gap(P, D)
             hist.append((it, P, D, g))
             if g <= tol:
                 conv = True
                 break
+    if ergodic:
+        u, *pl = [a / it for a in sums]
+        p = tuple(pl)
     return RofResult(u, p, it, P, D, g, conv, hist)
 
 
@@ -229,27 +238,37 @@ class EmdResult:
     history: list = field(default_factory=list)
 
 
-def emd_solve(rho0, rho1, h, tau=1.0, sigma=None, tol=1e-5, max_iter=100000, check_every=10, norm=ISO):
+def emd_solve(rho0, rho1, h, tau=1.0, sigma=None, tol=1e-5, max_iter=100000, check_every=10, norm=ISO,
+              ergodic=False):
     """From u0 = 0, p0 = 0 until the relative gap (P - D)/|P| <= tol or max_iter;
-    ``m`` is the flux u + grad psi."""
+    ``m`` is the flux u + grad psi.  ergodic: evaluate the gap on, and return,
+    the averages of the iterates n = 1..N (u, p and so m)."""
     sigma = 1.0 / tau if sigma is None else sigma
     f, psi = emd_setup(rho0, rho1, h)
     gpsi = grad(psi, h)
     u = tuple(np.zeros_like(f) for _ in range(3))
     p = tuple(np.zeros_like(f) for _ in range(3))
     pbar = tuple(a.copy() for a in p)
+    sums = [np.zeros_like(f) for _ in range(6)]
     it, P, D, g, conv, hist = 0, np.nan, np.nan, np.nan, False, []
     while it < max_iter:
         u, p, pbar = emd_step(u, p, pbar, gpsi, h, tau, sigma, norm)
         it += 1
+        if ergodic:
+            for acc, x in zip(sums, u + p):
+                acc += x
         if it % check_every == 0 or it == max_iter:
-            P = emd_primal(u, gpsi, h, norm)
-            D = emd_certificate(p, f, h, norm)[0]
+            avg = [a / it for a in sums] if ergodic else list(u + p)
+            P = emd_primal(tuple(avg[:3]), gpsi, h, norm)
+            D = emd_certificate(tuple(avg[3:]), f, h, norm)[0]
             g = rel_gap(P, D)
             hist.append((it, P, D, g))
             if g <= tol:
                 conv = True
                 break
+    if ergodic:
+        avg = [a / it for a in sums]
+        u, p = tuple(avg[:3]), tuple(avg[3:])
     m = tuple(a + b for a, b in zip(u, gpsi))
     return EmdResult(u, p, f, psi, m, it, P, D, g, conv, hist)
 

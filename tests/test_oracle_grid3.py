@@ -203,3 +203,43 @@ def test_single_variable_emd_equals_the_two_variable_iteration(norm):
         scale = max(np.abs(x).max() for x in u) + 1.0
         assert max(np.abs(x - z).max() for x, z in zip(u2, u)) <= 1e-12 * scale
         assert max(np.abs(x - z).max() for x, z in zip(q, p)) <= 1e-12
+
+
+def test_ergodic_averages_are_the_means_and_bracket_the_optimum():
+    """ergodic=True returns (1/N) sum_{n<=N} of the iterates (against a separate
+    step loop) and, the averages being feasible, D <= F* <= P brackets the
+    optimum (ROF: F* from a tight solve; EMD: the certificate below the primal)."""
+    rng = np.random.default_rng(41)
+    I = rng.random((6, 8, 8))
+    h, lam, tau, K = 1.0, 8.0, 0.05, 7
+    u = np.zeros_like(I)
+    p = tuple(np.zeros_like(I) for _ in range(3))
+    pb = tuple(a.copy() for a in p)
+    acc = [np.zeros_like(I) for _ in range(4)]
+    for _ in range(K):
+        u, p, pb = g3.rof_step(u, p, pb, I, h, lam, tau, 1 / tau)
+        for a, x in zip(acc, (u,) + p):
+            a += x
+    r = g3.rof_solve(I, h, lam, tau, tol=0.0, max_iter=K, check_every=K, ergodic=True)
+    for got, a in zip((r.u,) + r.p, acc):
+        np.testing.assert_allclose(got, a / K, rtol=0, atol=1e-14)
+    assert abs(r.primal - g3.rof_primal(acc[0] / K, I, h, lam)) < 1e-12
+    fstar = g3.rof_solve(I, h, lam, tau, tol=1e-10, max_iter=100000, check_every=50).primal
+    assert r.dual <= fstar * (1 + 1e-12) <= r.primal * (1 + 2e-12)
+    a = rng.random((8, 8, 8)) + 0.5
+    b = rng.random((8, 8, 8)) + 0.5
+    b *= a.sum() / b.sum()
+    e = g3.emd_solve(a, b, 1 / 8, tau=0.3, tol=0.0, max_iter=K, check_every=K, ergodic=True)
+    f, psi = g3.emd_setup(a, b, 1 / 8)
+    gp = g3.grad(psi, 1 / 8)
+    u = tuple(np.zeros_like(f) for _ in range(3))
+    p = tuple(np.zeros_like(f) for _ in range(3))
+    pb = tuple(x.copy() for x in p)
+    acc = [np.zeros_like(f) for _ in range(6)]
+    for _ in range(K):
+        u, p, pb = g3.emd_step(u, p, pb, gp, 1 / 8, 0.3, 1 / 0.3)
+        for s_, x in zip(acc, u + p):
+            s_ += x
+    for got, s_ in zip(e.u + e.p, acc):
+        np.testing.assert_allclose(got, s_ / K, rtol=0, atol=1e-14)
+    assert e.dual <= e.primal
