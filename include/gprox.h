@@ -69,8 +69,9 @@ typedef struct gp_ctx gp_ctx; /* opaque: stream, twiddle tables, workspace */
  *   this call (the ergodic iterates that the convergence rates of section 2
  *   are stated for; EMD averages the flux m_n = u_n + grad psi).  The sums are
  *   FP64 in the context's workspace (ROF 9, EMD 10 more floats of workspace
- *   per cell) and cost one more pass over them per iteration.  rof_solve and
- *   emd_solve only; gp_batch_solve rejects it (GP_EUNSUPPORTED).
+ *   per cell) and cost one more pass over them per iteration.  rof_solve,
+ *   emd_solve, rof3_solve and emd3_solve; gp_batch_solve rejects it
+ *   (GP_EUNSUPPORTED).
  */
 typedef struct {
   double tau, sigma, tol;
@@ -169,8 +170,8 @@ int dct_poisson3_f64(gp_ctx* ctx, const double* b, double* x, int nz, int ny, in
 /* ROF denoising of the volume I (section 3.1 updates in d = 3) from u = 0,
  * p = 0, or from the caller's u and p with opts->warm_start.  u: in/out
  * [nz][ny][nx]; p: nullable in/out [3][nz][ny][nx].  Gap, stopping rule and
- * report as rof_solve (P and D with h^3 sums).  opts->ergodic is not
- * supported (GP_EUNSUPPORTED). */
+ * report as rof_solve (P and D with h^3 sums); opts->ergodic averages as
+ * rof_solve (about 44 more bytes of workspace per cell). */
 int rof3_solve(gp_ctx* ctx, const float* I, float* u, float* p, int nz, int ny, int nx, double h, double lambda,
                const gp_opts* opts, gp_report* rep);
 
@@ -178,8 +179,10 @@ int rof3_solve(gp_ctx* ctx, const float* I, float* u, float* p, int nz, int ny, 
  * d = 3, projected form, FP64 potentials) from the zero start.  m: out flux
  * u + grad psi [3][nz][ny][nx]; phi: nullable out [nz][ny][nx], the scaled
  * certificate potential.  rep->primal = h^3 sum |m|, rep->dual the
- * certificate's lower bound.  warm_start and ergodic are not supported.
- * With sigma tau = 1 (the default sigma) the same iterates are formed in the
+ * certificate's lower bound.  warm_start is not supported; opts->ergodic
+ * averages the flux and p as emd_solve (about 72 more bytes per cell).
+ * With sigma tau = 1 (the default sigma) and no averaging the same iterates
+ * are formed in the
  * equivalent single-variable form (state y = p_prev + sigma (u + grad psi),
  * p = proj(y); the Douglas-Rachford case of section 2), which stores one
  * vector field instead of two. */

@@ -219,6 +219,38 @@ def test_3d_full_size_256(gpctx):
     assert abs(rep["dual"] - D) <= 2e-6 * ref.primal
 
 
+@pytest.mark.parametrize("kind", ["rof", "emd"])
+def test_3d_ergodic_averages_match_oracle(gpctx, kind):
+    """ergodic=True: the averages of the iterates and the gap of the averages,
+    against the oracle's ergodic solve (11 iterations, checks every 4)."""
+    from paper_1805_09453_amd import Options
+    shape, K = (64, 64, 64), 11
+    if kind == "rof":
+        I = f32(synth.rof_volume(shape, 17))
+        announce("rof3_solve ergodic")
+        u, p, rep = gpctx.rof3_solve(dev(I), 1.0, 8.0, Options(tau=0.05, tol=0.0, max_iter=K, check_every=4,
+                                                               ergodic=True))
+        ref = g3.rof_solve(I, 1.0, 8.0, 0.05, tol=0.0, max_iter=K, check_every=4, ergodic=True)
+        pg = host(p)
+        errs = [rel(host(u), ref.u)] + [rel(pg[i], ref.p[i]) for i in range(3)]
+        P, D = ref.primal, ref.dual
+    else:
+        r0, r1 = (f32(a) for a in synth.emd_volume_pair(shape, 18))
+        h = 1.0 / 64
+        announce("emd3_solve ergodic")
+        m, phi, rep = gpctx.emd3_solve(dev(r0), dev(r1), h, Options(tau=0.3, tol=0.0, max_iter=K, check_every=4,
+                                                                    ergodic=True))
+        ref = g3.emd_solve(r0, r1, h, tau=0.3, tol=0.0, max_iter=K, check_every=4, ergodic=True)
+        D, L, phit = g3.emd_certificate(ref.p, ref.f, h)
+        mg = host(m)
+        errs = [rel(mg[i], ref.m[i]) for i in range(3)] + [rel(host(phi), phit)]
+        P = ref.primal
+    print(kind, ["%.2e" % e for e in errs], rep["primal"], P, rep["dual"], D)
+    assert rep["iters"] == K
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - P) <= 1e-6 * abs(P) and abs(rep["dual"] - D) <= 2e-6 * abs(P)
+
+
 def test_3d_degenerate_problems(gpctx):
     """rho0 = rho1: f = 0, psi = 0, the zero flux is optimal and P = D = 0 at the
     first check; I = c: u* = c, p* = 0, F* = 0."""
@@ -246,9 +278,6 @@ def test_3d_errors(gpctx):
     ok = dev(np.ones((64, 64, 64)))
     with pytest.raises(GPError) as e:
         gpctx.rof3_solve(dev(np.ones((32, 64, 64))), 1.0, 8.0, Options(tau=0.1))
-    assert e.value.code == GP_EUNSUPPORTED
-    with pytest.raises(GPError) as e:
-        gpctx.rof3_solve(ok, 1.0, 8.0, Options(tau=0.1, ergodic=True))
     assert e.value.code == GP_EUNSUPPORTED
     with pytest.raises(GPError) as e:
         gpctx.emd3_solve(ok, ok, 1 / 64, Options(tau=0.1, warm_start=True))
