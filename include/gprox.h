@@ -176,11 +176,13 @@ int rof3_solve(gp_ctx* ctx, const float* I, float* u, float* p, int nz, int ny, 
                const gp_opts* opts, gp_report* rep);
 
 /* EMD between volumes rho0, rho1 >= 0 of equal mass (section 3.2 updates in
- * d = 3, projected form, FP64 potentials) from the zero start.  m: out flux
- * u + grad psi [3][nz][ny][nx]; phi: nullable out [nz][ny][nx], the scaled
- * certificate potential.  rep->primal = h^3 sum |m|, rep->dual the
- * certificate's lower bound.  warm_start is not supported; opts->ergodic
- * averages the flux and p as emd_solve (about 72 more bytes per cell).
+ * d = 3, projected form, FP64 potentials) from the zero start or a warm
+ * start.  m: out flux u + grad psi [3][nz][ny][nx]; rep->primal = h^3 sum
+ * |m|, rep->dual the certificate's lower bound.  phi: nullable
+ * [nz][ny][nx]; in: the warm-start potential
+ * phi0 when opts->warm_start (p0 = proj(grad phi0), u0 = 0, as emd_solve),
+ * out: the scaled certificate potential.  opts->ergodic averages the flux
+ * and p as emd_solve (about 72 more bytes per cell).
  * With sigma tau = 1 (the default sigma) and no averaging the same iterates
  * are formed in the
  * equivalent single-variable form (state y = p_prev + sigma (u + grad psi),

@@ -239,15 +239,19 @@ class EmdResult:
 
 
 def emd_solve(rho0, rho1, h, tau=1.0, sigma=None, tol=1e-5, max_iter=100000, check_every=10, norm=ISO,
-              ergodic=False):
-    """From u0 = 0, p0 = 0 until the relative gap (P - D)/|P| <= tol or max_iter;
-    ``m`` is the flux u + grad psi.  ergodic: evaluate the gap on, and return,
-    the averages of the iterates n = 1..N (u, p and so m)."""
+              ergodic=False, phi0=None):
+    """From u0 = 0 and p0 = 0 (or p0 = proj(grad phi0) for a warm start from a
+    potential) until the relative gap (P - D)/|P| <= tol or max_iter; ``m`` is
+    the flux u + grad psi.  ergodic: evaluate the gap on, and return, the
+    averages of the iterates n = 1..N (u, p and so m)."""
     sigma = 1.0 / tau if sigma is None else sigma
     f, psi = emd_setup(rho0, rho1, h)
     gpsi = grad(psi, h)
     u = tuple(np.zeros_like(f) for _ in range(3))
-    p = tuple(np.zeros_like(f) for _ in range(3))
+    if phi0 is None:
+        p = tuple(np.zeros_like(f) for _ in range(3))
+    else:
+        p = project_unit_ball(*grad(np.asarray(phi0, np.float64), h), norm)
     pbar = tuple(a.copy() for a in p)
     sums = [np.zeros_like(f) for _ in range(6)]
     it, P, D, g, conv, hist = 0, np.nan, np.nan, np.nan, False, []

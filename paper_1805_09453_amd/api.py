@@ -194,11 +194,12 @@ class Context:
         self._check(rc, allow_notconv=True)
         return u, p, rep.as_dict()
 
-    def emd3_solve(self, rho0, rho1, h, opts: Options, want_phi=True):
+    def emd3_solve(self, rho0, rho1, h, opts: Options, phi=None, want_phi=True):
         torch = _torch()
         nz, ny, nx = rho0.shape
         m = torch.empty((3, nz, ny, nx), device=rho0.device, dtype=rho0.dtype)
-        phi = torch.empty_like(rho0) if want_phi else None
+        if phi is None and want_phi:
+            phi = torch.empty_like(rho0)
         rep = L.gp_report()
         rc = self._lib.emd3_solve(self._h, _ptr(rho0, torch.float32, (nz, ny, nx), "rho0"),
                                   _ptr(rho1, torch.float32, (nz, ny, nx), "rho1"),

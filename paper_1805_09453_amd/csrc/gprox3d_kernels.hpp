@@ -480,6 +480,20 @@ __global__ __launch_bounds__(256) void k3_drs_emd_update(float* __restrict__ y, 
   }
 }
 
+// warm start of the EMD iteration from a potential phi0: p = proj(grad phi0)
+// (forward differences in FP32, zero on the far faces)
+__global__ __launch_bounds__(256) void k3_warm_p(const float* __restrict__ phi0, float* __restrict__ p, int nz,
+                                                 int ny, int nx, float inv_h, int aniso) {
+  const Cell3 c(nz, ny, nx);
+  const size_t n = size_t(nz) * ny * nx;
+  const float fc = phi0[c.o], fx = phi0[c.o + c.fx], fy = phi0[c.o + c.fy], fz = phi0[c.o + c.fz];
+  float qx = c.hx ? (fx - fc) * inv_h : 0.f, qy = c.hy ? (fy - fc) * inv_h : 0.f, qz = c.hz ? (fz - fc) * inv_h : 0.f;
+  proj_ball3(qx, qy, qz, aniso);
+  p[c.o] = qx;
+  p[n + c.o] = qy;
+  p[2 * n + c.o] = qz;
+}
+
 // p = proj(y), pointwise over n cells (the dual iterate of the single-variable form)
 __global__ __launch_bounds__(256) void k3_proj3(const float* __restrict__ y, float* __restrict__ p, size_t n,
                                                 int aniso) {

@@ -251,6 +251,29 @@ def test_3d_ergodic_averages_match_oracle(gpctx, kind):
     assert abs(rep["primal"] - P) <= 1e-6 * abs(P) and abs(rep["dual"] - D) <= 2e-6 * abs(P)
 
 
+@pytest.mark.parametrize("sigma_tau", [1.0, 0.5])
+def test_emd3_warm_start_matches_oracle(gpctx, sigma_tau):
+    """Warm start from a potential phi0 (p0 = proj(grad phi0)) in both forms:
+    sigma tau = 1 (single-variable, y0 = p0) and 1/2 (two-variable)."""
+    from paper_1805_09453_amd import Options
+    shape, K = (64, 64, 64), 6
+    r0, r1 = (f32(a) for a in synth.emd_volume_pair(shape, 19))
+    h, tau = 1.0 / 64, 0.3
+    z = (np.arange(64) + 0.5) * h
+    phi0 = f32(0.4 * np.sin(3 * z)[:, None, None] + 0.3 * np.cos(2 * z)[None, :, None] * z[None, None, :])
+    announce(f"emd3_solve warm start sigma tau = {sigma_tau}")
+    phi = dev(phi0)
+    m, phi, rep = gpctx.emd3_solve(dev(r0), dev(r1), h, Options(tau=tau, sigma=sigma_tau / tau, tol=0.0, max_iter=K,
+                                                                check_every=K, warm_start=True), phi=phi)
+    ref = g3.emd_solve(r0, r1, h, tau=tau, sigma=sigma_tau / tau, tol=0.0, max_iter=K, check_every=K, phi0=phi0)
+    D, L, phit = g3.emd_certificate(ref.p, ref.f, h)
+    mg = host(m)
+    errs = [rel(mg[i], ref.m[i]) for i in range(3)] + [rel(host(phi), phit)]
+    print(["%.2e" % e for e in errs], rep["primal"], ref.primal, rep["dual"], D)
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - ref.primal) <= 1e-6 * ref.primal and abs(rep["dual"] - D) <= 2e-6 * ref.primal
+
+
 def test_3d_degenerate_problems(gpctx):
     """rho0 = rho1: f = 0, psi = 0, the zero flux is optimal and P = D = 0 at the
     first check; I = c: u* = c, p* = 0, F* = 0."""
@@ -274,14 +297,14 @@ def test_3d_degenerate_problems(gpctx):
 
 def test_3d_errors(gpctx):
     from paper_1805_09453_amd import GPError, Options
-    from paper_1805_09453_amd._lib import GP_EMASS, GP_EUNSUPPORTED
+    from paper_1805_09453_amd._lib import GP_EINVAL, GP_EMASS, GP_EUNSUPPORTED
     ok = dev(np.ones((64, 64, 64)))
     with pytest.raises(GPError) as e:
         gpctx.rof3_solve(dev(np.ones((32, 64, 64))), 1.0, 8.0, Options(tau=0.1))
     assert e.value.code == GP_EUNSUPPORTED
     with pytest.raises(GPError) as e:
-        gpctx.emd3_solve(ok, ok, 1 / 64, Options(tau=0.1, warm_start=True))
-    assert e.value.code == GP_EUNSUPPORTED
+        gpctx.emd3_solve(ok, ok, 1 / 64, Options(tau=0.1, warm_start=True), want_phi=False)
+    assert e.value.code == GP_EINVAL and "phi" in str(e.value)
     with pytest.raises(GPError) as e:
         gpctx.emd3_solve(ok, dev(1.01 * np.ones((64, 64, 64))), 1 / 64, Options(tau=0.1))
     assert e.value.code == GP_EMASS

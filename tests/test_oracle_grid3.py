@@ -243,3 +243,28 @@ def test_ergodic_averages_are_the_means_and_bracket_the_optimum():
     for got, s_ in zip(e.u + e.p, acc):
         np.testing.assert_allclose(got, s_ / K, rtol=0, atol=1e-14)
     assert e.dual <= e.primal
+
+
+def test_single_variable_emd_from_a_warm_start():
+    """A warm start u0 = 0, p0 = pbar0 = proj(grad phi0) is y0 = p0 in the
+    single-variable form: the iterates agree with the two-variable ones."""
+    rng = np.random.default_rng(43)
+    a = rng.random((8, 8, 8)) + 0.5
+    b = rng.random((8, 8, 8)) + 0.5
+    b *= a.sum() / b.sum()
+    h, tau = 1.0 / 8, 0.4
+    f, psi = g3.emd_setup(a, b, h)
+    gp = g3.grad(psi, h)
+    phi0 = 0.7 * rng.standard_normal((8, 8, 8)) * h
+    p0 = g3.project_unit_ball(*g3.grad(phi0, h))
+    u = tuple(np.zeros_like(f) for _ in range(3))
+    p, pb, y = p0, p0, p0
+    for _ in range(8):
+        u, p, pb = g3.emd_step(u, p, pb, gp, h, tau, 1 / tau)
+        u2, y = g3.emd_drs_step(y, gp, h, tau)
+        q = g3.project_unit_ball(*y)
+        assert max(np.abs(x - z).max() for x, z in zip(u2, u)) <= 1e-12 * (1 + max(np.abs(x).max() for x in u))
+        assert max(np.abs(x - z).max() for x, z in zip(q, p)) <= 1e-12
+    # and the solve's warm start is that start
+    r = g3.emd_solve(a, b, h, tau=tau, tol=0.0, max_iter=8, check_every=8, phi0=phi0)
+    assert max(np.abs(x - z).max() for x, z in zip(r.p, p)) <= 1e-12
