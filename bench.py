@@ -69,7 +69,7 @@ def kernel_source_hash():
 # gp_profile kernel kind -> kernel symbol (as summarised from rocprofv3) for an n x n grid
 PROF2SYM = {"rof_A_prox_rhs_dct": "k_rof_A<{n}, false>", "rof_B_idct_update": "k_rof_B<{n}>",
             "cols_solve": "k_cols_solve<{n}, f32>", "cols_solve_f64": "k_cols_solve<{n}, f64>",
-            "emd_A_prox_rhs_dct": "k_emd_A<{n}, false>", "emd_B_idct": "k_rows_inv<{n}, f64>",
+            "emd_A_prox_rhs_dct": "k_emd_A_drs<{n}, false>", "emd_B_idct": "k_rows_inv<{n}, f64>",
             "rows_fwd_dct2": "k_rows_fwd<{n}, f32>", "rows_inv_dct2": "k_rows_inv<{n}, f32>"}
 
 

@@ -424,6 +424,21 @@ template <int N> struct Fused {
                 c->stream, wt_in, phi, pin, gpsi, f, pout, wt_out, rhat, ny, nyi, active, col_lgtw<double2>(c, nyi, N),
                 inv_h, tau, sigma, aniso, mode, partials, T.tw64, T.dw64);
   }
+  static void emd_A_drs(gp_ctx* c, const float* y_in, const double* phi, const float* gpsi, float* y_out,
+                        double* rhat, int nyi, int m, const int* active, double inv_h, float tau, float sigma, int aniso,
+                        int mode, double* partials) {
+    const int G = c->row_g[1][ilog2i(N)];
+    const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
+    const Tables& T = c->tab[ilog2i(N)];
+    if (partials)
+      GP_LAUNCH(c, (k_emd_A_drs<N, true>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, double2>::GROUP_LDS),
+                c->stream, y_in, phi, gpsi, y_out, rhat, ny, nyi, active, col_lgtw<double2>(c, nyi, N), inv_h, tau,
+                sigma, aniso, mode, partials, T.tw64, T.dw64);
+    else
+      GP_LAUNCH(c, (k_emd_A_drs<N, false>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, double2>::GROUP_LDS),
+                c->stream, y_in, phi, gpsi, y_out, rhat, ny, nyi, active, col_lgtw<double2>(c, nyi, N), inv_h, tau,
+                sigma, aniso, mode, partials, T.tw64, T.dw64);
+  }
 };
 
 // (alpha I - Delta) x = b for m stacked instances: row DCT into the tiled
@@ -635,6 +650,21 @@ int emd_A(EmdPipe& P, int mode, bool partials) {
   LAUNCHCHK(c);
   std::swap(P.WX, P.WY);
   if (mode == 0) std::swap(P.X, P.Y);
+  return GP_OK;
+}
+
+// single-variable form (sigma tau = 1): the y field ping-pongs between WX and WY
+// (WX = latest); the entry reads y_0 from the group's u buffer
+int emd_A_drs(EmdPipe& P, int mode, bool partials) {
+  gp_ctx* c = P.c;
+  const Group& g = *P.g;
+  const int ps = prof_begin(c, K_EMD_A, (mode == 1 ? 24.0 : 40.0) * double(g.ntot()));
+  const float* yin = (mode == 1) ? g.u : P.WX;
+  GP_DISPATCH_NM(g.nx, Fused, emd_A_drs, c, yin, g.phi, g.gpsi, P.WY, g.rhat64, g.nyi, g.m, g.active, 1.0 / g.h,
+                 float(g.tau), float(g.sigma), g.norm, mode, partials ? g.gpart : nullptr);
+  prof_end(c, ps);
+  LAUNCHCHK(c);
+  std::swap(P.WX, P.WY);
   return GP_OK;
 }
 
@@ -1350,14 +1380,18 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   double P = NAN, D = NAN, gap = NAN, L = 0;
   bool conv = false;
   int it = 0;
+  // sigma tau = 1 without averaging: the single-variable form (y_0 = p_0 in the u buffer, u_0 = 0
+  // being implied); p = proj(y) is formed into P0 on checks
+  const bool single = !erg && std::fabs(sigma * tau - 1.0) <= 1e-12;
+  if (single) HIPCHK(c, hipMemcpyAsync(u, P0, 2 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   EmdPipe pipe{c, &g, g.p, g.pbar, g.w0, g.w1};
-  RCHK(emd_A(pipe, 1, false));
+  RCHK(single ? emd_A_drs(pipe, 1, false) : emd_A(pipe, 1, false));
   // device result slots: [0] primal sum, [8..9] certificate sums
   double* cpart = c->partials + size_t(ny / 2);
   while (it < o->max_iter) {
     RCHK(emd_CB(pipe));  // phi_it
     const bool chk = ((it + 1) % o->check_every == 0) || (it + 1 == o->max_iter);
-    RCHK(emd_A(pipe, 0, chk && !erg));  // u_{it+1}, p_{it+1}
+    RCHK(single ? emd_A_drs(pipe, 0, chk) : emd_A(pipe, 0, chk && !erg));  // u_{it+1}, p_{it+1}
     ++it;
     if (erg) {
       // sums of m_1..m_it (m_it = the field A read minus grad phi, now in WY) and p_1..p_it
@@ -1371,6 +1405,11 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
     }
     if (chk) {
       const float* pc = pipe.X;
+      if (single) {
+        GP_LAUNCH(c, k_proj2, dim3(grid_for(n)), dim3(256), 0, c->stream, pipe.WX, P0, n, o->norm);
+        LAUNCHCHK(c);
+        pc = P0;
+      }
       if (erg) {
         // averaged flux into the caller's m with its primal partials, averaged dual for the certificate
         const int nb = red_blocks(n);
@@ -1407,7 +1446,14 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
   }
   // flux m_it = wt_{it-1} - grad phi_{it-1}: the stored field the last A read, now in WY
   // (ergodic: the loop ended on a check, which wrote the averaged flux into m)
-  if (!erg) RCHK(emd_finish(pipe, pipe.WY, false, m));
+  // (single-variable form: m = -tau (R(y) - grad phi) + grad psi from the y the last A read)
+  if (single) {
+    GP_LAUNCH(c, k_emd_finish_drs, dim3(grid_for(n)), dim3(256), 0, c->stream, pipe.WY, g.phi, gpsi, m, ny, nx, ny,
+              1.0 / h, float(tau), o->norm);
+    LAUNCHCHK(c);
+  } else if (!erg) {
+    RCHK(emd_finish(pipe, pipe.WY, false, m));
+  }
   if (phi) {
     // cphi holds -phi_c from the last certificate; phi~ = phi_c / max(1, L)
     GP_LAUNCH(c, k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->stream, cphi, phi, n,
@@ -1570,7 +1616,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
   };
   int rc = GP_OK;
   for (size_t k = 0; k < G.size() && !rc; ++k)
-    rc = G[k].g.kind == GP_KIND_ROF ? rof_A(rp[k], 1, false) : emd_A(ep[k], 1, false);
+    rc = G[k].g.kind == GP_KIND_ROF ? rof_A(rp[k], 1, false) : emd_A_drs(ep[k], 1, false);
   if (rc) return restore(rc);
   // side streams: independent groups form parallel branches of the graph
   const int nside = int(std::min<size_t>(G.size(), size_t(kSideStreams))) - 1;
@@ -1609,7 +1655,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
         if (!rc) rc = rof_A(rp[k], 0, last);
       } else {
         rc = emd_CB(ep[k]);
-        if (!rc) rc = emd_A(ep[k], 0, last);
+        if (!rc) rc = emd_A_drs(ep[k], 0, last);
       }
     }
     if (rc) break;
@@ -1619,8 +1665,15 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
       set_err(c, "k_finalize launch failed during capture");
       rc = GP_EHIP;
     }
-    if (!rc && g.kind == GP_KIND_EMD) rc = emd_cert_enqueue(c, g, ep[k].X, G[k].cphi, G[k].ctmp, G[k].cpart,
-                                                           G[k].cert_dev);
+    if (!rc && g.kind == GP_KIND_EMD) {
+      // p = proj(y) of the latest iterate into the (otherwise unused) dual buffer, then its certificate
+      GP_LAUNCH(c, k_proj2, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, ep[k].WX, g.p, g.ntot(), g.norm);
+      if (hipGetLastError() != hipSuccess) {
+        set_err(c, "k_proj2 launch failed during capture");
+        rc = GP_EHIP;
+      }
+      if (!rc) rc = emd_cert_enqueue(c, g, g.p, G[k].cphi, G[k].ctmp, G[k].cpart, G[k].cert_dev);
+    }
   }
   c->stream = c->bstream;
   for (int s = 0; s < nside && !rc; ++s)
@@ -1717,8 +1770,13 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     if (g.kind == GP_KIND_ROF) {
       for (int q = 0; q < g.m; ++q) cp(inst[bg.idx[q]].out, g.u + q * n, n * sizeof(float));
     } else {
-      rc = emd_finish(ep[k], ep[k].WY, false, bg.mflux);
-      if (rc) return restore(rc);
+      // flux of the single-variable form: m = -tau (R(y) - grad phi) + grad psi from the y the last A read
+      GP_LAUNCH(c, k_emd_finish_drs, dim3(grid_for(nt)), dim3(256), 0, c->bstream, ep[k].WY, g.phi, g.gpsi,
+                bg.mflux, g.nyi * g.m, g.nx, g.nyi, 1.0 / g.h, float(g.tau), g.norm);
+      if (hipGetLastError() != hipSuccess) {
+        set_err(c, "k_emd_finish_drs launch failed");
+        return restore(GP_EHIP);
+      }
       for (int q = 0; q < g.m; ++q) {
         const gp_instance& in = inst[bg.idx[q]];
         cp(in.out, bg.mflux + q * n, n * sizeof(float));

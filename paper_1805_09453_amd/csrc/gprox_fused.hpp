@@ -492,6 +492,195 @@ __global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>
   }
 }
 
+// ---------------------------------------------------------------- EMD A, single-variable form
+// With sigma = 1/tau the EMD iterates depend on (u, p, pbar) only through the
+// one field y_n = p_{n-1} + sigma (u_n + grad psi) (p_n = proj(y_n); the
+// Douglas-Rachford case of section 2); with R(y) = 2 proj(y) - y:
+//   phi_n = Delta^{-1} div R(y_n),  u_{n+1} = -tau (R(y_n) - grad phi_n),
+//   y_{n+1} = y_n - proj(y_n) + grad phi_n + sigma grad psi.
+// mode 0 (steady): y_in = y_n, phi = phi_n -> y_out = y_{n+1}; partials
+//                  (nullable): [sum |m_{n+1}|], m = u + grad psi;
+// mode 1 (entry):  y_in = y_n -> y_out = y_n.
+// Then r = -div R(y_out) / h (FP64) -> row DCT, as k_emd_A.  Reads y, phi and
+// grad psi, writes y and the transform: no p, pbar or stored field.
+template <int N, bool PART>
+__global__ __launch_bounds__((RowShape<N, double2>::MAXT), (RowShape<N, double2>::MINW)) void k_emd_A_drs(
+    const float* __restrict__ y_in, const double* __restrict__ phi, const float* __restrict__ gpsi,
+    float* __restrict__ y_out, double* __restrict__ rhat, int ny, int nyi, const int* __restrict__ active, int lgtw,
+    double inv_h, float tau, float sigma, int aniso, int mode, double* __restrict__ partials,
+    const double2* __restrict__ tw, const double2* __restrict__ dctw) {
+  using SH = RowShape<N, double2>;
+  constexpr int T = SH::T;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* smem = reinterpret_cast<double2*>(smem_raw);
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  double2* lds = smem + g * Sched<N>::LDS;
+  const int a = 2 * (blockIdx.x * int(blockDim.x / T) + g), b = a + 1;
+  const bool valid = a < ny && inst_active(active, a / nyi);
+  const size_t n = size_t(ny) * N;
+  double acc[1] = {0};
+  if (valid) {
+    const bool has_up = (a % nyi) > 0, has_dn = ((a + 2) % nyi) != 0;
+    const size_t oa = size_t(a) * N, ob = size_t(b) * N, ou = oa - (has_up ? N : 0), od = ob + (has_dn ? N : 0);
+#pragma unroll 2
+    for (int k = 0; k < Sched<N>::E / 4; ++k) {
+      const int c = 4 * (t + T * k);
+      const bool has_l = c > 0, has_r = c + 4 < N;
+      const int cl = has_l ? c - 1 : c, cr = has_r ? c + 4 : c;  // in-bounds halo columns
+      // R of the new y at (a, c-1..c+3), (b, c-1..c+3) and, y component only, (a-1, c..c+3)
+      float RxA[5], RyA[5], RxB[5], RyB[5], RyU[4];
+      float YxA[4], YyA[4], YxB[4], YyB[4];  // the new y at (a, c..c+3), (b, c..c+3)
+      const float4 yxa = ld4(y_in + oa + c), yya = ld4(y_in + n + oa + c);
+      const float4 yxb = ld4(y_in + ob + c), yyb = ld4(y_in + n + ob + c);
+      const float4 yxu = sel4(has_up, ld4(y_in + ou + c)), yyu = sel4(has_up, ld4(y_in + n + ou + c));
+      const float yxal = sel(has_l, y_in[oa + cl]), yyal = sel(has_l, y_in[n + oa + cl]);
+      const float yxbl = sel(has_l, y_in[ob + cl]), yybl = sel(has_l, y_in[n + ob + cl]);
+      // steady mode: grad phi_n and grad psi at the same cells (entry mode: zero step)
+      double fA[6] = {0, 0, 0, 0, 0, 0}, fB[6] = {0, 0, 0, 0, 0, 0}, fU[5] = {0, 0, 0, 0, 0}, fD[5] = {0, 0, 0, 0, 0};
+      float4 sxa = make_float4(0.f, 0.f, 0.f, 0.f), sya = sxa, sxb = sxa, syb = sxa, sxu = sxa, syu = sxa;
+      float sxal = 0.f, syal = 0.f, sxbl = 0.f, sybl = 0.f;
+      const bool steady = mode == 0;
+      if (steady) {
+        const double2* pa = reinterpret_cast<const double2*>(phi + oa + c);
+        const double2* pb = reinterpret_cast<const double2*>(phi + ob + c);
+        const double2 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+        fA[1] = a0.x; fA[2] = a0.y; fA[3] = a1.x; fA[4] = a1.y;
+        fB[1] = b0.x; fB[2] = b0.y; fB[3] = b1.x; fB[4] = b1.y;
+        fA[0] = sel(has_l, phi[oa + cl]);
+        fB[0] = sel(has_l, phi[ob + cl]);
+        fA[5] = sel(has_r, phi[oa + cr]);
+        fB[5] = sel(has_r, phi[ob + cr]);
+        const double2* pu = reinterpret_cast<const double2*>(phi + ou + c);
+        const double2* pd = reinterpret_cast<const double2*>(phi + od + c);
+        const double2 u0 = pu[0], u1 = pu[1], d0 = pd[0], d1 = pd[1];
+        const double fu4 = phi[ou + cr], fdl = phi[od + cl];
+        fU[0] = sel(has_up, u0.x); fU[1] = sel(has_up, u0.y); fU[2] = sel(has_up, u1.x); fU[3] = sel(has_up, u1.y);
+        fU[4] = sel(has_up && has_r, fu4);
+        fD[1] = sel(has_dn, d0.x); fD[2] = sel(has_dn, d0.y); fD[3] = sel(has_dn, d1.x); fD[4] = sel(has_dn, d1.y);
+        fD[0] = sel(has_dn && has_l, fdl);
+        sxa = ld4(gpsi + oa + c); sya = ld4(gpsi + n + oa + c);
+        sxb = ld4(gpsi + ob + c); syb = ld4(gpsi + n + ob + c);
+        sxu = sel4(has_up, ld4(gpsi + ou + c)); syu = sel4(has_up, ld4(gpsi + n + ou + c));
+        sxal = sel(has_l, gpsi[oa + cl]); syal = sel(has_l, gpsi[n + oa + cl]);
+        sxbl = sel(has_l, gpsi[ob + cl]); sybl = sel(has_l, gpsi[n + ob + cl]);
+      }
+      // one cell: the new y (steady: y - proj(y) + g + sigma s; entry: y) and its R;
+      // (mx, my): the flux of the new iterate (steady mode)
+      auto cell = [&](float yx, float yy, float gx, float gy, float sx, float sy, bool hx, bool hy, float& nyx,
+                      float& nyy, float& rx, float& ry, float& mx, float& my) {
+        float qx = yx, qy = yy;
+        proj_ball(qx, qy, aniso);
+        if (steady) {
+          nyx = hx ? (yx - qx) + gx + sigma * sx : 0.f;
+          nyy = hy ? (yy - qy) + gy + sigma * sy : 0.f;
+          mx = hx ? -tau * ((2.f * qx - yx) - gx) + sx : 0.f;
+          my = hy ? -tau * ((2.f * qy - yy) - gy) + sy : 0.f;
+        } else {
+          nyx = hx ? yx : 0.f;
+          nyy = hy ? yy : 0.f;
+          mx = my = 0.f;
+        }
+        float px = nyx, py = nyy;
+        proj_ball(px, py, aniso);
+        rx = 2.f * px - nyx;
+        ry = 2.f * py - nyy;
+      };
+#pragma unroll
+      for (int e = -1; e < 4; ++e) {
+        const int j = c + e;
+        const bool inx = j >= 0, xin = j < N - 1;
+        float nx0, ny0, rx, ry, mx, my;
+        // row a (its row below, b, always exists)
+        cell(e < 0 ? yxal : f4(yxa, e), e < 0 ? yyal : f4(yya, e),
+             xin ? float((fA[e + 2] - fA[e + 1]) * inv_h) : 0.f, float((fB[e + 1] - fA[e + 1]) * inv_h),
+             e < 0 ? sxal : f4(sxa, e), e < 0 ? syal : f4(sya, e), xin, true, nx0, ny0, rx, ry, mx, my);
+        RxA[e + 1] = inx ? rx : 0.f;
+        RyA[e + 1] = inx ? ry : 0.f;
+        if (e >= 0) {
+          YxA[e] = nx0;
+          YyA[e] = ny0;
+          if constexpr (PART) acc[0] += double(pnorm(mx, my, aniso));
+        }
+        // row b
+        cell(e < 0 ? yxbl : f4(yxb, e), e < 0 ? yybl : f4(yyb, e),
+             xin ? float((fB[e + 2] - fB[e + 1]) * inv_h) : 0.f, has_dn ? float((fD[e + 1] - fB[e + 1]) * inv_h) : 0.f,
+             e < 0 ? sxbl : f4(sxb, e), e < 0 ? sybl : f4(syb, e), xin, has_dn, nx0, ny0, rx, ry, mx, my);
+        RxB[e + 1] = inx ? rx : 0.f;
+        RyB[e + 1] = inx ? ry : 0.f;
+        if (e >= 0) {
+          YxB[e] = nx0;
+          YyB[e] = ny0;
+          if constexpr (PART) acc[0] += double(pnorm(mx, my, aniso));
+          // row a-1: the y component of R only
+          cell(f4(yxu, e), f4(yyu, e), xin ? float((fU[e + 1] - fU[e]) * inv_h) : 0.f,
+               float((fA[e + 1] - fU[e]) * inv_h), f4(sxu, e), f4(syu, e), xin, true, nx0, ny0, rx, ry, mx, my);
+          RyU[e] = has_up ? ry : 0.f;
+        }
+      }
+      st4(y_out + oa + c, make_float4(YxA[0], YxA[1], YxA[2], YxA[3]));
+      st4(y_out + n + oa + c, make_float4(YyA[0], YyA[1], YyA[2], YyA[3]));
+      st4(y_out + ob + c, make_float4(YxB[0], YxB[1], YxB[2], YxB[3]));
+      st4(y_out + n + ob + c, make_float4(YyB[0], YyB[1], YyB[2], YyB[3]));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float dva = (RxA[e + 1] - RxA[e]) + (RyA[e + 1] - RyU[e]);
+        const float dvb = (RxB[e + 1] - RxB[e]) + (RyB[e + 1] - RyA[e + 1]);
+        mk_put<N, double2>(lds, c + e, -double(dva) * inv_h, -double(dvb) * inv_h);
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int m = t; m < N; m += T) lds[lpad(m)] = make_double2(0.0, 0.0);
+  }
+  if constexpr (PART) group_reduce_store<1, T>(acc, valid ? partials + size_t(a / 2) : nullptr, t);
+  __syncthreads();
+  Vals<N, double2> v;
+  dct2_fwd_lds<N>(t, v, lds, tw, dctw);
+  if (valid) {
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const SlotTile<N> ta(a, t, slot, nyi, lgtw), tb(b, t, slot, nyi, lgtw);
+#pragma unroll
+      for (int s = 0; s < Sched<N>::H; ++s) {
+        rhat[ta.at(s)] = v[slot * Sched<N>::H + s].x;
+        rhat[tb.at(s)] = v[slot * Sched<N>::H + s].y;
+      }
+    }
+  }
+}
+
+// flux of the single-variable form's latest iterate: m = -tau (R(y) - grad phi) + grad psi,
+// y the field the last A read and phi the potential it read; p = proj(y_latest) into pout
+// when y_latest is given.  Tall batch layout: y-neighbours stop at instance edges.
+__global__ __launch_bounds__(256) void k_emd_finish_drs(const float* __restrict__ y, const double* __restrict__ phi,
+                                                        const float* __restrict__ gpsi, float* __restrict__ mout,
+                                                        int ny, int nx, int nyi, double inv_h, float tau, int aniso) {
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const bool hx = j < nx - 1, hy = i % nyi < nyi - 1;
+    const double fc = phi[o];
+    const float gx = hx ? float((phi[o + 1] - fc) * inv_h) : 0.f;
+    const float gy = hy ? float((phi[o + nx] - fc) * inv_h) : 0.f;
+    const float yx = y[o], yy = y[o + n];
+    float qx = yx, qy = yy;
+    proj_ball(qx, qy, aniso);
+    mout[o] = hx ? -tau * ((2.f * qx - yx) - gx) + gpsi[o] : 0.f;
+    mout[o + n] = hy ? -tau * ((2.f * qy - yy) - gy) + gpsi[o + n] : 0.f;
+  }
+}
+
+// p = proj(y) for a planar 2-component field of n cells
+__global__ __launch_bounds__(256) void k_proj2(const float* __restrict__ y, float* __restrict__ p, size_t n,
+                                               int aniso) {
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    float qx = y[o], qy = y[o + n];
+    proj_ball(qx, qy, aniso);
+    p[o] = qx;
+    p[o + n] = qy;
+  }
+}
+
 // ---------------------------------------------------------------- EMD finish
 // m = wt - grad phi; if pout: p_out = proj(p_in + sigma m), pbar = 2 p_out - p_in;
 // u = m - grad psi (if u); flux = m (if mout).  Pointwise in p (p_in may alias
