@@ -95,6 +95,28 @@ def test_emd_pd_step_anisotropic_and_rectangular(gpctx, ny, nx):
         assert abs(g["primal"] - P) <= 1e-6 * P and abs(g["dual"] - D) <= 2e-6 * P
 
 
+@pytest.mark.parametrize("ny,nx,norm", [(64, 128, 0), (128, 64, 1), (64, 1024, 0)])
+def test_emd_solve_rectangular_matches_oracle(gpctx, ny, nx, norm):
+    """emd_solve (the single-variable form at sigma tau = 1) on rectangular grids,
+    both norms, rows of the radix-8 length class: 9 iterations against the
+    two-variable FP64 oracle."""
+    from paper_1805_09453_amd import Options
+    h = 1.0 / max(ny, nx)
+    rho0, rho1 = synth.emd_mixture_pair(max(ny, nx), 31, k=4)
+    r0, r1 = f32(rho0[:ny, :nx]), f32(rho1[:ny, :nx])
+    r1 *= r0.sum() / r1.sum()
+    r1 = f32(r1)
+    announce(f"emd_solve {ny}x{nx} norm={norm}, 9 iterations")
+    m, phi, rep = gpctx.emd_solve(dev(r0), dev(r1), h, Options(tau=0.3, tol=0.0, max_iter=9, check_every=9, norm=norm))
+    ref = oemd.solve(r0, r1, h, tau=0.3, tol=0.0, max_iter=9, check_every=9, norm=norm)
+    D, L, phit = oemd.certificate(ref.px, ref.py, ref.f, h, norm)
+    mg = host(m)
+    errs = [rel(mg[0], ref.m[0]), rel(mg[1], ref.m[1]), rel(host(phi), phit)]
+    print(["%.2e" % e for e in errs], rep["primal"], ref.primal, rep["dual"], D)
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - ref.primal) <= 1e-6 * ref.primal and abs(rep["dual"] - D) <= 2e-6 * ref.primal
+
+
 def test_emd_solve_anisotropic_value(gpctx):
     """64x64 two-Gaussian pair in the l1 grid norm: the converged GPU solve's
     certificate brackets the oracle's converged value (tests/golden, written by
