@@ -908,9 +908,13 @@ int tune_group(gp_ctx* c, const Group& g0) {
         c->row_g[di][lx] = rg;
         const double t = time_ms(c, [&] {
           if (f64) {
-            // dual and stored field to scratch; the potential's row inverse to scratch
+            // dual and stored field (or y, in the single-variable form the solvers run at
+            // sigma tau = 1) to scratch; the potential's row inverse to scratch
             EmdPipe P{c, &g, g.p, scr, g.w0, scr + 2 * nt};
-            (void)emd_A(P, 0, false);
+            if (std::fabs(g.sigma * g.tau - 1.0) <= 1e-12)
+              (void)emd_A_drs(P, 0, false);
+            else
+              (void)emd_A(P, 0, false);
             GP_DISPATCH_NM(g.nyi, P64, cols, c, g.rhat64, g.nx, g.m, g.active, g.mux64, g.muy64, 0.0,
                            1.0 / (double(g.nyi) * g.nx));
             GP_DISPATCH_NM(g.nx, P64, rows_inv, c, g.rhat64, reinterpret_cast<double*>(scr), g.nyi, g.m, g.active);
