@@ -164,3 +164,17 @@ def flux_value(mx, my, f, h, norm=ISO):
 def step_rule_tau_singular(eps, M):
     """Section 4.2 rule for singular (Dirac) measures: tau = min(sqrt(1/(eps |log eps|)), 2 M^{1/4})."""
     return float(min(np.sqrt(1.0 / (eps * abs(np.log(eps)))), 2.0 * M ** 0.25))
+
+
+def drs_step(yx, yy, gpx, gpy, h, tau, norm=ISO):
+    """One step of the single-variable form at sigma = 1/tau (the Douglas-Rachford
+    case of section 2): with y_n = p_{n-1} + sigma (u_n + grad psi), p_n = proj(y_n)
+    and R(y) = 2 proj(y) - y, the updates of section 3.2 become
+        phi = Delta^{-1} div R(y_n),  u_{n+1} = -tau (R(y_n) - grad phi),
+        y_{n+1} = y_n - proj(y_n) + grad phi + sigma grad psi;
+    the zero start is y_0 = 0 and a warm start p_0 = proj(grad phi0) is y_0 = p_0.
+    Returns (ux+, uy+, yx+, yy+)."""
+    qx, qy = grid.project_unit_ball(yx, yy, norm)
+    rx, ry = 2.0 * qx - yx, 2.0 * qy - yy
+    gx, gy = grid.grad(grid.inv_laplacian(grid.div(rx, ry, h), h), h)
+    return (-tau * (rx - gx), -tau * (ry - gy), yx - qx + gx + gpx / tau, yy - qy + gy + gpy / tau)

@@ -251,3 +251,30 @@ def test_ergodic_average_is_the_mean_of_the_iterates_and_brackets_the_optimum():
     for res in (r, long):
         assert res.dual <= exact * (1 + 1e-9) and exact <= res.primal * (1 + 1e-9)
     assert long.rel_gap < r.rel_gap and long.rel_gap < 5e-2
+
+
+def test_single_variable_form_reproduces_the_iterates():
+    """drs_step from y_0 = 0 (and from y_0 = p_0 for a warm start) gives the
+    iterates u_n and p_n = proj(y_n) of step at sigma = 1/tau."""
+    n = 16
+    h = 1.0 / n
+    rho0, rho1 = synth.emd_mixture_pair(n, 5, k=3)
+    f, psi = emd.setup(rho0, rho1, h)
+    gpx, gpy = grid.grad(psi, h)
+    tau = 0.4
+    for warm in (False, True):
+        z = np.zeros_like(f)
+        if warm:
+            phi0 = np.random.default_rng(3).standard_normal((n, n)) * h
+            px, py = grid.project_unit_ball(*grid.grad(phi0, h))
+        else:
+            px, py = z.copy(), z.copy()
+        st = (z.copy(), z.copy(), px, py, px.copy(), py.copy())
+        yx, yy = px.copy(), py.copy()
+        for _ in range(10):
+            st = emd.step(*st, gpx, gpy, h, tau, 1.0 / tau)
+            ux, uy, yx, yy = emd.drs_step(yx, yy, gpx, gpy, h, tau)
+            qx, qy = grid.project_unit_ball(yx, yy)
+            scale = 1.0 + np.abs(st[0]).max() + np.abs(st[1]).max()
+            assert max(np.abs(ux - st[0]).max(), np.abs(uy - st[1]).max()) <= 1e-12 * scale
+            assert max(np.abs(qx - st[2]).max(), np.abs(qy - st[3]).max()) <= 1e-12
