@@ -132,7 +132,11 @@ int rof_solve(gp_ctx* ctx, const float* I, float* u, float* p, int ny, int nx, d
  * m: out flux u + grad psi [2][ny][nx]; phi: nullable [ny][nx]; in: warm-start
  * potential phi0 (p0 = proj(grad phi0)) when opts->warm_start, out: the
  * scaled dual potential of the certificate (|grad phi| <= 1).  rep->primal is
- * the EMD upper bound h^2 sum |m|, rep->dual the certificate's lower bound. */
+ * the EMD upper bound h^2 sum |m|, rep->dual the certificate's lower bound.
+ * With sigma tau = 1 (the default sigma) and no averaging, the iterates are
+ * formed in the equivalent single-variable form (state y = p_prev + sigma
+ * (u + grad psi), p = proj(y); the Douglas-Rachford case of section 2; a
+ * warm start is y0 = p0); otherwise in the two-variable form. */
 int emd_solve(gp_ctx* ctx, const float* rho0, const float* rho1, float* m, float* phi, int ny, int nx, double h,
               const gp_opts* opts, gp_report* rep);
 
@@ -216,7 +220,8 @@ typedef struct {
  * check where it converged: its kernels skip it from then on, so its outputs
  * equal those of the matching single-instance solve with the same
  * check_every (rounded up to even, the chunk length; iteration counts are
- * multiples of it).  opts->tau/sigma are ignored (per-instance tau) and
+ * multiples of it).  opts->tau/sigma are ignored (per-instance tau, sigma
+ * = 1/tau: EMD instances run the single-variable form as emd_solve) and
  * opts->warm_start must be 0.  reps: nullable array of count reports;
  * seconds_loop is the time from the first replay to the instance's last
  * check.  Allocates the batch workspace (grow-only, kept in the context) and
