@@ -165,6 +165,29 @@ def test_rof3_warm_start_from_a_solution(gpctx):
     assert rep2["converged"] and rep2["iters"] <= 10
 
 
+def test_rof3_ball_closed_form(gpctx):
+    """Ball indicator of radius r = 1/4 in [0,1]^3, h = 1/n, lambda = 40: the d = 3
+    counterpart of the disc solution, u* = a = 1 - 3/(lambda r) on the ball and
+    b = 4 pi r^2 / (lambda (1 - 4 pi r^3 / 3)) outside (surface over lambda times
+    volume, as in 2-D; valid for a > b), up to the grid's discretisation of the
+    sphere; the mean is preserved exactly."""
+    from paper_1805_09453_amd import Options
+    n, lam, rad = 128, 40.0, 0.25
+    X, Y, Z = synth.cell_centres3(n, n, n)
+    d = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2)
+    I = (d <= rad).astype(np.float64)
+    announce("rof3_solve ball 128^3")
+    u, p, rep = gpctx.rof3_solve(dev(I), 1.0 / n, lam, Options(tau=2.0, tol=1e-5, max_iter=20000, check_every=20))
+    uu = host(u)
+    a = 1 - 3 / (lam * rad)
+    b = 4 * np.pi * rad ** 2 / (lam * (1 - 4 * np.pi * rad ** 3 / 3))
+    inside, outside = uu[d < rad - 0.1].mean(), uu[d > rad + 0.1].mean()
+    print(rep, inside, a, outside, b)
+    assert rep["converged"]
+    assert abs(inside - a) < 0.01 and abs(outside - b) < 0.005
+    assert abs(uu.mean() - I.mean()) < 1e-5
+
+
 def test_emd3_z_only_closed_form(gpctx):
     """Densities varying along z only: EMD = (slice area) x h sum |C_k| with
     C_k = h sum_{j<=k}(rho1_j - rho0_j); the GPU's primal value matches it and
