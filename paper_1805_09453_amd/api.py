@@ -24,7 +24,8 @@ class GPError(RuntimeError):
 
 @dataclass
 class Options:
-    """Step sizes and stopping rule (gp_opts).  sigma <= 0 means 1/tau."""
+    """Step sizes and stopping rule (gp_opts).  sigma <= 0 means 1/tau; ergodic
+    selects the averaged iterates (gap and outputs of the averages)."""
     tau: float
     sigma: float = 0.0
     tol: float = 1e-5
@@ -172,6 +173,7 @@ class Context:
 
     # -- 3-D grids
     def dct_poisson3(self, b, x=None, h=1.0, alpha=0.0):
+        """(alpha I - Delta) x = b on an [nz][ny][nx] grid (FP32 or FP64 by b's dtype)."""
         torch = _torch()
         nz, ny, nx = b.shape
         x = torch.empty_like(b) if x is None else x
@@ -182,6 +184,7 @@ class Context:
         return x
 
     def rof3_solve(self, I, h, lam, opts: Options, u=None, p=None):
+        """ROF on an [nz][ny][nx] volume; returns (u, p [3][nz][ny][nx], report)."""
         torch = _torch()
         nz, ny, nx = I.shape
         u = torch.empty_like(I) if u is None else u
@@ -195,6 +198,8 @@ class Context:
         return u, p, rep.as_dict()
 
     def emd3_solve(self, rho0, rho1, h, opts: Options, phi=None, want_phi=True):
+        """EMD between [nz][ny][nx] densities; returns (flux m [3][nz][ny][nx], phi, report).
+        phi: the warm-start potential when opts.warm_start (overwritten with the certificate's)."""
         torch = _torch()
         nz, ny, nx = rho0.shape
         m = torch.empty((3, nz, ny, nx), device=rho0.device, dtype=rho0.dtype)
