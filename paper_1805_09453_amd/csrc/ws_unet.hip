@@ -192,7 +192,7 @@ struct WgArgs {
   int c1, s1, c2, s2;
   int B, H, W;     // pixel space of the m-operand
   int taps, ck, ckeep;
-  int chunk;       // pixels per block (multiple of 32)
+  int chunk;       // pixels per block (multiple of 64)
 };
 
 template <int MODE>
@@ -215,7 +215,9 @@ __device__ __forceinline__ uint4 wg_k(const WgArgs& a, int p, int k0) {
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
-  constexpr int PS = 32, LD = PS + 8;
+  // 64 pixels per step (two K = 32 MFMA blocks between barriers); the operands
+  // of the next step are loaded into registers while this step's MFMAs run
+  constexpr int PS = 64, LD = PS + 8;
   __shared__ __align__(16) bf16 At[64 * LD];  // [m][p]
   __shared__ __align__(16) bf16 Bt[64 * LD];  // [k][p]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -225,28 +227,39 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   f32x4 acc[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int px = tid >> 3, q = tid & 7;
-  for (int ps = pb; ps < pe; ps += PS) {
-    const int p = ps + px;
-    V8 va, vb;
+  const int px = tid >> 3, q = tid & 7;  // this thread's pixels px and px + 32 of a step, channels 8q..8q+7
+  auto load = [&](int p, V8& va, V8& vb) {
     va.u = uint4{0u, 0u, 0u, 0u};
     vb.u = va.u;
     if (p < pe) {
       if (m0 + 8 * q < a.c1m) va.u = ld16(a.t1 + size_t(p) * a.s1m + m0 + 8 * q);
       vb.u = wg_k<MODE>(a, p, k0 + 8 * q);
     }
+  };
+  V8 a0, b0, a1, b1;
+  load(pb + px, a0, b0);
+  load(pb + px + 32, a1, b1);
+  for (int ps = pb; ps < pe; ps += PS) {
     __syncthreads();  // the previous step's operand reads are done
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      At[(8 * q + j) * LD + px] = va.h[j];
-      Bt[(8 * q + j) * LD + px] = vb.h[j];
+      At[(8 * q + j) * LD + px] = a0.h[j];
+      At[(8 * q + j) * LD + px + 32] = a1.h[j];
+      Bt[(8 * q + j) * LD + px] = b0.h[j];
+      Bt[(8 * q + j) * LD + px + 32] = b1.h[j];
     }
     __syncthreads();
-    const bf16x8 av = *reinterpret_cast<const bf16x8*>(&At[(w * 16 + (lane & 15)) * LD + (lane >> 4) * 8]);
+    load(ps + PS + px, a0, b0);
+    load(ps + PS + px + 32, a1, b1);
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Bt[(ni * 16 + (lane & 15)) * LD + (lane >> 4) * 8]);
-      acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
+    for (int kk = 0; kk < 2; ++kk) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&At[(w * 16 + (lane & 15)) * LD + kk * 32 + (lane >> 4) * 8]);
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        const bf16x8 bv =
+            *reinterpret_cast<const bf16x8*>(&Bt[(ni * 16 + (lane & 15)) * LD + kk * 32 + (lane >> 4) * 8]);
+        acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
@@ -682,7 +695,7 @@ int launch_wgrad(ws_net* net, hipStream_t s, WgArgs a) {
   chunks = chunks < 1 ? 1 : chunks;
   const int maxc = (P + 255) / 256;
   chunks = chunks > maxc ? maxc : chunks;
-  a.chunk = rup((P + chunks - 1) / chunks, 32);
+  a.chunk = rup((P + chunks - 1) / chunks, 64);
   chunks = (P + a.chunk - 1) / a.chunk;
   hipLaunchKernelGGL((k_wgrad<MODE>), dim3(mt, kt, chunks), dim3(256), 0, s, a);
   WLAUNCH(net);
