@@ -216,7 +216,8 @@ __device__ __forceinline__ uint4 wg_k(const WgArgs& a, int p, int k0) {
 template <int MODE>
 __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   // 64 pixels per step (two K = 32 MFMA blocks between barriers); the operands
-  // of the next step are loaded into registers while this step's MFMAs run
+  // of the next step are loaded into registers while this step's MFMAs run.
+  // (128-pixel steps with 8-byte stores measured no faster.)
   constexpr int PS = 64, LD = PS + 8;
   __shared__ __align__(16) bf16 At[64 * LD];  // [m][p]
   __shared__ __align__(16) bf16 Bt[64 * LD];  // [k][p]
@@ -227,7 +228,9 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   f32x4 acc[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int px = tid >> 3, q = tid & 7;  // this thread's pixels px and px + 32 of a step, channels 8q..8q+7
+  // this thread's pixels 2 px and 2 px + 1 of a step (adjacent in the [m][p] tiles, so each
+  // channel's pair is one 4-byte LDS store), channels 8q..8q+7
+  const int px = tid >> 3, q = tid & 7;
   auto load = [&](int p, V8& va, V8& vb) {
     va.u = uint4{0u, 0u, 0u, 0u};
     vb.u = va.u;
@@ -236,21 +239,22 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
       vb.u = wg_k<MODE>(a, p, k0 + 8 * q);
     }
   };
+  auto pack = [](bf16 lo, bf16 hi) {
+    return uint32_t(__builtin_bit_cast(unsigned short, lo)) | (uint32_t(__builtin_bit_cast(unsigned short, hi)) << 16);
+  };
   V8 a0, b0, a1, b1;
-  load(pb + px, a0, b0);
-  load(pb + px + 32, a1, b1);
+  load(pb + 2 * px, a0, b0);
+  load(pb + 2 * px + 1, a1, b1);
   for (int ps = pb; ps < pe; ps += PS) {
     __syncthreads();  // the previous step's operand reads are done
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      At[(8 * q + j) * LD + px] = a0.h[j];
-      At[(8 * q + j) * LD + px + 32] = a1.h[j];
-      Bt[(8 * q + j) * LD + px] = b0.h[j];
-      Bt[(8 * q + j) * LD + px + 32] = b1.h[j];
+      *reinterpret_cast<uint32_t*>(&At[(8 * q + j) * LD + 2 * px]) = pack(a0.h[j], a1.h[j]);
+      *reinterpret_cast<uint32_t*>(&Bt[(8 * q + j) * LD + 2 * px]) = pack(b0.h[j], b1.h[j]);
     }
     __syncthreads();
-    load(ps + PS + px, a0, b0);
-    load(ps + PS + px + 32, a1, b1);
+    load(ps + PS + 2 * px, a0, b0);
+    load(ps + PS + 2 * px + 1, a1, b1);
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
       const bf16x8 av = *reinterpret_cast<const bf16x8*>(&At[(w * 16 + (lane & 15)) * LD + kk * 32 + (lane >> 4) * 8]);
