@@ -318,6 +318,36 @@ def test_3d_degenerate_problems(gpctx):
     assert rep["primal"] <= 1e-6 * 0.5 * 8.0 * c * c * 64 ** 3  # 1e-6 of the zero start's objective
 
 
+def test_3d_largest_grid_properties(gpctx):
+    """512^3 (2^27 cells, the largest grid the 3-D calls accept): properties that
+    hold at any size.  ROF: the incremental u-step preserves the mean of I from the
+    first iteration on (div has zero mean), and P >= D; EMD: P >= D > 0 and the
+    flux's x-component vanishes on the far face."""
+    import torch
+    from paper_1805_09453_amd import Options
+    n = 512
+    z = (torch.arange(n, dtype=torch.float32, device="cuda") + 0.5) / n
+    I = (torch.sin(6 * z)[:, None, None] * torch.cos(5 * z)[None, :, None] + (z[None, None, :] > 0.5)).contiguous()
+    announce("rof3_solve 512^3, 3 iterations")
+    u, p, rep = gpctx.rof3_solve(I, 1.0, 8.0, Options(tau=0.01, tol=0.0, max_iter=3, check_every=3))
+    mu, mi = float(u.double().mean()), float(I.double().mean())
+    print(rep, mu, mi)
+    assert abs(mu - mi) <= 1e-5 * (abs(mi) + 1e-3)
+    assert rep["primal"] >= rep["dual"] and torch.isfinite(u).all()
+    del u, p
+    g0 = torch.exp(-((z - 0.3) / 0.1) ** 2)
+    g1 = torch.exp(-((z - 0.6) / 0.12) ** 2)
+    r0 = (g0[:, None, None] * g1[None, :, None] * g0[None, None, :] + 1e-3)
+    r1 = (g1[:, None, None] * g0[None, :, None] * g1[None, None, :] + 1e-3)
+    r1 = (r1 * (r0.double().sum() / r1.double().sum()).float()).contiguous()
+    r0 = r0.contiguous()
+    announce("emd3_solve 512^3, 3 iterations")
+    m, phi, rep = gpctx.emd3_solve(r0, r1, 1.0 / n, Options(tau=0.3, tol=0.0, max_iter=3, check_every=3))
+    print(rep)
+    assert rep["primal"] >= rep["dual"] > 0
+    assert float(m[0, :, :, -1].abs().max()) == 0.0 and torch.isfinite(m).all()
+
+
 def test_3d_errors(gpctx):
     from paper_1805_09453_amd import GPError, Options
     from paper_1805_09453_amd._lib import GP_EINVAL, GP_EMASS, GP_EUNSUPPORTED
