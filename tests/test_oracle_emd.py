@@ -123,6 +123,9 @@ def test_isotropic_bracketed_by_polygonal_lp():
 
 
 @pytest.mark.slow
+# the quasi-Newton update of scipy's trust-region solver notes a linear
+# objective (the dual's is linear); the result is checked below regardless
+@pytest.mark.filterwarnings("ignore:delta_grad == 0.0")
 def test_isotropic_matches_constrained_dual_solve():
     n, h = 6, 1.0 / 6
     rho0, rho1, _, _ = synth.integer_mass_pair(n, 5)
