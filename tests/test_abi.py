@@ -83,3 +83,24 @@ def test_python_layer_refuses_without_gpu():
     from paper_1805_09453_amd import Context, GPError
     with pytest.raises(GPError):
         Context(64, 64)
+
+
+def test_product_path_is_independent_of_the_oracle():
+    """The package (binding, build, experiment and training drivers, HIP sources)
+    neither imports nor includes anything from oracle/, and importing it in a
+    fresh interpreter loads no oracle module: every solve runs in the HIP
+    library, so the GPU parity tests compare two independent implementations."""
+    import subprocess
+    import sys
+    pkg = os.path.join(ROOT, "paper_1805_09453_amd")
+    pat = re.compile(r"^\s*(?:from\s+oracle\b|import\s+oracle\b|#\s*include\s*[<\"][^>\"]*oracle)", re.M)
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".inc", ".h")):
+                path = os.path.join(dirpath, f)
+                assert not pat.search(open(path).read()), f"{path} reaches into oracle/"
+    code = ("import sys; sys.path.insert(0, %r); import paper_1805_09453_amd, paper_1805_09453_amd.api; "
+            "print(sorted(m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "[]"
