@@ -2,8 +2,11 @@
 the adjoint identity, a dense linear solve of the assembled 7-point operator,
 exact reduction to the pinned 2-D oracle for data constant along one axis
 (each axis in turn, both norms), the 1-D closed form of the EMD for
-densities that vary along z only, and the ROF invariants (mean preservation,
-maximum principle, weak duality)."""
+densities that vary along z only, the ROF invariants (mean preservation,
+maximum principle, weak duality), and, on volumes with structure along every
+axis, the anisotropic EMD against a linear program and a min-cost flow and the
+anisotropic ROF against a box-constrained maximisation of its dual (both with
+the divergence assembled in the test from its definition)."""
 import numpy as np
 import pytest
 
@@ -268,3 +271,91 @@ def test_single_variable_emd_from_a_warm_start():
     # and the solve's warm start is that start
     r = g3.emd_solve(a, b, h, tau=tau, tol=0.0, max_iter=8, check_every=8, phi0=phi0)
     assert max(np.abs(x - z).max() for x, z in zip(r.p, p)) <= 1e-12
+
+
+def _face_divergence(nz, ny, nx, h):
+    """Divergence of a face field assembled from its definition, independently of
+    oracle/grid3.py: one variable per interior face (x faces, then y, then z;
+    far-face components are zero and have no variable), each entering the cell
+    on its low side with +1/h and the cell on its high side with -1/h (backward
+    differences).  Returns the (cells x faces) matrix."""
+    cell = np.arange(nz * ny * nx).reshape(nz, ny, nx)
+    cols = []
+    for (dz, dy, dx) in ((0, 0, 1), (0, 1, 0), (1, 0, 0)):
+        lo = cell[:nz - dz, :ny - dy, :nx - dx].ravel()
+        hi = cell[dz:, dy:, dx:].ravel()
+        for a, b in zip(lo, hi):
+            c = np.zeros(nz * ny * nx)
+            c[a], c[b] = 1.0 / h, -1.0 / h
+            cols.append(c)
+    return np.array(cols).T
+
+
+def test_emd_anisotropic_3d_matches_lp_and_min_cost_flow():
+    """Anisotropic 3-D EMD of integer masses on a 4x4x4 grid (all three axes
+    carry flux): the oracle's converged value equals the Beckmann linear program
+    min h^3 sum |m| s.t. div m = rho1 - rho0, assembled here from the
+    definition, and the min-cost flow on the 6-neighbour grid graph."""
+    import networkx as nx_
+    from scipy.optimize import linprog
+    n, h = 4, 0.25
+    rng = np.random.default_rng(41)
+    c0 = rng.integers(0, 6, (n, n, n))
+    c1 = rng.integers(0, 6, (n, n, n))
+    c1[0, 0, 0] += c0.sum() - c1.sum() if c0.sum() >= c1.sum() else 0
+    c0[0, 0, 0] += c1.sum() - c0.sum() if c1.sum() > c0.sum() else 0
+    assert c0.sum() == c1.sum()
+    rho0, rho1 = c0 / (c0.sum() * h ** 3), c1 / (c1.sum() * h ** 3)
+    A = _face_divergence(n, n, n, h)
+    f = (rho1 - rho0).ravel()
+    nf = A.shape[1]
+    lp = linprog(h ** 3 * np.ones(2 * nf), A_eq=np.hstack([A, -A]), b_eq=f, bounds=(0, None), method="highs")
+    G = nx_.DiGraph()
+    for k in range(n):
+        for i in range(n):
+            for j in range(n):
+                G.add_node((k, i, j), demand=int(c1[k, i, j] - c0[k, i, j]))
+                for d in ((0, 0, 1), (0, 1, 0), (1, 0, 0), (0, 0, -1), (0, -1, 0), (-1, 0, 0)):
+                    q = (k + d[0], i + d[1], j + d[2])
+                    if all(0 <= x < n for x in q):
+                        G.add_edge((k, i, j), q, weight=1)
+    v_flow = h * nx_.min_cost_flow_cost(G) / float(c0.sum())
+    assert abs(lp.fun - v_flow) <= 1e-12 * v_flow
+    r = g3.emd_solve(rho0, rho1, h, tau=0.3, tol=1e-10, max_iter=200000, check_every=10, norm=g3.ANISO)
+    assert r.converged
+    assert r.dual <= v_flow * (1 + 1e-12) <= r.primal * (1 + 2e-12)
+    assert abs(r.primal - v_flow) <= 1e-9 * v_flow
+
+
+def test_rof_anisotropic_3d_matches_box_constrained_dual():
+    """Anisotropic 3-D ROF on a 4x4x4 volume with structure along every axis:
+    the oracle's converged energy equals the maximum of the dual
+    -h^3 I.(A p) - h^3/(2 lambda) |A p|^2 over the box |p| <= 1 (the l-infinity
+    ball, dual of the l1 norm), with A the face divergence assembled here and the
+    maximum found by L-BFGS-B; the minimiser is I + A p / lambda."""
+    from scipy.optimize import minimize
+    n, h, lam = 4, 1.0, 3.0
+    rng = np.random.default_rng(43)
+    I = np.zeros((n, n, n))
+    I[1:3, 0:3, 1:4] = 1.0
+    I[2:4, 2:4, 0:2] += 0.6
+    I += 0.2 * rng.standard_normal(I.shape)
+    A = _face_divergence(n, n, n, h)
+    Iv = I.ravel()
+
+    def neg_dual(p):
+        d = A @ p
+        val = -h ** 3 * (Iv @ d) - h ** 3 / (2 * lam) * (d @ d)
+        grad_ = -h ** 3 * (A.T @ (Iv + d / lam))
+        return -val, -grad_
+
+    res = minimize(neg_dual, np.zeros(A.shape[1]), jac=True, method="L-BFGS-B",
+                   bounds=[(-1.0, 1.0)] * A.shape[1], options=dict(ftol=1e-16, gtol=1e-13, maxiter=50000))
+    d_star = -res.fun
+    u_star = (Iv + A @ res.x / lam).reshape(I.shape)
+    r = g3.rof_solve(I, h, lam, 0.05, tol=1e-11, max_iter=200000, check_every=10, norm=g3.ANISO)
+    assert r.converged
+    assert r.dual <= d_star * (1 + 1e-9) and d_star <= r.primal * (1 + 1e-12)
+    assert abs(r.primal - d_star) <= 1e-9 * abs(d_star)
+    # strong convexity: h^3 |u - u*|^2 <= 2 (P(u) - P*) / lambda
+    assert np.sqrt(h ** 3 * np.sum((r.u - u_star) ** 2)) <= 1e-4
