@@ -5,8 +5,10 @@ exact reduction to the pinned 2-D oracle for data constant along one axis
 densities that vary along z only, the ROF invariants (mean preservation,
 maximum principle, weak duality), and, on volumes with structure along every
 axis, the anisotropic EMD against a linear program and a min-cost flow and the
-anisotropic ROF against a box-constrained maximisation of its dual (both with
-the divergence assembled in the test from its definition)."""
+anisotropic ROF against a box-constrained maximisation of its dual, and the
+isotropic ROF inside the primal-dual bracket of an accelerated projected
+gradient on its dual (all with the divergence assembled in the test from its
+definition)."""
 import numpy as np
 import pytest
 
@@ -359,3 +361,49 @@ def test_rof_anisotropic_3d_matches_box_constrained_dual():
     assert abs(r.primal - d_star) <= 1e-9 * abs(d_star)
     # strong convexity: h^3 |u - u*|^2 <= 2 (P(u) - P*) / lambda
     assert np.sqrt(h ** 3 * np.sum((r.u - u_star) ** 2)) <= 1e-4
+
+
+def test_rof_isotropic_3d_inside_an_independent_dual_bracket():
+    """Isotropic 3-D ROF on a 4x4x4 volume with structure along every axis: the
+    oracle's converged energy lies in the bracket [D(p), P(I + A p / lambda)]
+    that accelerated projected gradient (FISTA) on the dual reaches, with A the
+    face divergence assembled in the test and the unit l2 ball taken over the
+    three faces each cell owns (its x, y and z faces on the high side), a
+    method and operators shared with nothing in oracle/grid3.py."""
+    n, h, lam = 4, 1.0, 3.0
+    rng = np.random.default_rng(47)
+    I = np.zeros((n, n, n))
+    I[0:3, 1:4, 1:3] = 1.0
+    I[2:4, 0:2, 2:4] += 0.7
+    I += 0.2 * rng.standard_normal(I.shape)
+    Iv = I.ravel()
+    A = _face_divergence(n, n, n, h)
+    owner = np.argmax(A > 0, axis=0)  # the cell on a face's low side
+
+    def proj(p):
+        s = np.maximum(1.0, np.sqrt(np.bincount(owner, p * p, minlength=A.shape[0])))
+        return p / s[owner]
+
+    def dual(p):
+        d = A @ p
+        return -h ** 3 * (Iv @ d) - h ** 3 / (2 * lam) * (d @ d)
+
+    def primal(u):
+        g = -(A.T @ u)  # forward differences
+        return h ** 3 * np.sum(np.sqrt(np.bincount(owner, g * g, minlength=A.shape[0]))) + \
+            0.5 * lam * h ** 3 * np.sum((u - Iv) ** 2)
+
+    L = h ** 3 * np.linalg.norm(A, 2) ** 2 / lam
+    p = np.zeros(A.shape[1])
+    q, t = p.copy(), 1.0
+    for _ in range(20000):
+        p_new = proj(q + (h ** 3 * (A.T @ (Iv + (A @ q) / lam))) * (-1.0 / L))
+        t_new = 0.5 * (1 + np.sqrt(1 + 4 * t * t))
+        q = p_new + ((t - 1) / t_new) * (p_new - p)
+        p, t = p_new, t_new
+    lo, hi = dual(p), primal(Iv + A @ p / lam)
+    assert hi - lo <= 1e-7 * abs(hi)
+    r = g3.rof_solve(I, h, lam, 0.05, tol=1e-10, max_iter=200000, check_every=10)
+    assert r.converged
+    assert lo * (1 - 1e-12) <= r.primal and r.dual <= hi * (1 + 1e-12)
+    assert abs(r.primal - hi) <= 2e-7 * abs(hi)
