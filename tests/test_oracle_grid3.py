@@ -7,7 +7,7 @@ maximum principle, weak duality), and, on volumes with structure along every
 axis, the anisotropic EMD against a linear program and a min-cost flow and the
 anisotropic ROF against a box-constrained maximisation of its dual, and the
 isotropic ROF inside the primal-dual bracket of an accelerated projected
-gradient on its dual (all with the divergence assembled in the test from its
+gradient on its dual, and the isotropic EMD inside a polygonal-LP bracket (all with the divergence assembled in the test from its
 definition)."""
 import numpy as np
 import pytest
@@ -407,3 +407,55 @@ def test_rof_isotropic_3d_inside_an_independent_dual_bracket():
     assert r.converged
     assert lo * (1 - 1e-12) <= r.primal and r.dual <= hi * (1 + 1e-12)
     assert abs(r.primal - hi) <= 2e-7 * abs(hi)
+
+
+def test_emd_isotropic_3d_inside_a_polygonal_lp_bracket():
+    """Isotropic 3-D EMD of a 4x4x4 pair with structure along every axis.  With
+    unit directions d_k (a Fibonacci sphere), max_k <d_k, m> <= |m|_2 per cell,
+    so the linear program min h^3 sum_c t_c, t_c >= <d_k, m_c>, div m = f is a
+    lower bound, and the l2 cost of its own feasible flux an upper bound; the
+    oracle's converged value lies in that bracket (divergence assembled in the
+    test; each cell's vector is its x, y and z faces on the high side)."""
+    import scipy.sparse as sp
+    from scipy.optimize import linprog
+    n, h, K = 4, 0.25, 1600
+    rng = np.random.default_rng(53)
+    rho0 = rng.random((n, n, n)) + 0.2
+    rho1 = rng.random((n, n, n)) + 0.2
+    rho1 *= rho0.sum() / rho1.sum()
+    A = _face_divergence(n, n, n, h)
+    nc, nf = A.shape
+    owner = np.argmax(A > 0, axis=0)
+    axis_of = np.concatenate([np.full(n * n * (n - 1), a) for a in range(3)])  # x faces, y faces, z faces
+    k = np.arange(K) + 0.5
+    zc = 1 - 2 * k / K
+    th = np.pi * (1 + 5 ** 0.5) * k
+    D = np.stack([np.sqrt(1 - zc * zc) * np.cos(th), np.sqrt(1 - zc * zc) * np.sin(th), zc], axis=1)
+    # rows (cell c, direction j): sum over c's faces of d_j[axis] m_face - t_c <= 0
+    rows, cols, vals = [], [], []
+    for fidx in range(nf):
+        c, a = owner[fidx], axis_of[fidx]
+        for j in range(K):
+            rows.append(c * K + j)
+            cols.append(fidx)
+            vals.append(D[j, a])
+    for c in range(nc):
+        for j in range(K):
+            rows.append(c * K + j)
+            cols.append(nf + c)
+            vals.append(-1.0)
+    Aub = sp.csr_matrix((vals, (rows, cols)), shape=(nc * K, nf + nc))
+    f = (rho1 - rho0).ravel()
+    f = f - f.mean()
+    Aeq = sp.hstack([sp.csr_matrix(A), sp.csr_matrix((nc, nc))])
+    res = linprog(np.concatenate([np.zeros(nf), h ** 3 * np.ones(nc)]), A_ub=Aub, b_ub=np.zeros(nc * K),
+                  A_eq=Aeq, b_eq=f, bounds=(None, None), method="highs")
+    assert res.status == 0
+    m = res.x[:nf]
+    assert np.abs(A @ m - f).max() <= 1e-9 * np.abs(f).max()
+    lo = res.fun
+    hi = h ** 3 * np.sum(np.sqrt(np.bincount(owner, m * m, minlength=nc)))
+    assert hi - lo <= 2e-3 * hi
+    r = g3.emd_solve(rho0, rho1, h, tau=0.3, tol=1e-9, max_iter=200000, check_every=10)
+    assert r.converged
+    assert lo * (1 - 1e-12) <= r.primal and r.dual <= hi * (1 + 1e-12)
