@@ -47,12 +47,15 @@ def parse():
     ap.add_argument("--warm-tol", type=float, default=1e-5)
     ap.add_argument("--warm-max-iter", type=int, default=60000)
     ap.add_argument("--batch-count", type=int, default=512)
-    ap.add_argument("--batch-tol", type=float, default=1e-4)
-    ap.add_argument("--batch-max-iter", type=int, default=5000)
+    ap.add_argument("--batch-tol", type=float, default=1e-5)
+    ap.add_argument("--batch-max-iter", type=int, default=60000)
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D grid leg")
     ap.add_argument("--n3", type=int, default=256, help="side of the 3-D grid leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
+    ap.add_argument("--cpu-workers", type=int, default=0, help="scipy.fft threads of the CPU baseline "
+                    "(0: the host's cores, at most 16)")
+    ap.add_argument("--warm-pairs", type=int, default=4, help="4096^2 EMD pairs of the plain-vs-warm leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -87,10 +90,14 @@ def traffic_for(kernel, n):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(n, iters_budget_s):
+def cpu_baseline(n, iters_budget_s, iters_to_tol, workers):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
-    whole ROF iterations on the same 4096x4096 image, timed with perf_counter."""
+    whole ROF iterations on the same 4096x4096 image, timed with perf_counter;
+    scipy.fft runs its 1-D transforms on `workers` threads (NumPy's elementwise
+    work is single-threaded).  The projection to tolerance uses the iteration
+    count the GPU solve needed in this run."""
     import numpy as np
+    import scipy.fft
 
     import synth
     from oracle import rof as orof
@@ -99,19 +106,21 @@ def cpu_baseline(n, iters_budget_s):
     px, py = np.zeros_like(I), np.zeros_like(I)
     pbx, pby = px.copy(), py.copy()
     tau = 0.01
-    t0 = time.perf_counter()
-    it = 0
-    while True:
-        u, px, py, pbx, pby = orof.step(u, px, py, pbx, pby, I, 1.0, 8.0, tau, 1.0 / tau)
-        it += 1
-        if time.perf_counter() - t0 >= iters_budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n * n * it / dt, "unit": "pixel-iters/s", "cores": 1, "kind": "oracle",
+    with scipy.fft.set_workers(workers):
+        t0 = time.perf_counter()
+        it = 0
+        while True:
+            u, px, py, pbx, pby = orof.step(u, px, py, pbx, pby, I, 1.0, 8.0, tau, 1.0 / tau)
+            it += 1
+            if time.perf_counter() - t0 >= iters_budget_s:
+                break
+        dt = time.perf_counter() - t0
+    proj = f"{iters_to_tol * dt / it:.0f} s" if iters_to_tol else "n/a"
+    return {"value": n * n * it / dt, "unit": "pixel-iters/s", "cores": workers, "kind": "oracle",
             "sample": f"{it} ROF iterations of the FP64 NumPy/SciPy oracle on the same {n}x{n} image "
-                      f"({dt:.1f} s; scipy.fft single-threaded, NumPy elementwise single-threaded); "
-                      f"projected time for the 490 iterations the GPU solve needs to a 1e-5 gap: "
-                      f"{490 * dt / it:.0f} s"}
+                      f"({dt:.1f} s; scipy.fft on {workers} threads, NumPy elementwise single-threaded); "
+                      f"projected time for the {iters_to_tol} iterations the GPU solve needed to a 1e-5 gap "
+                      f"in this run: {proj}"}
 
 
 def batch_leg(ctx, dev, count, tol, max_iter):
@@ -141,7 +150,8 @@ def batch_leg(ctx, dev, count, tol, max_iter):
     wall = time.perf_counter() - t0
     loop = max(r["seconds_loop"] for r in reps)
     pxit = sum(q["n"] ** 2 * r["iters"] for q, r in zip(insts, reps))
-    tt = np.array([r["seconds_loop"] for r in reps])
+    # time to tolerance: over the instances that met it (the others stopped at the cap)
+    tt = np.array([r["seconds_loop"] for r in reps if r["converged"]] or [np.nan])
     per = {}
     for kind in ("rof", "emd"):
         for n in sorted({q["n"] for q in insts}):
@@ -154,19 +164,24 @@ def batch_leg(ctx, dev, count, tol, max_iter):
             "max_iter": max_iter, "check_every": 20, "pixel_iters_per_s": pxit / loop, "loop_s": loop,
             "setup_s": reps[0]["seconds_setup"], "wall_s": wall,
             "converged": int(sum(r["converged"] for r in reps)),
+            "unconverged": int(sum(not r["converged"] for r in reps)),
             "time_to_tol_p50_s": float(np.percentile(tt, 50)), "time_to_tol_p99_s": float(np.percentile(tt, 99)),
+            "time_to_tol_over": "converged instances only",
             "groups": per,
             "tuned_shapes": {f"{'f64' if fp else 'f32'}_{n}": list(ctx.get_shape(fp, n))
                              for fp in (False, True) for n in sorted({q["n"] for q in insts})}}
 
 
-def warm_leg(ctx, r0, r1, n, tol, max_iter):
-    """EMD time to `tol` on the same n x n pair: plain zero start vs the learned
-    warm start (block mean to the network's native size -> prediction -> bilinear
-    potential, certificate check, fallback), each timed whole."""
+def warm_leg(ctx, dev, n, tol, max_iter, pairs):
+    """EMD time to `tol` on `pairs` n x n pairs of 16-Gaussian mixtures (the bench's
+    pair and further seeds of the same recipe, none seen in training): plain zero
+    start vs the learned warm start (block mean to the network's native size ->
+    prediction -> bilinear potential, certificate check, fallback), each timed
+    whole."""
     import numpy as np
     import torch
 
+    import synth
     from paper_1805_09453_amd import Options, WarmStart
     wpath = os.path.join(ROOT, "paper_1805_09453_amd", "weights", "ws_unet.f32")
     if not os.path.exists(wpath):
@@ -176,22 +191,34 @@ def warm_leg(ctx, r0, r1, n, tol, max_iter):
     ws = WarmStart(ctx, 1, native, native)
     ws.set_params(torch.tensor(np.fromfile(wpath, dtype="<f4"), device="cuda"))
     opts = Options(tau=0.3, tol=tol, max_iter=max_iter, check_every=50)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, _, rp = ctx.emd_solve(r0, r1, 1.0 / n, opts, want_phi=False)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    _, _, rw, wr = ws.emd_solve(r0, r1, 1.0 / n, opts)
-    torch.cuda.synchronize()
-    tw = time.perf_counter() - t0
+    rows = []
+    for j in range(pairs):
+        rho0, rho1 = synth.emd_mixture_pair(n, synth.config_seed(2, 0 if j == 0 else 100 + j), k=16)
+        r0 = torch.tensor(rho0, dtype=torch.float32, device=dev)
+        r1 = torch.tensor(rho1, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, rp = ctx.emd_solve(r0, r1, 1.0 / n, opts, want_phi=False)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, _, rw, wr = ws.emd_solve(r0, r1, 1.0 / n, opts)
+        torch.cuda.synchronize()
+        tw = time.perf_counter() - t0
+        rows.append({"seed_instance": 0 if j == 0 else 100 + j,
+                     "plain": {"seconds": tp, "iters": rp["iters"], "converged": bool(rp["converged"])},
+                     "warm": {"seconds": tw, "iters": rw["iters"], "converged": bool(rw["converged"]),
+                              "fallback": wr["fallback"], "warm_iters": wr["warm_iters"], "d0": wr["d0"],
+                              "seconds_predict": wr["seconds_predict"]},
+                     "speedup": tp / tw if tw > 0 else None})
+        print(json.dumps({"warm_leg_pair": rows[-1]}), file=sys.stderr, flush=True)
     ws.close()
-    return {"grid": [n, n], "network_native": native, "tol": tol, "plain": {"seconds": tp, "iters": rp["iters"], "rel_gap": rp["rel_gap"],
-                                                  "converged": bool(rp["converged"])},
-            "warm": {"seconds": tw, "iters": rw["iters"], "rel_gap": rw["rel_gap"], "converged": bool(rw["converged"]),
-                     "fallback": wr["fallback"], "warm_iters": wr["warm_iters"], "d0": wr["d0"],
-                     "seconds_predict": wr["seconds_predict"]},
-            "speedup": tp / tw if tw > 0 else None}
+    sp = np.array([r["speedup"] for r in rows], dtype=float)
+    return {"grid": [n, n], "network_native": native, "tol": tol, "pairs": rows,
+            "speedup_mean": float(sp.mean()), "speedup_min": float(sp.min()), "speedup_max": float(sp.max()),
+            "speedup_std": float(sp.std(ddof=1)) if len(sp) > 1 else None,
+            "plain_seconds_total": float(sum(r["plain"]["seconds"] for r in rows)),
+            "warm_seconds_total": float(sum(r["warm"]["seconds"] for r in rows))}
 
 
 # HBM bytes per cell and iteration that the 3-D loops stream (FP32 state; EMD potential FP64):
@@ -336,14 +363,15 @@ def main():
                         "ms_per_step_with_kernel_events": 1e3 * edt_ev / K,
                         "kernels": {k: {"avg_ms": v["avg_ms"], "calls": v["calls"], "gbps": v["gbps"]}
                                     for k, v in eprof.items()}}
-    # ---- optional: time to tolerance (outside the timed steps)
+    # ---- time to tolerance (outside the timed steps): ROF always (a fraction of a second)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, rep = ctx.rof_solve(I_d, 1.0, 8.0, Options(tau=args.rof_tau, tol=args.tol, max_iter=20000,
+                                                     check_every=10))
+    torch.cuda.synchronize()
+    extra["rof"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
+    rof_iters_to_tol = rep["iters"] if rep["converged"] else None
     if args.solve:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, _, rep = ctx.rof_solve(I_d, 1.0, 8.0, Options(tau=args.rof_tau, tol=args.tol, max_iter=20000,
-                                                         check_every=10))
-        torch.cuda.synchronize()
-        extra["rof"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
         if not args.no_emd:
             t0 = time.perf_counter()
             _, _, rep = ctx.emd_solve(r0, r1, 1.0 / n, Options(tau=args.emd_tau, tol=args.tol,
@@ -352,13 +380,14 @@ def main():
             torch.cuda.synchronize()
             extra["emd"]["solve"] = dict(rep, wall_s=time.perf_counter() - t0, tol=args.tol)
     if not args.no_warm and not args.no_emd:
-        extra["warm_start"] = warm_leg(ctx, r0, r1, n, args.warm_tol, args.warm_max_iter)
+        extra["warm_start"] = warm_leg(ctx, dev, n, args.warm_tol, args.warm_max_iter, args.warm_pairs)
     if not args.no_batch:
         extra["batch"] = batch_leg(ctx, dev, args.batch_count, args.batch_tol, args.batch_max_iter)
     if not args.no_3d:
         extra["grid3d"] = grid3_leg(ctx, dev, args.n3, C, K, W)
     ctx.close()
-    cpu = None if args.no_cpu else cpu_baseline(n, args.cpu_seconds)
+    workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+    cpu = None if args.no_cpu else cpu_baseline(n, args.cpu_seconds, rof_iters_to_tol, workers)
     out = {
         "metric": "pixel-iters/s",
         "value": rof_pxit,

@@ -94,6 +94,7 @@ typedef struct {
  *                      u = divergence-free part u_n [2][ny][nx].
  *   p, pbar: dual iterate p_n and its extrapolation 2 p_n - p_{n-1} [2][ny][nx]
  *            (pbar = p at n = 0).
+ *   tau, sigma: steps (sigma <= 0 selects 1/tau, as in gp_opts); lambda: ROF only.
  *   iter: iterations done; pd_step adds n_iter. */
 typedef struct {
   int kind, ny, nx, norm;
@@ -146,8 +147,40 @@ int emd_solve(gp_ctx* ctx, const float* rho0, const float* rho1, float* m, float
 int emd_setup(gp_ctx* ctx, const float* rho0, const float* rho1, float* f, float* gpsi, int ny, int nx,
               double h);
 
-/* Advance a device-resident iterate by n_iter G-prox PDHG iterations (ROF or
- * EMD updates).  Enqueues work only: never synchronises, never allocates. */
+/* Step sizes from the data, computed before a solve.
+ *
+ * ROF (section 4.1): tau = min(sqrt(lambda) ||I||_TV / sqrt(eps), ||grad I||_L2),
+ * sigma = 1/tau, where ||I||_TV = h^2 sum |grad I| (the pointwise norm `norm`)
+ * and ||grad I||_L2 = sqrt(h^2 sum |grad I|_2^2), forward differences as the
+ * solver's.  The first term alone is the grid-independent choice (section 4.1,
+ * the lambda = 20 experiment without the grid cap).  tv_bound is the bound of
+ * section 3.1 on the minimiser, ||u*||_TV <= min(||I||_TV, lambda/2 ||I0 - I||^2)
+ * with I0 the mean of I.  eps is the absolute objective error the rule targets.
+ * FP64 sums on the device from the FP32 image; synchronises the stream.
+ * GP_EINVAL for NULL arguments, lambda or eps not positive and finite, a bad
+ * norm or a non-finite image; sizes as rof_solve. */
+typedef struct {
+  double tv, grad_l2, tv_bound;
+  double tau;            /* min(tau_continuum, grad_l2) */
+  double tau_continuum;  /* sqrt(lambda) tv / sqrt(eps) */
+} gp_rof_rule;
+int rof_step_rule(gp_ctx* ctx, const float* I, int ny, int nx, double h, double lambda, double eps, int norm,
+                  gp_rof_rule* out);
+
+/* EMD rule for singular measures (section 4.2): tau = min(sqrt(1 / (eps |ln eps|)),
+ * 2 m^(1/4)), sigma = 1/tau, for a grid of side m (the paper's statements about
+ * which term binds on its grids hold for m the side length and the natural
+ * logarithm).  Host arithmetic only; returns -1 unless 0 < eps < 1 and m > 0. */
+double emd_step_rule_singular(double eps, double m);
+
+/* Advance a device-resident iterate by n_iter G-prox PDHG iterations:
+ * Algorithm 2 (u-step in the H-inner product, dual prox, extrapolation
+ * pbar = 2 p_{n+1} - p_n) with the ROF updates of section 3.1 (u-step by the
+ * screened Poisson solve with alpha = lambda tau, incremental form) or the EMD
+ * updates of section 3.2 (u-step by the Leray projection, projected form
+ * u+ = P(u - tau pbar)); the dual steps project pointwise onto |p| <= 1.
+ * The state is the two-variable iterate (u_n, p_n, pbar_n) in either case.
+ * Enqueues work only: never synchronises, never allocates. */
 int pd_step(gp_ctx* ctx, gp_state* st, int n_iter);
 
 /* Primal value, dual value and relative gap of the state's (u_n, p_n);
@@ -219,10 +252,14 @@ typedef struct {
  * or run opts->max_iter iterations.  A converged instance retires at the
  * check where it converged: its kernels skip it from then on, so its outputs
  * equal those of the matching single-instance solve with the same
- * check_every (rounded up to even, the chunk length; iteration counts are
- * multiples of it).  opts->tau/sigma are ignored (per-instance tau, sigma
- * = 1/tau: EMD instances run the single-variable form as emd_solve) and
- * opts->warm_start must be 0.  reps: nullable array of count reports;
+ * check_every (rounded up to even, the chunk length C; iteration counts are
+ * multiples of C).  An instance that has not converged stops at the first
+ * check at or after opts->max_iter, so it may run up to C - 1 iterations
+ * beyond max_iter (check_every 5, max_iter 20: C = 6, 24 iterations).
+ * opts->tau/sigma are ignored (per-instance tau, sigma = 1/tau: EMD instances
+ * run the single-variable form as emd_solve); opts->warm_start must be 0
+ * (GP_EINVAL otherwise), and so must be a non-finite ROF image or negative or
+ * non-finite densities (the error names the instance).  reps: nullable array of count reports;
  * seconds_loop is the time from the first replay to the instance's last
  * check.  Allocates the batch workspace (grow-only, kept in the context) and
  * synchronises.  Returns GP_OK when every instance converged, GP_ENOTCONV

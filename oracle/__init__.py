@@ -28,7 +28,13 @@ inversion is done by FFT after even reflection, which is the DCT-II).
 
 Parity status: every function is pinned by a CPU test (tests/test_oracle_*.py)
 to something other than itself: adjointness, dense linear solves, BVLS, linear
-programs and network flow, closed forms and invariants.  No function here is
+programs and network flow, closed forms and invariants.  The step-size helpers
+(rof.tv_norm, rof.step_rule_tau, rof.tv_bound, emd.step_rule_tau_singular) are
+pinned in tests/test_oracle_step_rules.py by values worked out by hand on
+images with closed-form differences and by the paper's own statements about
+which term of the section 4.2 rule binds on its grids.  Small helpers that
+only feed pinned functions (rel_gap, pointwise_norm, dual_norm_max, the
+network's elementwise layers) are covered through them.  No function here is
 "parity unpinned".
 """
 from . import grid, rof, emd, unet  # noqa: F401

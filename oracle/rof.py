@@ -115,6 +115,7 @@ def solve(I, h, lam, tau, sigma=None, tol=1e-8, max_iter=100000, check_every=10,
 
 
 def tv_norm(u, h, norm=ISO) -> float:
+    """||u||_TV = h^2 sum |grad u| (the discrete total variation of section 3.1)."""
     gx, gy = grid.grad(u, h)
     return h * h * float(np.sum(grid.pointwise_norm(gx, gy, norm)))
 

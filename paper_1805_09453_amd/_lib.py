@@ -37,6 +37,14 @@ class gp_instance(ctypes.Structure):
                 ("tau", c_double), ("in0", c_void_p), ("in1", c_void_p), ("out", c_void_p), ("phi", c_void_p)]
 
 
+class gp_rof_rule(ctypes.Structure):
+    _fields_ = [("tv", c_double), ("grad_l2", c_double), ("tv_bound", c_double), ("tau", c_double),
+                ("tau_continuum", c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ws_report(ctypes.Structure):
     _fields_ = [("used_warm", c_int), ("fallback", c_int), ("warm_iters", c_int), ("d0", c_double),
                 ("seconds_predict", c_double), ("seconds_total", c_double)]
@@ -68,6 +76,9 @@ _SIGS = {
     "emd3_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double,
                            ctypes.POINTER(gp_opts), ctypes.POINTER(gp_report)]),
     "emd_setup": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double]),
+    "rof_step_rule": (c_int, [c_void_p, c_void_p, c_int, c_int, c_double, c_double, c_double, c_int,
+                              ctypes.POINTER(gp_rof_rule)]),
+    "emd_step_rule_singular": (c_double, [c_double, c_double]),
     "pd_step": (c_int, [c_void_p, ctypes.POINTER(gp_state), c_int]),
     "pd_gap": (c_int, [c_void_p, ctypes.POINTER(gp_state), ctypes.POINTER(gp_report)]),
     "gp_batch_solve": (c_int, [c_void_p, ctypes.POINTER(gp_instance), c_int, ctypes.POINTER(gp_opts),

@@ -67,8 +67,8 @@ class State:
 
     def __init__(self, kind, ny, nx, h, lam, tau, sigma, norm, f, gpsi, u, p, pbar):
         self.tensors = dict(f=f, gpsi=gpsi, u=u, p=p, pbar=pbar)
-        sig = sigma if sigma > 0 else 1.0 / tau
-        self.c = L.gp_state(kind, ny, nx, norm, h, lam, tau, sig,
+        # sigma <= 0 is passed through: the library takes sigma = 1/tau then
+        self.c = L.gp_state(kind, ny, nx, norm, h, lam, tau, sigma,
                             ctypes.c_void_p(f.data_ptr()),
                             ctypes.c_void_p(gpsi.data_ptr()) if gpsi is not None else None,
                             ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(p.data_ptr()),
@@ -224,6 +224,17 @@ class Context:
                                         _ptr(f, torch.float32, (ny, nx), "f"),
                                         _ptr(gpsi, torch.float32, (2, ny, nx), "gpsi"), ny, nx, float(h)))
         return f, gpsi
+
+    def rof_step_rule(self, I, h, lam, eps, norm=L.GP_NORM_ISO):
+        """Section 4.1 step rule on the device: dict with tv = ||I||_TV, grad_l2 = ||grad I||_L2,
+        tv_bound (section 3.1 bound on ||u*||_TV), tau = min(tau_continuum, grad_l2) and
+        tau_continuum = sqrt(lam) tv / sqrt(eps)."""
+        torch = _torch()
+        ny, nx = I.shape
+        out = L.gp_rof_rule()
+        self._check(self._lib.rof_step_rule(self._h, _ptr(I, torch.float32, (ny, nx), "I"), ny, nx, float(h),
+                                            float(lam), float(eps), int(norm), ctypes.byref(out)))
+        return out.as_dict()
 
     def make_state(self, kind, f, h, tau, sigma=0.0, lam=0.0, gpsi=None, u=None, p=None, pbar=None,
                    norm=L.GP_NORM_ISO):
@@ -385,6 +396,15 @@ class WarmStart:
                                         ctypes.byref(opts.c()), ctypes.byref(rep), ctypes.byref(wrep))
         self.ctx._check(rc, allow_notconv=True)
         return m, phi, rep.as_dict(), wrep.as_dict()
+
+
+def emd_step_rule_singular(eps: float, m: float) -> float:
+    """Section 4.2 step rule for singular measures, computed by the library:
+    min(sqrt(1 / (eps |ln eps|)), 2 m^(1/4)) for a grid of side m."""
+    t = L.load().emd_step_rule_singular(float(eps), float(m))
+    if t < 0:
+        raise ValueError("emd_step_rule_singular needs 0 < eps < 1 and m > 0")
+    return t
 
 
 def ws_downsample(ctx: Context, x, f: int):

@@ -736,7 +736,7 @@ Group state_group(gp_ctx* c, const gp_state* s) {
   g.h = s->h;
   g.lambda = s->lambda;
   g.tau = s->tau;
-  g.sigma = s->sigma;
+  g.sigma = s->sigma > 0 ? s->sigma : 1.0 / s->tau;  // sigma <= 0 selects 1/tau, as in gp_opts
   g.f = s->f;
   g.gpsi = s->gpsi;
   g.u = s->u;
@@ -814,7 +814,8 @@ int validate_state(gp_ctx* c, const gp_state* s) {
     set_err(c, "state kind must be GP_KIND_ROF or GP_KIND_EMD");
     return GP_EINVAL;
   }
-  if (!(s->tau > 0) || !(s->sigma > 0) || s->tau * s->sigma > 1.0 + 1e-12 ||
+  const double sig = s->sigma > 0 ? s->sigma : 1.0 / s->tau;
+  if (!(s->tau > 0) || !std::isfinite(s->tau) || !std::isfinite(sig) || s->tau * sig > 1.0 + 1e-12 ||
       (s->kind == GP_KIND_ROF && !(s->lambda > 0))) {
     set_err(c, "state steps invalid (tau, sigma > 0, tau*sigma <= 1, lambda > 0)");
     return GP_EINVAL;
@@ -1332,6 +1333,53 @@ int emd_setup(gp_ctx* c, const float* rho0, const float* rho1, float* f, float* 
   return GP_OK;
 }
 
+int rof_step_rule(gp_ctx* c, const float* I, int ny, int nx, double h, double lambda, double eps, int norm,
+                  gp_rof_rule* out) {
+  if (!c) return GP_EINVAL;
+  if (!I || !out) {
+    set_err(c, "NULL argument");
+    return GP_EINVAL;
+  }
+  RCHK(check_size(c, ny, nx, h));
+  if (!(lambda > 0) || !std::isfinite(lambda) || !(eps > 0) || !std::isfinite(eps)) {
+    set_err(c, "lambda and eps must be positive and finite");
+    return GP_EINVAL;
+  }
+  if (norm != GP_NORM_ISO && norm != GP_NORM_ANISO) {
+    set_err(c, "norm must be GP_NORM_ISO or GP_NORM_ANISO");
+    return GP_EINVAL;
+  }
+  const size_t n = size_t(ny) * nx;
+  double bad;
+  RCHK(count_nonfinite(c, I, n, &bad));
+  if (bad > 0) {
+    set_err(c, "image has %.0f non-finite values", bad);
+    return GP_EINVAL;
+  }
+  const int nb = red_blocks(n);
+  GP_LAUNCH(c, k_rule_sums, dim3(nb), dim3(256), 0, c->stream, I, ny, nx, 1.0 / h, norm, c->partials);
+  LAUNCHCHK(c);
+  double r[3];
+  RCHK(finalize_read(c, c->partials, nb, 1, 3, 0u, r));
+  // c->result still holds the three sums: the mean for the centred second moment
+  GP_LAUNCH(c, k_centered_sq, dim3(nb), dim3(256), 0, c->stream, I, n, c->result, 1.0 / double(n), c->partials);
+  LAUNCHCHK(c);
+  double v;
+  RCHK(finalize_read(c, c->partials, nb, 1, 1, 0u, &v));
+  const double h2 = h * h;
+  out->tv = h2 * r[0];
+  out->grad_l2 = sqrt(h2 * r[1]);
+  out->tv_bound = std::min(out->tv, 0.5 * lambda * h2 * v);
+  out->tau_continuum = sqrt(lambda) * out->tv / sqrt(eps);
+  out->tau = std::min(out->tau_continuum, out->grad_l2);
+  return GP_OK;
+}
+
+double emd_step_rule_singular(double eps, double m) {
+  if (!(eps > 0) || !(eps < 1) || !(m > 0)) return -1.0;
+  return std::min(sqrt(1.0 / (eps * fabs(log(eps)))), 2.0 * pow(m, 0.25));
+}
+
 int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* phi, int ny, int nx, double h,
               const gp_opts* o, gp_report* rep) {
   if (!c) return GP_EINVAL;
@@ -1495,6 +1543,10 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     set_err(c, "ergodic averages are not supported by the batch solver");
     return GP_EUNSUPPORTED;
   }
+  if (o->warm_start) {
+    set_err(c, "the batch solver starts every instance from zero (warm_start must be 0)");
+    return GP_EINVAL;
+  }
   // the chunk between checks has an even length, so the ping-pong buffers hold
   // the same roles at every check
   const int C = (o->check_every + 1) / 2 * 2;
@@ -1559,9 +1611,17 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     const size_t nt = g.ntot(), n = size_t(g.nyi) * g.nx;
     float* f = const_cast<float*>(g.f);
     if (g.kind == GP_KIND_ROF) {
-      for (int k = 0; k < g.m; ++k)
+      for (int k = 0; k < g.m; ++k) {
+        // a non-finite image is an argument error, as in rof_solve
+        double bad;
+        RCHK(count_nonfinite(c, inst[bg.idx[k]].in0, n, &bad));
+        if (bad > 0) {
+          set_err(c, "instance %d: image has %.0f non-finite values", bg.idx[k], bad);
+          return GP_EINVAL;
+        }
         HIPCHK(c, hipMemcpyAsync(f + k * n, inst[bg.idx[k]].in0, n * sizeof(float), hipMemcpyDeviceToDevice,
                                  c->stream));
+      }
       HIPCHK(c, hipMemsetAsync(g.u, 0, nt * sizeof(float), c->stream));
     } else {
       // per instance: FP64 mass check and potential, then scatter grad psi into the stack

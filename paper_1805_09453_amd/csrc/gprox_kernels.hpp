@@ -577,6 +577,42 @@ __global__ __launch_bounds__(256) void k_grad_f64(const double* __restrict__ psi
   }
 }
 
+// ------------------------------------------------------------ step-size rules
+// Partial sums for the ROF step rule of section 4.1 and the bound on ||u*||_TV of
+// section 3.1: [sum |grad I| (grid norm), sum |grad I|_2^2, sum I], the forward
+// differences formed in FP64 from the FP32 image (1/h units).
+__global__ __launch_bounds__(256) void k_rule_sums(const float* __restrict__ I, int ny, int nx, double inv_h,
+                                                   int aniso, double* __restrict__ partials) {
+  double acc[3] = {0, 0, 0};
+  const size_t n = size_t(ny) * nx;
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(o / nx), j = int(o - size_t(i) * nx);
+    const double c = I[o];
+    const double gx = (j < nx - 1) ? (double(I[o + 1]) - c) * inv_h : 0.0;
+    const double gy = (i < ny - 1) ? (double(I[o + nx]) - c) * inv_h : 0.0;
+    const double g2 = gx * gx + gy * gy;
+    acc[0] += aniso ? fabs(gx) + fabs(gy) : sqrt(g2);
+    acc[1] += g2;
+    acc[2] += c;
+  }
+  const bool m[3] = {false, false, false};
+  block_reduce_store<3>(acc, m, partials);
+}
+
+// [sum (I - mean)^2] with mean = sums[2] * inv_n (the finalised k_rule_sums)
+__global__ __launch_bounds__(256) void k_centered_sq(const float* __restrict__ I, size_t n,
+                                                     const double* __restrict__ sums, double inv_n,
+                                                     double* __restrict__ partials) {
+  const double mean = sums[2] * inv_n;
+  double acc[1] = {0};
+  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < n; o += size_t(gridDim.x) * blockDim.x) {
+    const double e = double(I[o]) - mean;
+    acc[0] += e * e;
+  }
+  const bool m[1] = {false};
+  block_reduce_store<1>(acc, m, partials);
+}
+
 // count of non-finite values (block partials)
 __global__ __launch_bounds__(256) void k_nonfinite(const float* __restrict__ x, size_t n,
                                                    double* __restrict__ partials) {

@@ -32,8 +32,6 @@ import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -43,22 +41,18 @@ import synth  # noqa: E402
 EMD_EXACT = 1.0 / math.sqrt(8.0)
 
 
-def rof_tau_rule(I, h, lam, eps, grid_independent=False):
-    """Section 4.1 step size in unit-square units: min(sqrt(lam) |I|_TV / sqrt(eps),
-    |grad I|_L2) (forward differences, zero on the far faces)."""
-    gx = np.zeros_like(I)
-    gy = np.zeros_like(I)
-    gx[:, :-1] = (I[:, 1:] - I[:, :-1]) / h
-    gy[:-1, :] = (I[1:, :] - I[:-1, :]) / h
-    mag = np.hypot(gx, gy)
-    tv = h * h * float(mag.sum())
-    l2 = math.sqrt(h * h * float((mag * mag).sum()))
-    a = math.sqrt(lam) * tv / math.sqrt(eps)
-    return a if grid_independent else min(a, l2)
+def rof_tau_rule(ctx, Id, h, lam, eps, grid_independent=False):
+    """Section 4.1 step size in unit-square units, computed by the library
+    (rof_step_rule): min(sqrt(lam) |I|_TV / sqrt(eps), |grad I|_L2), or the first
+    term alone for the grid-independent choice."""
+    r = ctx.rof_step_rule(Id, h, lam, eps)
+    return r["tau_continuum"] if grid_independent else r["tau"]
 
 
 def emd_delta_tau(eps, n):
-    return min(math.sqrt(1.0 / (eps * abs(math.log(eps)))), 2.0 * n ** 0.25)
+    """Section 4.2 rule for the Dirac pairs (library: emd_step_rule_singular), M = n."""
+    from .api import emd_step_rule_singular
+    return emd_step_rule_singular(eps, n)
 
 
 def _sync():
@@ -84,25 +78,29 @@ def rof_ground_truth(ctx, Id, n, lam):
     of 1e-6 (absolute gap ~1e-6 here, far below eps/10); cached per (n, lam)."""
     from . import Options
     if (n, lam) not in _FSTAR:
-        tau = rof_tau_rule(synth.disc_image(n, 0.25), 1.0 / n, lam, 1e-3)
+        tau = rof_tau_rule(ctx, Id, 1.0 / n, lam, 1e-3)
         _, _, ref = ctx.rof_solve(Id, 1.0 / n, lam, Options(tau=tau, tol=1e-6, max_iter=50000, check_every=50))
         _FSTAR[(n, lam)] = ref
     return _FSTAR[(n, lam)]
 
 
-def rof_case(ctx, n, lam, eps, grid_independent, max_iter):
+def rof_case(ctx, n, lam, eps, grid_independent, max_iter, ground_truth=None):
+    """Table 1-3 protocol at side n.  ground_truth: optional (F*, certified gap) from
+    elsewhere (the tests pass the FP64 oracle's); by default a long library solve."""
     import torch
 
     from . import Options
     from ._lib import GP_KIND_ROF
     h = 1.0 / n
     I = synth.disc_image(n, 0.25)
-    tau = rof_tau_rule(I, h, lam, eps, grid_independent)
     Id = torch.tensor(I, dtype=torch.float32, device="cuda")
-    ref = rof_ground_truth(ctx, Id, n, lam)
-    fstar = ref["primal"]
-    certified = (ref["primal"] - ref["dual"]) <= 0.1 * eps
-    st = ctx.make_state(GP_KIND_ROF, Id, h, tau, sigma=1.0 / tau, lam=lam)
+    tau = rof_tau_rule(ctx, Id, h, lam, eps, grid_independent)
+    if ground_truth is None:
+        ref = rof_ground_truth(ctx, Id, n, lam)
+        ground_truth = (ref["primal"], ref["primal"] - ref["dual"])
+    fstar, fgap = ground_truth
+    certified = fgap <= 0.1 * eps
+    st = ctx.make_state(GP_KIND_ROF, Id, h, tau, lam=lam)  # sigma = 1/tau
     it = count_to_eps(ctx, st, fstar, eps, max_iter)
     secs = None
     if it:
@@ -112,8 +110,7 @@ def rof_case(ctx, n, lam, eps, grid_independent, max_iter):
         _sync()
         secs = time.perf_counter() - t0
     return {"n": n, "lambda": lam, "eps": eps, "tau": tau, "grid_independent_tau": grid_independent,
-            "fstar": fstar, "fstar_gap": ref["primal"] - ref["dual"], "fstar_certified": bool(certified),
-            "iters": it, "seconds": secs}
+            "fstar": fstar, "fstar_gap": fgap, "fstar_certified": bool(certified), "iters": it, "seconds": secs}
 
 
 def emd_ground_truth(ctx, R0, R1, n, kind):
@@ -128,7 +125,9 @@ def emd_ground_truth(ctx, R0, R1, n, kind):
     return _FSTAR[(n, kind)]
 
 
-def emd_case(ctx, n, kind, eps, tau, max_iter):
+def emd_case(ctx, n, kind, eps, tau, max_iter, ground_truth=None):
+    """Table 6-8 protocol at side n (kind "discs" or "deltas").  ground_truth:
+    optional (F*, certified gap) from elsewhere; by default a long library solve."""
     import torch
 
     from . import Options
@@ -137,11 +136,13 @@ def emd_case(ctx, n, kind, eps, tau, max_iter):
     r0, r1 = synth.uniform_disc_pair(n) if kind == "discs" else synth.delta_pair(n)
     R0 = torch.tensor(r0, dtype=torch.float32, device="cuda")
     R1 = torch.tensor(r1, dtype=torch.float32, device="cuda")
-    ref = emd_ground_truth(ctx, R0, R1, n, kind)  # (also tunes the launch shapes outside the timings)
-    fstar = ref["primal"]
-    certified = (ref["primal"] - ref["dual"]) <= 0.1 * eps
+    if ground_truth is None:
+        ref = emd_ground_truth(ctx, R0, R1, n, kind)  # (also tunes the launch shapes outside the timings)
+        ground_truth = (ref["primal"], ref["primal"] - ref["dual"])
+    fstar, fgap = ground_truth
+    certified = fgap <= 0.1 * eps
     f, gpsi = ctx.emd_setup(R0, R1, h)
-    st = ctx.make_state(GP_KIND_EMD, f, h, tau, sigma=1.0 / tau, gpsi=gpsi)
+    st = ctx.make_state(GP_KIND_EMD, f, h, tau, gpsi=gpsi)  # sigma = 1/tau
     it = count_to_eps(ctx, st, fstar, eps, max_iter)
     secs = None
     if it:
@@ -150,7 +151,7 @@ def emd_case(ctx, n, kind, eps, tau, max_iter):
         ctx.emd_solve(R0, R1, h, Options(tau=tau, tol=0.0, max_iter=it, check_every=it), want_phi=False)
         _sync()
         secs = time.perf_counter() - t0
-    return {"n": n, "pair": kind, "eps": eps, "tau": tau, "fstar": fstar, "fstar_gap": ref["primal"] - ref["dual"],
+    return {"n": n, "pair": kind, "eps": eps, "tau": tau, "fstar": fstar, "fstar_gap": fgap,
             "fstar_certified": bool(certified), "fstar_minus_continuum": fstar - EMD_EXACT, "iters": it,
             "seconds": secs}
 

@@ -33,3 +33,18 @@ def gpctx():
 def announce(msg):
     """Name the case before a GPU step (flushed, so a crash log still shows it)."""
     print(f"\n[gpu case] {msg}", flush=True)
+
+
+def field_err(a, b):
+    """Error of a field a against a reference b: the larger of the relative L2 error
+    ||a - b|| / ||b|| and the elementwise error max|a - b| / max|b|, so that an error
+    confined to a few cells (one halo row, a tile or strip edge) is not diluted by
+    the rest of the field."""
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    l2 = np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    mb = np.abs(b).max() if b.size else 0.0
+    mx = np.abs(a - b).max() / (mb if mb > 0 else 1.0) if b.size else 0.0
+    return float(max(l2, mx))

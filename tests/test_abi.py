@@ -104,3 +104,16 @@ def test_product_path_is_independent_of_the_oracle():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "[]"
+
+
+def test_singular_emd_rule_is_the_oracles(lib):
+    """Host arithmetic of emd_step_rule_singular (section 4.2) against the pinned
+    oracle helper, and its argument checks."""
+    from oracle import emd
+    for eps in (1e-2, 1e-3, 1e-4, 0.5):
+        for m in (16, 128, 512, 4096):
+            assert lib.emd_step_rule_singular(eps, m) == pytest.approx(emd.step_rule_tau_singular(eps, m),
+                                                                       rel=1e-14)
+    for eps, m in ((0.0, 64), (1.0, 64), (-1e-3, 64), (1e-3, 0.0)):
+        assert lib.emd_step_rule_singular(eps, m) == -1.0
+    assert lib.rof_step_rule(None, None, 64, 64, 1.0, 8.0, 1e-3, 0, None) == -1

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from conftest import announce
+from conftest import announce, field_err
 from oracle import grid3 as g3
 
 pytestmark = pytest.mark.gpu
@@ -27,8 +27,8 @@ def host(t):
 
 
 def rel(a, b):
-    nb = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+    """relative L2 and elementwise (relative to max|b|) error, the larger"""
+    return field_err(a, b)
 
 
 @pytest.mark.parametrize("shape,h,alpha", [((64, 64, 64), 1 / 64, 0.5), ((64, 128, 256), 1.0, 0.0),

@@ -117,6 +117,20 @@ def test_batch_max_iter_and_errors(gpctx):
     announce("gp_batch_solve max_iter 20")
     outs, reps, rc = gpctx.batch_solve(probs, Options(tau=0.01, tol=0.0, max_iter=20, check_every=10))
     assert rc == GP_ENOTCONV and all(r["iters"] == 20 and not r["converged"] for r in reps)
+    # an odd check_every: chunks of C = 6 iterations, the first check at or after max_iter = 20 is 24
+    announce("gp_batch_solve max_iter 20, check_every 5")
+    outs, reps, rc = gpctx.batch_solve(probs, Options(tau=0.01, tol=0.0, max_iter=20, check_every=5))
+    assert rc == GP_ENOTCONV and all(r["iters"] == 24 and not r["converged"] for r in reps)
+    # the batch starts from zero: a warm start is refused, and so is a non-finite image
+    from paper_1805_09453_amd._lib import GP_EINVAL
+    with pytest.raises(GPError) as e:
+        gpctx.batch_solve(probs, Options(tau=0.01, warm_start=True))
+    assert e.value.code == GP_EINVAL
+    nan = rof_problem(64, 4, 8.0, 0.01)
+    nan["I"][7, 9] = float("nan")
+    with pytest.raises(GPError) as e:
+        gpctx.batch_solve([probs[0], nan], Options(tau=0.01))
+    assert e.value.code == GP_EINVAL and "instance 1" in str(e.value)
     bad = emd_problem(64, 3, 0.3)
     bad["rho1"] = bad["rho1"] * 1.01
     announce("gp_batch_solve mass mismatch")

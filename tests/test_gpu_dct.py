@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from conftest import announce
+from conftest import announce, field_err
 from oracle import grid
 
 pytestmark = pytest.mark.gpu
@@ -21,7 +21,8 @@ def smooth_field(ny, nx, seed, noise=1e-3):
 
 
 def rel_l2(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    """relative L2 and elementwise (relative to max|b|) error, the larger"""
+    return field_err(a, b)
 
 
 CASES = [

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from conftest import announce
+from conftest import announce, field_err
 from oracle import emd as oemd
 from oracle import grid
 from oracle import rof as orof
@@ -27,8 +27,8 @@ def host(t):
 
 
 def rel(a, b):
-    nb = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+    """relative L2 and elementwise (relative to max|b|) error, the larger"""
+    return field_err(a, b)
 
 
 def emd_state(n_y, n_x, seed, tau, norm, steps=4):

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from conftest import announce
+from conftest import announce, field_err
 from oracle import emd as oemd
 from oracle import rof as orof
 
@@ -29,8 +29,8 @@ def host(t):
 
 
 def rel(a, b):
-    nb = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+    """relative L2 and elementwise (relative to max|b|) error, the larger"""
+    return field_err(a, b)
 
 
 @pytest.mark.parametrize("n,lam,tau,iters", [(256, 8.0, 0.02, 37), (512, 20.0, 0.05, 25)])

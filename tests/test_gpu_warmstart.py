@@ -8,10 +8,11 @@ import numpy as np
 import pytest
 
 import synth
-from conftest import announce
+from conftest import announce, field_err
 from oracle import unet
 
 pytestmark = pytest.mark.gpu
+GOLDEN_REFS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_references.json")
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_09453_amd",
                        "weights", "ws_unet.f32")
 
@@ -48,7 +49,8 @@ def bf16_round(a):
 
 
 def rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+    """relative L2 and elementwise (relative to max|b|) error, the larger"""
+    return field_err(a, b)
 
 
 def params(seed):
@@ -241,3 +243,109 @@ def test_trained_network_gain_on_held_out_pairs(gpctx):
     w.close()
     print("total iterations plain", tot_p, "warm", tot_w)
     assert tot_w < tot_p
+
+
+# ---------------------------------------------------------------- warm starts against the FP64 oracle
+def smooth_potential(n, seed):
+    """A smooth seeded potential in unit-square units (slope of order one)."""
+    rng = np.random.default_rng(seed)
+    X, Y = synth.cell_centres(n, n)
+    phi = np.zeros((n, n))
+    for _ in range(4):
+        a, b, c, w = rng.uniform(1, 4), rng.uniform(1, 4), rng.uniform(0, 6), rng.uniform(-0.3, 0.3)
+        phi += w * np.sin(a * X + c) * np.cos(b * Y - c)
+    return np.asarray(phi, np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("n, sigma_tau, norm", [(128, 1.0, 0), (256, 1.0, 0), (128, 0.5, 0), (128, 1.0, 1)])
+def test_emd_warm_start_matches_oracle(gpctx, n, sigma_tau, norm):
+    """emd_solve from a caller's potential phi0 (p0 = proj(grad phi0), u0 = 0):
+    sigma tau = 1 runs the single-variable form (y0 = p0), 1/2 the two-variable
+    form; both against the oracle's solve(phi0=...) for the same iterations."""
+    from oracle import emd as oemd
+    from oracle import grid
+    from paper_1805_09453_amd import Options
+    K, h, tau = 8, 1.0 / n, 0.3
+    r0, r1 = (np.asarray(a, np.float32).astype(np.float64) for a in synth.emd_mixture_pair(n, 41, k=5))
+    phi0 = smooth_potential(n, n + 3)
+    announce(f"emd_solve warm start {n}x{n} sigma tau = {sigma_tau} norm {norm}")
+    m, phi, rep = gpctx.emd_solve(dev(r0), dev(r1), h, Options(tau=tau, sigma=sigma_tau / tau, tol=0.0, max_iter=K,
+                                                               check_every=K, warm_start=True, norm=norm),
+                                  phi=dev(phi0))
+    ref = oemd.solve(r0, r1, h, tau=tau, sigma=sigma_tau / tau, tol=0.0, max_iter=K, check_every=K, phi0=phi0,
+                     norm=norm)
+    D, L, phit = oemd.certificate(ref.px, ref.py, ref.f, h, norm)
+    mg = host(m)
+    errs = [rel(mg[0], ref.m[0]), rel(mg[1], ref.m[1]), rel(host(phi), phit)]
+    print(["%.2e" % e for e in errs], rep["primal"], ref.primal, rep["dual"], D)
+    assert rep["iters"] == K
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - ref.primal) <= 1e-6 * ref.primal and abs(rep["dual"] - D) <= 2e-6 * ref.primal
+    # the zero start differs: the warm start reached the kernels
+    ref0 = oemd.solve(r0, r1, h, tau=tau, sigma=sigma_tau / tau, tol=0.0, max_iter=K, check_every=K, norm=norm)
+    assert rel(ref0.m[0], ref.m[0]) > 1e2 * max(errs[0], 1e-9)
+    del grid
+
+
+@pytest.mark.parametrize("n, norm", [(128, 0), (256, 1)])
+def test_rof_warm_start_matches_oracle(gpctx, n, norm):
+    """rof_solve from the caller's (u0, p0) against the oracle's solve(u0=, p0=)."""
+    from oracle import grid
+    from oracle import rof as orof
+    from paper_1805_09453_amd import Options
+    K, h, lam, tau = 10, 1.0, 8.0, 0.02
+    I = np.asarray(synth.rof_scene(n, 55), np.float32).astype(np.float64)
+    rng = np.random.default_rng(n)
+    u0 = np.asarray(I + 0.05 * rng.standard_normal(I.shape), np.float32).astype(np.float64)
+    px0, py0 = grid.project_unit_ball(*(0.7 * rng.standard_normal((2,) + I.shape)), norm)
+    px0[:, -1] = 0.0
+    py0[-1, :] = 0.0  # no flux through the far faces
+    px0, py0 = (np.asarray(a, np.float32).astype(np.float64) for a in (px0, py0))
+    announce(f"rof_solve warm start {n}x{n} norm {norm}")
+    u, p, rep = gpctx.rof_solve(dev(I), h, lam, Options(tau=tau, tol=0.0, max_iter=K, check_every=K, warm_start=True,
+                                                        norm=norm),
+                                u=dev(u0), p=dev(np.stack([px0, py0])))
+    ref = orof.solve(I, h, lam, tau, tol=0.0, max_iter=K, check_every=K, u0=u0, p0=(px0, py0), norm=norm)
+    pg = host(p)
+    errs = [rel(host(u), ref.u), rel(pg[0], ref.px), rel(pg[1], ref.py)]
+    print(["%.2e" % e for e in errs], rep["primal"], ref.primal, rep["dual"], ref.dual)
+    assert rep["iters"] == K
+    assert max(errs) <= 1e-5
+    assert abs(rep["primal"] - ref.primal) <= 1e-6 * abs(ref.primal)
+    assert abs(rep["dual"] - ref.dual) <= 1e-6 * abs(ref.primal)
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
+def test_learned_start_converges_to_the_oracle_optimum(gpctx):
+    """ws_emd_solve with the committed network on a held-out 512^2 pair, run to a
+    1e-5 gap: the FP64 value of its re-projected flux lies within 1e-5 of the
+    oracle's certified optimum (a long oracle solve of the same pair from the zero
+    start), and its certificate lies below the oracle's primal value."""
+    import json
+
+    import torch
+    from oracle import emd as oemd
+    from paper_1805_09453_amd import Options, WarmStart
+    n, h = 512, 1.0 / 512
+    with open(GOLDEN_REFS) as fh:
+        ref = json.load(fh)["emd_ws_512"]
+    with open(WEIGHTS.replace(".f32", ".json")) as fh:
+        native = json.load(fh)["native"]
+    w = WarmStart(gpctx, 1, native, native)
+    w.set_params(torch.tensor(np.fromfile(WEIGHTS, dtype=np.float32), device="cuda"))
+    s = ref["held_out"]
+    k = int(np.random.default_rng(synth.config_seed(4, 900_000 + s)).integers(4, 17))
+    r0, r1 = (np.asarray(a, np.float32).astype(np.float64)
+              for a in synth.emd_mixture_pair(n, synth.config_seed(4, 900_000 + s), k=k))
+    announce(f"ws_emd_solve 512x512 held-out pair {s} vs oracle optimum")
+    m, _, rep, wrep = w.emd_solve(dev(r0), dev(r1), h, Options(tau=0.3, tol=1e-5, max_iter=40000, check_every=20))
+    w.close()
+    f_ref, _ = oemd.setup(r0, r1, h)
+    val, resid = oemd.flux_value(host(m)[0], host(m)[1], f_ref, h)
+    print(rep, wrep, val, ref["primal"], ref["dual"], resid)
+    assert rep["converged"] and wrep["used_warm"] == 1
+    # oracle bracket [D_o, P_o] of F*: the GPU flux is feasible (val >= F* >= D_o) and within
+    # its own 1e-5 gap of F* <= P_o; the GPU certificate is a lower bound (<= F* <= P_o)
+    assert ref["dual"] <= val * (1 + 1e-6)
+    assert val <= ref["primal"] * (1 + 1e-5)
+    assert rep["dual"] <= ref["primal"] * (1 + 1e-6)
