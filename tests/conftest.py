@@ -35,11 +35,25 @@ def announce(msg):
     print(f"\n[gpu case] {msg}", flush=True)
 
 
+# Elementwise allowance relative to the L2 gate.  One dual step multiplies the
+# FP32 rounding of u by sigma/h (100 at the benchmark's tau = 0.01, h = 1).  At
+# the 4096^2 benchmark scene after two iterations, a plain FP32 NumPy/SciPy
+# evaluation of the same updates differs from FP64 by 3.2e-5 of max|p| at its
+# worst cell (4.6e-6 in L2) and the library by 6.5e-5 (5.7e-6 in L2; its u is
+# off by at most 8.3e-7 of max|u|, the twiddles of its FFTs carrying up to
+# three roundings).  A halo or strip-edge mistake shows as an error of the size
+# of the field's own differences in the affected cells (1e-2 and more), far
+# above this allowance.
+ELEMENTWISE_FACTOR = 10.0
+
+
 def field_err(a, b):
     """Error of a field a against a reference b: the larger of the relative L2 error
-    ||a - b|| / ||b|| and the elementwise error max|a - b| / max|b|, so that an error
-    confined to a few cells (one halo row, a tile or strip edge) is not diluted by
-    the rest of the field."""
+    ||a - b|| / ||b|| and the elementwise error max|a - b| / max|b| divided by
+    ELEMENTWISE_FACTOR, so that `field_err <= tol` bounds both the L2 error (tol)
+    and every cell (ELEMENTWISE_FACTOR * tol of the field's maximum), and an error
+    confined to a few cells (one halo row, a tile or strip edge) is not diluted
+    by the rest of the field."""
     import numpy as np
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -47,4 +61,4 @@ def field_err(a, b):
     l2 = np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
     mb = np.abs(b).max() if b.size else 0.0
     mx = np.abs(a - b).max() / (mb if mb > 0 else 1.0) if b.size else 0.0
-    return float(max(l2, mx))
+    return float(max(l2, mx / ELEMENTWISE_FACTOR))
