@@ -112,7 +112,7 @@ typedef struct {
 int gp_create(gp_ctx** ctx, int max_ny, int max_nx, void* stream);
 int gp_destroy(gp_ctx* ctx);
 const char* gp_strerror(int code);
-const char* gp_last_error(const gp_ctx* ctx);
+const char* gp_last_error(const gp_ctx* ctx); /* ctx NULL: see dct_poisson_noalloc */
 
 /* Screened Poisson solve (alpha I - Delta) x = b with Neumann boundary (the
  * linear solve of the ROF u-update, section 3.1, with alpha = lambda tau; the
@@ -122,6 +122,24 @@ const char* gp_last_error(const gp_ctx* ctx);
 int dct_poisson(gp_ctx* ctx, const float* b, float* x, int ny, int nx, double h, double alpha);
 /* The same in FP64 (used for the EMD set-up potential). */
 int dct_poisson_f64(gp_ctx* ctx, const double* b, double* x, int ny, int nx, double h, double alpha);
+
+/* dct_poisson for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  No
+ * context: the work is enqueued on `stream` (NULL = the null stream of the
+ * current device) and the call never synchronises and never allocates (no
+ * hipMalloc, hipFree, memset or host-to-device copy).  Its workspace is one
+ * file-scope device array of about 4.4 MB that each GPU the library runs on
+ * holds until the process ends (its address is looked up once per device).
+ * Limits: sides powers of two in [64, 4096] with ny * nx <= 2^20 (1024 x 1024,
+ * 512 x 2048, 256 x 4096, ...); larger grids return GP_EUNSUPPORTED.  The
+ * solve, the arguments and the other errors are those of dct_poisson (launch
+ * shapes are the defaults, not tuned ones); gp_last_error(NULL) gives the
+ * message of the last failed call of this kind on the calling thread.  Calls
+ * on one GPU share the workspace: calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller; each call rewrites every table it reads, so no state carries
+ * over from an earlier call. */
+int dct_poisson_noalloc(const float* b, float* x, int ny, int nx, double h, double alpha, void* stream);
 
 /* ROF denoising of I (section 3.1 updates of Algorithm 2).  u: out (and in
  * when opts->warm_start) [ny][nx]; p: nullable [2][ny][nx] dual out (and in

@@ -10,6 +10,7 @@ from .api import (  # noqa: F401
     Context,
     Options,
     WarmStart,
+    dct_poisson_noalloc,
     emd_step_rule_singular,
     lib_path,
     ws_downsample,

@@ -65,6 +65,7 @@ _SIGS = {
     "gp_last_error": (ctypes.c_char_p, [c_void_p]),
     "dct_poisson": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_double, c_double]),
     "dct_poisson_f64": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_double, c_double]),
+    "dct_poisson_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_int, c_double, c_double, c_void_p]),
     "rof_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double, c_double,
                           ctypes.POINTER(gp_opts), ctypes.POINTER(gp_report)]),
     "emd_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double,

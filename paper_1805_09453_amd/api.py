@@ -398,6 +398,24 @@ class WarmStart:
         return m, phi, rep.as_dict(), wrep.as_dict()
 
 
+def dct_poisson_noalloc(b, x=None, h=1.0, alpha=0.0, stream=None):
+    """(alpha I - Delta) x = b without a context and without device allocation in
+    the library (its workspace is a fixed device array; ny * nx <= 2^20).  x may
+    be b (in place) or a caller tensor; a new tensor is allocated here only when
+    x is None.  Enqueued on `stream` (default: torch's current stream)."""
+    torch = _torch()
+    lib = L.load()
+    ny, nx = b.shape
+    if x is None:
+        x = torch.empty_like(b)
+    st = torch.cuda.current_stream() if stream is None else stream
+    rc = lib.dct_poisson_noalloc(_ptr(b, torch.float32, (ny, nx), "b"), _ptr(x, torch.float32, (ny, nx), "x"), ny,
+                                 nx, float(h), float(alpha), ctypes.c_void_p(st.cuda_stream))
+    if rc != L.GP_OK:
+        raise GPError(rc, f"{lib.gp_strerror(rc).decode()}: {lib.gp_last_error(None).decode()}")
+    return x
+
+
 def emd_step_rule_singular(eps: float, m: float) -> float:
     """Section 4.2 step rule for singular measures, computed by the library:
     min(sqrt(1 / (eps |ln eps|)), 2 m^(1/4)) for a grid of side m."""

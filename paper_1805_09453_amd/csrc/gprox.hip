@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -1031,6 +1032,118 @@ void carve(Carver& A, BatchGroup& bg) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free Poisson solve
+// dct_poisson_noalloc works without a context and allocates nothing: its
+// workspace is the file-scope device array `scratch` below.  In host code the
+// array's name is not a device address; the address of each device's copy is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and only that address is handed to kernels.
+//   layout (bytes):  [0, kNaTiles)              tiled row-transformed field, <= kNaMaxCells floats
+//                    then per axis (x, y):      Stockham twiddles (float2), DCT twiddles (float2, N),
+//                                               eigenvalues of -Delta (FP64 and FP32, N each)
+constexpr size_t kNaMaxCells = size_t(1) << 20;  // ny * nx <= 2^20 (1024 x 1024, 256 x 4096, ...)
+constexpr size_t kNaTiles = kNaMaxCells * sizeof(float);
+constexpr size_t kNaAxisTw = 4096;               // float2 slots >= Sched<N>::total_tw() for every N
+constexpr size_t kNaAxisBytes = kNaAxisTw * sizeof(float2) + size_t(kMaxN) * (sizeof(float2) + sizeof(double) +
+                                                                                 sizeof(float));
+constexpr size_t kNaBytes = kNaTiles + 2 * kNaAxisBytes;
+constexpr int kNaMaxDevices = 64;
+static_assert(Sched<4096>::total_tw() <= int(kNaAxisTw) && Sched<512>::total_tw() <= int(kNaAxisTw),
+              "twiddle slots");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+std::mutex g_na_mutex;
+void* g_na_ptr[kNaMaxDevices] = {};      // device address of `scratch` per device
+thread_local char g_na_err[256] = "";   // message of the last failed context-free call
+
+int na_fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_na_err, sizeof(g_na_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+// Stockham twiddles (as build_tables: per direction and pass, W_{LS R}^j for j < LS,
+// then W_{LS R}^{4j}; the inverse passes hold the conjugates) and the DCT twiddles
+// exp(-i pi k / 2N), from FP64 sincospi on the device, rounded to FP32
+template <int N> __global__ __launch_bounds__(256) void k_na_tables(float2* __restrict__ tw, float2* __restrict__ dw) {
+  using S = Sched<N>;
+  const int stride = int(gridDim.x * blockDim.x);
+  for (int k = int(blockIdx.x * blockDim.x + threadIdx.x); k < N; k += stride) {
+    double sn, cs;
+    sincospi(-double(k) / (2.0 * N), &sn, &cs);
+    dw[k] = make_float2(float(cs), float(sn));
+  }
+  for (int e = int(blockIdx.x * blockDim.x + threadIdx.x); e < S::total_tw(); e += stride) {
+    const int dir = e >= S::tsize() ? 1 : 0;
+    int p = 0;
+    while (p + 1 < S::NP && e >= (dir ? S::itoff(p + 1) : S::toff(p + 1))) ++p;
+    const int R = dir ? S::irad(p) : S::rad(p), LS = dir ? S::ils(p) : S::ls(p);
+    const int r = e - (dir ? S::itoff(p) : S::toff(p));  // in [0, 2 LS)
+    const int j = r < LS ? r : r - LS;
+    const int num = r < LS ? j : (4 * j) % (LS * R);
+    double sn, cs;
+    sincospi((dir ? 2.0 : -2.0) * double(num) / double(LS * R), &sn, &cs);
+    tw[e] = make_float2(float(cs), float(sn));
+  }
+}
+
+struct NaAxis {
+  float2* tw;
+  float2* dw;
+  double* mu64;
+  float* mu32;
+};
+NaAxis na_axis(unsigned char* base, int which) {
+  unsigned char* a = base + kNaTiles + size_t(which) * kNaAxisBytes;
+  NaAxis x;
+  x.tw = reinterpret_cast<float2*>(a);
+  x.dw = reinterpret_cast<float2*>(a + kNaAxisTw * sizeof(float2));
+  x.mu64 = reinterpret_cast<double*>(a + kNaAxisTw * sizeof(float2) + kMaxN * sizeof(float2));
+  x.mu32 = reinterpret_cast<float*>(a + kNaAxisTw * sizeof(float2) + kMaxN * (sizeof(float2) + sizeof(double)));
+  return x;
+}
+
+// launches of the three passes with the default launch shapes (no tuner state)
+template <int N> struct NaPass {
+  static void tables(const NaAxis& a, int n, double h, hipStream_t st) {
+    hipLaunchKernelGGL((k_na_tables<N>), dim3((N + 255) / 256), dim3(256), 0, st, a.tw, a.dw);
+    hipLaunchKernelGGL(k_mu, dim3((n + 255) / 256), dim3(256), 0, st, a.mu64, a.mu32, n, h);
+  }
+  static void rows_fwd(const NaAxis& a, const float* in, float* out, int ny, int lgtw, hipStream_t st) {
+    using SH = RowShape<N, float2>;
+    hipLaunchKernelGGL((k_rows_fwd<N, float2>), dim3((ny / 2 + SH::G - 1) / SH::G), dim3(SH::THREADS),
+                       SH::LDS_BYTES, st, in, out, ny, ny, nullptr, lgtw, a.tw, a.dw);
+  }
+  static void rows_inv(const NaAxis& a, const float* in, float* out, int ny, int lgtw, hipStream_t st) {
+    using SH = RowShape<N, float2>;
+    hipLaunchKernelGGL((k_rows_inv<N, float2>), dim3((ny / 2 + SH::G - 1) / SH::G), dim3(SH::THREADS),
+                       SH::LDS_BYTES, st, in, out, ny, ny, nullptr, lgtw, a.tw, a.dw);
+  }
+  // here N is the column length ny; G column pairs per block (2G <= nx)
+  static void cols(const NaAxis& ay, const NaAxis& ax, float* buf, int nx, int G, int lgtw, float alpha,
+                   float inv_nn, hipStream_t st) {
+    hipLaunchKernelGGL((k_cols_solve<N, float2>), dim3((nx / 2 + G - 1) / G, 1), dim3(G * Sched<N>::T),
+                       (size_t(G) * ColShape<N, float2>::GROUP_LDS), st, buf, nx, nullptr, ay.tw, ay.dw, ax.mu32,
+                       ay.mu32, alpha, inv_nn, lgtw);
+  }
+};
+template <int N> using NaP = NaPass<N>;
+int na_col_groups(int ny) {
+  switch (ny) {
+#define GP_NA_G(NN) case NN: return ColShape<NN, float2>::G;
+    GP_NA_G(64) GP_NA_G(128) GP_NA_G(256) GP_NA_G(512) GP_NA_G(1024) GP_NA_G(2048) GP_NA_G(4096)
+#undef GP_NA_G
+  }
+  return 1;
+}
+
+}  // namespace
+
 // ======================================================================== C ABI
 extern "C" {
 
@@ -1047,7 +1160,7 @@ const char* gp_strerror(int code) {
   return "unknown error code";
 }
 
-const char* gp_last_error(const gp_ctx* ctx) { return ctx ? ctx->err : "no context"; }
+const char* gp_last_error(const gp_ctx* ctx) { return ctx ? ctx->err : g_na_err; }
 
 int gp_create(gp_ctx** out, int max_ny, int max_nx, void* stream) {
   if (!out) return GP_EINVAL;
@@ -1128,6 +1241,49 @@ int dct_poisson(gp_ctx* c, const float* b, float* x, int ny, int nx, double h, d
   }
   RCHK(prepare(c, ny, nx, h));
   return poisson_f32(c, b, x, ny, nx, 1, c->mux32, c->muy32, alpha, c->work);
+}
+
+int dct_poisson_noalloc(const float* b, float* x, int ny, int nx, double h, double alpha, void* stream) {
+  if (!b || !x) return na_fail(GP_EINVAL, "NULL buffer");
+  if (!is_pow2_in_range(ny) || !is_pow2_in_range(nx))
+    return na_fail(GP_EUNSUPPORTED, "grid %dx%d unsupported: sides must be powers of two in [%d, %d]", ny, nx,
+                   kMinN, kMaxN);
+  if (size_t(ny) * size_t(nx) > kNaMaxCells)
+    return na_fail(GP_EUNSUPPORTED, "grid %dx%d has %zu cells; dct_poisson_noalloc takes at most %zu", ny, nx,
+                   size_t(ny) * size_t(nx), kNaMaxCells);
+  if (!(h > 0.0) || !std::isfinite(h)) return na_fail(GP_EINVAL, "h must be positive and finite");
+  if (!(alpha >= 0) || !std::isfinite(alpha)) return na_fail(GP_EINVAL, "alpha must be >= 0 and finite");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNaMaxDevices)
+    return na_fail(GP_EHIP, "no current HIP device (or more than %d devices)", kNaMaxDevices);
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_na_mutex);
+    if (!g_na_ptr[dev]) {
+      // this device's copy of the scratch array; the current device is `dev`
+      const hipError_t e = hipGetSymbolAddress(&g_na_ptr[dev], HIP_SYMBOL(scratch));
+      if (e != hipSuccess) {
+        g_na_ptr[dev] = nullptr;
+        return na_fail(GP_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      }
+    }
+    base = g_na_ptr[dev];
+  }
+  unsigned char* sb = static_cast<unsigned char*>(base);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const NaAxis ax = na_axis(sb, 0), ay = na_axis(sb, 1);
+  float* tmp = reinterpret_cast<float*>(sb);
+  // every table is rewritten by this call (no state survives from an earlier one)
+  GP_DISPATCH_NM(nx, NaP, tables, ax, nx, h, st);
+  GP_DISPATCH_NM(ny, NaP, tables, ay, ny, h, st);
+  const int Gc = std::min(na_col_groups(ny), nx / 2);
+  const int lgtw = std::max(ilog2i(2 * Gc), std::min(kTileLgDefault[0], ilog2i(nx)));
+  GP_DISPATCH_NM(nx, NaP, rows_fwd, ax, b, tmp, ny, lgtw, st);
+  GP_DISPATCH_NM(ny, NaP, cols, ay, ax, tmp, nx, Gc, lgtw, float(alpha), float(1.0 / (double(nx) * ny)), st);
+  GP_DISPATCH_NM(nx, NaP, rows_inv, ax, tmp, x, ny, lgtw, st);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return na_fail(GP_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return GP_OK;
 }
 
 int dct_poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, double h, double alpha) {
