@@ -24,8 +24,13 @@
  * its context, sized at gp_create for grids up to max_ny x max_nx (solve
  * calls may grow it; pd_step and pd_gap never allocate).
  *
- * Sizes.  ny and nx must be powers of two in [64, 4096] and at most the
- * context's maxima; other sizes return GP_EUNSUPPORTED.
+ * Sizes.  ny and nx must lie in [64, 4096] with no prime factor above 7
+ * (7-smooth: 64, 72, 75, 80, 81, 84, 90, 96, ... 720, ... 4096) and at most the
+ * context's maxima; other sizes return GP_EUNSUPPORTED.  Powers of two run the
+ * fused register-resident transforms; other sides run the same iteration
+ * unfused, with mixed-radix (2, 3, 4, 5, 7, 8) DCTs out of LDS and transposes
+ * for the column pass (gp_opts.ergodic, the 3-D calls, dct_poisson_noalloc,
+ * the launch-shape calls and the learned warm start need powers of two).
  *
  * Errors.  Every entry point returns GP_OK (0), a negative GP_E* code, or
  * GP_ENOTCONV (> 0: max_iter reached, outputs valid, report filled).  No C++

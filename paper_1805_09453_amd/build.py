@@ -8,7 +8,8 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libgprox.so")
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("gprox.hip", "ws_unet.hip")]
 DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp",
-                                                         "gprox3d.inc", "gprox3d_kernels.hpp", "ws_unet.hpp")] + [os.path.join(ROOT, "include", "gprox.h")]
+                                                         "gprox3d.inc", "gprox3d_kernels.hpp", "ws_unet.hpp",
+                                                         "gprox_generic.hpp", "gprox_generic.inc")] + [os.path.join(ROOT, "include", "gprox.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -24,6 +24,7 @@
 
 #include "../../include/gprox.h"
 #include "gprox_fused.hpp"
+#include "gprox_generic.hpp"
 #include "gprox_kernels.hpp"
 #include "ws_unet.hpp"
 
@@ -43,6 +44,11 @@ constexpr int kSideStreams = 8;   // parallel branches of the batch graph
 
 bool is_pow2_in_range(int n) { return n >= kMinN && n <= kMaxN && (n & (n - 1)) == 0; }
 int ilog2i(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
+
+struct GenTab {  // per length n of the non-power-of-two path: W_n^m and exp(-i pi m / 2n)
+  float2 *w32 = nullptr, *d32 = nullptr;
+  double2 *w64 = nullptr, *d64 = nullptr;
+};
 
 struct Tables {  // per transform length N
   float2* tw32 = nullptr;
@@ -85,6 +91,10 @@ struct gp_ctx {
   // warm-start scratch (grow-only): coarse densities, coarse and fine potential
   float* wsbuf = nullptr;
   size_t wsbuf_floats = 0;
+  // non-power-of-two sides: tables per length, solver arena (grow-only)
+  std::map<int, GenTab> gtab;
+  float* garena = nullptr;
+  size_t garena_floats = 0;
   // batch arena (grow-only)
   char* barena = nullptr;
   size_t barena_bytes = 0;
@@ -479,9 +489,12 @@ int poisson_f64(gp_ctx* c, const double* b, double* x, int nyi, int nx, int m, c
   return GP_OK;
 }
 
+bool is_side(int n);  // a supported side: 7-smooth in [kMinN, kMaxN] (gprox_generic.inc)
+
 int check_size(gp_ctx* c, int ny, int nx, double h) {
-  if (!is_pow2_in_range(ny) || !is_pow2_in_range(nx)) {
-    set_err(c, "grid %dx%d unsupported: sides must be powers of two in [%d, %d]", ny, nx, kMinN, kMaxN);
+  if (!is_side(ny) || !is_side(nx)) {
+    set_err(c, "grid %dx%d unsupported: sides must be in [%d, %d] with no prime factor above 7", ny, nx, kMinN,
+            kMaxN);
     return GP_EUNSUPPORTED;
   }
   if (ny > c->max_ny || nx > c->max_nx) {
@@ -828,6 +841,8 @@ int validate_state(gp_ctx* c, const gp_state* s) {
   return prepare(c, s->ny, s->nx, s->h);
 }
 
+#include "gprox_generic.inc"
+
 // ---------------------------------------------------------------- autotuner
 // median time (ms) of `reps` runs of launch() on the context stream, after one warm-up
 template <class F> double time_ms(gp_ctx* c, F&& launch, int reps = 3) {
@@ -1165,7 +1180,7 @@ const char* gp_last_error(const gp_ctx* ctx) { return ctx ? ctx->err : g_na_err;
 int gp_create(gp_ctx** out, int max_ny, int max_nx, void* stream) {
   if (!out) return GP_EINVAL;
   *out = nullptr;
-  if (!is_pow2_in_range(max_ny) || !is_pow2_in_range(max_nx)) return GP_EUNSUPPORTED;
+  if (!is_side(max_ny) || !is_side(max_nx)) return GP_EUNSUPPORTED;
   gp_ctx* c = new (std::nothrow) gp_ctx();
   if (!c) return GP_ENOMEM;
   c->stream = static_cast<hipStream_t>(stream);
@@ -1223,6 +1238,13 @@ int gp_destroy(gp_ctx* c) {
     if (p) (void)hipFree(p);
   if (c->barena) (void)hipFree(c->barena);
   if (c->wsbuf) (void)hipFree(c->wsbuf);
+  if (c->garena) (void)hipFree(c->garena);
+  for (auto& kv : c->gtab) {
+    GenTab& T = kv.second;
+    void* gb[] = {T.w32, T.d32, T.w64, T.d64};
+    for (void* p : gb)
+      if (p) (void)hipFree(p);
+  }
   for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
   if (c->host_result) (void)hipHostFree(c->host_result);
   delete c;
@@ -1240,6 +1262,8 @@ int dct_poisson(gp_ctx* c, const float* b, float* x, int ny, int nx, double h, d
     return GP_EINVAL;
   }
   RCHK(prepare(c, ny, nx, h));
+  if (is_gen(ny, nx))
+    return poisson_gen<float2>(c, b, x, ny, nx, 1, nullptr, c->mux32, c->muy32, alpha, c->work, c->work2, false);
   return poisson_f32(c, b, x, ny, nx, 1, c->mux32, c->muy32, alpha, c->work);
 }
 
@@ -1297,6 +1321,9 @@ int dct_poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, doubl
     return GP_EINVAL;
   }
   RCHK(prepare(c, ny, nx, h));
+  if (is_gen(ny, nx))
+    return poisson_gen<double2>(c, b, x, ny, nx, 1, nullptr, c->mux64, c->muy64, alpha, c->work64,
+                                c->work64 + size_t(ny) * nx, false);
   return poisson_f64(c, b, x, ny, nx, 1, nullptr, c->mux64, c->muy64, alpha, c->work64);
 }
 
@@ -1308,6 +1335,12 @@ int pd_step(gp_ctx* c, gp_state* s, int n_iter) {
   }
   RCHK(validate_state(c, s));
   if (n_iter == 0) return GP_OK;
+  if (is_gen(s->ny, s->nx)) {
+    const GenGroup g = gen_state_group(c, s);
+    for (int i = 0; i < n_iter; ++i) RCHK(s->kind == GP_KIND_ROF ? gen_rof_iter(c, g) : gen_emd_iter(c, g));
+    s->iter += n_iter;
+    return GP_OK;
+  }
   const Group g = state_group(c, s);
   RCHK(s->kind == GP_KIND_ROF ? rof_advance(c, g, n_iter) : emd_advance(c, g, n_iter));
   s->iter += n_iter;
@@ -1322,14 +1355,22 @@ int pd_gap(gp_ctx* c, gp_state* s, gp_report* rep) {
     RCHK(rof_gap_state(c, s, &P, &D));
   } else {
     RCHK(emd_primal_state(c, s, &P));
-    // the certificate overwrites the pipeline's phi: the next pd_step starts
-    // from the state (its entry step does not read phi)
-    const Group g = state_group(c, s);
-    const size_t n = size_t(s->ny) * s->nx;
-    RCHK(emd_cert_enqueue(c, g, s->p, c->work64, c->work64 + n, c->partials, c->result));
-    HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    D = emd_dual_from(c->host_result, s->h);
+    if (is_gen(s->ny, s->nx)) {
+      const GenGroup g = gen_state_group(c, s);
+      RCHK(gen_emd_values_enqueue(c, g, c->result, c->result + 8, nullptr));
+      HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      D = gen_emd_dual(c->host_result + 8, s->h);
+    } else {
+      // the certificate overwrites the pipeline's phi: the next pd_step starts
+      // from the state (its entry step does not read phi)
+      const Group g = state_group(c, s);
+      const size_t n = size_t(s->ny) * s->nx;
+      RCHK(emd_cert_enqueue(c, g, s->p, c->work64, c->work64 + n, c->partials, c->result));
+      HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      D = emd_dual_from(c->host_result, s->h);
+    }
   }
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
@@ -1362,6 +1403,13 @@ int rof_solve(gp_ctx* c, const float* I, float* u, float* p, int ny, int nx, dou
   if (bad > 0) {
     set_err(c, "image has %.0f non-finite values", bad);
     return GP_EINVAL;
+  }
+  if (is_gen(ny, nx)) {
+    if (o->ergodic) {
+      set_err(c, "ergodic averages need power-of-two sides");
+      return GP_EUNSUPPORTED;
+    }
+    return rof_solve_gen(c, I, u, p, ny, nx, h, lambda, o, rep, tau, sigma, t0);
   }
   // arena: P0, P1 (2 n floats each); ergodic: sums of u and p (3 n doubles), averages (3 n floats)
   const bool erg = o->ergodic != 0;
@@ -1461,6 +1509,7 @@ int emd_setup(gp_ctx* c, const float* rho0, const float* rho1, float* f, float* 
     return GP_EINVAL;
   }
   RCHK(prepare(c, ny, nx, h));
+  if (is_gen(ny, nx)) return emd_setup_gen(c, rho0, rho1, f, gpsi, ny, nx, h);
   const size_t n = size_t(ny) * nx;
   const int nb = red_blocks(n);
   GP_LAUNCH(c, k_mass, dim3(nb), dim3(256), 0, c->stream, rho0, rho1, n, c->partials);
@@ -1551,6 +1600,13 @@ int emd_solve(gp_ctx* c, const float* rho0, const float* rho1, float* m, float* 
     return GP_EINVAL;
   }
   RCHK(prepare(c, ny, nx, h));
+  if (is_gen(ny, nx)) {
+    if (o->ergodic) {
+      set_err(c, "ergodic averages need power-of-two sides");
+      return GP_EUNSUPPORTED;
+    }
+    return emd_solve_gen(c, rho0, rho1, m, phi, ny, nx, h, o, rep, tau, sigma, t0);
+  }
   const size_t n = size_t(ny) * nx;
   // arena: f, grad psi, u, P0, P1, certificate potential and its intermediate (n doubles each);
   // ergodic: sums of m and p (4 n doubles) and the averaged dual (2 n floats)
@@ -1720,7 +1776,11 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
       set_err(c, "instance %d: tau (and lambda for ROF) must be positive and finite", i);
       return GP_EINVAL;
     }
-    const int rc = check_size(c, q.ny, q.nx, q.h);
+    int rc = check_size(c, q.ny, q.nx, q.h);
+    if (!rc && is_gen(q.ny, q.nx)) {
+      set_err(c, "sides must be powers of two in the batch solver");
+      rc = GP_EUNSUPPORTED;
+    }
     if (rc) {
       char msg[512];
       std::snprintf(msg, sizeof(msg), "instance %d: %s", i, c->err);

@@ -71,7 +71,7 @@ def test_warm_start_blob_size_matches_the_oracle_network(lib):
 
 def test_unsupported_sizes_rejected_before_allocation(lib):
     h = ctypes.c_void_p()
-    assert lib.gp_create(ctypes.byref(h), 100, 64, None) == -5
+    assert lib.gp_create(ctypes.byref(h), 110, 64, None) == -5  # 110 = 2 * 5 * 11
     assert lib.gp_create(ctypes.byref(h), 64, 8192, None) == -5
     assert not h.value
 

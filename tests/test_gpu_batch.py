@@ -137,7 +137,7 @@ def test_batch_max_iter_and_errors(gpctx):
     with pytest.raises(GPError) as e:
         gpctx.batch_solve([probs[0], bad], Options(tau=0.3))
     assert e.value.code == GP_EMASS and "instance 1" in str(e.value)
-    odd = {"kind": GP_KIND_EMD, "rho0": dev(np.ones((96, 96))), "rho1": dev(np.ones((96, 96))), "h": 1.0,
+    odd = {"kind": GP_KIND_EMD, "rho0": dev(np.ones((88, 88))), "rho1": dev(np.ones((88, 88))), "h": 1.0,
            "tau": 0.3}
     with pytest.raises(GPError) as e:
         gpctx.batch_solve([odd], Options(tau=0.3))
