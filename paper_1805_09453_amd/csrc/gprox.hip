@@ -995,6 +995,8 @@ struct BatchGroup {
   double* cert_dev = nullptr;  // EMD: [m][2] certificate sums
   double *cphi = nullptr, *ctmp = nullptr, *cpart = nullptr;  // EMD certificate workspace
   float* mflux = nullptr;      // EMD: flux [2][m nyi][nx]
+  bool gen = false;            // sides not powers of two: the unfused iteration on gg
+  GenGroup gg;
 };
 
 // sub-allocator over the batch arena; with base == nullptr it only measures
@@ -1020,6 +1022,48 @@ void carve(Carver& A, BatchGroup& bg) {
   g.mux32 = bg.mu32 ? bg.mu32 + g.nyi : nullptr;
   g.muy64 = bg.mu64;
   g.mux64 = bg.mu64 ? bg.mu64 + g.nyi : nullptr;
+  if (bg.gen) {
+    GenGroup& q = bg.gg;
+    q.kind = g.kind;
+    q.nyi = g.nyi;
+    q.nx = g.nx;
+    q.m = g.m;
+    q.norm = g.norm;
+    q.h = g.h;
+    q.lambda = g.lambda;
+    q.tau = g.tau;
+    q.sigma = g.sigma;
+    q.active = g.active;
+    q.muy32 = g.muy32;
+    q.mux32 = g.mux32;
+    q.muy64 = g.muy64;
+    q.mux64 = g.mux64;
+    const int nbk = red_blocks(n);
+    g.f = q.f = A.take<float>(nt);
+    if (g.kind == GP_KIND_ROF) {
+      g.u = q.u = A.take<float>(nt);
+      g.p = q.p = A.take<float>(2 * nt);
+      g.pbar = q.pbar = A.take<float>(2 * nt);
+      q.r = A.take<float>(nt);
+      q.t1 = A.take<float>(nt);
+      q.t2 = A.take<float>(nt);
+      q.part = A.take<double>(size_t(g.m) * nbk * 4);
+      bg.gap_dev = A.take<double>(size_t(g.m) * 4);
+    } else {
+      g.gpsi = q.gpsi = A.take<float>(2 * nt);
+      g.u = q.u = A.take<float>(2 * nt);
+      g.p = q.p = A.take<float>(2 * nt);
+      g.pbar = q.pbar = A.take<float>(2 * nt);
+      q.phi = A.take<double>(nt);
+      q.t1d = A.take<double>(nt);
+      q.t2d = A.take<double>(nt);
+      q.part = A.take<double>(size_t(g.m) * nbk * 2);
+      bg.gap_dev = A.take<double>(g.m);
+      bg.cert_dev = A.take<double>(size_t(g.m) * 2);
+      bg.mflux = A.take<float>(2 * nt);
+    }
+    return;
+  }
   const int vec = g.kind == GP_KIND_ROF ? 1 : 2;  // components of u
   g.f = A.take<float>(nt);
   g.u = A.take<float>(vec * nt);
@@ -1776,11 +1820,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
       set_err(c, "instance %d: tau (and lambda for ROF) must be positive and finite", i);
       return GP_EINVAL;
     }
-    int rc = check_size(c, q.ny, q.nx, q.h);
-    if (!rc && is_gen(q.ny, q.nx)) {
-      set_err(c, "sides must be powers of two in the batch solver");
-      rc = GP_EUNSUPPORTED;
-    }
+    const int rc = check_size(c, q.ny, q.nx, q.h);
     if (rc) {
       char msg[512];
       std::snprintf(msg, sizeof(msg), "instance %d: %s", i, c->err);
@@ -1803,6 +1843,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     g.m = int(kv.second.size());
     g.norm = o->norm;
     bg.idx = kv.second;
+    bg.gen = is_gen(g.nyi, g.nx);
     G.push_back(bg);
   }
   // ---- arena
@@ -1864,9 +1905,16 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     RCHK(fill_mu(c, bg.mu64, bg.mu32, bg.mu64 + g.nyi, bg.mu32 + g.nyi, g.nyi, g.nx, g.h));
     HIPCHK(c, hipStreamSynchronize(c->stream));  // `ones` leaves scope
   }
+  // ---- transform tables of the non-power-of-two sides (no allocation inside the capture)
+  for (auto& bg : G)
+    if (bg.gen) {
+      const GenTab* T;
+      RCHK(gen_tables(c, bg.g.nyi, &T));
+      RCHK(gen_tables(c, bg.g.nx, &T));
+    }
   // ---- launch shapes: measured per precision and size on first use
   for (auto& bg : G) {
-    if (tune_group(c, bg.g)) {
+    if (!bg.gen && tune_group(c, bg.g)) {
       set_err(c, "autotuning launch failed");
       return GP_EHIP;
     }
@@ -1896,7 +1944,7 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
   };
   int rc = GP_OK;
   for (size_t k = 0; k < G.size() && !rc; ++k)
-    rc = G[k].g.kind == GP_KIND_ROF ? rof_A(rp[k], 1, false) : emd_A_drs(ep[k], 1, false);
+    if (!G[k].gen) rc = G[k].g.kind == GP_KIND_ROF ? rof_A(rp[k], 1, false) : emd_A_drs(ep[k], 1, false);
   if (rc) return restore(rc);
   // side streams: independent groups form parallel branches of the graph
   const int nside = int(std::min<size_t>(G.size(), size_t(kSideStreams))) - 1;
@@ -1928,6 +1976,16 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
   for (size_t k = 0; k < G.size() && !rc; ++k) {
     c->stream = k == 0 || nside == 0 ? c->bstream : c->side[(k - 1) % nside];
     const Group& g = G[k].g;
+    if (G[k].gen) {
+      // unfused iteration; per-instance gap values (EMD: primal sums and certificates)
+      const GenGroup& q = G[k].gg;
+      for (int it = 0; it < C && !rc; ++it) rc = g.kind == GP_KIND_ROF ? gen_rof_iter(c, q) : gen_emd_iter(c, q);
+      if (!rc)
+        rc = g.kind == GP_KIND_ROF ? gen_rof_gap_enqueue(c, q, G[k].gap_dev)
+                                   : gen_emd_values_enqueue(c, q, G[k].gap_dev, G[k].cert_dev, nullptr);
+      if (rc) break;
+      continue;
+    }
     for (int it = 0; it < C && !rc; ++it) {
       const bool last = it + 1 == C;
       if (g.kind == GP_KIND_ROF) {
@@ -1956,9 +2014,11 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     }
   }
   c->stream = c->bstream;
-  for (int s = 0; s < nside && !rc; ++s)
-    if (hipEventRecord(c->side_ev[s], c->side[s]) != hipSuccess ||
-        hipStreamWaitEvent(c->bstream, c->side_ev[s], 0) != hipSuccess) {
+  // join every side stream, also after a failure, so that ending the capture
+  // takes all of them out of capture mode
+  for (int s = 0; s < nside; ++s)
+    if ((hipEventRecord(c->side_ev[s], c->side[s]) != hipSuccess ||
+         hipStreamWaitEvent(c->bstream, c->side_ev[s], 0) != hipSuccess) && !rc) {
       set_err(c, "join inside the capture failed");
       rc = GP_EHIP;
     }
@@ -2014,7 +2074,8 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
           D = -g.h * r[2] - r[3] / (2.0 * g.lambda);
         } else {
           P = g.h * g.h * hbuf[k];
-          D = emd_dual_from(&hbuf[g.m + 2 * size_t(k)], g.h);
+          // (the fused path's certificate holds -phi_c, the unfused one phi_c)
+          D = bg.gen ? gen_emd_dual(&hbuf[g.m + 2 * size_t(k)], g.h) : emd_dual_from(&hbuf[g.m + 2 * size_t(k)], g.h);
           Lv[i] = hbuf[g.m + 2 * size_t(k) + 1];
         }
         const double gp = rel_gap(P, D);
@@ -2050,11 +2111,17 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     if (g.kind == GP_KIND_ROF) {
       for (int q = 0; q < g.m; ++q) cp(inst[bg.idx[q]].out, g.u + q * n, n * sizeof(float));
     } else {
-      // flux of the single-variable form: m = -tau (R(y) - grad phi) + grad psi from the y the last A read
-      GP_LAUNCH(c, k_emd_finish_drs, dim3(grid_for(nt)), dim3(256), 0, c->bstream, ep[k].WY, g.phi, g.gpsi,
-                bg.mflux, g.nyi * g.m, g.nx, g.nyi, 1.0 / g.h, float(g.tau), g.norm);
+      if (bg.gen) {
+        // flux m = u + grad psi of the unfused iteration (the primal partials land in scratch)
+        GP_LAUNCH(c, k_gen_emd_primal, dim3(bg.gg.nb(), g.m), dim3(256), 0, c->bstream, g.u, g.gpsi, bg.mflux, g.nyi,
+                  g.nx, g.m, g.norm, bg.gg.part);
+      } else {
+        // flux of the single-variable form: m = -tau (R(y) - grad phi) + grad psi from the y the last A read
+        GP_LAUNCH(c, k_emd_finish_drs, dim3(grid_for(nt)), dim3(256), 0, c->bstream, ep[k].WY, g.phi, g.gpsi,
+                  bg.mflux, g.nyi * g.m, g.nx, g.nyi, 1.0 / g.h, float(g.tau), g.norm);
+      }
       if (hipGetLastError() != hipSuccess) {
-        set_err(c, "k_emd_finish_drs launch failed");
+        set_err(c, "flux kernel launch failed");
         return restore(GP_EHIP);
       }
       for (int q = 0; q < g.m; ++q) {
@@ -2063,8 +2130,10 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
         cp(in.out + n, bg.mflux + nt + q * n, n * sizeof(float));
         if (in.phi) {
           const double L = Lv[bg.idx[q]];
-          GP_LAUNCH(c, k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->bstream, bg.cphi + q * n, in.phi, n,
-                             -1.0 / (L > 1.0 ? L : 1.0));
+          // fused path: cphi holds -phi_c; unfused: phi holds phi_c (each instance's last check)
+          const double* src = bg.gen ? bg.gg.phi + q * n : bg.cphi + q * n;
+          GP_LAUNCH(c, k_scale<double>, dim3(grid_for(n)), dim3(256), 0, c->bstream, src, in.phi, n,
+                    (bg.gen ? 1.0 : -1.0) / (L > 1.0 ? L : 1.0));
           ok = ok && hipGetLastError() == hipSuccess;
         }
       }

@@ -185,3 +185,43 @@ def test_unsupported_sides_and_options(gpctx):
     with pytest.raises(GPError) as e:
         gpctx.rof_solve(dev(np.ones((96, 96))), 1.0, 8.0, Options(tau=0.01, ergodic=True))
     assert e.value.code == GP_EUNSUPPORTED
+
+
+def test_batch_with_generic_sides_equals_single_solves(gpctx):
+    """A batch mixing non-power-of-two sides (square, rectangular, odd) with a
+    power-of-two instance: every instance equals its single-instance solve bit for
+    bit, and one ROF instance reaches the oracle's optimum."""
+    from paper_1805_09453_amd import Options
+    from paper_1805_09453_amd._lib import GP_KIND_EMD, GP_KIND_ROF
+
+    def rof_p(ny, nx, seed, lam=8.0, tau=0.01):
+        return {"kind": GP_KIND_ROF, "I": dev(scene(ny, nx, seed)), "h": 1.0, "lam": lam, "tau": tau}
+
+    def emd_p(ny, nx, seed, tau=0.3):
+        r0, r1 = mixture(ny, nx, seed)
+        return {"kind": GP_KIND_EMD, "rho0": dev(r0), "rho1": dev(r1), "h": 1.0 / max(ny, nx), "tau": tau}
+
+    probs = [rof_p(96, 96, 1), emd_p(75, 105, 2), rof_p(96, 160, 3), emd_p(96, 96, 4), rof_p(96, 96, 5),
+             rof_p(64, 64, 6), emd_p(96, 96, 7), rof_p(320, 320, 8, lam=4.0, tau=0.02)]
+    opts = Options(tau=1.0, tol=1e-4, max_iter=2000, check_every=10)
+    announce(f"gp_batch_solve with non-power-of-two sides, {len(probs)} instances")
+    outs, reps, rc = gpctx.batch_solve(probs, opts)
+    for i, q in enumerate(probs):
+        announce(f"single solve for batch instance {i}")
+        o = Options(tau=q["tau"], tol=opts.tol, max_iter=opts.max_iter, check_every=10)
+        if q["kind"] == GP_KIND_ROF:
+            ref, _, rrep = gpctx.rof_solve(q["I"], q["h"], q["lam"], o)
+        else:
+            ref, _, rrep = gpctx.emd_solve(q["rho0"], q["rho1"], q["h"], o, want_phi=False)
+        print(i, tuple(q[k].shape for k in ("I", "rho0") if k in q), reps[i]["iters"], rrep["iters"],
+              reps[i]["rel_gap"], rrep["rel_gap"])
+        assert reps[i]["iters"] == rrep["iters"] and reps[i]["converged"] == rrep["converged"]
+        assert reps[i]["primal"] == rrep["primal"] and reps[i]["dual"] == rrep["dual"]
+        np.testing.assert_array_equal(host(outs[i]), host(ref))
+    assert len({r["iters"] for r in reps}) > 1
+    # ROF 96 x 160 instance: objective within 1e-4 of the oracle's optimum at this tolerance
+    I = host(probs[2]["I"])
+    ref = orof.solve(I, 1.0, 8.0, 0.01, tol=1e-9, max_iter=200000, check_every=100)
+    err = abs(orof.primal(host(outs[2]), I, 1.0, 8.0) - ref.primal) / ref.primal
+    print("oracle objective error", err)
+    assert err <= 1e-4
