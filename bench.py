@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-tol", type=float, default=1e-5)
     ap.add_argument("--batch-max-iter", type=int, default=60000)
+    ap.add_argument("--batch-primes", type=int, nargs="+", default=[2, 3, 5, 7],
+                    help="batch sides are snapped to the nearest number with these prime factors")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D grid leg")
     ap.add_argument("--n3", type=int, default=256, help="side of the 3-D grid leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -123,16 +125,17 @@ def cpu_baseline(n, iters_budget_s, iters_to_tol, workers):
                       f"in this run: {proj}"}
 
 
-def batch_leg(ctx, dev, count, tol, max_iter):
+def batch_leg(ctx, dev, count, tol, max_iter, primes):
     """Mixed batch: `count` ROF/EMD instances (kind ~ Bernoulli(1/2), side 2^U[6,10]
-    snapped to a power of two), solved together by gp_batch_solve."""
+    snapped to the nearest size with prime factors in `primes`), solved together by
+    gp_batch_solve."""
     import numpy as np
     import torch
 
     import synth
     from paper_1805_09453_amd import Options
     from paper_1805_09453_amd._lib import GP_KIND_EMD, GP_KIND_ROF
-    insts = synth.batch_instances(count)
+    insts = synth.batch_instances(count, primes=primes)
     probs = []
     for q in insts:
         x = synth.batch_instance_inputs(q)
@@ -160,7 +163,8 @@ def batch_leg(ctx, dev, count, tol, max_iter):
                 per[f"{kind}_{n}"] = {"count": len(sel), "median_iters": int(np.median([r["iters"] for r in sel])),
                                       "max_iters": max(r["iters"] for r in sel),
                                       "converged": int(sum(r["converged"] for r in sel))}
-    return {"instances": len(insts), "pixels": int(sum(q["n"] ** 2 for q in insts)), "tol": tol,
+    return {"instances": len(insts), "sides_snapped_to_primes": list(primes), "distinct_sides": len({q["n"] for q in insts}),
+            "pixels": int(sum(q["n"] ** 2 for q in insts)), "tol": tol,
             "max_iter": max_iter, "check_every": 20, "pixel_iters_per_s": pxit / loop, "loop_s": loop,
             "setup_s": reps[0]["seconds_setup"], "wall_s": wall,
             "converged": int(sum(r["converged"] for r in reps)),
@@ -169,7 +173,7 @@ def batch_leg(ctx, dev, count, tol, max_iter):
             "time_to_tol_over": "converged instances only",
             "groups": per,
             "tuned_shapes": {f"{'f64' if fp else 'f32'}_{n}": list(ctx.get_shape(fp, n))
-                             for fp in (False, True) for n in sorted({q["n"] for q in insts})}}
+                             for fp in (False, True) for n in sorted({q["n"] for q in insts}) if n & (n - 1) == 0}}
 
 
 def warm_leg(ctx, dev, n, tol, max_iter, pairs):
@@ -382,7 +386,8 @@ def main():
     if not args.no_warm and not args.no_emd:
         extra["warm_start"] = warm_leg(ctx, dev, n, args.warm_tol, args.warm_max_iter, args.warm_pairs)
     if not args.no_batch:
-        extra["batch"] = batch_leg(ctx, dev, args.batch_count, args.batch_tol, args.batch_max_iter)
+        extra["batch"] = batch_leg(ctx, dev, args.batch_count, args.batch_tol, args.batch_max_iter,
+                                   tuple(args.batch_primes))
     if not args.no_3d:
         extra["grid3d"] = grid3_leg(ctx, dev, args.n3, C, K, W)
     ctx.close()

@@ -1964,73 +1964,91 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     return restore(GP_EHIP);
   }
   // chunk, per group: C x (column pass + B, then A), the last A with gap partials,
-  // then the per-instance reductions (ROF: finalize; EMD: finalize + certificate)
-  if (hipStreamBeginCapture(c->bstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    set_err(c, "hipStreamBeginCapture failed");
-    return restore(GP_EHIP);
-  }
-  if (hipEventRecord(c->fork_ev, c->bstream) != hipSuccess) rc = GP_EHIP;
-  for (int s = 0; s < nside && !rc; ++s)
-    if (hipStreamWaitEvent(c->side[s], c->fork_ev, 0) != hipSuccess) rc = GP_EHIP;
-  if (rc) set_err(c, "fork inside the capture failed");
-  for (size_t k = 0; k < G.size() && !rc; ++k) {
-    c->stream = k == 0 || nside == 0 ? c->bstream : c->side[(k - 1) % nside];
-    const Group& g = G[k].g;
-    if (G[k].gen) {
-      // unfused iteration; per-instance gap values (EMD: primal sums and certificates)
-      const GenGroup& q = G[k].gg;
-      for (int it = 0; it < C && !rc; ++it) rc = g.kind == GP_KIND_ROF ? gen_rof_iter(c, q) : gen_emd_iter(c, q);
-      if (!rc)
-        rc = g.kind == GP_KIND_ROF ? gen_rof_gap_enqueue(c, q, G[k].gap_dev)
-                                   : gen_emd_values_enqueue(c, q, G[k].gap_dev, G[k].cert_dev, nullptr);
-      if (rc) break;
-      continue;
+  // then the per-instance reductions (ROF: finalize; EMD: finalize + certificate).
+  // Only the groups in `live` are captured: the graph is captured again when
+  // enough groups have retired completely (their launches would only exit).
+  // Every pipeline's buffers return to their roles after the even chunk, so each
+  // capture starts from the same state.
+  auto capture = [&](const std::vector<int>& live) -> int {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    const int nsd = int(std::min<size_t>(live.size(), size_t(nside + 1))) - 1;
+    int rc = GP_OK;
+    if (hipStreamBeginCapture(c->bstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      set_err(c, "hipStreamBeginCapture failed");
+      return GP_EHIP;
     }
-    for (int it = 0; it < C && !rc; ++it) {
-      const bool last = it + 1 == C;
-      if (g.kind == GP_KIND_ROF) {
-        rc = rof_CB(rp[k]);
-        if (!rc) rc = rof_A(rp[k], 0, last);
-      } else {
-        rc = emd_CB(ep[k]);
-        if (!rc) rc = emd_A_drs(ep[k], 0, last);
+    if (hipEventRecord(c->fork_ev, c->bstream) != hipSuccess) rc = GP_EHIP;
+    for (int s = 0; s < nsd && !rc; ++s)
+      if (hipStreamWaitEvent(c->side[s], c->fork_ev, 0) != hipSuccess) rc = GP_EHIP;
+    if (rc) set_err(c, "fork inside the capture failed");
+    for (size_t li = 0; li < live.size() && !rc; ++li) {
+      const int k = live[li];
+      c->stream = li == 0 || nsd == 0 ? c->bstream : c->side[(li - 1) % nsd];
+      const Group& g = G[k].g;
+      if (G[k].gen) {
+        // unfused iteration; per-instance gap values (EMD: primal sums and certificates)
+        const GenGroup& q = G[k].gg;
+        for (int it = 0; it < C && !rc; ++it) rc = g.kind == GP_KIND_ROF ? gen_rof_iter(c, q) : gen_emd_iter(c, q);
+        if (!rc)
+          rc = g.kind == GP_KIND_ROF ? gen_rof_gap_enqueue(c, q, G[k].gap_dev)
+                                     : gen_emd_values_enqueue(c, q, G[k].gap_dev, G[k].cert_dev, nullptr);
+        continue;
       }
-    }
-    if (rc) break;
-    GP_LAUNCH(c, k_finalize, dim3(g.m), dim3(256), 0, c->stream, g.gpart, g.nyi / 2,
-                       g.kind == GP_KIND_ROF ? 4 : 1, 0u, G[k].gap_dev);
-    if (hipGetLastError() != hipSuccess) {
-      set_err(c, "k_finalize launch failed during capture");
-      rc = GP_EHIP;
-    }
-    if (!rc && g.kind == GP_KIND_EMD) {
-      // p = proj(y) of the latest iterate into the (otherwise unused) dual buffer, then its certificate
-      GP_LAUNCH(c, k_proj2, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, ep[k].WX, g.p, g.ntot(), g.norm);
+      for (int it = 0; it < C && !rc; ++it) {
+        const bool last = it + 1 == C;
+        if (g.kind == GP_KIND_ROF) {
+          rc = rof_CB(rp[k]);
+          if (!rc) rc = rof_A(rp[k], 0, last);
+        } else {
+          rc = emd_CB(ep[k]);
+          if (!rc) rc = emd_A_drs(ep[k], 0, last);
+        }
+      }
+      if (rc) break;
+      GP_LAUNCH(c, k_finalize, dim3(g.m), dim3(256), 0, c->stream, g.gpart, g.nyi / 2,
+                g.kind == GP_KIND_ROF ? 4 : 1, 0u, G[k].gap_dev);
       if (hipGetLastError() != hipSuccess) {
-        set_err(c, "k_proj2 launch failed during capture");
+        set_err(c, "k_finalize launch failed during capture");
         rc = GP_EHIP;
       }
-      if (!rc) rc = emd_cert_enqueue(c, g, g.p, G[k].cphi, G[k].ctmp, G[k].cpart, G[k].cert_dev);
+      if (!rc && g.kind == GP_KIND_EMD) {
+        // p = proj(y) of the latest iterate into the (otherwise unused) dual buffer, then its certificate
+        GP_LAUNCH(c, k_proj2, dim3(grid_for(g.ntot())), dim3(256), 0, c->stream, ep[k].WX, g.p, g.ntot(), g.norm);
+        if (hipGetLastError() != hipSuccess) {
+          set_err(c, "k_proj2 launch failed during capture");
+          rc = GP_EHIP;
+        }
+        if (!rc) rc = emd_cert_enqueue(c, g, g.p, G[k].cphi, G[k].ctmp, G[k].cpart, G[k].cert_dev);
+      }
     }
-  }
-  c->stream = c->bstream;
-  // join every side stream, also after a failure, so that ending the capture
-  // takes all of them out of capture mode
-  for (int s = 0; s < nside; ++s)
-    if ((hipEventRecord(c->side_ev[s], c->side[s]) != hipSuccess ||
-         hipStreamWaitEvent(c->bstream, c->side_ev[s], 0) != hipSuccess) && !rc) {
-      set_err(c, "join inside the capture failed");
-      rc = GP_EHIP;
+    c->stream = c->bstream;
+    // join every side stream, also after a failure, so that ending the capture
+    // takes all of them out of capture mode
+    for (int s = 0; s < nsd; ++s)
+      if ((hipEventRecord(c->side_ev[s], c->side[s]) != hipSuccess ||
+           hipStreamWaitEvent(c->bstream, c->side_ev[s], 0) != hipSuccess) && !rc) {
+        set_err(c, "join inside the capture failed");
+        rc = GP_EHIP;
+      }
+    const hipError_t ce = hipStreamEndCapture(c->bstream, &graph);
+    if (rc || ce != hipSuccess) {
+      if (!rc) set_err(c, "hipStreamEndCapture failed: %s", hipGetErrorString(ce));
+      return rc ? rc : GP_EHIP;
     }
-  const hipError_t ce = hipStreamEndCapture(c->bstream, &graph);
-  if (rc || ce != hipSuccess) {
-    if (!rc) set_err(c, "hipStreamEndCapture failed: %s", hipGetErrorString(ce));
-    return restore(rc ? rc : GP_EHIP);
-  }
-  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-    set_err(c, "hipGraphInstantiate failed");
-    return restore(GP_EHIP);
-  }
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      set_err(c, "hipGraphInstantiate failed");
+      return GP_EHIP;
+    }
+    return GP_OK;
+  };
+  std::vector<int> live(G.size());
+  for (size_t k = 0; k < G.size(); ++k) live[k] = int(k);
+  size_t captured = live.size();
+  rc = capture(live);
+  if (rc) return restore(rc);
   // ---- replay until every instance has retired
   std::vector<char> retired(count, 0);
   std::vector<int> iters(count, 0);
@@ -2045,7 +2063,8 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
       return restore(GP_EHIP);
     }
     done += C;
-    for (auto& bg : G) {
+    for (int k : live) {
+      BatchGroup& bg = G[k];
       const Group& g = bg.g;
       const int K = g.kind == GP_KIND_ROF ? 4 : 1;
       hbuf.assign(size_t(g.m) * (K + 2), 0.0);
@@ -2095,6 +2114,20 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
         set_err(c, "active-flag update failed");
         return restore(GP_EHIP);
       }
+    }
+    // drop the groups whose instances have all retired; capture again once a
+    // quarter of the captured groups are gone
+    std::vector<int> still;
+    for (int k : live) {
+      bool any = false;
+      for (int i : G[k].idx) any = any || !retired[i];
+      if (any) still.push_back(k);
+    }
+    live.swap(still);
+    if (left > 0 && 4 * live.size() <= 3 * captured) {
+      rc = capture(live);
+      if (rc) return restore(rc);
+      captured = live.size();
     }
   }
   // ---- outputs: ROF u_t (B never ran after an instance's last check); EMD flux
