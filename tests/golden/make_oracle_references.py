@@ -177,9 +177,33 @@ def emd_ws_512():
                 held_out=s, tau=0.3, iters=r.iters, primal=r.primal, dual=r.dual, rel_gap=r.rel_gap)
 
 
+def batch_1024():
+    """F* of the first ROF and the first EMD 1024^2 instance of the 512-instance
+    mixed batch (inputs rounded to FP32): ROF to a relative gap of 1e-7, EMD to 1e-5."""
+    import numpy as np
+    insts = synth.batch_instances(512)
+    out = {}
+    for kind in ("rof", "emd"):
+        i = next(j for j, q in enumerate(insts) if q["kind"] == kind and q["n"] == 1024)
+        x = synth.batch_instance_inputs(insts[i])
+        if kind == "rof":
+            I = np.asarray(x["image"], np.float32).astype(np.float64)
+            r = rof.solve(I, 1.0, 8.0, 0.01, tol=1e-7, max_iter=200000, check_every=50)
+            out[kind] = dict(index=i, seed=insts[i]["seed"], tau=0.01, lam=8.0, h=1.0, iters=r.iters,
+                             primal=r.primal, dual=r.dual, rel_gap=r.rel_gap)
+        else:
+            r0, r1 = (np.asarray(x[k], np.float32).astype(np.float64) for k in ("rho0", "rho1"))
+            r = emd.solve(r0, r1, 1.0 / 1024, tau=0.3, tol=1e-5, max_iter=400000, check_every=250)
+            out[kind] = dict(index=i, seed=insts[i]["seed"], tau=0.3, h=1.0 / 1024, iters=r.iters,
+                             primal=r.primal, dual=r.dual, rel_gap=r.rel_gap)
+        print(" ", kind, out[kind], flush=True)
+    return dict(workload="first ROF and first EMD 1024x1024 instance of synth.batch_instances(512), FP32 inputs",
+                cases=out)
+
+
 JOBS = {"rof_c0": rof_c0, "emd_c1_mixture": emd_c1_mixture, "emd_aniso_64": emd_aniso_64,
         "rof_c2_4096": rof_c2_4096, "emd_c2_1024": emd_c2_1024, "paper_protocol_128": paper_protocol_128,
-        "emd_ws_512": emd_ws_512}
+        "emd_ws_512": emd_ws_512, "batch_1024": batch_1024}
 
 if __name__ == "__main__":
     import scipy.fft
