@@ -27,7 +27,8 @@ HBM_PEAK_GBPS = 8000.0
 # the per-iteration kernels (the set-up, checks and certificate kernels are excluded
 # from the per-iteration byte count)
 ITER_KERNELS = {"rof_A_prox_rhs_dct", "cols_solve", "rof_B_idct_update", "emd_A_prox_rhs_dct", "cols_solve_f64",
-                "emd_B_idct"}
+                "emd_B_idct", "gen_rows_dct", "gen_rows_dct_f64", "gen_transpose", "gen_rof_rhs", "gen_rof_dual",
+                "gen_emd_rhs", "gen_emd_update"}
 
 
 def parse():
@@ -65,7 +66,8 @@ def parse():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("gprox.hip", "gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp"):
+    for f in ("gprox.hip", "gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp", "gprox_generic.hpp",
+              "gprox_generic.inc"):
         with open(os.path.join(ROOT, "paper_1805_09453_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -332,6 +334,8 @@ def main():
     dt, prof, rep, dt_ev = run(rof)
     rof_pxit = n * n * C * K / dt
     ms_per_step = 1e3 * dt / K
+    if not prof:
+        raise SystemExit("the library recorded no kernel durations for the ROF leg")
     dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     dname, d = dom
     achieved = d["bytes"] / d["calls"] / (d["avg_ms"] * 1e6)
@@ -340,7 +344,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dname, n), "kernel": dname,
                 "bytes_per_launch": d["bytes"] / d["calls"], "avg_launch_ms": d["avg_ms"],
                 "measured": "HIP events bound to each dispatch of the kernel on the solver stream "
-                            "(hipExtLaunchKernelGGL), over a repeat of the K timed steps"}
+                            "(hipExtLaunchKernelGGL), over a repeat of the K timed steps",
+                "kernel_source_hash": kernel_source_hash()}
     extra = {"rof": {"pixel_iters_per_s": rof_pxit, "iters": rep["iters"], "last_rel_gap": rep["rel_gap"],
                      "algorithmic_bytes_per_pixel_iter": iter_bytes / (n * n),
                      "iteration_hbm_frac": iter_bytes * C * K / dt / 1e9 / HBM_PEAK_GBPS,

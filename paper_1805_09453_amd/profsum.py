@@ -1,13 +1,17 @@
 """Summarise rocprofv3 CSV output into a short text report and HBM traffic figures.
 
     python -m paper_1805_09453_amd.profsum --trace DIR --fetch DIR --write DIR \
-        --cmd "<command that produced them>" --out profiles/NAME.md [--traffic profiles/traffic.json]
+        --cmd "<command that produced them>" --out profiles/NAME.md [--traffic profiles/traffic.json] \
+        [--logs FETCH_LOG WRITE_LOG]
 
 --trace: a `rocprofv3 --kernel-trace --stats` output directory (kernel_stats.csv);
 --fetch / --write: `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` directories
 (counter_collection.csv, KiB per dispatch).  The counters are scaled by what they
 read for the plain 256 MiB device copy that `bench.py --calib-copy` runs first
 (the largest __amd_rocclr_copyBuffer dispatch): scale = 256 MiB / counter value.
+Each traffic entry carries the hash of the kernel sources it was measured on
+(from the counter runs' own output when --logs is given); bench.py reports the
+figure only while the sources still hash the same.
 """
 import argparse
 import csv
@@ -38,7 +42,8 @@ def short(name):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("gprox.hip", "gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp"):
+    for f in ("gprox.hip", "gprox_fft.hpp", "gprox_kernels.hpp", "gprox_fused.hpp", "gprox_generic.hpp",
+              "gprox_generic.inc"):
         with open(os.path.join(ROOT, "paper_1805_09453_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -65,6 +70,21 @@ def counter_means(rows):
     return out, copy
 
 
+def run_source_hash(logs):
+    """The kernel source hash that bench.py printed in both counter runs (they
+    must agree): the traffic figures belong to the sources that were measured."""
+    hs = set()
+    for p in logs:
+        with open(p) as fh:
+            rows = [json.loads(ln) for ln in fh if ln.startswith("{")]
+        if not rows:
+            raise ValueError(f"no JSON line in {p}")
+        hs.add(rows[-1]["roofline"]["kernel_source_hash"])
+    if len(hs) != 1:
+        raise ValueError(f"the counter runs measured different sources: {sorted(hs)}")
+    return hs.pop()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -74,6 +94,8 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic")
     ap.add_argument("--title", default="rocprofv3 kernel summary")
+    ap.add_argument("--logs", nargs=2, metavar=("FETCH_LOG", "WRITE_LOG"),
+                    help="stdout of the two counter runs: the kernel source hash is taken from their JSON lines")
     a = ap.parse_args()
 
     stats = _csv(a.trace, "kernel_stats.csv")
@@ -91,7 +113,7 @@ def main():
         lines += ["", f"HBM bytes per dispatch: FETCH_SIZE x {fs:.3f}, WRITE_SIZE x {ws:.3f} "
                       f"(scales from the 256 MiB copy: it reads {fcopy:.0f} KiB fetch, {wcopy:.0f} KiB write).",
                   "", "| kernel | FETCH KiB | WRITE KiB | HBM MB per dispatch (scaled) |", "|---|---:|---:|---:|"]
-        h = kernel_source_hash()
+        h = run_source_hash(a.logs) if a.logs else kernel_source_hash()
         for k in sorted(set(fm) | set(wm)):
             fb, wb = fm.get(k, 0.0), wm.get(k, 0.0)
             tot = (fb * fs + wb * ws) * 1024

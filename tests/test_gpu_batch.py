@@ -231,3 +231,48 @@ def test_batch_rectangular_anisotropic_equals_single_solves(gpctx):
         assert reps[i]["rel_gap"] == rrep["rel_gap"]
         assert reps[i]["primal"] == rrep["primal"] and reps[i]["dual"] == rrep["dual"]
         np.testing.assert_array_equal(host(outs[i]), host(ref))
+
+
+def test_batch_1024_instances_match_oracle_optimum(gpctx):
+    """The first ROF and the first EMD 1024^2 instance of the 512-instance mixed
+    batch (power-of-two sides), solved inside a batch with the six instances that
+    precede the first of them, to a 1e-5 relative gap: the FP64 objective of each
+    downloaded result lies within 1e-5 of the oracle's certified optimum."""
+    from paper_1805_09453_amd import Options
+    from paper_1805_09453_amd._lib import GP_KIND_EMD, GP_KIND_ROF
+    with open(os.path.join(GOLDEN, "oracle_references.json")) as fh:
+        refs = json.load(fh)["batch_1024"]["cases"]
+    insts = synth.batch_instances(512)
+    first = min(refs["rof"]["index"], refs["emd"]["index"])
+    pick = sorted(set(range(max(0, first - 6), first)) | {refs["rof"]["index"], refs["emd"]["index"]})
+    probs, xs = [], []
+    for i in pick:
+        q = insts[i]
+        x = synth.batch_instance_inputs(q)
+        xs.append(x)
+        if q["kind"] == "rof":
+            probs.append({"kind": GP_KIND_ROF, "I": dev(x["image"]), "h": 1.0, "lam": 8.0, "tau": 0.01})
+        else:
+            probs.append({"kind": GP_KIND_EMD, "rho0": dev(x["rho0"]), "rho1": dev(x["rho1"]),
+                          "h": 1.0 / q["n"], "tau": 0.3})
+    announce(f"gp_batch_solve of instances {pick} of the 512-instance batch to 1e-5")
+    outs, reps, rc = gpctx.batch_solve(probs, Options(tau=1.0, tol=1e-5, max_iter=40000, check_every=20))
+    assert all(r["converged"] for r in reps)
+    for kind in ("rof", "emd"):
+        ref = refs[kind]
+        j = pick.index(ref["index"])
+        q, x = insts[ref["index"]], xs[j]
+        assert q["kind"] == kind and q["n"] == 1024 and q["seed"] == ref["seed"]
+        if kind == "rof":
+            I32 = np.asarray(x["image"], np.float32).astype(np.float64)
+            val = orof.primal(host(outs[j]), I32, 1.0, 8.0)
+            assert val >= ref["dual"] * (1 - 1e-12)
+        else:
+            r0, r1 = (np.asarray(x[k], np.float32).astype(np.float64) for k in ("rho0", "rho1"))
+            f_ref, _ = oemd.setup(r0, r1, 1.0 / 1024)
+            val, _ = oemd.flux_value(host(outs[j])[0], host(outs[j])[1], f_ref, 1.0 / 1024)
+            assert val >= ref["dual"] * (1 - 1e-6)
+        err = abs(val - ref["primal"]) / ref["primal"]
+        print(kind, "iters", reps[j]["iters"], "gap %.2e" % reps[j]["rel_gap"], "FP64 value", val,
+              "oracle", ref["primal"], "err %.2e" % err)
+        assert err <= 1e-5
