@@ -175,7 +175,11 @@ def batch_leg(ctx, dev, count, tol, max_iter, primes):
             "time_to_tol_over": "converged instances only",
             "groups": per,
             "tuned_shapes": {f"{'f64' if fp else 'f32'}_{n}": list(ctx.get_shape(fp, n))
-                             for fp in (False, True) for n in sorted({q["n"] for q in insts}) if n & (n - 1) == 0}}
+                             for fp in (False, True) for n in sorted({q["n"] for q in insts}) if n & (n - 1) == 0},
+            # the radix plans the batch measured (ROF transforms in FP32, EMD in FP64)
+            "radix_plans": {f"{'f64' if q['kind'] == 'emd' else 'f32'}_{q['n']}":
+                            "x".join(map(str, ctx.get_radix_plan(q["kind"] == "emd", q["n"])))
+                            for q in insts if q["n"] & (q["n"] - 1)}}
 
 
 def warm_leg(ctx, dev, n, tol, max_iter, pairs):
@@ -349,7 +353,8 @@ def main():
     extra = {"rof": {"pixel_iters_per_s": rof_pxit, "iters": rep["iters"], "last_rel_gap": rep["rel_gap"],
                      "algorithmic_bytes_per_pixel_iter": iter_bytes / (n * n),
                      "iteration_hbm_frac": iter_bytes * C * K / dt / 1e9 / HBM_PEAK_GBPS,
-                     "launch_shape_f32": list(ctx.get_shape(False, n)),
+                     "launch_shape_f32": list(ctx.get_shape(False, n)) if n & (n - 1) == 0 else None,
+                     "radix_plan_f32": ctx.get_radix_plan(False, n) if n & (n - 1) else None,
                      "ms_per_step_with_kernel_events": 1e3 * dt_ev / K,
                      "kernels": {k: {"avg_ms": v["avg_ms"], "calls": v["calls"], "gbps": v["gbps"]}
                                  for k, v in prof.items()}}}
@@ -368,7 +373,8 @@ def main():
                         "last_rel_gap": erep["rel_gap"], "ms_per_step": 1e3 * edt / K,
                         "algorithmic_bytes_per_pixel_iter": ebytes / (n * n),
                         "iteration_hbm_frac": ebytes * C * K / edt / 1e9 / HBM_PEAK_GBPS,
-                        "launch_shape_f64": list(ctx.get_shape(True, n)),
+                        "launch_shape_f64": list(ctx.get_shape(True, n)) if n & (n - 1) == 0 else None,
+                        "radix_plan_f64": ctx.get_radix_plan(True, n) if n & (n - 1) else None,
                         "ms_per_step_with_kernel_events": 1e3 * edt_ev / K,
                         "kernels": {k: {"avg_ms": v["avg_ms"], "calls": v["calls"], "gbps": v["gbps"]}
                                     for k, v in eprof.items()}}

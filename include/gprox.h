@@ -311,6 +311,26 @@ int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opt
 int gp_get_shape(gp_ctx* ctx, int fp64, int n, int* row_groups, int* col_groups, int* tile_width);
 int gp_set_shape(gp_ctx* ctx, int fp64, int n, int row_groups, int col_groups, int tile_width);
 
+/* Radix plan of the transforms of a side n that is 7-smooth but not a power of
+ * two (appendix A: the cosine-series inversion holds for any n).  A plan lists
+ * the radices of the Stockham passes in order: each 2, 3, 4, 5, 7 or 8, with
+ * product n, at most 16 passes.  On the first transform of such a length in a
+ * precision the library times its candidate plans (the odd radices first or
+ * last, the power-of-two factor as radix-8 or radix-4 passes) and keeps the
+ * fastest; the default (odd radices first, radix-8 passes) unless another is at
+ * least 3% faster.  Every plan computes the same DCT; only rounding differs.
+ * Nothing is measured on a stream under graph capture (the default is used
+ * there without being kept); gp_batch_solve measures before it captures.
+ * gp_get_radix_plan writes the plan the next length-n transform in FP32
+ * (fp64 = 0: ROF, dct_poisson) or FP64 (fp64 = 1: EMD, dct_poisson_f64) will
+ * use -- the default if none has been measured or set -- into radices[0..16)
+ * (unused entries 0) and its pass count into *count.  gp_set_radix_plan fixes
+ * a plan and exempts the length from measurement (it synchronises the
+ * context stream).  GP_EUNSUPPORTED if n is not such a side in [64, 4096];
+ * GP_EINVAL for NULL pointers or an invalid plan. */
+int gp_get_radix_plan(gp_ctx* ctx, int fp64, int n, int* radices, int* count);
+int gp_set_radix_plan(gp_ctx* ctx, int fp64, int n, const int* radices, int count);
+
 /* ---------------------------------------------------------------- learned warm start
  * Not part of the paper.  A U-Net predicts the dual potential phi0 of the EMD
  * problem from (rho0, rho1); the iteration of section 3.2 then starts from

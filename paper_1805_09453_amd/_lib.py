@@ -87,6 +87,8 @@ _SIGS = {
     "gp_get_shape": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                              ctypes.POINTER(c_int)]),
     "gp_set_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int]),
+    "gp_get_radix_plan": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+    "gp_set_radix_plan": (c_int, [c_void_p, c_int, c_int, ctypes.POINTER(c_int), c_int]),
     "ws_param_count": (c_longlong, []),
     "ws_create": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_int, c_int, c_int]),
     "ws_destroy": (c_int, [c_void_p]),

@@ -315,6 +315,17 @@ class Context:
         self._check(self._lib.gp_set_shape(self._h, int(bool(fp64)), int(n), int(row_groups), int(col_groups),
                                            int(tile_width)))
 
+    def get_radix_plan(self, fp64: bool, n: int):
+        """Radices of the Stockham passes of length-n transforms (n 7-smooth, not a power of two)."""
+        r = (ctypes.c_int * 16)()
+        k = ctypes.c_int()
+        self._check(self._lib.gp_get_radix_plan(self._h, int(bool(fp64)), int(n), r, ctypes.byref(k)))
+        return [r[i] for i in range(k.value)]
+
+    def set_radix_plan(self, fp64: bool, n: int, radices):
+        r = (ctypes.c_int * 16)(*[int(x) for x in radices][:16])
+        self._check(self._lib.gp_set_radix_plan(self._h, int(bool(fp64)), int(n), r, len(radices)))
+
     def pd_gap(self, st: State):
         rep = L.gp_report()
         self._check(self._lib.pd_gap(self._h, ctypes.byref(st.c), ctypes.byref(rep)))

@@ -93,6 +93,7 @@ struct gp_ctx {
   size_t wsbuf_floats = 0;
   // non-power-of-two sides: tables per length, solver arena (grow-only)
   std::map<int, GenTab> gtab;
+  std::map<int, GenSched> gplan[2];  // radix plan per length [FP32, FP64]: measured or set
   float* garena = nullptr;
   size_t garena_floats = 0;
   // batch arena (grow-only)
@@ -843,8 +844,6 @@ int validate_state(gp_ctx* c, const gp_state* s) {
   return prepare(c, s->ny, s->nx, s->h);
 }
 
-#include "gprox_generic.inc"
-
 // ---------------------------------------------------------------- autotuner
 // median time (ms) of `reps` runs of launch() on the context stream, after one warm-up
 template <class F> double time_ms(gp_ctx* c, F&& launch, int reps = 3) {
@@ -870,6 +869,8 @@ template <class F> double time_ms(gp_ctx* c, F&& launch, int reps = 3) {
   std::sort(ts.begin(), ts.end());
   return (hipGetLastError() == hipSuccess) ? ts[ts.size() / 2] : 1e30;
 }
+
+#include "gprox_generic.inc"
 
 // Chooses the launch shapes of a group's kernels by measurement.  The column
 // setting also fixes the strip width of the tiled intermediate that the row
@@ -1907,12 +1908,21 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     RCHK(fill_mu(c, bg.mu64, bg.mu32, bg.mu64 + g.nyi, bg.mu32 + g.nyi, g.nyi, g.nx, g.h));
     HIPCHK(c, hipStreamSynchronize(c->stream));  // `ones` leaves scope
   }
-  // ---- transform tables of the non-power-of-two sides (no allocation inside the capture)
+  // ---- transform tables and radix plans of the non-power-of-two sides (no
+  // allocation or measurement inside the capture)
   for (auto& bg : G)
     if (bg.gen) {
       const GenTab* T;
+      GenSched sp;
       RCHK(gen_tables(c, bg.g.nyi, &T));
       RCHK(gen_tables(c, bg.g.nx, &T));
+      if (bg.g.kind == GP_KIND_EMD) {
+        RCHK(gen_plan<double2>(c, bg.g.nyi, &sp));
+        RCHK(gen_plan<double2>(c, bg.g.nx, &sp));
+      } else {
+        RCHK(gen_plan<float2>(c, bg.g.nyi, &sp));
+        RCHK(gen_plan<float2>(c, bg.g.nx, &sp));
+      }
     }
   // ---- launch shapes: measured per precision and size on first use
   for (auto& bg : G) {
@@ -2233,6 +2243,39 @@ int gp_set_shape(gp_ctx* c, int fp64, int n, int row_groups, int col_groups, int
   if (col_groups) c->col_g[di][ln] = col_groups;
   if (tile_width) c->col_lw[di][ln] = ilog2i(tile_width);
   if (col_groups || tile_width) c->col_tuned[di][ln] = true;
+  return GP_OK;
+}
+
+int gp_get_radix_plan(gp_ctx* c, int fp64, int n, int* radices, int* count) {
+  if (!c || !radices || !count) return GP_EINVAL;
+  if (!is_side(n) || is_pow2i(n)) {
+    set_err(c, "n=%d is not a 7-smooth side in [%d, %d] other than a power of two", n, kMinN, kMaxN);
+    return GP_EUNSUPPORTED;
+  }
+  const auto& P = c->gplan[fp64 ? 1 : 0];
+  const auto it = P.find(n);
+  const GenSched sp = it != P.end() ? it->second : gen_candidates(n)[0];
+  for (int i = 0; i < kGenMaxPasses; ++i) radices[i] = i < sp.np ? sp.r[i] : 0;
+  *count = sp.np;
+  return GP_OK;
+}
+
+int gp_set_radix_plan(gp_ctx* c, int fp64, int n, const int* radices, int count) {
+  if (!c || !radices) return GP_EINVAL;
+  if (!is_side(n) || is_pow2i(n)) {
+    set_err(c, "n=%d is not a 7-smooth side in [%d, %d] other than a power of two", n, kMinN, kMaxN);
+    return GP_EUNSUPPORTED;
+  }
+  if (!valid_plan(n, radices, count)) {
+    set_err(c, "radix plan invalid for n=%d (radices 2, 3, 4, 5, 7, 8 with product n, at most %d passes)", n,
+            kGenMaxPasses);
+    return GP_EINVAL;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  GenSched sp{};
+  sp.n = n;
+  for (int i = 0; i < count; ++i) sp.r[sp.np++] = radices[i];
+  c->gplan[fp64 ? 1 : 0][n] = sp;
   return GP_OK;
 }
 

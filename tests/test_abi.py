@@ -58,6 +58,8 @@ def test_strerror_and_null_arguments(lib):
     assert lib.dct_poisson3_f64(None, None, None, 64, 64, 64, 1.0, 0.0) == -1
     assert lib.rof3_solve(None, None, None, None, 64, 64, 64, 1.0, 8.0, None, None) == -1
     assert lib.emd3_solve(None, None, None, None, None, 64, 64, 64, 1.0, None, None) == -1
+    assert lib.gp_get_radix_plan(None, 0, 720, None, None) == -1
+    assert lib.gp_set_radix_plan(None, 0, 720, None, 0) == -1
 
 
 def test_warm_start_blob_size_matches_the_oracle_network(lib):

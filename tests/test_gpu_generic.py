@@ -225,3 +225,47 @@ def test_batch_with_generic_sides_equals_single_solves(gpctx):
     err = abs(orof.primal(host(outs[2]), I, 1.0, 8.0) - ref.primal) / ref.primal
     print("oracle objective error", err)
     assert err <= 1e-4
+
+
+PLANS_720 = [[5, 3, 3, 8, 2], [8, 2, 5, 3, 3], [5, 3, 3, 4, 4], [4, 4, 5, 3, 3], [2, 3, 2, 5, 2, 3, 2]]
+
+
+@pytest.mark.parametrize("plan", PLANS_720)
+def test_every_radix_plan_computes_the_same_solve(plan):
+    """720 = 2^4 3^2 5: the candidate plans the tuner times and one it never
+    picks (radix 2 and 3 passes interleaved) all give the oracle's solve in FP32
+    and FP64, and the plan set is the plan used."""
+    import torch
+    from paper_1805_09453_amd import Context
+    n = 720
+    b = f32(np.random.default_rng(5).standard_normal((n, n)))
+    ref = grid.poisson_solve(b, 1.0, 0.3)
+    with Context(n, n) as ctx:
+        ctx.set_radix_plan(False, n, plan)
+        ctx.set_radix_plan(True, n, plan)
+        assert ctx.get_radix_plan(False, n) == plan and ctx.get_radix_plan(True, n) == plan
+        announce(f"dct_poisson {n}x{n} with radix plan {plan}")
+        err = field_err(host(ctx.dct_poisson(dev(b), h=1.0, alpha=0.3)), ref)
+        err64 = field_err(ctx.dct_poisson_f64(dev(b, torch.float64), h=1.0, alpha=0.3).cpu().numpy(), ref)
+        print(plan, f"FP32 {err:.2e}  FP64 {err64:.2e}")
+        assert err <= 5e-6 and err64 <= 1e-12
+        assert ctx.get_radix_plan(False, n) == plan
+
+
+def test_radix_plan_tuned_on_first_use_and_validated():
+    from paper_1805_09453_amd import Context, GPError
+    n = 720
+    with Context(n, n) as ctx:
+        default = ctx.get_radix_plan(False, n)
+        assert default == [5, 3, 3, 8, 2]
+        ctx.dct_poisson(dev(np.ones((n, n))), h=1.0, alpha=0.3)   # measures the FP32 candidates
+        plan = ctx.get_radix_plan(False, n)
+        print("tuned FP32 plan for 720:", plan)
+        assert plan in PLANS_720[:4] and int(np.prod(plan)) == n
+        for bad in ([6, 120], [8, 2, 5, 3, 2], [2] * 17, []):
+            with pytest.raises(GPError):
+                ctx.set_radix_plan(False, n, bad)
+        with pytest.raises(GPError):
+            ctx.get_radix_plan(False, 512)   # powers of two have their fixed schedule
+        with pytest.raises(GPError):
+            ctx.get_radix_plan(False, 110)   # 11 is not a supported factor
