@@ -2275,6 +2275,7 @@ int gp_set_radix_plan(gp_ctx* c, int fp64, int n, const int* radices, int count)
   GenSched sp{};
   sp.n = n;
   for (int i = 0; i < count; ++i) sp.r[sp.np++] = radices[i];
+  plan_spans(sp);
   c->gplan[fp64 ? 1 : 0][n] = sp;
   return GP_OK;
 }

@@ -22,10 +22,15 @@ namespace gp {
 
 constexpr int kGenMaxPasses = 16;
 constexpr int kGenThreads = 256;
-// radix schedule of a length: passes in order
+// radix schedule of a length: passes in order; per pass the span ns of the
+// sub-transforms already done (product of the earlier radices) and M = 2^32 / ns
+// rounded up, so that j / ns = umulhi(j, M) for every j < n (exact while j and
+// ns are below 2^16; ns = 1 is handled apart)
 struct GenSched {
   int n, np;
   int r[kGenMaxPasses];
+  int ns[kGenMaxPasses];
+  unsigned mg[kGenMaxPasses];
 };
 
 // DFT of R points (R = 3, 5, 7) by direct sums, sign exp(-+2 pi i / R)
@@ -57,48 +62,51 @@ template <int R, bool INV, class C> __device__ __forceinline__ void dft_any(C* a
 
 // One Stockham butterfly of radix R: inputs src[j + r n/R], twiddled by
 // W_n^{r k n/(ns R)} (k = j mod ns), outputs dst[(j/ns) ns R + k + r ns].
-// W holds W_n^m = exp(-2 pi i m / n), m < n (conjugated for the inverse).
+// W holds W_n^m = exp(-2 pi i m / n), m < n (conjugated for the inverse); the
+// twiddle index r k n/(ns R) is below n since r < R and k < ns.
 template <int R, bool INV, class C>
-__device__ __forceinline__ void gen_bfly(const C* src, C* dst, int j, int n, int ns, const C* __restrict__ W) {
-  const int k = j % ns;
+__device__ __forceinline__ void gen_bfly(const C* src, C* dst, int j, int n, int ns, unsigned mg, const C* W) {
+  const int jq = ns == 1 ? j : int(__umulhi(unsigned(j), mg));
+  const int k = j - jq * ns;
   const int step = n / (ns * R);
   C x[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     C v = src[j + r * (n / R)];
     if (r > 0 && k > 0) {
-      C w = W[(r * k * step) % n];
+      C w = W[r * k * step];
       if (INV) w.y = -w.y;
       v = cmul(v, w);
     }
     x[r] = v;
   }
   dft_any<R, INV, C>(x);
-  const int base = (j / ns) * ns * R + k;
+  const int base = jq * ns * R + k;
 #pragma unroll
   for (int r = 0; r < R; ++r) dst[base + r * ns] = x[r];
 }
 
-// FFT of the sequence in buf[0] (length n); returns the buffer holding the result
+// FFT of the sequence in b0 (length n) by the tid-th of TG threads of a group;
+// returns the buffer holding the result.  Every thread of the workgroup calls it
+// (it synchronises the workgroup after each pass).
 template <bool INV, class C>
-__device__ C* gen_fft(C* b0, C* b1, const GenSched& s, const C* __restrict__ W) {
+__device__ C* gen_fft(C* b0, C* b1, const GenSched& s, const C* W, int tid, int TG) {
   C* src = b0;
   C* dst = b1;
-  int ns = 1;
   for (int p = 0; p < s.np; ++p) {
-    const int R = s.r[p], nb = s.n / R;
-    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    const int R = s.r[p], nb = s.n / R, ns = s.ns[p];
+    const unsigned mg = s.mg[p];
+    for (int j = tid; j < nb; j += TG) {
       switch (R) {
-        case 2: gen_bfly<2, INV>(src, dst, j, s.n, ns, W); break;
-        case 3: gen_bfly<3, INV>(src, dst, j, s.n, ns, W); break;
-        case 4: gen_bfly<4, INV>(src, dst, j, s.n, ns, W); break;
-        case 5: gen_bfly<5, INV>(src, dst, j, s.n, ns, W); break;
-        case 7: gen_bfly<7, INV>(src, dst, j, s.n, ns, W); break;
-        default: gen_bfly<8, INV>(src, dst, j, s.n, ns, W); break;
+        case 2: gen_bfly<2, INV>(src, dst, j, s.n, ns, mg, W); break;
+        case 3: gen_bfly<3, INV>(src, dst, j, s.n, ns, mg, W); break;
+        case 4: gen_bfly<4, INV>(src, dst, j, s.n, ns, mg, W); break;
+        case 5: gen_bfly<5, INV>(src, dst, j, s.n, ns, mg, W); break;
+        case 7: gen_bfly<7, INV>(src, dst, j, s.n, ns, mg, W); break;
+        default: gen_bfly<8, INV>(src, dst, j, s.n, ns, mg, W); break;
       }
     }
     __syncthreads();
-    ns *= R;
     C* t = src;
     src = dst;
     dst = t;
@@ -107,63 +115,79 @@ __device__ C* gen_fft(C* b0, C* b1, const GenSched& s, const C* __restrict__ W) 
 }
 
 // Row transforms of stacked instances (m instances of `rows` rows of length n,
-// row-major, row stride n).  One workgroup per row pair of an instance (rows
-// 2q, 2q + 1; a lone last row is paired with zeros), so an instance's results do
-// not depend on the others in the stack.
+// row-major, row stride n).  A group of TG = blockDim.x / PB threads per row
+// pair of an instance (rows 2q, 2q + 1; a lone last row is paired with zeros),
+// PB pairs per workgroup, so an instance's results do not depend on the others
+// in the stack or on PB.  With WL the twiddle table W is staged in LDS.
 //   mode 0: forward DCT-II, X_k = sum_j x_j cos(pi k (2j + 1) / 2n)
 //   mode 1: inverse of it times n (out += result when acc)
 //   mode 2: forward, times inv_nn / (alpha + mu_seq[k] + mu_row[row]) (the
 //           zero mode dropped where that is 0), inverse times n: the column
 //           solve of the transposed field
-template <class C>
+template <class C, bool WL>
 __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::R* in, typename Cx<C>::R* out,
-                                                          int rows, int m, GenSched s, const C* __restrict__ W,
+                                                          int rows, int m, GenSched s, const C* __restrict__ Wg,
                                                           const C* __restrict__ dw, const int* __restrict__ active,
                                                           int mode, int acc, const typename Cx<C>::R* __restrict__ mu_seq,
                                                           const typename Cx<C>::R* __restrict__ mu_row,
-                                                          typename Cx<C>::R alpha, typename Cx<C>::R inv_nn) {
+                                                          typename Cx<C>::R alpha, typename Cx<C>::R inv_nn, int PB) {
   using Re = typename Cx<C>::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* b0 = reinterpret_cast<C*>(smem_raw);
-  C* b1 = b0 + s.n;
   const int n = s.n;
+  const int TG = blockDim.x / PB, g = threadIdx.x / TG, tid = threadIdx.x - g * TG;
   const int ppi = (rows + 1) / 2;
-  const int inst = blockIdx.x / ppi, q = blockIdx.x - inst * ppi;
-  if (inst >= m || !inst_active(active, inst)) return;  // whole workgroup
+  // the whole workgroup leaves when none of its row pairs is live
+  bool any = false;
+  for (int e = 0; e < PB; ++e) {
+    const int pe = blockIdx.x * PB + e, ie = pe / ppi;
+    any = any || (ie < m && inst_active(active, ie));
+  }
+  if (!any) return;
+  C* b0 = reinterpret_cast<C*>(smem_raw) + size_t(g) * 2 * n;
+  C* b1 = b0 + n;
+  const C* W = Wg;
+  if constexpr (WL) {
+    C* wl = reinterpret_cast<C*>(smem_raw) + size_t(PB) * 2 * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) wl[i] = Wg[i];
+    W = wl;  // visible after the barrier below
+  }
+  const int pair = blockIdx.x * PB + g;
+  const int inst = pair / ppi, q = pair - inst * ppi;
+  const bool live = inst < m && inst_active(active, inst);
   const int r0 = 2 * q, r1 = r0 + 1;
-  const bool has1 = r1 < rows;
-  const size_t o0 = (size_t(inst) * rows + r0) * n, o1 = (size_t(inst) * rows + (has1 ? r1 : r0)) * n;
+  const bool has1 = live && r1 < rows;
+  const size_t o0 = live ? (size_t(inst) * rows + r0) * n : 0, o1 = has1 ? o0 + n : o0;
   if (mode == 1) {
     // Z_k = V^a_k + i V^b_k, V_k = conj(w_k) (X_k - i X_{n-k}), X_n = 0
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-      const Re xa = in[o0 + k], xb = has1 ? in[o1 + k] : Re(0);
-      const Re ya = k ? in[o0 + n - k] : Re(0), yb = (k && has1) ? in[o1 + n - k] : Re(0);
+    for (int k = tid; k < n; k += TG) {
+      const Re xa = live ? in[o0 + k] : Re(0), xb = has1 ? in[o1 + k] : Re(0);
+      const Re ya = (k && live) ? in[o0 + n - k] : Re(0), yb = (k && has1) ? in[o1 + n - k] : Re(0);
       const C w = mk<C>(dw[k].x, -dw[k].y);
       const C va = cmul(w, mk<C>(xa, -ya)), vb = cmul(w, mk<C>(xb, -yb));
       b0[k] = mk<C>(va.x - vb.y, va.y + vb.x);
     }
   } else {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int j = tid; j < n; j += TG) {
       const int src = j < (n + 1) / 2 ? 2 * j : 2 * (n - 1 - j) + 1;  // Makhoul order
-      b0[j] = mk<C>(in[o0 + src], has1 ? in[o1 + src] : Re(0));
+      b0[j] = mk<C>(live ? in[o0 + src] : Re(0), has1 ? in[o1 + src] : Re(0));
     }
   }
   __syncthreads();
   C* res;
   if (mode == 1) {
-    res = gen_fft<true>(b0, b1, s, W);
+    res = gen_fft<true>(b0, b1, s, W, tid, TG);
   } else {
-    res = gen_fft<false>(b0, b1, s, W);
+    res = gen_fft<false>(b0, b1, s, W, tid, TG);
     C* oth = res == b0 ? b1 : b0;
     // split the two real transforms: A_k = (Z_k + conj Z_{n-k}) / 2, B_k = (Z_k - conj Z_{n-k}) / 2i,
     // X_k = Re(w_k A_k); mode 2 scales and re-packs for the inverse
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    for (int k = tid; k < n; k += TG) {
       const C z = res[k], zr = res[k ? n - k : 0];
       const C A = mk<C>(Re(0.5) * (z.x + zr.x), Re(0.5) * (z.y - zr.y));
       const C B = mk<C>(Re(0.5) * (z.y + zr.y), Re(-0.5) * (z.x - zr.x));
       Re xa = dw[k].x * A.x - dw[k].y * A.y, xb = dw[k].x * B.x - dw[k].y * B.y;
       if (mode == 0) {
-        out[o0 + k] = xa;
+        if (live) out[o0 + k] = xa;
         if (has1) out[o1 + k] = xb;
       } else {
         const Re da = alpha + mu_seq[k] + mu_row[r0], db = alpha + mu_seq[k] + mu_row[has1 ? r1 : r0];
@@ -174,17 +198,18 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
     }
     if (mode == 0) return;
     __syncthreads();
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    for (int k = tid; k < n; k += TG) {
       const C x = oth[k], y = k ? oth[n - k] : mk<C>(Re(0), Re(0));
       const C w = mk<C>(dw[k].x, -dw[k].y);
       const C va = cmul(w, mk<C>(x.x, -y.x)), vb = cmul(w, mk<C>(x.y, -y.y));
       res[k] = mk<C>(va.x - vb.y, va.y + vb.x);
     }
     __syncthreads();
-    res = gen_fft<true>(res, oth, s, W);
+    res = gen_fft<true>(res, oth, s, W, tid, TG);
   }
   // un-Makhoul: x_{2m} = z_m, x_{2m+1} = z_{n-1-m}
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  if (!live) return;
+  for (int j = tid; j < n; j += TG) {
     const int src = (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
     const C v = res[src];
     if (acc) {
