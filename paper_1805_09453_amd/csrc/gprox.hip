@@ -115,13 +115,13 @@ namespace {
 // kernel kinds for gp_profile
 enum KId {
   K_ROWS_FWD, K_COLS, K_ROWS_INV, K_ROWS_FWD64, K_COLS64, K_ROWS_INV64, K_ROF_A, K_ROF_B, K_ROF_FINISH,
-  K_EMD_A, K_EMD_B, K_EMD_FINISH, K_DIV64, K_REDUCE, K_GEN_ROWS, K_GEN_ROWS64, K_GEN_T, K_GEN_ROF_RHS,
+  K_EMD_A, K_EMD_B, K_EMD_FINISH, K_DIV64, K_REDUCE, K_GEN_ROWS, K_GEN_ROWS64, K_GEN_ROF_RHS,
   K_GEN_ROF_DUAL, K_GEN_EMD_RHS, K_GEN_EMD_UPDATE, K_COUNT
 };
 const char* kKName[K_COUNT] = {"rows_fwd_dct2", "cols_solve", "rows_inv_dct2", "rows_fwd_dct2_f64",
                                "cols_solve_f64", "rows_inv_dct2_f64", "rof_A_prox_rhs_dct", "rof_B_idct_update",
                                "rof_finish", "emd_A_prox_rhs_dct", "emd_B_idct", "emd_finish", "div_f64",
-                               "reduce", "gen_rows_dct", "gen_rows_dct_f64", "gen_transpose", "gen_rof_rhs",
+                               "reduce", "gen_rows_dct", "gen_rows_dct_f64", "gen_rof_rhs",
                                "gen_rof_dual", "gen_emd_rhs", "gen_emd_update"};
 constexpr int kProfPool = 16384;
 

@@ -7,9 +7,9 @@
 // reordering (v_m = x_{2m} for 2m < n, v_{n-1-m} = x_{2m+1} for 2m + 1 < n;
 // X_k = Re(exp(-i pi k / 2n) V_k)); here the FFT is a mixed-radix Stockham
 // transform (radices 8, 4, 2, 3, 5, 7, so n must be 7-smooth) running out of
-// two LDS buffers, one workgroup per row pair, one butterfly per thread and
-// pass.  The 2-D solve is row transform -> transpose -> column transform,
-// diagonal scale and inverse column transform (one kernel) -> transpose ->
+// two LDS buffers, a thread group per row pair, one butterfly per thread and
+// pass.  The 2-D solve is row transform -> column transform, diagonal scale
+// and inverse column transform (one kernel reading the columns in place) ->
 // inverse row transform.  The iteration around it is unfused: separate
 // kernels form the right-hand side, update the primal and take the dual step.
 #pragma once
@@ -115,22 +115,26 @@ __device__ C* gen_fft(C* b0, C* b1, const GenSched& s, const C* W, int tid, int 
 }
 
 // Row transforms of stacked instances (m instances of `rows` rows of length n,
-// row-major, row stride n).  A group of TG = blockDim.x / PB threads per row
-// pair of an instance (rows 2q, 2q + 1; a lone last row is paired with zeros),
-// PB pairs per workgroup, so an instance's results do not depend on the others
-// in the stack or on PB.  With WL the twiddle table W is staged in LDS.
+// row-major, row stride n), or with cols = 1 column transforms (m instances of
+// n rows by `rows` columns, row-major: the sequences are the columns, element
+// stride `rows`).  A group of TG = blockDim.x / PB threads per row (column) pair
+// of an instance (2q, 2q + 1; a lone last one is paired with zeros), PB pairs
+// per workgroup, so an instance's results do not depend on the others in the
+// stack or on PB.  With WL the twiddle table W is staged in LDS.  A pair is read
+// whole before it is written, so in may equal out.
 //   mode 0: forward DCT-II, X_k = sum_j x_j cos(pi k (2j + 1) / 2n)
 //   mode 1: inverse of it times n (out += result when acc)
 //   mode 2: forward, times inv_nn / (alpha + mu_seq[k] + mu_row[row]) (the
 //           zero mode dropped where that is 0), inverse times n: the column
-//           solve of the transposed field
+//           solve (with cols = 1)
 template <class C, bool WL>
 __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::R* in, typename Cx<C>::R* out,
                                                           int rows, int m, GenSched s, const C* __restrict__ Wg,
                                                           const C* __restrict__ dw, const int* __restrict__ active,
                                                           int mode, int acc, const typename Cx<C>::R* __restrict__ mu_seq,
                                                           const typename Cx<C>::R* __restrict__ mu_row,
-                                                          typename Cx<C>::R alpha, typename Cx<C>::R inv_nn, int PB) {
+                                                          typename Cx<C>::R alpha, typename Cx<C>::R inv_nn, int PB,
+                                                          int cols) {
   using Re = typename Cx<C>::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = s.n;
@@ -156,12 +160,14 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
   const bool live = inst < m && inst_active(active, inst);
   const int r0 = 2 * q, r1 = r0 + 1;
   const bool has1 = live && r1 < rows;
-  const size_t o0 = live ? (size_t(inst) * rows + r0) * n : 0, o1 = has1 ? o0 + n : o0;
+  const size_t es = cols ? size_t(rows) : 1;  // element stride of a sequence
+  const size_t o0 = !live ? 0 : cols ? size_t(inst) * n * rows + r0 : (size_t(inst) * rows + r0) * n;
+  const size_t o1 = !has1 ? o0 : cols ? o0 + 1 : o0 + n;
   if (mode == 1) {
     // Z_k = V^a_k + i V^b_k, V_k = conj(w_k) (X_k - i X_{n-k}), X_n = 0
     for (int k = tid; k < n; k += TG) {
-      const Re xa = live ? in[o0 + k] : Re(0), xb = has1 ? in[o1 + k] : Re(0);
-      const Re ya = (k && live) ? in[o0 + n - k] : Re(0), yb = (k && has1) ? in[o1 + n - k] : Re(0);
+      const Re xa = live ? in[o0 + k * es] : Re(0), xb = has1 ? in[o1 + k * es] : Re(0);
+      const Re ya = (k && live) ? in[o0 + (n - k) * es] : Re(0), yb = (k && has1) ? in[o1 + (n - k) * es] : Re(0);
       const C w = mk<C>(dw[k].x, -dw[k].y);
       const C va = cmul(w, mk<C>(xa, -ya)), vb = cmul(w, mk<C>(xb, -yb));
       b0[k] = mk<C>(va.x - vb.y, va.y + vb.x);
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
   } else {
     for (int j = tid; j < n; j += TG) {
       const int src = j < (n + 1) / 2 ? 2 * j : 2 * (n - 1 - j) + 1;  // Makhoul order
-      b0[j] = mk<C>(live ? in[o0 + src] : Re(0), has1 ? in[o1 + src] : Re(0));
+      b0[j] = mk<C>(live ? in[o0 + src * es] : Re(0), has1 ? in[o1 + src * es] : Re(0));
     }
   }
   __syncthreads();
@@ -187,8 +193,8 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
       const C B = mk<C>(Re(0.5) * (z.y + zr.y), Re(-0.5) * (z.x - zr.x));
       Re xa = dw[k].x * A.x - dw[k].y * A.y, xb = dw[k].x * B.x - dw[k].y * B.y;
       if (mode == 0) {
-        if (live) out[o0 + k] = xa;
-        if (has1) out[o1 + k] = xb;
+        if (live) out[o0 + k * es] = xa;
+        if (has1) out[o1 + k * es] = xb;
       } else {
         const Re da = alpha + mu_seq[k] + mu_row[r0], db = alpha + mu_seq[k] + mu_row[has1 ? r1 : r0];
         xa = da > Re(0) ? xa * (inv_nn / da) : Re(0);
@@ -213,32 +219,12 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
     const int src = (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
     const C v = res[src];
     if (acc) {
-      out[o0 + j] += v.x;
-      if (has1) out[o1 + j] += v.y;
+      out[o0 + j * es] += v.x;
+      if (has1) out[o1 + j * es] += v.y;
     } else {
-      out[o0 + j] = v.x;
-      if (has1) out[o1 + j] = v.y;
+      out[o0 + j * es] = v.x;
+      if (has1) out[o1 + j * es] = v.y;
     }
-  }
-}
-
-// out[inst][c][r] = in[inst][r][c] for each instance (blockIdx.z); 32 x 32 tiles
-template <class T>
-__global__ __launch_bounds__(256) void k_gen_transpose(const T* __restrict__ in, T* __restrict__ out, int rows,
-                                                       int cols, const int* __restrict__ active) {
-  __shared__ T tile[32][33];
-  const int inst = blockIdx.z;
-  if (!inst_active(active, inst)) return;
-  const size_t base = size_t(inst) * rows * cols;
-  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
-  for (int i = threadIdx.y; i < 32; i += 8) {
-    const int r = r0 + i, c = c0 + threadIdx.x;
-    if (r < rows && c < cols) tile[i][threadIdx.x] = in[base + size_t(r) * cols + c];
-  }
-  __syncthreads();
-  for (int i = threadIdx.y; i < 32; i += 8) {
-    const int c = c0 + i, r = r0 + threadIdx.x;
-    if (r < rows && c < cols) out[base + size_t(c) * rows + r] = tile[threadIdx.x][i];
   }
 }
 
