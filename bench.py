@@ -27,8 +27,8 @@ HBM_PEAK_GBPS = 8000.0
 # the per-iteration kernels (the set-up, checks and certificate kernels are excluded
 # from the per-iteration byte count)
 ITER_KERNELS = {"rof_A_prox_rhs_dct", "cols_solve", "rof_B_idct_update", "emd_A_prox_rhs_dct", "cols_solve_f64",
-                "emd_B_idct", "gen_rows_dct", "gen_rows_dct_f64", "gen_rof_rhs", "gen_rof_dual",
-                "gen_emd_rhs", "gen_emd_update"}
+                "emd_B_idct", "gen_rows_dct", "gen_rows_dct_f64", "gen_rof_dual",
+                "gen_emd_update"}
 
 
 def parse():

@@ -115,14 +115,14 @@ namespace {
 // kernel kinds for gp_profile
 enum KId {
   K_ROWS_FWD, K_COLS, K_ROWS_INV, K_ROWS_FWD64, K_COLS64, K_ROWS_INV64, K_ROF_A, K_ROF_B, K_ROF_FINISH,
-  K_EMD_A, K_EMD_B, K_EMD_FINISH, K_DIV64, K_REDUCE, K_GEN_ROWS, K_GEN_ROWS64, K_GEN_ROF_RHS,
-  K_GEN_ROF_DUAL, K_GEN_EMD_RHS, K_GEN_EMD_UPDATE, K_COUNT
+  K_EMD_A, K_EMD_B, K_EMD_FINISH, K_DIV64, K_REDUCE, K_GEN_ROWS, K_GEN_ROWS64,
+  K_GEN_ROF_DUAL, K_GEN_EMD_UPDATE, K_COUNT
 };
 const char* kKName[K_COUNT] = {"rows_fwd_dct2", "cols_solve", "rows_inv_dct2", "rows_fwd_dct2_f64",
                                "cols_solve_f64", "rows_inv_dct2_f64", "rof_A_prox_rhs_dct", "rof_B_idct_update",
                                "rof_finish", "emd_A_prox_rhs_dct", "emd_B_idct", "emd_finish", "div_f64",
-                               "reduce", "gen_rows_dct", "gen_rows_dct_f64", "gen_rof_rhs",
-                               "gen_rof_dual", "gen_emd_rhs", "gen_emd_update"};
+                               "reduce", "gen_rows_dct", "gen_rows_dct_f64",
+                               "gen_rof_dual", "gen_emd_update"};
 constexpr int kProfPool = 16384;
 
 // records a start event for a launch of kind id moving `bytes`; returns the slot or -1
@@ -1047,9 +1047,7 @@ void carve(Carver& A, BatchGroup& bg) {
       g.u = q.u = A.take<float>(nt);
       g.p = q.p = A.take<float>(2 * nt);
       g.pbar = q.pbar = A.take<float>(2 * nt);
-      q.r = A.take<float>(nt);
       q.t1 = A.take<float>(nt);
-      q.t2 = A.take<float>(nt);
       q.part = A.take<double>(size_t(g.m) * nbk * 4);
       bg.gap_dev = A.take<double>(size_t(g.m) * 4);
     } else {
@@ -1059,7 +1057,6 @@ void carve(Carver& A, BatchGroup& bg) {
       g.pbar = q.pbar = A.take<float>(2 * nt);
       q.phi = A.take<double>(nt);
       q.t1d = A.take<double>(nt);
-      q.t2d = A.take<double>(nt);
       q.part = A.take<double>(size_t(g.m) * nbk * 2);
       bg.gap_dev = A.take<double>(g.m);
       bg.cert_dev = A.take<double>(size_t(g.m) * 2);
@@ -1310,7 +1307,7 @@ int dct_poisson(gp_ctx* c, const float* b, float* x, int ny, int nx, double h, d
   }
   RCHK(prepare(c, ny, nx, h));
   if (is_gen(ny, nx))
-    return poisson_gen<float2>(c, b, x, ny, nx, 1, nullptr, c->mux32, c->muy32, alpha, c->work, c->work2, false);
+    return poisson_gen<float2>(c, b, x, ny, nx, 1, nullptr, c->mux32, c->muy32, alpha, c->work, false);
   return poisson_f32(c, b, x, ny, nx, 1, c->mux32, c->muy32, alpha, c->work);
 }
 
@@ -1369,8 +1366,7 @@ int dct_poisson_f64(gp_ctx* c, const double* b, double* x, int ny, int nx, doubl
   }
   RCHK(prepare(c, ny, nx, h));
   if (is_gen(ny, nx))
-    return poisson_gen<double2>(c, b, x, ny, nx, 1, nullptr, c->mux64, c->muy64, alpha, c->work64,
-                                c->work64 + size_t(ny) * nx, false);
+    return poisson_gen<double2>(c, b, x, ny, nx, 1, nullptr, c->mux64, c->muy64, alpha, c->work64, false);
   return poisson_f64(c, b, x, ny, nx, 1, nullptr, c->mux64, c->muy64, alpha, c->work64);
 }
 

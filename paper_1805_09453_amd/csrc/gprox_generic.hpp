@@ -15,6 +15,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/gprox.h"
 #include "gprox_fft.hpp"
 #include "gprox_kernels.hpp"
 
@@ -114,6 +115,37 @@ __device__ C* gen_fft(C* b0, C* b1, const GenSched& s, const C* W, int tid, int 
   return src;
 }
 
+// Optional right-hand side formed in the loads of a forward row transform
+// (mode 0, rows), from a stacked vector field [2][m rows][n] (ntot cells per
+// component) in the expressions of the unfused iteration:
+//   EMD (FP64): b = -div(u - tau pbar) / h, so that the solve of
+//               (0 - Delta) phi = b gives phi = Delta^{-1} div(u - tau pbar);
+//   ROF (FP32): r = lt (I - u) + tau_h div pbar  (lt = lambda tau, tau_h = tau / h).
+struct GenRhs {
+  int kind;  // GP_KIND_ROF or GP_KIND_EMD
+  const float* u;
+  const float* pb;
+  const float* I;
+  size_t ntot;
+  float tau, lt, tau_h;
+  double inv_h;
+};
+__device__ __forceinline__ double gen_emd_b(const GenRhs& R, size_t o, int i, int j, int rows, int n) {
+  const double xr = j < n - 1 ? double(R.u[o]) - double(R.tau) * R.pb[o] : 0.0;
+  const double xl = j > 0 ? double(R.u[o - 1]) - double(R.tau) * R.pb[o - 1] : 0.0;
+  const double yu = i < rows - 1 ? double(R.u[R.ntot + o]) - double(R.tau) * R.pb[R.ntot + o] : 0.0;
+  const double yd = i > 0 ? double(R.u[R.ntot + o - n]) - double(R.tau) * R.pb[R.ntot + o - n] : 0.0;
+  return -((xr - xl) + (yu - yd)) * R.inv_h;
+}
+__device__ __forceinline__ float gen_rof_r(const GenRhs& R, size_t o, int i, int j, int rows, int n) {
+  const float xr = j < n - 1 ? R.pb[o] : 0.f, xl = j > 0 ? R.pb[o - 1] : 0.f;
+  const float yu = i < rows - 1 ? R.pb[R.ntot + o] : 0.f, yd = i > 0 ? R.pb[R.ntot + o - n] : 0.f;
+  return R.lt * (R.I[o] - R.u[o]) + R.tau_h * ((xr - xl) + (yu - yd));
+}
+template <class Re> __device__ __forceinline__ Re gen_rhs(const GenRhs& R, size_t o, int i, int j, int rows, int n) {
+  return R.kind == GP_KIND_EMD ? Re(gen_emd_b(R, o, i, j, rows, n)) : Re(gen_rof_r(R, o, i, j, rows, n));
+}
+
 // Row transforms of stacked instances (m instances of `rows` rows of length n,
 // row-major, row stride n), or with cols = 1 column transforms (m instances of
 // n rows by `rows` columns, row-major: the sequences are the columns, element
@@ -121,7 +153,8 @@ __device__ C* gen_fft(C* b0, C* b1, const GenSched& s, const C* W, int tid, int 
 // of an instance (2q, 2q + 1; a lone last one is paired with zeros), PB pairs
 // per workgroup, so an instance's results do not depend on the others in the
 // stack or on PB.  With WL the twiddle table W is staged in LDS.  A pair is read
-// whole before it is written, so in may equal out.
+// whole before it is written, so in may equal out.  With rh.u set (mode 0, rows)
+// the input is the right-hand side formed from the iterates instead of in.
 //   mode 0: forward DCT-II, X_k = sum_j x_j cos(pi k (2j + 1) / 2n)
 //   mode 1: inverse of it times n (out += result when acc)
 //   mode 2: forward, times inv_nn / (alpha + mu_seq[k] + mu_row[row]) (the
@@ -134,7 +167,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
                                                           int mode, int acc, const typename Cx<C>::R* __restrict__ mu_seq,
                                                           const typename Cx<C>::R* __restrict__ mu_row,
                                                           typename Cx<C>::R alpha, typename Cx<C>::R inv_nn, int PB,
-                                                          int cols) {
+                                                          int cols, GenRhs rh) {
   using Re = typename Cx<C>::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = s.n;
@@ -175,7 +208,11 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
   } else {
     for (int j = tid; j < n; j += TG) {
       const int src = j < (n + 1) / 2 ? 2 * j : 2 * (n - 1 - j) + 1;  // Makhoul order
-      b0[j] = mk<C>(live ? in[o0 + src * es] : Re(0), has1 ? in[o1 + src * es] : Re(0));
+      if (rh.u)  // rows, es = 1
+        b0[j] = mk<C>(live ? gen_rhs<Re>(rh, o0 + src, r0, src, rows, n) : Re(0),
+                      has1 ? gen_rhs<Re>(rh, o1 + src, r1, src, rows, n) : Re(0));
+      else
+        b0[j] = mk<C>(live ? in[o0 + src * es] : Re(0), has1 ? in[o1 + src * es] : Re(0));
     }
   }
   __syncthreads();
@@ -231,23 +268,6 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
 // ---------------------------------------------------------------- iteration kernels
 // Cells of m stacked instances of nyi x nx; stencils stop at instance edges.
 
-// ROF right-hand side r = lt (I - u) + tau_h div pbar
-__global__ __launch_bounds__(256) void k_gen_rof_rhs(const float* __restrict__ u, const float* __restrict__ pb,
-                                                     const float* __restrict__ I, float* __restrict__ r, int nyi,
-                                                     int nx, int m, float lt, float tau_h,
-                                                     const int* __restrict__ active) {
-  const size_t ntot = size_t(m) * nyi * nx, nn = size_t(nyi) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < ntot; o += size_t(gridDim.x) * blockDim.x) {
-    const int inst = int(o / nn);
-    if (!inst_active(active, inst)) continue;
-    const size_t l = o - size_t(inst) * nn;
-    const int i = int(l / nx), j = int(l - size_t(i) * nx);
-    const float xr = j < nx - 1 ? pb[o] : 0.f, xl = j > 0 ? pb[o - 1] : 0.f;
-    const float yu = i < nyi - 1 ? pb[ntot + o] : 0.f, yd = i > 0 ? pb[ntot + o - nx] : 0.f;
-    r[o] = lt * (I[o] - u[o]) + tau_h * ((xr - xl) + (yu - yd));
-  }
-}
-
 // ROF dual step p+ = proj(p + sig_h grad u), pbar = 2 p+ - p (pointwise in p)
 __global__ __launch_bounds__(256) void k_gen_rof_dual(const float* __restrict__ u, float* __restrict__ p,
                                                       float* __restrict__ pb, int nyi, int nx, int m, float sig_h,
@@ -294,25 +314,6 @@ __global__ __launch_bounds__(256) void k_gen_rof_gap(const float* __restrict__ u
   }
   const bool mx[4] = {false, false, false, false};
   block_reduce_store<4>(acc, mx, partials + size_t(inst) * gridDim.x * 4);
-}
-
-// EMD right-hand side of the projection (FP64): b = -div(u - tau pbar) / h
-// (the solve of (0 - Delta) phi = b gives phi = Delta^{-1} div(u - tau pbar))
-__global__ __launch_bounds__(256) void k_gen_emd_rhs(const float* __restrict__ u, const float* __restrict__ pb,
-                                                     double* __restrict__ b, int nyi, int nx, int m, float tau,
-                                                     double inv_h, const int* __restrict__ active) {
-  const size_t ntot = size_t(m) * nyi * nx, nn = size_t(nyi) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < ntot; o += size_t(gridDim.x) * blockDim.x) {
-    const int inst = int(o / nn);
-    if (!inst_active(active, inst)) continue;
-    const size_t l = o - size_t(inst) * nn;
-    const int i = int(l / nx), j = int(l - size_t(i) * nx);
-    const double xr = j < nx - 1 ? double(u[o]) - double(tau) * pb[o] : 0.0;
-    const double xl = j > 0 ? double(u[o - 1]) - double(tau) * pb[o - 1] : 0.0;
-    const double yu = i < nyi - 1 ? double(u[ntot + o]) - double(tau) * pb[ntot + o] : 0.0;
-    const double yd = i > 0 ? double(u[ntot + o - nx]) - double(tau) * pb[ntot + o - nx] : 0.0;
-    b[o] = -((xr - xl) + (yu - yd)) * inv_h;
-  }
 }
 
 // EMD update, pointwise in u, p, pbar: u+ = (u - tau pbar) - grad phi,
