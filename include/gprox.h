@@ -22,15 +22,17 @@
  * the caller; the library keeps no pointer after a call returns.  All work is
  * enqueued on the context's stream.  The library owns only the workspace in
  * its context, sized at gp_create for grids up to max_ny x max_nx (solve
- * calls may grow it; pd_step and pd_gap never allocate).
+ * calls may grow it; pd_step and pd_gap allocate nothing on power-of-two
+ * grids, see pd_step for the other sides).
  *
  * Sizes.  ny and nx must lie in [64, 4096] with no prime factor above 7
  * (7-smooth: 64, 72, 75, 80, 81, 84, 90, 96, ... 720, ... 4096) and at most the
  * context's maxima; other sizes return GP_EUNSUPPORTED.  Powers of two run the
  * fused register-resident transforms; other sides run the same iteration
- * unfused, with mixed-radix (2, 3, 4, 5, 7, 8) DCTs out of LDS and transposes
- * for the column pass (gp_opts.ergodic, the 3-D calls, dct_poisson_noalloc,
- * the launch-shape calls and the learned warm start need powers of two).
+ * unfused, with mixed-radix (2, 3, 4, 5, 7, 8) DCTs out of LDS, the column
+ * pass reading the columns in place (gp_opts.ergodic, the 3-D calls,
+ * dct_poisson_noalloc, the launch-shape calls and the learned warm start need
+ * powers of two).
  *
  * Errors.  Every entry point returns GP_OK (0), a negative GP_E* code, or
  * GP_ENOTCONV (> 0: max_iter reached, outputs valid, report filled).  No C++
@@ -203,7 +205,12 @@ double emd_step_rule_singular(double eps, double m);
  * updates of section 3.2 (u-step by the Leray projection, projected form
  * u+ = P(u - tau pbar)); the dual steps project pointwise onto |p| <= 1.
  * The state is the two-variable iterate (u_n, p_n, pbar_n) in either case.
- * Enqueues work only: never synchronises, never allocates. */
+ * On power-of-two grids it enqueues work only: never synchronises, never
+ * allocates.  On other grids the iteration's launches read a small device
+ * table of their arguments (the form gp_batch_solve uses, so that both compute
+ * the same bits); the first call for a state, and any call after the state's
+ * buffers or parameters changed, writes that table: it synchronises the
+ * stream once and may allocate a few KB.  Later calls only enqueue. */
 int pd_step(gp_ctx* ctx, gp_state* st, int n_iter);
 
 /* Primal value, dual value and relative gap of the state's (u_n, p_n);

@@ -59,6 +59,9 @@ struct Tables {  // per transform length N
 
 }  // namespace
 
+namespace {
+struct GenSingle;  // job tables of the single-group iteration on non-power-of-two grids
+}
 struct gp_ctx {
   hipStream_t stream = nullptr;   // the caller's stream
   hipStream_t bstream = nullptr;  // private stream of gp_batch_solve (graph capture and replay)
@@ -94,6 +97,7 @@ struct gp_ctx {
   // non-power-of-two sides: tables per length, solver arena (grow-only)
   std::map<int, GenTab> gtab;
   std::map<int, GenSched> gplan[2];  // radix plan per length [FP32, FP64]: measured or set
+  GenSingle* gsingle = nullptr;
   float* garena = nullptr;
   size_t garena_floats = 0;
   // batch arena (grow-only)
@@ -1283,6 +1287,7 @@ int gp_destroy(gp_ctx* c) {
   if (c->barena) (void)hipFree(c->barena);
   if (c->wsbuf) (void)hipFree(c->wsbuf);
   if (c->garena) (void)hipFree(c->garena);
+  delete c->gsingle;  // frees its job tables
   for (auto& kv : c->gtab) {
     GenTab& T = kv.second;
     void* gb[] = {T.w32, T.d32, T.w64, T.d64};
@@ -1380,7 +1385,7 @@ int pd_step(gp_ctx* c, gp_state* s, int n_iter) {
   if (n_iter == 0) return GP_OK;
   if (is_gen(s->ny, s->nx)) {
     const GenGroup g = gen_state_group(c, s);
-    for (int i = 0; i < n_iter; ++i) RCHK(s->kind == GP_KIND_ROF ? gen_rof_iter(c, g) : gen_emd_iter(c, g));
+    for (int i = 0; i < n_iter; ++i) RCHK(gen_single_iter(c, g));
     s->iter += n_iter;
     return GP_OK;
   }
@@ -1977,12 +1982,29 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
   // enough groups have retired completely (their launches would only exit).
   // Every pipeline's buffers return to their roles after the even chunk, so each
   // capture starts from the same state.
+  // groups with sides that are not powers of two: per kind, every live group's
+  // iteration as one set of launches (job tables written before each capture)
+  GenMulti mrof, memd;
+  auto build_multi = [&](const std::vector<int>& live) -> int {
+    std::vector<const GenGroup*> gr, ge;
+    for (int k : live)
+      if (G[k].gen) (G[k].g.kind == GP_KIND_ROF ? gr : ge).push_back(&G[k].gg);
+    RCHK(gen_multi_build<float2>(c, mrof, GP_KIND_ROF, gr));
+    RCHK(gen_multi_build<double2>(c, memd, GP_KIND_EMD, ge));
+    return GP_OK;
+  };
   auto capture = [&](const std::vector<int>& live) -> int {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
     graph = nullptr;
-    const int nsd = int(std::min<size_t>(live.size(), size_t(nside + 1))) - 1;
+    // branches: one per kind for the groups with other sides, one per power-of-two group
+    std::vector<int> units;
+    if (mrof.nj) units.push_back(-1);
+    if (memd.nj) units.push_back(-2);
+    for (int k : live)
+      if (!G[k].gen) units.push_back(k);
+    const int nsd = int(std::min<size_t>(units.size(), size_t(nside + 1))) - 1;
     int rc = GP_OK;
     if (hipStreamBeginCapture(c->bstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       set_err(c, "hipStreamBeginCapture failed");
@@ -1992,19 +2014,24 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     for (int s = 0; s < nsd && !rc; ++s)
       if (hipStreamWaitEvent(c->side[s], c->fork_ev, 0) != hipSuccess) rc = GP_EHIP;
     if (rc) set_err(c, "fork inside the capture failed");
-    for (size_t li = 0; li < live.size() && !rc; ++li) {
-      const int k = live[li];
+    for (size_t li = 0; li < units.size() && !rc; ++li) {
       c->stream = li == 0 || nsd == 0 ? c->bstream : c->side[(li - 1) % nsd];
-      const Group& g = G[k].g;
-      if (G[k].gen) {
-        // unfused iteration; per-instance gap values (EMD: primal sums and certificates)
-        const GenGroup& q = G[k].gg;
-        for (int it = 0; it < C && !rc; ++it) rc = g.kind == GP_KIND_ROF ? gen_rof_iter(c, q) : gen_emd_iter(c, q);
-        if (!rc)
-          rc = g.kind == GP_KIND_ROF ? gen_rof_gap_enqueue(c, q, G[k].gap_dev)
-                                     : gen_emd_values_enqueue(c, q, G[k].gap_dev, G[k].cert_dev, nullptr);
+      if (units[li] < 0) {
+        // the unfused iteration of every live group of the kind, then per-instance
+        // gap values (EMD: primal sums and certificates) group by group
+        const int kind = units[li] == -1 ? GP_KIND_ROF : GP_KIND_EMD;
+        for (int it = 0; it < C && !rc; ++it)
+          rc = kind == GP_KIND_ROF ? gen_multi_iter<float2>(c, mrof) : gen_multi_iter<double2>(c, memd);
+        for (int k : live) {
+          if (rc || !G[k].gen || G[k].g.kind != kind) continue;
+          const GenGroup& q = G[k].gg;
+          rc = kind == GP_KIND_ROF ? gen_rof_gap_enqueue(c, q, G[k].gap_dev)
+                                   : gen_emd_values_enqueue(c, q, G[k].gap_dev, G[k].cert_dev, nullptr);
+        }
         continue;
       }
+      const int k = units[li];
+      const Group& g = G[k].g;
       for (int it = 0; it < C && !rc; ++it) {
         const bool last = it + 1 == C;
         if (g.kind == GP_KIND_ROF) {
@@ -2055,7 +2082,8 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
   std::vector<int> live(G.size());
   for (size_t k = 0; k < G.size(); ++k) live[k] = int(k);
   size_t captured = live.size();
-  rc = capture(live);
+  rc = build_multi(live);
+  if (!rc) rc = capture(live);
   if (rc) return restore(rc);
   // ---- replay until every instance has retired
   std::vector<char> retired(count, 0);
@@ -2133,7 +2161,13 @@ int gp_batch_solve(gp_ctx* c, const gp_instance* inst, int count, const gp_opts*
     }
     live.swap(still);
     if (left > 0 && 4 * live.size() <= 3 * captured) {
-      rc = capture(live);
+      // the replays are done with the job tables before they are rewritten
+      if (hipStreamSynchronize(c->bstream) != hipSuccess) {
+        set_err(c, "batch stream synchronisation failed");
+        return restore(GP_EHIP);
+      }
+      rc = build_multi(live);
+      if (!rc) rc = capture(live);
       if (rc) return restore(rc);
       captured = live.size();
     }

@@ -91,7 +91,7 @@ __device__ __forceinline__ void gen_bfly(const C* src, C* dst, int j, int n, int
 // returns the buffer holding the result.  Every thread of the workgroup calls it
 // (it synchronises the workgroup after each pass).
 template <bool INV, class C>
-__device__ C* gen_fft(C* b0, C* b1, const GenSched& s, const C* W, int tid, int TG) {
+__device__ __forceinline__ C* gen_fft(C* b0, C* b1, const GenSched& s, const C* W, int tid, int TG) {
   C* src = b0;
   C* dst = b1;
   for (int p = 0; p < s.np; ++p) {
@@ -160,14 +160,15 @@ template <class Re> __device__ __forceinline__ Re gen_rhs(const GenRhs& R, size_
 //   mode 2: forward, times inv_nn / (alpha + mu_seq[k] + mu_row[row]) (the
 //           zero mode dropped where that is 0), inverse times n: the column
 //           solve (with cols = 1)
+// One workgroup's share (workgroup index bid) of a row or column transform launch.
 template <class C, bool WL>
-__global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::R* in, typename Cx<C>::R* out,
-                                                          int rows, int m, GenSched s, const C* __restrict__ Wg,
-                                                          const C* __restrict__ dw, const int* __restrict__ active,
-                                                          int mode, int acc, const typename Cx<C>::R* __restrict__ mu_seq,
-                                                          const typename Cx<C>::R* __restrict__ mu_row,
-                                                          typename Cx<C>::R alpha, typename Cx<C>::R inv_nn, int PB,
-                                                          int cols, GenRhs rh) {
+__device__ __forceinline__ void gen_rows_block(const typename Cx<C>::R* in, typename Cx<C>::R* out, int rows, int m,
+                                               const GenSched& s, const C* __restrict__ Wg,
+                                               const C* __restrict__ dw, const int* __restrict__ active, int mode,
+                                               int acc, const typename Cx<C>::R* __restrict__ mu_seq,
+                                               const typename Cx<C>::R* __restrict__ mu_row, typename Cx<C>::R alpha,
+                                               typename Cx<C>::R inv_nn, int PB, int cols, const GenRhs& rh,
+                                               int bid) {
   using Re = typename Cx<C>::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = s.n;
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
   // the whole workgroup leaves when none of its row pairs is live
   bool any = false;
   for (int e = 0; e < PB; ++e) {
-    const int pe = blockIdx.x * PB + e, ie = pe / ppi;
+    const int pe = bid * PB + e, ie = pe / ppi;
     any = any || (ie < m && inst_active(active, ie));
   }
   if (!any) return;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
     for (int i = threadIdx.x; i < n; i += blockDim.x) wl[i] = Wg[i];
     W = wl;  // visible after the barrier below
   }
-  const int pair = blockIdx.x * PB + g;
+  const int pair = bid * PB + g;
   const int inst = pair / ppi, q = pair - inst * ppi;
   const bool live = inst < m && inst_active(active, inst);
   const int r0 = 2 * q, r1 = r0 + 1;
@@ -265,15 +266,61 @@ __global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::
   }
 }
 
+template <class C, bool WL>
+__global__ __launch_bounds__(kGenThreads) void k_gen_rows(const typename Cx<C>::R* in, typename Cx<C>::R* out,
+                                                          int rows, int m, GenSched s, const C* __restrict__ Wg,
+                                                          const C* __restrict__ dw, const int* __restrict__ active,
+                                                          int mode, int acc, const typename Cx<C>::R* __restrict__ mu_seq,
+                                                          const typename Cx<C>::R* __restrict__ mu_row,
+                                                          typename Cx<C>::R alpha, typename Cx<C>::R inv_nn, int PB,
+                                                          int cols, GenRhs rh) {
+  gen_rows_block<C, WL>(in, out, rows, m, s, Wg, dw, active, mode, acc, mu_seq, mu_row, alpha, inv_nn, PB, cols, rh,
+                        blockIdx.x);
+}
+
+// The transforms of several groups (sizes, instance stacks) in one launch: job j
+// takes the workgroups [block0_j, block0_{j+1}); its arguments are those of
+// k_gen_rows.  Every job runs exactly as it would in a launch of its own.
+template <class C> struct GenRowsJob {
+  using Re = typename Cx<C>::R;
+  GenSched s;
+  const Re* in;
+  Re* out;
+  const C* W;
+  const C* dw;
+  const int* active;
+  const Re* mu_seq;
+  const Re* mu_row;
+  GenRhs rh;
+  Re alpha, inv_nn;
+  int rows, m, mode, acc, PB, cols, block0;
+};
+// the job whose workgroup range holds workgroup b (block0 ascending, jobs[0].block0 = 0)
+template <class J> __device__ __forceinline__ int gen_find_job(const J* jobs, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+template <class C, bool WL>
+__global__ __launch_bounds__(kGenThreads) void k_gen_rows_multi(const GenRowsJob<C>* __restrict__ jobs, int njobs) {
+  const GenRowsJob<C>& J = jobs[gen_find_job(jobs, njobs, blockIdx.x)];
+  gen_rows_block<C, WL>(J.in, J.out, J.rows, J.m, J.s, J.W, J.dw, J.active, J.mode, J.acc, J.mu_seq, J.mu_row, J.alpha,
+                        J.inv_nn, J.PB, J.cols, J.rh, blockIdx.x - J.block0);
+}
+
 // ---------------------------------------------------------------- iteration kernels
 // Cells of m stacked instances of nyi x nx; stencils stop at instance edges.
 
 // ROF dual step p+ = proj(p + sig_h grad u), pbar = 2 p+ - p (pointwise in p)
-__global__ __launch_bounds__(256) void k_gen_rof_dual(const float* __restrict__ u, float* __restrict__ p,
-                                                      float* __restrict__ pb, int nyi, int nx, int m, float sig_h,
-                                                      int aniso, const int* __restrict__ active) {
+__device__ __forceinline__ void gen_rof_dual_cells(const float* __restrict__ u, float* __restrict__ p,
+                                                   float* __restrict__ pb, int nyi, int nx, int m, float sig_h,
+                                                   int aniso, const int* __restrict__ active, int bid, int nblk) {
   const size_t ntot = size_t(m) * nyi * nx, nn = size_t(nyi) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < ntot; o += size_t(gridDim.x) * blockDim.x) {
+  for (size_t o = size_t(bid) * blockDim.x + threadIdx.x; o < ntot; o += size_t(nblk) * blockDim.x) {
     const int inst = int(o / nn);
     if (!inst_active(active, inst)) continue;
     const size_t l = o - size_t(inst) * nn;
@@ -288,6 +335,29 @@ __global__ __launch_bounds__(256) void k_gen_rof_dual(const float* __restrict__ 
     pb[o] = 2.f * qx - ox;
     pb[ntot + o] = 2.f * qy - oy;
   }
+}
+
+__global__ __launch_bounds__(256) void k_gen_rof_dual(const float* __restrict__ u, float* __restrict__ p,
+                                                      float* __restrict__ pb, int nyi, int nx, int m, float sig_h,
+                                                      int aniso, const int* __restrict__ active) {
+  gen_rof_dual_cells(u, p, pb, nyi, nx, m, sig_h, aniso, active, blockIdx.x, gridDim.x);
+}
+
+// The pointwise step of several groups in one launch (as GenRowsJob): the ROF
+// dual step (sigma = sig_h) or the EMD update.
+struct GenCellJob {
+  float *u, *p, *pb;
+  const double* phi;
+  const float* gpsi;
+  const int* active;
+  double inv_h;
+  float tau, sigma;
+  int nyi, nx, m, aniso, block0, nblocks;
+};
+__global__ __launch_bounds__(256) void k_gen_rof_dual_multi(const GenCellJob* __restrict__ jobs, int njobs) {
+  const GenCellJob& J = jobs[gen_find_job(jobs, njobs, blockIdx.x)];
+  gen_rof_dual_cells(J.u, J.p, J.pb, J.nyi, J.nx, J.m, J.sigma, J.aniso, J.active, blockIdx.x - J.block0,
+                     J.nblocks);
 }
 
 // per-instance (blockIdx.y) ROF gap partials [sum |grad u|, sum (u - I)^2, sum I div p, sum (div p)^2]
@@ -318,13 +388,13 @@ __global__ __launch_bounds__(256) void k_gen_rof_gap(const float* __restrict__ u
 
 // EMD update, pointwise in u, p, pbar: u+ = (u - tau pbar) - grad phi,
 // p+ = proj(p + sigma (u+ + grad psi)), pbar = 2 p+ - p
-__global__ __launch_bounds__(256) void k_gen_emd_update(float* __restrict__ u, float* __restrict__ p,
-                                                        float* __restrict__ pb, const double* __restrict__ phi,
-                                                        const float* __restrict__ gpsi, int nyi, int nx, int m,
-                                                        float tau, float sigma, double inv_h, int aniso,
-                                                        const int* __restrict__ active) {
+__device__ __forceinline__ void gen_emd_update_cells(float* __restrict__ u, float* __restrict__ p,
+                                                     float* __restrict__ pb, const double* __restrict__ phi,
+                                                     const float* __restrict__ gpsi, int nyi, int nx, int m,
+                                                     float tau, float sigma, double inv_h, int aniso,
+                                                     const int* __restrict__ active, int bid, int nblk) {
   const size_t ntot = size_t(m) * nyi * nx, nn = size_t(nyi) * nx;
-  for (size_t o = size_t(blockIdx.x) * blockDim.x + threadIdx.x; o < ntot; o += size_t(gridDim.x) * blockDim.x) {
+  for (size_t o = size_t(bid) * blockDim.x + threadIdx.x; o < ntot; o += size_t(nblk) * blockDim.x) {
     const int inst = int(o / nn);
     if (!inst_active(active, inst)) continue;
     const size_t l = o - size_t(inst) * nn;
@@ -345,6 +415,18 @@ __global__ __launch_bounds__(256) void k_gen_emd_update(float* __restrict__ u, f
     pb[o] = 2.f * qx - ox;
     pb[ntot + o] = 2.f * qy - oy;
   }
+}
+__global__ __launch_bounds__(256) void k_gen_emd_update(float* __restrict__ u, float* __restrict__ p,
+                                                        float* __restrict__ pb, const double* __restrict__ phi,
+                                                        const float* __restrict__ gpsi, int nyi, int nx, int m,
+                                                        float tau, float sigma, double inv_h, int aniso,
+                                                        const int* __restrict__ active) {
+  gen_emd_update_cells(u, p, pb, phi, gpsi, nyi, nx, m, tau, sigma, inv_h, aniso, active, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(256) void k_gen_emd_update_multi(const GenCellJob* __restrict__ jobs, int njobs) {
+  const GenCellJob& J = jobs[gen_find_job(jobs, njobs, blockIdx.x)];
+  gen_emd_update_cells(J.u, J.p, J.pb, J.phi, J.gpsi, J.nyi, J.nx, J.m, J.tau, J.sigma, J.inv_h, J.aniso, J.active,
+                       blockIdx.x - J.block0, J.nblocks);
 }
 
 // per-instance (blockIdx.y) EMD primal partials [sum |u + grad psi|]; with mout the flux too
