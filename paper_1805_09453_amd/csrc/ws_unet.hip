@@ -70,29 +70,30 @@ struct ConvArgs {
   int relu;
 };
 
-// 8 consecutive K entries of row p of the implicit A matrix
+// 8 consecutive K entries (from k0) of row p of the implicit A matrix, with the
+// pixel given as (b, y, x) and k0 as (tap, ci), k0 = tap ct + ci (3x3: ct = c1 +
+// c2, tap = 3 dy + dx; transposed backward: ct = c1, the 2x2 output block): the
+// K loop keeps these without integer divisions.  pin: p lies in the pixel space.
 template <int MODE>
-__device__ __forceinline__ uint4 conv_a(const ConvArgs& a, int p, int k0) {
+__device__ __forceinline__ uint4 conv_a_at(const ConvArgs& a, bool pin, size_t p, int b, int y, int x, int k0, int tap,
+                                           int ci) {
   const uint4 z = {0u, 0u, 0u, 0u};
-  const int hw = a.H * a.W;
-  if (p >= a.B * hw) return z;
-  const int b = p / hw, r = p - b * hw, y = r / a.W, x = r - y * a.W;
+  if (!pin) return z;
   if (MODE == M_CONV3) {
-    const int ct = a.c1 + a.c2;
-    const int tap = k0 / ct, ci = k0 - tap * ct;
     if (tap >= 9) return z;
-    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+    const int dy = (tap >= 3) + (tap >= 6), dx = tap - 3 * dy;
+    const int yy = y + dy - 1, xx = x + dx - 1;
     if (yy < 0 || yy >= a.H || xx < 0 || xx >= a.W) return z;
-    const size_t q = (size_t(b) * a.H + yy) * a.W + xx;
+    // the neighbour is pixel p + (dy - 1) W + (dx - 1) of the same image
+    const long long q = (long long)p + (dy - 1) * a.W + (dx - 1);
     return ci < a.c1 ? ld16(a.x1 + q * a.s1 + ci) : ld16(a.x2 + q * a.s2 + (ci - a.c1));
   } else if (MODE == M_TFWD) {
     if (k0 >= a.c1) return z;
-    return ld16(a.x1 + size_t(p) * a.s1 + k0);
+    return ld16(a.x1 + p * a.s1 + k0);
   } else {
-    const int tap = k0 / a.c1, co = k0 - tap * a.c1;
     if (tap >= 4) return z;
     const size_t q = (size_t(b) * 2 * a.H + 2 * y + (tap >> 1)) * size_t(2 * a.W) + 2 * x + (tap & 1);
-    return ld16(a.x1 + q * a.s1 + co);
+    return ld16(a.x1 + q * a.s1 + ci);
   }
 }
 
@@ -107,13 +108,33 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int M = a.B * a.H * a.W;
   const int nsteps = a.kpad / KS;
   uint4 ra[2], rb = {0u, 0u, 0u, 0u};
-  auto gload = [&](int s) {
+  // this thread's two A rows (pixels p0 + tid/4 and 64 further) and its K offset
+  // (tid % 4) * 8 + s KS, the same for both rows
+  int pb_[2], py_[2], px_[2];
+  bool pin[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int v = tid + 256 * j;
-      ra[j] = conv_a<MODE>(a, p0 + (v >> 2), s * KS + (v & 3) * 8);
-    }
+  for (int j = 0; j < 2; ++j) {
+    const int p = p0 + ((tid + 256 * j) >> 2);
+    const int hw = a.H * a.W;
+    pin[j] = p < M;
+    pb_[j] = p / hw;
+    const int r = p - pb_[j] * hw;
+    py_[j] = r / a.W;
+    px_[j] = r - py_[j] * a.W;
+  }
+  const int ct = max(1, MODE == M_CONV3 ? a.c1 + a.c2 : a.c1);
+  int ktap = ((tid & 3) * 8) / ct, kci = (tid & 3) * 8 - ktap * ct;
+  auto gload = [&](int s) {  // called for s = 0, 1, 2, ... in turn
+    const int k0 = s * KS + (tid & 3) * 8;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      ra[j] = conv_a_at<MODE>(a, pin[j], size_t(p0 + ((tid + 256 * j) >> 2)), pb_[j], py_[j], px_[j], k0, ktap, kci);
     if (tid < NT * 4) rb = ld16(a.w + size_t(n0 + (tid >> 2)) * a.kpad + s * KS + (tid & 3) * 8);
+    kci += KS;
+    while (kci >= ct) {
+      kci -= ct;
+      ++ktap;
+    }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
@@ -149,8 +170,15 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     if (s + 1 < nsteps) lstore(buf ^ 1);
     __syncthreads();
   }
-  // epilogue: bias, ReLU, BF16, staged through LDS for 16-byte stores
+  // epilogue: bias, ReLU, BF16, staged through LDS for 16-byte stores; a lane's
+  // output columns are the same for every row it holds, so their biases are read once
   bf16* Cs = As;
+  float bias[NT / 16];
+#pragma unroll
+  for (int ni = 0; ni < NT / 16; ++ni) {
+    const int col = n0 + ni * 16 + (lane & 15);
+    bias[ni] = (a.bias && col < a.n) ? a.bias[col % a.bmod] : 0.f;
+  }
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -159,7 +187,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
       for (int i = 0; i < 4; ++i) {
         const int row = w * 32 + mi * 16 + (lane >> 4) * 4 + i, col = ni * 16 + (lane & 15);
         float v = acc[mi][ni][i];
-        if (a.bias && n0 + col < a.n) v += a.bias[(n0 + col) % a.bmod];
+        if (a.bias && n0 + col < a.n) v += bias[ni];
         if (a.relu) v = fmaxf(v, 0.f);
         Cs[row * LC + col] = f2b(v);
       }
@@ -195,12 +223,10 @@ struct WgArgs {
   int chunk;       // pixels per block (multiple of 64)
 };
 
+// 8 consecutive k entries of the k operand at pixel (b, y, x), k = tap ck + c
 template <int MODE>
-__device__ __forceinline__ uint4 wg_k(const WgArgs& a, int p, int k0) {
+__device__ __forceinline__ uint4 wg_k(const WgArgs& a, int b, int y, int x, int tap, int c) {
   const uint4 z = {0u, 0u, 0u, 0u};
-  const int hw = a.H * a.W;
-  const int b = p / hw, r = p - b * hw, y = r / a.W, x = r - y * a.W;
-  const int tap = k0 / a.ck, c = k0 - tap * a.ck;
   if (tap >= a.taps) return z;
   if (MODE == W_CONV3) {
     const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
@@ -231,20 +257,52 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   // this thread's pixels 2 px and 2 px + 1 of a step (adjacent in the [m][p] tiles, so each
   // channel's pair is one 4-byte LDS store), channels 8q..8q+7
   const int px = tid >> 3, q = tid & 7;
-  auto load = [&](int p, V8& va, V8& vb) {
+  const int ktap = (k0 + 8 * q) / a.ck, kc = (k0 + 8 * q) - ktap * a.ck;
+  auto load = [&](int p, int b, int y, int x, V8& va, V8& vb) {
     va.u = uint4{0u, 0u, 0u, 0u};
     vb.u = va.u;
     if (p < pe) {
       if (m0 + 8 * q < a.c1m) va.u = ld16(a.t1 + size_t(p) * a.s1m + m0 + 8 * q);
-      vb.u = wg_k<MODE>(a, p, k0 + 8 * q);
+      vb.u = wg_k<MODE>(a, b, y, x, ktap, kc);
+    }
+  };
+  // (b, y, x) of the thread's first pixel of a step, moved on by whole steps
+  // without divisions; the second pixel is the next one in raster order
+  int cb, cy, cx;
+  {
+    const int p = pb + 2 * px, hw = a.H * a.W;
+    cb = p / hw;
+    const int r = p - cb * hw;
+    cy = r / a.W;
+    cx = r - cy * a.W;
+  }
+  auto load2 = [&](int p, V8& va0, V8& vb0, V8& va1, V8& vb1) {
+    load(p, cb, cy, cx, va0, vb0);
+    int b1 = cb, y1 = cy, x1 = cx + 1;
+    if (x1 == a.W) {
+      x1 = 0;
+      if (++y1 == a.H) {
+        y1 = 0;
+        ++b1;
+      }
+    }
+    load(p + 1, b1, y1, x1, va1, vb1);
+  };
+  auto advance = [&](int d) {
+    cx += d;
+    while (cx >= a.W) {
+      cx -= a.W;
+      if (++cy == a.H) {
+        cy = 0;
+        ++cb;
+      }
     }
   };
   auto pack = [](bf16 lo, bf16 hi) {
     return uint32_t(__builtin_bit_cast(unsigned short, lo)) | (uint32_t(__builtin_bit_cast(unsigned short, hi)) << 16);
   };
   V8 a0, b0, a1, b1;
-  load(pb + 2 * px, a0, b0);
-  load(pb + 2 * px + 1, a1, b1);
+  load2(pb + 2 * px, a0, b0, a1, b1);
   for (int ps = pb; ps < pe; ps += PS) {
     __syncthreads();  // the previous step's operand reads are done
 #pragma unroll
@@ -253,8 +311,8 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
       *reinterpret_cast<uint32_t*>(&Bt[(8 * q + j) * LD + 2 * px]) = pack(b0.h[j], b1.h[j]);
     }
     __syncthreads();
-    load(ps + PS + 2 * px, a0, b0);
-    load(ps + PS + 2 * px + 1, a1, b1);
+    advance(PS);
+    load2(ps + PS + 2 * px, a0, b0, a1, b1);
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
       const bf16x8 av = *reinterpret_cast<const bf16x8*>(&At[(w * 16 + (lane & 15)) * LD + kk * 32 + (lane >> 4) * 8]);
@@ -408,21 +466,29 @@ __global__ __launch_bounds__(256) void k_head_bwd(const bf16* __restrict__ x, co
   }
 }
 
-// bias gradient: out[c] += sum_p g[p * S + c]  (C a power of two <= 256)
+// bias gradient: out[c] += sum_p g[p * S + c]  (C = 32, 64, 128 or 256; S a multiple
+// of 8): each thread sums one 16-byte vector of 8 channels over a strided set of
+// pixels, then the block adds its partial sums per channel
 __global__ __launch_bounds__(256) void k_chsum(const bf16* __restrict__ g, int C, int S, size_t P,
                                                float* __restrict__ out) {
-  const int per = 256 / C;  // pixels handled side by side
-  const int c = threadIdx.x % C, r = threadIdx.x / C;
-  float s = 0.f;
-  if (r < per)
-    for (size_t p = size_t(blockIdx.x) * per + r; p < P; p += size_t(gridDim.x) * per) s += b2f(g[p * S + c]);
-  __shared__ float red[256];
-  red[threadIdx.x] = s;
+  const int G = C / 8, per = 256 / G;  // vectors per pixel; pixels side by side
+  const int q = threadIdx.x % G, r = threadIdx.x / G;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (size_t p = size_t(blockIdx.x) * per + r; p < P; p += size_t(gridDim.x) * per) {
+    V8 v;
+    v.u = ld16(g + p * S + 8 * q);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += b2f(v.h[j]);
+  }
+  __shared__ float red[256 * 8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) red[threadIdx.x * 8 + j] = s[j];
   __syncthreads();
-  if (threadIdx.x < C) {
+  if (int(threadIdx.x) < C) {
+    const int c = threadIdx.x, cq = c / 8, cj = c % 8;
     float v = 0.f;
-    for (int q = 0; q < per; ++q) v += red[q * C + threadIdx.x];
-    atomicAdd(&out[threadIdx.x], v);
+    for (int rr = 0; rr < per; ++rr) v += red[(rr * G + cq) * 8 + cj];
+    atomicAdd(&out[c], v);
   }
 }
 
@@ -707,9 +773,10 @@ int launch_wgrad(ws_net* net, hipStream_t s, WgArgs a) {
 }
 
 int chsum(ws_net* net, hipStream_t s, const bf16* g, int C, int S, size_t P, float* out) {
-  const int per = 256 / C;
-  size_t blocks = (P + per * 64 - 1) / (per * 64);
-  if (blocks > 1024) blocks = 1024;
+  if (C < 8 || C > 256 || (C & (C - 1)) || S % 8) return GP_EINVAL;  // the network's widths are 32 ... 256
+  const int per = 256 / (C / 8);  // pixels per block and step; about 16 steps per thread
+  size_t blocks = (P + per * 16 - 1) / (per * 16);
+  if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(k_chsum, dim3(blocks ? blocks : 1), dim3(256), 0, s, g, C, S, P, out);
   WLAUNCH(net);
   return GP_OK;
