@@ -115,6 +115,38 @@ def test_emd_pd_step_generic_sizes(gpctx, ny, nx):
     assert abs(g["primal"] - P) <= 1e-6 * P and abs(g["dual"] - D) <= 2e-6 * P
 
 
+def test_pd_step_alternating_states_and_parameters(gpctx):
+    """pd_step on 7-smooth grids keeps the arguments of its launches in a device
+    table that it rewrites when the state changes: two states of different sizes
+    stepped in turn, and one of them with its step size changed between calls,
+    each match the oracle's iterations."""
+    from paper_1805_09453_amd._lib import GP_KIND_ROF
+    h, lam = 1.0, 8.0
+    cases = [(96, 160, 21), (75, 105, 22)]
+    host_st, dev_st = [], []
+    for ny, nx, seed in cases:
+        I = scene(ny, nx, seed)
+        z = np.zeros_like(I)
+        host_st.append([I, z, z, z, z, z])  # I, u, px, py, pbx, pby
+        dev_st.append(gpctx.make_state(GP_KIND_ROF, dev(I), h, 0.02, lam=lam, u=dev(z), p=dev(np.stack([z, z])),
+                                       pbar=dev(np.stack([z, z]))))
+    announce("pd_step on two 7-smooth states in turn, one with its tau changed")
+    for rnd, tau in enumerate((0.02, 0.02, 0.05)):
+        for k in (0, 1):
+            I, u, px, py, pbx, pby = host_st[k]
+            t = tau if k == 0 else 0.02
+            dev_st[k].c.tau = t
+            dev_st[k].c.sigma = 1.0 / t
+            gpctx.pd_step(dev_st[k], 1)
+            # the oracle's state rounded to FP32 before each step, as the GPU stores it
+            u, px, py, pbx, pby = orof.step(*(f32(a) for a in (u, px, py, pbx, pby)), I, h, lam, t, 1 / t)
+            host_st[k] = [I, u, px, py, pbx, pby]
+            got = (host(dev_st[k].u), host(dev_st[k].p)[0], host(dev_st[k].p)[1])
+            errs = [field_err(g_, r) for g_, r in zip(got, (u, px, py))]
+            print(rnd, k, ["%.2e" % e for e in errs])
+            assert max(errs) <= 1e-5
+
+
 @pytest.mark.parametrize("ny,nx,norm", [(720, 720, 0), (96, 160, 1)])
 def test_rof_solver_loop_generic_sizes(gpctx, ny, nx, norm):
     from paper_1805_09453_amd import Options
