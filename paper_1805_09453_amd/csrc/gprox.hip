@@ -2307,6 +2307,8 @@ int gp_set_radix_plan(gp_ctx* c, int fp64, int n, const int* radices, int count)
   for (int i = 0; i < count; ++i) sp.r[sp.np++] = radices[i];
   plan_spans(sp);
   c->gplan[fp64 ? 1 : 0][n] = sp;
+  // the launch tables of the single-solve path hold the plan they were built with
+  if (c->gsingle) c->gsingle->valid = false;
   return GP_OK;
 }
 

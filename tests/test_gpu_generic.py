@@ -301,3 +301,30 @@ def test_radix_plan_tuned_on_first_use_and_validated():
             ctx.get_radix_plan(False, 512)   # powers of two have their fixed schedule
         with pytest.raises(GPError):
             ctx.get_radix_plan(False, 110)   # 11 is not a supported factor
+
+
+def test_radix_plan_set_between_solves_is_used():
+    """A plan set between two solves of the same size on one context is the plan
+    the second solve runs (the single-solve launch tables are rebuilt): its result
+    equals, bit for bit, that of a fresh context given the same plan."""
+    import torch
+    from paper_1805_09453_amd import Context, Options
+    n = 720
+    I = dev(scene(n, n, 11))
+    opts = Options(tau=0.01, tol=0.0, max_iter=30, check_every=30)
+    plan_a, plan_b = PLANS_720[0], PLANS_720[3]
+    announce(f"rof_solve {n}x{n}: plan {plan_a}, then {plan_b} on the same context")
+    with Context(n, n) as ctx:
+        u = torch.empty_like(I)
+        p = torch.empty((2, n, n), device="cuda")
+        ctx.set_radix_plan(False, n, plan_a)
+        ctx.rof_solve(I, 1.0, 8.0, opts, u=u, p=p)
+        ua = u.clone()
+        ctx.set_radix_plan(False, n, plan_b)
+        ctx.rof_solve(I, 1.0, 8.0, opts, u=u, p=p)
+        ub = u.clone()
+    with Context(n, n) as ctx:
+        ctx.set_radix_plan(False, n, plan_b)
+        uc, _, _ = ctx.rof_solve(I, 1.0, 8.0, opts)
+    print("plan a vs b max diff", float((ua - ub).abs().max()))
+    assert torch.equal(ub, uc)
