@@ -2308,7 +2308,7 @@ int gp_set_radix_plan(gp_ctx* c, int fp64, int n, const int* radices, int count)
   plan_spans(sp);
   c->gplan[fp64 ? 1 : 0][n] = sp;
   // the launch tables of the single-solve path hold the plan they were built with
-  if (c->gsingle) c->gsingle->valid = false;
+  gen_single_invalidate(c);
   return GP_OK;
 }
 
