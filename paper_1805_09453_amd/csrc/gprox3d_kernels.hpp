@@ -76,7 +76,7 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
       for (int s = 0; s < Sched<N>::H; ++s)
         v[slot * Sched<N>::H + s] =
             valid ? *reinterpret_cast<const C*>(col + size_t(dc_index<N>(t, slot, s)) * ld) : mk<C>(Re(0), Re(0));
-    dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
+    dct2_inv<N>(t, v, lds, tw, dctw[t], [&](int m, C A, C B) {
       if (valid) {
         *reinterpret_cast<C*>(col + size_t(2 * m) * ld) = mk<C>(A.x, B.x);
         *reinterpret_cast<C*>(col + size_t(2 * m + 1) * ld) = mk<C>(A.y, B.y);

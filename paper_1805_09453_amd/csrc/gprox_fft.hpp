@@ -405,12 +405,12 @@ template <int N> __device__ __forceinline__ int dc_index(int t, int slot, int s)
 // spec[slot*H+s] = (A_k, B_k) (layout of dct2_fwd).  st(m, A, B) receives
 // A = N (a_{2m}, a_{2m+1}), B = N (b_{2m}, b_{2m+1}).
 template <int N, class C, class Hook>
-__device__ __forceinline__ void dct2_inv_core(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw,
-                                              const C* __restrict__ dctw, Hook&& before_last) {
+__device__ __forceinline__ void dct2_inv_core(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw, const C wt,
+                                              Hook&& before_last) {
+  // wt = exp(-i pi t / 2N) (the DCT twiddle table's entry t); the inverse uses conjugates
   using Re = typename Cx<C>::R;
   using S = Sched<N>;
   constexpr int H = S::H, E = S::E;
-  const C wt = dctw[t];  // exp(-i pi t / 2N); the inverse uses conjugates
   // ---- V_k = conj(w_k) (X_k - i X_{N-k}) for both spectra, Z_k = V^a_k + i V^b_k
   if (t != 0) {
     // pairs (slot0, s) <-> (slot1, H - 1 - s), s in [0, H)
@@ -483,11 +483,11 @@ template <int N> struct InvOut {
 };
 
 template <int N, class C, class Storer>
-__device__ __forceinline__ void dct2_inv(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw,
-                                         const C* __restrict__ dctw, Storer&& st) {
+__device__ __forceinline__ void dct2_inv(int t, Vals<N, C>& v, C* lds, const C* __restrict__ tw, const C wt,
+                                         Storer&& st) {
   using S = Sched<N>;
   constexpr int T = S::T;
-  dct2_inv_core<N>(t, v, lds, tw, dctw, [] {});
+  dct2_inv_core<N>(t, v, lds, tw, wt, [] {});
   {
     constexpr int RL = S::irad(S::NP - 1);
 #pragma unroll

@@ -278,7 +278,7 @@ __global__ __launch_bounds__((RowShape<N, float2>::MAXT), (RowShape<N, float2>::
   // u at this thread's output positions, loaded before the last pass so the
   // latency overlaps it
   float2 oa[IO::NQ][2][IO::NS], ob[IO::NQ][2][IO::NS];
-  dct2_inv_core<N>(t, v, lds, tw, dctw, [&] {
+  dct2_inv_core<N>(t, v, lds, tw, dctw[t], [&] {
 #pragma unroll
     for (int q = 0; q < IO::NQ; ++q)
 #pragma unroll

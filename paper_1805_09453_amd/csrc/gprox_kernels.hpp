@@ -155,7 +155,7 @@ __global__ __launch_bounds__((RowShape<N, C>::MAXT), (RowShape<N, C>::MINW)) voi
     for (int s = 0; s < Sched<N>::H; ++s)
       v[slot * Sched<N>::H + s] = mk<C>(va ? in[ta.at(s)] : Re(0), vb ? in[tb.at(s)] : Re(0));
   }
-  dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
+  dct2_inv<N>(t, v, lds, tw, dctw[t], [&](int m, C A, C B) {
     if (va) *reinterpret_cast<C*>(out + size_t(ra) * ld + 2 * m) = A;
     if (vb) *reinterpret_cast<C*>(out + size_t(rb) * ld + 2 * m) = B;
   });
@@ -202,6 +202,23 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
   const bool valid = c < nx;
   Re* col = buf + (valid ? size_t(strip) * N * TW + 2 * (sub * G + g) : 0);
   const int ld = TW;
+  // FP64: the spectral-scale operands are loaded before the forward transform so
+  // that their latency hides behind it (FP32 keeps its registers for the FFT)
+  constexpr bool PRE = sizeof(Re) == 8;
+  Re muv[PRE ? 2 * Sched<N>::H : 1];
+  Re mxa = Re(0), mxb = Re(0);
+  C wti{};  // FP64: the inverse transform's DCT twiddle base, loaded early as well
+  if constexpr (PRE) {
+    wti = dctw[t];
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot)
+#pragma unroll
+      for (int s = 0; s < Sched<N>::H; ++s) muv[slot * Sched<N>::H + s] = muy[dc_index<N>(t, slot, s)];
+    if (valid) {
+      mxa = mux[c];
+      mxb = mux[c + 1];
+    }
+  }
   Vals<N, C> v;
   dct2_fwd<N>(t, v, lds, tw, dctw, [&](int m, C& A, C& B) {
     if (valid) {
@@ -214,18 +231,23 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
       B = A;
     }
   });
-  const Re mxa = valid ? mux[c] : Re(0), mxb = valid ? mux[c + 1] : Re(0);
+  if constexpr (!PRE) {
+    if (valid) {
+      mxa = mux[c];
+      mxb = mux[c + 1];
+    }
+  }
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot)
 #pragma unroll
     for (int s = 0; s < Sched<N>::H; ++s) {
-      const int k = dc_index<N>(t, slot, s);
-      const Re da = alpha + muy[k] + mxa, db = alpha + muy[k] + mxb;
+      const Re my = PRE ? muv[PRE ? slot * Sched<N>::H + s : 0] : muy[dc_index<N>(t, slot, s)];
+      const Re da = alpha + my + mxa, db = alpha + my + mxb;
       C& z = v[slot * Sched<N>::H + s];
       z.x = da > Re(0) ? z.x * (inv_nn * recip(da)) : Re(0);
       z.y = db > Re(0) ? z.y * (inv_nn * recip(db)) : Re(0);
     }
-  dct2_inv<N>(t, v, lds, tw, dctw, [&](int m, C A, C B) {
+  dct2_inv<N>(t, v, lds, tw, PRE ? wti : dctw[t], [&](int m, C A, C B) {
     if (valid) {
       *reinterpret_cast<C*>(col + size_t(2 * m) * ld) = mk<C>(A.x, B.x);
       *reinterpret_cast<C*>(col + size_t(2 * m + 1) * ld) = mk<C>(A.y, B.y);
