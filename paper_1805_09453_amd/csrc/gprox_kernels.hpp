@@ -202,12 +202,13 @@ __global__ __launch_bounds__((ColShape<N, C>::MAXTHREADS), (ColShape<N, C>::MINW
   const bool valid = c < nx;
   Re* col = buf + (valid ? size_t(strip) * N * TW + 2 * (sub * G + g) : 0);
   const int ld = TW;
-  // FP64: the spectral-scale operands are loaded before the forward transform so
-  // that their latency hides behind it (FP32 keeps its registers for the FFT)
-  constexpr bool PRE = sizeof(Re) == 8;
+  // FP64 with 16 values per thread: the spectral-scale operands are loaded before
+  // the forward transform so that their latency hides behind it (FP32, and FP64
+  // with 32 values per thread, keep their registers for the FFT)
+  constexpr bool PRE = sizeof(Re) == 8 && Sched<N>::E == 16;
   Re muv[PRE ? 2 * Sched<N>::H : 1];
   Re mxa = Re(0), mxb = Re(0);
-  C wti{};  // FP64: the inverse transform's DCT twiddle base, loaded early as well
+  C wti{};  // with PRE: the inverse transform's DCT twiddle base, loaded early as well
   if constexpr (PRE) {
     wti = dctw[t];
 #pragma unroll
