@@ -13,9 +13,9 @@
 //     V_k = exp(+i pi k / 2N) (X_k - i X_{N-k}),   X_N = 0,   v = N * IFFT(V).
 //
 // FFT layout: a "group" of T = N/E threads owns one complex sequence; each
-// thread holds E complex values in registers (E = 32 for N <= 512, E = 16 for
+// thread holds E complex values in registers (E = 32 for N <= 128, E = 16 for
 // longer sequences, which doubles the threads -- and the waves a CU can keep in
-// flight -- for the same LDS).  Passes are Stockham (self-sorting,
+// flight -- for the same LDS, and halves the registers that FP64 values take).  Passes are Stockham (self-sorting,
 // natural-order output) with radix H = E/2 (16 or 8), plus one leading smaller
 // power-of-two pass when log2 N is not a multiple of log2 H.  Between passes
 // the group exchanges through its own LDS region.  Butterfly-to-thread
@@ -196,7 +196,7 @@ template <int R, class C> __device__ __forceinline__ void apply_tw(C* x, C w1, C
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
 // complex values per thread for sequences of length N
-constexpr int kE16MinN = 1024;
+constexpr int kE16MinN = 256;
 template <int N> struct Sched {
   static_assert(N >= 64 && N <= 4096 && (N & (N - 1)) == 0, "power-of-two N in [64, 4096]");
   static constexpr int E = N >= kE16MinN ? 16 : 32;  // complex values per thread

@@ -75,19 +75,25 @@ __device__ __forceinline__ bool inst_active(const int* active, int inst) { retur
 
 // Offset of spectrum value (slot, s) of row a in the tiled intermediate.  The
 // H values of a slot are the indices b + s N/H; when N/H is a multiple of the
-// strip width (always for E = 16: N/H >= 128 >= the widest strip) they sit
-// at a constant stride (N/H) nyi from the first one.
+// strip width they sit at a constant stride (N/H) nyi from the first one.  For
+// N/H >= 128 that holds for every strip width (the settings allow at most 64
+// columns, and twice the column-pass groups per block stays below that for
+// these lengths); for shorter sequences it is checked per row.
 template <int N> struct SlotTile {
+  static constexpr int NH = N / Sched<N>::H;
+  static constexpr bool ALWAYS = Sched<N>::E == 16 && NH >= 128;
   size_t base;
   int nyi, lgtw, a, b0;
+  bool cst;
   __device__ __forceinline__ SlotTile(int a_, int t, int slot, int nyi_, int lgtw_)
-      : nyi(nyi_), lgtw(lgtw_), a(a_), b0(0) {
-    b0 = slot == 0 ? t : ((t == 0) ? N / (2 * Sched<N>::H) : N / Sched<N>::H - t);
+      : nyi(nyi_), lgtw(lgtw_), a(a_), b0(0), cst(false) {
+    b0 = slot == 0 ? t : ((t == 0) ? N / (2 * Sched<N>::H) : NH - t);
     base = btile(a, b0, nyi, N, lgtw);
+    cst = (NH & ((1 << lgtw) - 1)) == 0;
   }
   __device__ __forceinline__ size_t at(int s) const {
-    if constexpr (Sched<N>::E == 16) return base + size_t(s) * (size_t(N / Sched<N>::H) * nyi);
-    else return btile(a, b0 + s * (N / Sched<N>::H), nyi, N, lgtw);
+    if constexpr (ALWAYS) return base + size_t(s) * (size_t(NH) * nyi);
+    else return cst ? base + size_t(s) * (size_t(NH) * nyi) : btile(a, b0 + s * NH, nyi, N, lgtw);
   }
 };
 
