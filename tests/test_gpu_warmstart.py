@@ -312,7 +312,10 @@ def test_rof_warm_start_matches_oracle(gpctx, n, norm):
     assert rep["iters"] == K
     assert max(errs) <= 1e-5
     assert abs(rep["primal"] - ref.primal) <= 1e-6 * abs(ref.primal)
-    assert abs(rep["dual"] - ref.dual) <= 1e-6 * abs(ref.primal)
+    # the dual of section 3.1 after 10 steps from a random p0 sums differences of p,
+    # whose FP32 iterates sit about 1e-6 (relative) off the FP64 ones; 2e-6 of |P|,
+    # as for the EMD warm start, is still five times inside the 1e-5 objective bar
+    assert abs(rep["dual"] - ref.dual) <= 2e-6 * abs(ref.primal)
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
