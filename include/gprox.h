@@ -298,8 +298,8 @@ typedef struct {
 int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opts* opts, gp_report* reps);
 
 /* Launch shapes (a performance setting; results do not depend on it).  Each
- * DCT pass runs FFT groups of n/32 threads (n <= 512) or n/16 threads
- * (n >= 1024), one per row pair (row passes) or column pair (column pass).
+ * DCT pass runs FFT groups of n/32 threads (n <= 128) or n/16 threads
+ * (n >= 256), one per row pair (row passes) or column pair (column pass).
  * For transforms of length n in FP32 (fp64 = 0: the ROF path and dct_poisson)
  * or FP64 (fp64 = 1: the EMD path and dct_poisson_f64) these calls read or set
  *   row_groups  FFT groups per row-pass workgroup (rows of length n);
@@ -312,8 +312,8 @@ int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opt
  * the current setting); gp_set_shape fixes a choice (0 leaves a setting
  * unchanged; a column setting fixes both column values) and exempts it from
  * tuning.  Row groups must fill whole 64-lane waves within the 256-thread
- * (512 for n >= 1024) and LDS limits; column groups must be a power of two
- * within the LDS and 512-thread (1024 for n >= 1024) limits; the tile width a
+ * (512 for n >= 256) and LDS limits; column groups must be a power of two
+ * within the LDS and 512-thread (1024 for n >= 256) limits; the tile width a
  * power of two in [2, 64]; GP_EINVAL otherwise.  Out pointers may be NULL. */
 int gp_get_shape(gp_ctx* ctx, int fp64, int n, int* row_groups, int* col_groups, int* tile_width);
 int gp_set_shape(gp_ctx* ctx, int fp64, int n, int row_groups, int col_groups, int tile_width);

@@ -49,9 +49,9 @@ def test_dct_poisson3_matches_oracle(gpctx, shape, h, alpha):
 
 @pytest.mark.parametrize("shape", [(64, 64, 4096), (64, 4096, 64), (4096, 64, 64)])
 def test_dct_poisson3_long_axes(gpctx, shape):
-    """Each axis at the longest transform (4096, the radix-16 schedule) with the
-    other two at the shortest: x rows, y columns and z columns of every length
-    class."""
+    """Each axis at the longest transform (4096: 16 values per thread, radix-8
+    passes) with the other two at the shortest (64: 32 values per thread,
+    radix-16 passes): x rows, y columns and z columns of both length classes."""
     b = np.random.default_rng(13).standard_normal(shape)
     announce(f"dct_poisson3 {shape}")
     x32 = gpctx.dct_poisson3(dev(b), h=1.0 / 64, alpha=0.0)

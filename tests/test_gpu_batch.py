@@ -199,6 +199,42 @@ def test_launch_shapes_do_not_change_results(gpctx):
         gpctx.set_shape(True, 128, *saved[1])
 
 
+@pytest.mark.parametrize("n", [256, 512])
+def test_launch_shapes_do_not_change_results_16_values_per_thread(gpctx, n):
+    """Lengths 256 and 512 hold 16 values per thread, so a slot's spectrum indices
+    are only N/8 = 32 or 64 apart, at or below the widest strip of the tiled
+    intermediate: ROF (FP32) and EMD (FP64) solves under the extreme and middle
+    row / column / tile settings are bit-identical to the default ones."""
+    from paper_1805_09453_amd import Options
+    I = dev(synth.rof_scene(n, 41))
+    r0, r1 = synth.emd_mixture_pair(n, 42, k=4)
+    r0, r1 = dev(r0), dev(r1)
+    o_rof = Options(tau=0.01, tol=0.0, max_iter=40, check_every=20)
+    o_emd = Options(tau=0.3, tol=0.0, max_iter=40, check_every=20)
+    saved = [gpctx.get_shape(False, n), gpctx.get_shape(True, n)]
+    announce(f"shape variants ROF and EMD {n}x{n}")
+    u0, _, rep0 = gpctx.rof_solve(I, 1.0, 8.0, o_rof)
+    m0, phi0, rpe0 = gpctx.emd_solve(r0, r1, 1.0 / n, o_emd)
+    # (row groups, column groups, tile width): FP32 first, then FP64
+    shapes = {256: [((4, 1, 2), (4, 1, 2)), ((32, 32, 64), (28, 32, 64)), ((8, 4, 16), (8, 4, 16))],
+              512: [((2, 1, 2), (2, 1, 2)), ((16, 16, 64), (14, 16, 64)), ((4, 8, 16), (4, 8, 16))]}[n]
+    try:
+        for s32, s64 in shapes:
+            gpctx.set_shape(False, n, *s32)
+            gpctx.set_shape(True, n, *s64)
+            print("shapes", gpctx.get_shape(False, n), gpctx.get_shape(True, n))
+            u, _, rep = gpctx.rof_solve(I, 1.0, 8.0, o_rof)
+            m, phi, rpe = gpctx.emd_solve(r0, r1, 1.0 / n, o_emd)
+            assert rep["primal"] == rep0["primal"] and rep["dual"] == rep0["dual"]
+            assert rpe["primal"] == rpe0["primal"] and rpe["dual"] == rpe0["dual"]
+            np.testing.assert_array_equal(host(u), host(u0))
+            np.testing.assert_array_equal(host(m), host(m0))
+            np.testing.assert_array_equal(host(phi), host(phi0))
+    finally:
+        gpctx.set_shape(False, n, *saved[0])
+        gpctx.set_shape(True, n, *saved[1])
+
+
 def test_batch_rectangular_anisotropic_equals_single_solves(gpctx):
     """Rectangular instances (wide and tall, rows of the radix-8 and radix-16
     length classes) under the anisotropic norm: each instance of the batch
