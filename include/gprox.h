@@ -391,6 +391,18 @@ int ws_grads(gp_ctx* ctx, ws_net* net, const float* rho0, const float* rho1, con
 /* One Adam step (beta 0.9, 0.999, eps 1e-8, bias-corrected) with learning
  * rate lr on the gradients of the last ws_grads. */
 int ws_adam(gp_ctx* ctx, ws_net* net, double lr);
+/* One training step: ws_grads (no gradient copy) then ws_adam with rate lr.
+ * *loss (nullable) receives the batch's loss before the step.  Synchronises. */
+int ws_train_step(gp_ctx* ctx, ws_net* net, const float* rho0, const float* rho1, const float* phi_star, int batch,
+                  double h, double lr, double* loss);
+/* Parameters from / to a file of ws_param_count() FP32 values, little-endian,
+ * no header (the blob layout above; paper_1805_09453_amd/weights/ws_unet.f32
+ * is such a file).  Loading resets the Adam state; a file that cannot be read
+ * or holds another number of values gives GP_EINVAL (path and reason in
+ * gp_last_error).  Both synchronise ctx's stream and use a temporary device
+ * buffer of the blob's size. */
+int ws_load_params(gp_ctx* ctx, ws_net* net, const char* path);
+int ws_save_params(gp_ctx* ctx, ws_net* net, const char* path);
 /* The resolution changes of ws_emd_solve: f x f block mean ([ny][nx] ->
  * [ny/f][nx/f], mass-preserving for densities) and bilinear interpolation
  * between cell centres ([ny][nx] -> [f ny][f nx], constant beyond the

@@ -98,6 +98,9 @@ _SIGS = {
     "ws_grads": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p,
                          ctypes.POINTER(c_double)]),
     "ws_adam": (c_int, [c_void_p, c_void_p, c_double]),
+    "ws_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double, c_double, c_void_p]),
+    "ws_load_params": (c_int, [c_void_p, c_void_p, ctypes.c_char_p]),
+    "ws_save_params": (c_int, [c_void_p, c_void_p, ctypes.c_char_p]),
     "ws_downsample": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
     "ws_upsample": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
     "ws_emd_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_double,

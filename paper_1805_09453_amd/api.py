@@ -6,6 +6,7 @@ every step of the method in its own kernels on the context's stream.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 
 from . import _lib as L
@@ -392,6 +393,25 @@ class WarmStart:
 
     def adam(self, lr):
         self.ctx._check(self.ctx._lib.ws_adam(self.ctx._h, self._h, float(lr)))
+
+    def train_step(self, rho0, rho1, phi_star, h, lr):
+        """grads then adam in one call; returns the batch's loss before the step."""
+        torch = _torch()
+        B = rho0.shape[0]
+        shp = (B, self.ny, self.nx)
+        loss = ctypes.c_double()
+        self.ctx._check(self.ctx._lib.ws_train_step(self.ctx._h, self._h, _ptr(rho0, torch.float32, shp, "rho0"),
+                                                    _ptr(rho1, torch.float32, shp, "rho1"),
+                                                    _ptr(phi_star, torch.float32, shp, "phi_star"), int(B), float(h),
+                                                    float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def load_params(self, path):
+        """Parameters from a raw FP32 file (resets the Adam state)."""
+        self.ctx._check(self.ctx._lib.ws_load_params(self.ctx._h, self._h, os.fsencode(path)))
+
+    def save_params(self, path):
+        self.ctx._check(self.ctx._lib.ws_save_params(self.ctx._h, self._h, os.fsencode(path)))
 
     def emd_solve(self, rho0, rho1, h, opts: Options, want_phi=False):
         """emd_solve from the learned start (with fallback); returns (m, phi, report, ws_report)."""

@@ -2365,6 +2365,90 @@ int ws_adam(gp_ctx* c, ws_net* net, double lr) {
   return GP_OK;
 }
 
+int ws_train_step(gp_ctx* c, ws_net* net, const float* rho0, const float* rho1, const float* phi_star, int batch,
+                  double h, double lr, double* loss) {
+  if (!c || !net || !rho0 || !rho1 || !phi_star || !(lr >= 0) || !std::isfinite(lr)) return GP_EINVAL;
+  double l = 0.0;
+  WSCHK(c, net, wsi::grads(net, c->stream, rho0, rho1, phi_star, batch, h, nullptr, &l));
+  WSCHK(c, net, wsi::adam(net, c->stream, lr));
+  if (loss) *loss = l;
+  return GP_OK;
+}
+
+// the parameter blob through a temporary device buffer: load = file -> host ->
+// device -> ws_set_params, save = ws_get_params -> device -> host -> file
+int ws_load_params(gp_ctx* c, ws_net* net, const char* path) {
+  if (!c || !net || !path) return GP_EINVAL;
+  const size_t np = size_t(wsi::param_count());
+  std::vector<float> h(np);
+  FILE* f = std::fopen(path, "rb");
+  if (!f) {
+    set_err(c, "cannot open %s", path);
+    return GP_EINVAL;
+  }
+  const size_t got = std::fread(h.data(), sizeof(float), np, f);
+  const bool more = std::fgetc(f) != EOF;
+  std::fclose(f);
+  if (got != np || more) {
+    set_err(c, "%s does not hold exactly %zu FP32 values", path, np);
+    return GP_EINVAL;
+  }
+  float* d = nullptr;
+  if (hipMalloc(&d, np * sizeof(float)) != hipSuccess) {
+    set_err(c, "parameter staging allocation of %zu bytes failed", np * sizeof(float));
+    return GP_ENOMEM;
+  }
+  int rc = GP_OK;
+  if (hipMemcpyAsync(d, h.data(), np * sizeof(float), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+    set_err(c, "parameter upload failed");
+    rc = GP_EHIP;
+  } else if (const int r = wsi::set_params(net, c->stream, d)) {
+    std::snprintf(c->err, sizeof(c->err), "%s", wsi::error(net));
+    rc = r;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess && !rc) {
+    set_err(c, "parameter upload failed");
+    rc = GP_EHIP;
+  }
+  (void)hipFree(d);
+  return rc;
+}
+
+int ws_save_params(gp_ctx* c, ws_net* net, const char* path) {
+  if (!c || !net || !path) return GP_EINVAL;
+  const size_t np = size_t(wsi::param_count());
+  std::vector<float> h(np);
+  float* d = nullptr;
+  if (hipMalloc(&d, np * sizeof(float)) != hipSuccess) {
+    set_err(c, "parameter staging allocation of %zu bytes failed", np * sizeof(float));
+    return GP_ENOMEM;
+  }
+  int rc = GP_OK;
+  if (const int r = wsi::get_params(net, c->stream, d)) {
+    std::snprintf(c->err, sizeof(c->err), "%s", wsi::error(net));
+    rc = r;
+  } else if (hipMemcpyAsync(h.data(), d, np * sizeof(float), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+             hipStreamSynchronize(c->stream) != hipSuccess) {
+    set_err(c, "parameter download failed");
+    rc = GP_EHIP;
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (rc) return rc;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) {
+    set_err(c, "cannot create %s", path);
+    return GP_EINVAL;
+  }
+  const size_t put = std::fwrite(h.data(), sizeof(float), np, f);
+  const bool closed = std::fclose(f) == 0;
+  if (put != np || !closed) {
+    set_err(c, "writing %s failed", path);
+    return GP_EINVAL;
+  }
+  return GP_OK;
+}
+
 int ws_downsample(gp_ctx* c, const float* in, int ny, int nx, int f, float* out) {
   if (!c || !in || !out || f < 1 || ny < f || nx < f || ny % f || nx % f) return GP_EINVAL;
   if (wsi::downsample(c->stream, in, ny, nx, f, out)) {

@@ -60,6 +60,9 @@ def test_strerror_and_null_arguments(lib):
     assert lib.emd3_solve(None, None, None, None, None, 64, 64, 64, 1.0, None, None) == -1
     assert lib.gp_get_radix_plan(None, 0, 720, None, None) == -1
     assert lib.gp_set_radix_plan(None, 0, 720, None, 0) == -1
+    assert lib.ws_train_step(None, None, None, None, None, 1, 1.0, 1e-3, None) == -1
+    assert lib.ws_load_params(None, None, b"weights.f32") == -1
+    assert lib.ws_save_params(None, None, b"weights.f32") == -1
 
 
 def test_warm_start_blob_size_matches_the_oracle_network(lib):

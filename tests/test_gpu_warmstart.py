@@ -352,3 +352,57 @@ def test_learned_start_converges_to_the_oracle_optimum(gpctx):
     assert ref["dual"] <= val * (1 + 1e-6)
     assert val <= ref["primal"] * (1 + 1e-5)
     assert rep["dual"] <= ref["primal"] * (1 + 1e-6)
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
+def test_params_file_and_train_step(gpctx, tmp_path):
+    """ws_load_params reads the committed weights file into the network (the same
+    blob as ws_set_params of its contents), ws_save_params writes it back byte for
+    byte, a file of the wrong size is refused, and ws_train_step is ws_grads then
+    ws_adam: the same loss and parameters (to the rounding of the weight-gradient
+    kernel's FP32 atomic sums, whose order varies from run to run)."""
+    import torch
+    from paper_1805_09453_amd import GPError, WarmStart
+    blob = np.fromfile(WEIGHTS, dtype=np.float32)
+    announce("ws_load_params / ws_save_params / ws_train_step at 64x64")
+    a = WarmStart(gpctx, 2, 64, 64)
+    b = WarmStart(gpctx, 2, 64, 64)
+    c = WarmStart(gpctx, 2, 64, 64)
+    try:
+        a.load_params(WEIGHTS)
+        assert np.array_equal(a.get_params().cpu().numpy(), blob)
+        out = tmp_path / "saved.f32"
+        a.save_params(str(out))
+        assert out.read_bytes() == open(WEIGHTS, "rb").read()
+        short = tmp_path / "short.f32"
+        short.write_bytes(blob[:100].tobytes())
+        with pytest.raises(GPError):
+            a.load_params(str(short))
+        with pytest.raises(GPError):
+            a.load_params(str(tmp_path / "missing.f32"))
+        b.set_params(torch.tensor(blob, device="cuda"))
+        c.set_params(torch.tensor(blob, device="cuda"))
+        rng = np.random.default_rng(5)
+        r0 = torch.tensor(1.0 + 0.1 * rng.random((2, 64, 64)), dtype=torch.float32, device="cuda")
+        r1 = torch.tensor(1.0 + 0.1 * rng.random((2, 64, 64)), dtype=torch.float32, device="cuda")
+        target = torch.tensor(0.01 * rng.standard_normal((2, 64, 64)), dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            la = a.train_step(r0, r1, target, 1.0 / 64, 1e-3)
+            lb = b.grads(r0, r1, target, 1.0 / 64)
+            b.adam(1e-3)
+            lc = c.grads(r0, r1, target, 1.0 / 64)
+            c.adam(1e-3)
+            assert abs(la - lb) <= 1e-6 * abs(lb) and abs(lc - lb) <= 1e-6 * abs(lb)
+        pa, pb, pc = (w.get_params().cpu().numpy() for w in (a, b, c))
+        assert np.abs(pa - blob).max() > 1e-4  # the steps moved the parameters
+        # Adam's first steps are about lr sign(g), and a gradient that the atomic sums
+        # leave within rounding of zero may step either way: two runs of ws_grads +
+        # ws_adam (b, c) differ in that way too; ws_train_step (a) may not differ more
+        fab = float(np.mean(np.abs(pa - pb) > 1e-6))
+        fbc = float(np.mean(np.abs(pb - pc) > 1e-6))
+        print("parameters differing by more than 1e-6: train_step vs grads+adam", fab, "; two grads+adam runs", fbc)
+        assert fab <= 2 * fbc + 1e-3 and fab < 0.05
+    finally:
+        a.close()
+        b.close()
+        c.close()
