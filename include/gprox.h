@@ -302,7 +302,10 @@ int gp_batch_solve(gp_ctx* ctx, const gp_instance* inst, int count, const gp_opt
  * (n >= 256), one per row pair (row passes) or column pair (column pass).
  * For transforms of length n in FP32 (fp64 = 0: the ROF path and dct_poisson)
  * or FP64 (fp64 = 1: the EMD path and dct_poisson_f64) these calls read or set
- *   row_groups  FFT groups per row-pass workgroup (rows of length n);
+ *   row_groups  FFT groups per row-pass workgroup (rows of length n; in FP32
+ *               the tuner measures the ROF row inverse on its own and may give
+ *               it another count; gp_set_shape sets both, gp_get_shape reports
+ *               the first row pass's);
  *   col_groups  FFT groups per column-pass workgroup (columns of length n);
  *   tile_width  strip width of the column-tiled intermediate between the row
  *               and column passes of columns of length n (used clamped to

@@ -76,6 +76,9 @@ struct gp_ctx {
   int row_g[2][13] = {}, col_g[2][13] = {};
   int col_lw[2][13] = {};  // log2 of the tile width of the intermediate, per column length
   bool row_tuned[2][13] = {}, col_tuned[2][13] = {};
+  // the ROF row inverse (kernel B) has its own row-pair count: measured after the
+  // joint setting, equal to the row passes' when that is fixed with gp_set_shape
+  int rowb_g[13] = {};
   float* work = nullptr;     // [max_n] FP32 tiled intermediate
   float* work2 = nullptr;    // [2 max_n] EMD stored field (ping)
   float* work3 = nullptr;    // [2 max_n] EMD stored field (pong)
@@ -329,6 +332,7 @@ void init_shapes(gp_ctx* c) {
   for (int ln = 6; ln <= 12; ++ln) {
     const ShapeInfo a = shape_info<float2>(1 << ln), b = shape_info<double2>(1 << ln);
     c->row_g[0][ln] = a.row_def;
+    c->rowb_g[ln] = a.row_def;
     c->col_g[0][ln] = a.col_def;
     c->col_lw[0][ln] = kTileLgDefault[0];
     c->col_lw[1][ln] = kTileLgDefault[1];
@@ -421,7 +425,7 @@ template <int N> struct Fused {
                 aniso, mode, partials, T.tw32, T.dw32);
   }
   static void rof_B(gp_ctx* c, const float* dhat, float* u, int nyi, int m, const int* active) {
-    const int G = c->row_g[0][ilog2i(N)];
+    const int G = c->rowb_g[ilog2i(N)];
     const int ny = nyi * m, blocks = (ny / 2 + G - 1) / G;
     const Tables& T = c->tab[ilog2i(N)];
     GP_LAUNCH(c, (k_rof_B<N>), dim3(blocks), dim3(G * Sched<N>::T), (G * RowShape<N, float2>::GROUP_LDS),
@@ -983,6 +987,24 @@ int tune_group(gp_ctx* c, const Group& g0) {
   c->col_g[di][ly] = bc;
   c->col_lw[di][ly] = bl;
   c->row_g[di][lx] = br;
+  if (!f64) c->rowb_g[lx] = br;
+  if (!f64 && rows.size() > 1) {
+    // the ROF row inverse alone, on the intermediate the last candidate left (its
+    // time does not depend on the values): kept at the joint choice unless
+    // another count is at least 3% faster
+    double tb_best = 1e30, tb_joint = 1e30;
+    int bb = br;
+    for (int rg : rows) {
+      c->rowb_g[lx] = rg;
+      const double t = time_ms(c, [&] { GP_DISPATCH_NM(g.nx, Fused, rof_B, c, g.rhat, scr, g.nyi, g.m, g.active); }, 7);
+      if (rg == br) tb_joint = t;
+      if (t < tb_best) {
+        tb_best = t;
+        bb = rg;
+      }
+    }
+    c->rowb_g[lx] = tb_joint <= 1.03 * tb_best ? br : bb;
+  }
   c->col_tuned[di][ly] = true;
   c->row_tuned[di][lx] = true;
   c->prof_on = prof;
@@ -2269,6 +2291,7 @@ int gp_set_shape(gp_ctx* c, int fp64, int n, int row_groups, int col_groups, int
   if (row_groups) {
     c->row_g[di][ln] = row_groups;
     c->row_tuned[di][ln] = true;
+    if (!fp64) c->rowb_g[ln] = row_groups;
   }
   if (col_groups) c->col_g[di][ln] = col_groups;
   if (tile_width) c->col_lw[di][ln] = ilog2i(tile_width);
