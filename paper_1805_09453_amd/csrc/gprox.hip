@@ -990,13 +990,16 @@ int tune_group(gp_ctx* c, const Group& g0) {
   if (!f64) c->rowb_g[lx] = br;
   if (!f64 && rows.size() > 1) {
     // the ROF row inverse alone, on the intermediate the last candidate left (its
-    // time does not depend on the values): kept at the joint choice unless
+    // time does not depend on the values), four launches per sample so that the
+    // launch overhead does not blur a few percent: kept at the joint choice unless
     // another count is at least 3% faster
     double tb_best = 1e30, tb_joint = 1e30;
     int bb = br;
     for (int rg : rows) {
       c->rowb_g[lx] = rg;
-      const double t = time_ms(c, [&] { GP_DISPATCH_NM(g.nx, Fused, rof_B, c, g.rhat, scr, g.nyi, g.m, g.active); }, 7);
+      const double t = time_ms(c, [&] {
+        for (int q = 0; q < 4; ++q) GP_DISPATCH_NM(g.nx, Fused, rof_B, c, g.rhat, scr, g.nyi, g.m, g.active);
+      }, 7);
       if (rg == br) tb_joint = t;
       if (t < tb_best) {
         tb_best = t;
