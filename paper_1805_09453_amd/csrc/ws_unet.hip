@@ -54,6 +54,14 @@ union V8 {
   bf16 h[8];
 };
 
+// Workgroups go to the 8 XCDs round-robin (block b runs on XCD b mod 8), each
+// XCD with its own L2.  This renumbering gives every XCD a contiguous range of
+// [0, nb), so blocks that read the same pixels run under one L2.
+__device__ __forceinline__ int xcd_range(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // ------------------------------------------------------------ implicit-GEMM convolution
 enum { M_CONV3 = 0, M_TFWD = 1, M_TBWD = 2 };
 
@@ -104,7 +112,10 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   __shared__ __align__(16) bf16 As[2 * MT * LD];
   __shared__ __align__(16) bf16 Bs[2 * NT * LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int p0 = blockIdx.x * MT, n0 = blockIdx.y * NT;
+  // the channel tiles of one pixel tile are consecutive blocks of one XCD (they
+  // gather the same activations)
+  const int gy = gridDim.y, lb = xcd_range(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gy);
+  const int p0 = (lb / gy) * MT, n0 = (lb - (lb / gy) * gy) * NT;
   const int M = a.B * a.H * a.W;
   const int nsteps = a.kpad / KS;
   uint4 ra[2], rb = {0u, 0u, 0u, 0u};
@@ -243,14 +254,23 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   // 64 pixels per step (two K = 32 MFMA blocks between barriers); the operands
   // of the next step are loaded into registers while this step's MFMAs run.
-  // (128-pixel steps with 8-byte stores measured no faster.)
+  // (128-pixel steps with 8-byte stores measured no faster.)  The [row][pixel]
+  // tiles hold each row's eight 8-pixel chunks in the order chunk ^ (row / 8 mod 8):
+  // the transposing 4-byte stores of the eight lanes that share a pixel pair then
+  // fall in distinct banks, and the 16-byte MFMA operand reads of eight
+  // consecutive rows stay conflict-free.
   constexpr int PS = 64, LD = PS + 8;
   __shared__ __align__(16) bf16 At[64 * LD];  // [m][p]
   __shared__ __align__(16) bf16 Bt[64 * LD];  // [k][p]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int m0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+  // the (m, k) tiles of one pixel chunk are consecutive blocks of one XCD (they
+  // read the same pixels)
+  const int gx = gridDim.x, gxy = gx * gridDim.y;
+  const int lb = xcd_range(blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z), gxy * gridDim.z);
+  const int bz = lb / gxy, by = (lb - bz * gxy) / gx, bx = lb - bz * gxy - by * gx;
+  const int m0 = bx * 64, k0 = by * 64;
   const int P = a.B * a.H * a.W;
-  const int pb = blockIdx.z * a.chunk, pe = min(P, pb + a.chunk);
+  const int pb = bz * a.chunk, pe = min(P, pb + a.chunk);
   f32x4 acc[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -258,6 +278,9 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   // channel's pair is one 4-byte LDS store), channels 8q..8q+7
   const int px = tid >> 3, q = tid & 7;
   const int ktap = (k0 + 8 * q) / a.ck, kc = (k0 + 8 * q) - ktap * a.ck;
+  // m rows at or beyond c1m (layers with 32 output channels fill half the tile)
+  // are neither staged nor multiplied: no wave reads them
+  const bool arow = m0 + 8 * q < a.c1m, wact = m0 + w * 16 < a.c1m;
   auto load = [&](int p, int b, int y, int x, V8& va, V8& vb) {
     va.u = uint4{0u, 0u, 0u, 0u};
     vb.u = va.u;
@@ -307,20 +330,25 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
     __syncthreads();  // the previous step's operand reads are done
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      *reinterpret_cast<uint32_t*>(&At[(8 * q + j) * LD + 2 * px]) = pack(a0.h[j], a1.h[j]);
-      *reinterpret_cast<uint32_t*>(&Bt[(8 * q + j) * LD + 2 * px]) = pack(b0.h[j], b1.h[j]);
+      // row 8q + j, 8-pixel chunk px / 4 stored at chunk (px / 4) ^ q
+      const int e = (8 * q + j) * LD + (((px >> 2) ^ q) << 3) + 2 * (px & 3);
+      if (arow) *reinterpret_cast<uint32_t*>(&At[e]) = pack(a0.h[j], a1.h[j]);
+      *reinterpret_cast<uint32_t*>(&Bt[e]) = pack(b0.h[j], b1.h[j]);
     }
     __syncthreads();
     advance(PS);
     load2(ps + PS + 2 * px, a0, b0, a1, b1);
+    if (wact) {
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&At[(w * 16 + (lane & 15)) * LD + kk * 32 + (lane >> 4) * 8]);
+      for (int kk = 0; kk < 2; ++kk) {
+        const int c8 = kk * 4 + (lane >> 4), ma = w * 16 + (lane & 15);
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(&At[ma * LD + ((c8 ^ (ma >> 3)) << 3)]);
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
-        const bf16x8 bv =
-            *reinterpret_cast<const bf16x8*>(&Bt[(ni * 16 + (lane & 15)) * LD + kk * 32 + (lane >> 4) * 8]);
-        acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
+        for (int ni = 0; ni < 4; ++ni) {
+          const int kb = ni * 16 + (lane & 15);
+          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Bt[kb * LD + ((c8 ^ (kb >> 3)) << 3)]);
+          acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
+        }
       }
     }
   }
