@@ -135,23 +135,66 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   }
   const int ct = max(1, MODE == M_CONV3 ? a.c1 + a.c2 : a.c1);
   int ktap = ((tid & 3) * 8) / ct, kci = (tid & 3) * 8 - ktap * ct;
-  auto gload = [&](int s) {  // called for s = 0, 1, 2, ... in turn
-    const int k0 = s * KS + (tid & 3) * 8;
+  // 3x3 layers whose source widths are multiples of KS (all but the input layer):
+  // every K step is one tap of one source for the whole block, so the tap, its
+  // pixel offset and the source are uniform; per thread only a precomputed
+  // pixel offset per source and a mask of the taps that stay inside the image
+  const bool uni = MODE == M_CONV3 && a.c1 % KS == 0 && a.c2 % KS == 0;
+  int utap = 0, ucib = 0;
+  long long o1[2] = {0, 0}, o2[2] = {0, 0};
+  unsigned tmask[2] = {0u, 0u};
+  bool rok[2] = {true, true};  // ra[j] holds data (else zeros are stored)
+  if (uni) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      ra[j] = conv_a_at<MODE>(a, pin[j], size_t(p0 + ((tid + 256 * j) >> 2)), pb_[j], py_[j], px_[j], k0, ktap, kci);
-    if (tid < NT * 4) rb = ld16(a.w + size_t(n0 + (tid >> 2)) * a.kpad + s * KS + (tid & 3) * 8);
-    kci += KS;
-    while (kci >= ct) {
-      kci -= ct;
-      ++ktap;
+    for (int j = 0; j < 2; ++j) {
+      const long long p = p0 + ((tid + 256 * j) >> 2);
+      o1[j] = p * a.s1;
+      o2[j] = p * a.s2;
+      for (int t = 0; t < 9; ++t) {
+        const int yy = py_[j] + t / 3 - 1, xx = px_[j] + t % 3 - 1;
+        if (pin[j] && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) tmask[j] |= 1u << t;
+      }
     }
+  }
+  auto gload = [&](int s) {  // called for s = 0, 1, 2, ... in turn
+    if (uni) {
+      const int dy = (utap >= 3) + (utap >= 6), dx = utap - 3 * dy;
+      const bool first = ucib < a.c1;
+      const bf16* base = first ? a.x1 : a.x2;
+      const long long toff = (long long)((dy - 1) * a.W + (dx - 1)) * (first ? a.s1 : a.s2) +
+                             (first ? ucib : ucib - a.c1) + (tid & 3) * 8;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // the load is issued from an in-bounds address in every case and masked
+        // where it is stored to LDS, so that no branch or wait follows it
+        rok[j] = (tmask[j] >> utap) & 1u;
+        ra[j] = ld16(rok[j] ? base + (first ? o1[j] : o2[j]) + toff : a.x1);
+      }
+      ucib += KS;
+      if (ucib >= ct) {
+        ucib = 0;
+        ++utap;
+      }
+    } else {
+      const int k0 = s * KS + (tid & 3) * 8;
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        ra[j] = conv_a_at<MODE>(a, pin[j], size_t(p0 + ((tid + 256 * j) >> 2)), pb_[j], py_[j], px_[j], k0, ktap, kci);
+      kci += KS;
+      while (kci >= ct) {
+        kci -= ct;
+        ++ktap;
+      }
+    }
+    if (tid < NT * 4) rb = ld16(a.w + size_t(n0 + (tid >> 2)) * a.kpad + s * KS + (tid & 3) * 8);
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int v = tid + 256 * j;
-      *reinterpret_cast<uint4*>(&As[buf * MT * LD + (v >> 2) * LD + (v & 3) * 8]) = ra[j];
+      const uint4 r = ra[j];
+      *reinterpret_cast<uint4*>(&As[buf * MT * LD + (v >> 2) * LD + (v & 3) * 8]) =
+          uint4{rok[j] ? r.x : 0u, rok[j] ? r.y : 0u, rok[j] ? r.z : 0u, rok[j] ? r.w : 0u};
     }
     if (tid < NT * 4) *reinterpret_cast<uint4*>(&Bs[buf * NT * LD + (tid >> 2) * LD + (tid & 3) * 8]) = rb;
   };
