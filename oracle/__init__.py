@@ -32,9 +32,11 @@ programs and network flow, closed forms and invariants.  The step-size helpers
 (rof.tv_norm, rof.step_rule_tau, rof.tv_bound, emd.step_rule_tau_singular) are
 pinned in tests/test_oracle_step_rules.py by values worked out by hand on
 images with closed-form differences and by the paper's own statements about
-which term of the section 4.2 rule binds on its grids.  Small helpers that
-only feed pinned functions (rel_gap, pointwise_norm, dual_norm_max, the
-network's elementwise layers) are covered through them.  No function here is
+which term of the section 4.2 rule binds on its grids.  The small helpers
+(rel_gap, pointwise_norm, dual_norm_max, reflect, the network's ReLU and 1x1
+head with their backward passes) are pinned directly in
+tests/test_oracle_helpers.py by hand values and finite differences, besides
+their coverage through the solvers that call them.  No function here is
 "parity unpinned".
 """
 from . import grid, rof, emd, unet  # noqa: F401
