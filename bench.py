@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--batch-primes", type=int, nargs="+", default=[2, 3, 5, 7],
                     help="batch sides are snapped to the nearest number with these prime factors")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D grid leg")
+    ap.add_argument("--no-net", action="store_true", help="skip the warm-start network throughput leg")
+    ap.add_argument("--only-net", action="store_true", help="run the warm-start network throughput leg alone")
     ap.add_argument("--n3", type=int, default=256, help="side of the 3-D grid leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
@@ -231,6 +233,59 @@ def warm_leg(ctx, dev, n, tol, max_iter, pairs):
             "warm_seconds_total": float(sum(r["warm"]["seconds"] for r in rows))}
 
 
+def unet_forward_macs_per_pixel():
+    """Multiply-adds per full-resolution pixel of the warm-start network's forward pass:
+    3x3 conv pairs at widths 32/64/128/256 on levels of 1, 1/4, 1/16, 1/64 of the pixels
+    (input: the 2 densities; decoder convs read [upsampled, skip]), 2x2 stride-2
+    transposed convs (a 1x1 GEMM to 4 cout outputs per coarse pixel), 1x1 head.  The
+    kernels' zero padding of the input channels to 8 is not counted."""
+    w = [32, 64, 128, 256]
+    macs, cin = 0.0, 2
+    for lv, c in enumerate(w):
+        macs += (9 * cin * c + 9 * c * c) / 4 ** lv
+        cin = c
+    for lv in (2, 1, 0):
+        c = w[lv]
+        macs += w[lv + 1] * 4 * c / 4 ** (lv + 1)          # transposed conv from level lv + 1
+        macs += (9 * 2 * c * c + 9 * c * c) / 4 ** lv      # conv pair on [upsampled, skip]
+    return macs + w[0]
+
+
+def net_leg(ctx, dev, batch, n, steps):
+    """Warm-start network throughput: one training step (forward, backward, Adam) and
+    one inference on `batch` n x n pairs of Gaussian mixtures, mean over `steps` after
+    warm-up; BF16 MFMA peak 2.5 PFLOP/s dense.  Training counts 3 forward passes of
+    work (data and weight gradients each cost about one forward)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1805_09453_amd import WarmStart
+    pairs = [synth.emd_mixture_pair(n, synth.config_seed(4, 500 + j), k=4) for j in range(batch)]
+    r0 = torch.tensor(np.stack([a for a, _ in pairs]), dtype=torch.float32, device=dev)
+    r1 = torch.tensor(np.stack([b for _, b in pairs]), dtype=torch.float32, device=dev)
+    phi = torch.zeros_like(r0)
+    ws = WarmStart(ctx, batch, n, n)
+    out = {"batch": batch, "grid": [n, n], "steps": steps}
+    for name, fn in (("train_step", lambda: ws.train_step(r0, r1, phi, 1.0 / n, 1e-4)),
+                     ("inference", lambda: ws.predict(r0, r1))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = (time.perf_counter() - t0) / steps * 1e3
+    ws.close()
+    fwd = 2.0 * unet_forward_macs_per_pixel() * batch * n * n
+    out["forward_gflop"] = fwd / 1e9
+    out["train_tflops"] = 3 * fwd / (out["train_step_ms"] * 1e-3) / 1e12
+    out["inference_tflops"] = fwd / (out["inference_ms"] * 1e-3) / 1e12
+    out["mfma_frac_train"] = out["train_tflops"] / 2500.0
+    return out
+
+
 # HBM bytes per cell and iteration that the 3-D loops stream (FP32 state; EMD potential FP64):
 # ROF  x-forward pass with the right-hand side (u, pbar, I -> tiles) 24 + four more passes 4 x 8
 #      + update (u, delta, p -> u, p, pbar) 48
@@ -300,6 +355,10 @@ def main():
         del a, b
     ctx = Context(n, n)
     K, W, C = args.steps, args.warmup, args.iters_per_step
+    if args.only_net:
+        print(json.dumps({"warm_start_network": net_leg(ctx, dev, 8, 512, 10)}))
+        ctx.close()
+        return
 
     from paper_1805_09453_amd import Options
 
@@ -401,6 +460,8 @@ def main():
                                    tuple(args.batch_primes))
     if not args.no_3d:
         extra["grid3d"] = grid3_leg(ctx, dev, args.n3, C, K, W)
+    if not args.no_net:
+        extra["warm_start_network"] = net_leg(ctx, dev, 8, 512, 10)
     ctx.close()
     workers = args.cpu_workers or min(16, os.cpu_count() or 1)
     cpu = None if args.no_cpu else cpu_baseline(n, args.cpu_seconds, rof_iters_to_tol, workers)

@@ -34,7 +34,11 @@ def _csv(d, suffix):
 
 
 def short(name):
-    n = name.split("(")[0]
+    n = name.replace("(anonymous namespace)::", "")
+    m = re.match(r"_ZN12_GLOBAL__N_1\d+(\w+?)E", n)  # a name rocprofv3 left mangled
+    if m:
+        n = re.sub(r"^\d+", "", m.group(1))
+    n = n.split("(")[0]
     n = n.replace("void ", "").replace("gp::", "")
     n = n.replace("HIP_vector_type<float, 2u>", "f32").replace("HIP_vector_type<double, 2u>", "f64")
     return re.sub(r"\s+>", ">", n).strip()

@@ -7,6 +7,10 @@ def test_short_names():
     assert profsum.short("void gp::k_rof_A<4096>(float const*, float*)") == "k_rof_A<4096>"
     assert profsum.short("void gp::k_cols_solve<4096, HIP_vector_type<double, 2u> >(double*, int)") == \
         "k_cols_solve<4096, f64>"
+    # kernels in an anonymous namespace, demangled or left mangled by the profiler
+    assert profsum.short("void (anonymous namespace)::k_conv<0, 32>((anonymous namespace)::ConvArgs)") == \
+        "k_conv<0, 32>"
+    assert profsum.short("_ZN12_GLOBAL__N_110k_head_bwdEPKDF16bPKfS3_mPDF16bPfS5_") == "k_head_bwd"
 
 
 def test_counter_figure_is_the_late_median():
