@@ -107,10 +107,14 @@ __device__ __forceinline__ uint4 conv_a_at(const ConvArgs& a, bool pin, size_t p
 
 template <int MODE, int NT>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
-  constexpr int MT = 128, KS = 32, LD = KS + 8, LC = NT + 8;
-  static_assert(MT * LC <= 2 * MT * LD, "epilogue tile fits the A buffers");
+  // LDS tiles [row][KS] without padding; the four 16-byte chunks of row r are
+  // stored in the order chunk ^ ((r / 2) mod 4), so that the 16-byte stores (two
+  // rows per eight lanes) and the MFMA operand reads (eight rows per eight lanes)
+  // are free of bank conflicts
+  constexpr int MT = 128, KS = 32, LD = KS;
   __shared__ __align__(16) bf16 As[2 * MT * LD];
   __shared__ __align__(16) bf16 Bs[2 * NT * LD];
+  auto tl = [](int row, int chunk) { return row * LD + ((chunk ^ ((row >> 1) & 3)) << 3); };
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // the channel tiles of one pixel tile are consecutive blocks of one XCD (they
   // gather the same activations)
@@ -193,10 +197,10 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     for (int j = 0; j < 2; ++j) {
       const int v = tid + 256 * j;
       const uint4 r = ra[j];
-      *reinterpret_cast<uint4*>(&As[buf * MT * LD + (v >> 2) * LD + (v & 3) * 8]) =
+      *reinterpret_cast<uint4*>(&As[buf * MT * LD + tl(v >> 2, v & 3)]) =
           uint4{rok[j] ? r.x : 0u, rok[j] ? r.y : 0u, rok[j] ? r.z : 0u, rok[j] ? r.w : 0u};
     }
-    if (tid < NT * 4) *reinterpret_cast<uint4*>(&Bs[buf * NT * LD + (tid >> 2) * LD + (tid & 3) * 8]) = rb;
+    if (tid < NT * 4) *reinterpret_cast<uint4*>(&Bs[buf * NT * LD + tl(tid >> 2, tid & 3)]) = rb;
   };
   f32x4 acc[2][NT / 16];
 #pragma unroll
@@ -212,52 +216,59 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     bf16x8 bv[NT / 16];
 #pragma unroll
     for (int ni = 0; ni < NT / 16; ++ni)
-      bv[ni] = *reinterpret_cast<const bf16x8*>(&Bs[buf * NT * LD + (ni * 16 + (lane & 15)) * LD + (lane >> 4) * 8]);
+      bv[ni] = *reinterpret_cast<const bf16x8*>(&Bs[buf * NT * LD + tl(ni * 16 + (lane & 15), lane >> 4)]);
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi) {
-      const bf16x8 av =
-          *reinterpret_cast<const bf16x8*>(&As[buf * MT * LD + (w * 32 + mi * 16 + (lane & 15)) * LD + (lane >> 4) * 8]);
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&As[buf * MT * LD + tl(w * 32 + mi * 16 + (lane & 15), lane >> 4)]);
+      // weights as the first operand: the accumulator of lane l holds output
+      // channels 4 (l / 16) + i, i < 4, of pixel l mod 16 of the 16 x 16 tile
 #pragma unroll
       for (int ni = 0; ni < NT / 16; ++ni)
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[ni], acc[mi][ni], 0, 0, 0);
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bv[ni], av, acc[mi][ni], 0, 0, 0);
     }
     if (s + 1 < nsteps) lstore(buf ^ 1);
     __syncthreads();
   }
-  // epilogue: bias, ReLU, BF16, staged through LDS for 16-byte stores; a lane's
-  // output columns are the same for every row it holds, so their biases are read once
-  bf16* Cs = As;
-  float bias[NT / 16];
+  // epilogue: bias, ReLU, BF16; each lane stores its 4 consecutive channels of a
+  // pixel as one 8-byte vector (channel counts are multiples of 8)
+  float bias[NT / 16][4];
 #pragma unroll
   for (int ni = 0; ni < NT / 16; ++ni) {
-    const int col = n0 + ni * 16 + (lane & 15);
-    bias[ni] = (a.bias && col < a.n) ? a.bias[col % a.bmod] : 0.f;
+    const int n = n0 + ni * 16 + 4 * (lane >> 4);
+    const int nb = a.bias && n < a.n ? n % a.bmod : -1;  // n and bmod are multiples of 4
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias[ni][i] = nb >= 0 ? a.bias[nb + i] : 0.f;
   }
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < 2; ++mi) {
+    const int p = p0 + w * 32 + mi * 16 + (lane & 15);
+    if (p >= M) continue;
+    // transposed forward: output pixel (2y + tap / 2, 2x + tap % 2) of the 2x2 block
+    size_t qb = 0;
+    if (MODE == M_TFWD) {
+      const int hw = a.H * a.W, b = p / hw, r = p - b * hw, y = r / a.W, x = r - y * a.W;
+      qb = (size_t(b) * 2 * a.H + 2 * y) * size_t(2 * a.W) + 2 * x;
+    }
 #pragma unroll
-    for (int ni = 0; ni < NT / 16; ++ni)
+    for (int ni = 0; ni < NT / 16; ++ni) {
+      const int n = n0 + ni * 16 + 4 * (lane >> 4);
+      if (n >= a.n) continue;
+      unsigned short h[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = w * 32 + mi * 16 + (lane >> 4) * 4 + i, col = ni * 16 + (lane & 15);
-        float v = acc[mi][ni][i];
-        if (a.bias && n0 + col < a.n) v += bias[ni];
+        float v = acc[mi][ni][i] + bias[ni][i];
         if (a.relu) v = fmaxf(v, 0.f);
-        Cs[row * LC + col] = f2b(v);
+        h[i] = __builtin_bit_cast(unsigned short, f2b(v));
       }
-  __syncthreads();
-  for (int v = tid; v < MT * NT / 8; v += 256) {
-    const int row = v / (NT / 8), cq = v - row * (NT / 8);
-    const int p = p0 + row, n = n0 + cq * 8;
-    if (p >= M || n >= a.n) continue;
-    const uint4 val = *reinterpret_cast<const uint4*>(&Cs[row * LC + cq * 8]);
-    if (MODE == M_TFWD) {
-      const int cout = a.bmod, tap = n / cout, co = n - tap * cout;
-      const int hw = a.H * a.W, b = p / hw, r = p - b * hw, y = r / a.W, x = r - y * a.W;
-      const size_t q = (size_t(b) * 2 * a.H + 2 * y + (tap >> 1)) * size_t(2 * a.W) + 2 * x + (tap & 1);
-      st16(a.y + q * a.ys + co, val);
-    } else {
-      st16(a.y + size_t(p) * a.ys + n, val);
+      const uint2 val = make_uint2(uint32_t(h[0]) | (uint32_t(h[1]) << 16), uint32_t(h[2]) | (uint32_t(h[3]) << 16));
+      bf16* dst;
+      if (MODE == M_TFWD) {
+        const int cout = a.bmod, tap = n / cout, co = n - tap * cout;
+        dst = a.y + (qb + size_t(tap >> 1) * size_t(2 * a.W) + (tap & 1)) * a.ys + co;
+      } else {
+        dst = a.y + size_t(p) * a.ys + n;
+      }
+      *reinterpret_cast<uint2*>(dst) = val;
     }
   }
 }
