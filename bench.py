@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--cpu-workers", type=int, default=0, help="scipy.fft threads of the CPU baseline "
                     "(0: the host's cores, at most 16)")
-    ap.add_argument("--warm-pairs", type=int, default=4, help="4096^2 EMD pairs of the plain-vs-warm leg")
+    ap.add_argument("--warm-pairs", type=int, default=8, help="4096^2 EMD pairs of the plain-vs-warm leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
