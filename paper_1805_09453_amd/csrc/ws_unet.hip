@@ -288,20 +288,28 @@ struct WgArgs {
   int chunk;       // pixels per block (multiple of 64)
 };
 
-// 8 consecutive k entries of the k operand at pixel (b, y, x), k = tap ck + c
+// Address of 8 consecutive k entries of the k operand at pixel (b, y, x), k = tap ck +
+// c.  Entries outside the image or past the taps are zero: ok is false and the
+// address is the first vector of x1, so that the load is issued unconditionally
+// and masked where it is stored (a load under a branch makes the compiler wait for
+// the loads before it).
 template <int MODE>
-__device__ __forceinline__ uint4 wg_k(const WgArgs& a, int b, int y, int x, int tap, int c) {
-  const uint4 z = {0u, 0u, 0u, 0u};
-  if (tap >= a.taps) return z;
+__device__ __forceinline__ const bf16* wg_k_src(const WgArgs& a, int b, int y, int x, int tap, int c, bool& ok) {
   if (MODE == W_CONV3) {
-    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-    if (yy < 0 || yy >= a.H || xx < 0 || xx >= a.W) return z;
-    const size_t q = (size_t(b) * a.H + yy) * a.W + xx;
-    return c < a.c1 ? ld16(a.x1 + q * a.s1 + c) : ld16(a.x2 + q * a.s2 + (c - a.c1));
+    const int t = tap < a.taps ? tap : 0;
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+    ok = tap < a.taps && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+    const size_t q = ok ? (size_t(b) * a.H + yy) * a.W + xx : 0;
+    const bf16* src = c < a.c1 ? a.x1 + q * a.s1 + c : a.x2 + q * a.s2 + (c - a.c1);
+    return ok ? src : a.x1;
   } else {
+    ok = tap < a.taps;
     const size_t q = (size_t(b) * 2 * a.H + 2 * y + (tap >> 1)) * size_t(2 * a.W) + 2 * x + (tap & 1);
-    return ld16(a.x1 + q * a.s1 + c);
+    return ok ? a.x1 + q * a.s1 + c : a.x1;
   }
+}
+__device__ __forceinline__ uint4 masked(bool ok, uint4 v) {
+  return uint4{ok ? v.x : 0u, ok ? v.y : 0u, ok ? v.z : 0u, ok ? v.w : 0u};
 }
 
 template <int MODE>
@@ -335,13 +343,17 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   // m rows at or beyond c1m (layers with 32 output channels fill half the tile)
   // are neither staged nor multiplied: no wave reads them
   const bool arow = m0 + 8 * q < a.c1m, wact = m0 + w * 16 < a.c1m;
-  auto load = [&](int p, int b, int y, int x, V8& va, V8& vb) {
-    va.u = uint4{0u, 0u, 0u, 0u};
-    vb.u = va.u;
-    if (p < pe) {
-      if (m0 + 8 * q < a.c1m) va.u = ld16(a.t1 + size_t(p) * a.s1m + m0 + 8 * q);
-      vb.u = wg_k<MODE>(a, b, y, x, ktap, kc);
-    }
+  // the four loads of a step are issued without branches; okA / okB say which hold
+  // data (the others are zeroed where they are stored)
+  bool okA[2], okB[2];
+  auto load = [&](int p, int b, int y, int x, V8& va, V8& vb, bool& oka, bool& okb) {
+    const bool in = p < pe;
+    oka = in && arow;
+    va.u = ld16(oka ? a.t1 + size_t(p) * a.s1m + m0 + 8 * q : a.t1);
+    bool ok;
+    const bf16* src = wg_k_src<MODE>(a, b, y, x, ktap, kc, ok);
+    okb = in && ok;
+    vb.u = ld16(okb ? src : a.x1);
   };
   // (b, y, x) of the thread's first pixel of a step, moved on by whole steps
   // without divisions; the second pixel is the next one in raster order
@@ -354,7 +366,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
     cx = r - cy * a.W;
   }
   auto load2 = [&](int p, V8& va0, V8& vb0, V8& va1, V8& vb1) {
-    load(p, cb, cy, cx, va0, vb0);
+    load(p, cb, cy, cx, va0, vb0, okA[0], okB[0]);
     int b1 = cb, y1 = cy, x1 = cx + 1;
     if (x1 == a.W) {
       x1 = 0;
@@ -363,7 +375,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
         ++b1;
       }
     }
-    load(p + 1, b1, y1, x1, va1, vb1);
+    load(p + 1, b1, y1, x1, va1, vb1, okA[1], okB[1]);
   };
   auto advance = [&](int d) {
     cx += d;
@@ -382,6 +394,10 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
   load2(pb + 2 * px, a0, b0, a1, b1);
   for (int ps = pb; ps < pe; ps += PS) {
     __syncthreads();  // the previous step's operand reads are done
+    a0.u = masked(okA[0], a0.u);
+    a1.u = masked(okA[1], a1.u);
+    b0.u = masked(okB[0], b0.u);
+    b1.u = masked(okB[1], b1.u);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       // row 8q + j, 8-pixel chunk px / 4 stored at chunk (px / 4) ^ q
