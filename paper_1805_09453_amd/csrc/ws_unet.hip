@@ -313,7 +313,7 @@ __device__ __forceinline__ uint4 masked(bool ok, uint4 v) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
+__global__ __launch_bounds__(256, 6) void k_wgrad(WgArgs a) {
   // 64 pixels per step (two K = 32 MFMA blocks between barriers); the operands
   // of the next step are loaded into registers while this step's MFMAs run.
   // (128-pixel steps with 8-byte stores measured no faster.)  The [row][pixel]
