@@ -78,42 +78,56 @@ struct ConvArgs {
   int relu;
 };
 
-// 8 consecutive K entries (from k0) of row p of the implicit A matrix, with the
-// pixel given as (b, y, x) and k0 as (tap, ci), k0 = tap ct + ci (3x3: ct = c1 +
-// c2, tap = 3 dy + dx; transposed backward: ct = c1, the 2x2 output block): the
+// 16 zero bytes in device memory: the source of the operand pieces that lie
+// outside the image or the padded K range (loads go straight to LDS, where no
+// value can be masked)
+__device__ __align__(16) uint4 g_zero16 = {0u, 0u, 0u, 0u};
+
+// Address of 8 consecutive K entries (from k0) of row p of the implicit A matrix,
+// with the pixel given as (b, y, x) and k0 as (tap, ci), k0 = tap ct + ci (3x3: ct =
+// c1 + c2, tap = 3 dy + dx; transposed backward: ct = c1, the 2x2 output block): the
 // K loop keeps these without integer divisions.  pin: p lies in the pixel space.
+// Entries outside the image or the padded K range read g_zero16.
 template <int MODE>
-__device__ __forceinline__ uint4 conv_a_at(const ConvArgs& a, bool pin, size_t p, int b, int y, int x, int k0, int tap,
-                                           int ci) {
-  const uint4 z = {0u, 0u, 0u, 0u};
-  if (!pin) return z;
+__device__ __forceinline__ const bf16* conv_a_src(const ConvArgs& a, bool pin, size_t p, int b, int y, int x, int k0,
+                                                  int tap, int ci) {
+  const bf16* zero = reinterpret_cast<const bf16*>(&g_zero16);
+  if (!pin) return zero;
   if (MODE == M_CONV3) {
-    if (tap >= 9) return z;
+    if (tap >= 9) return zero;
     const int dy = (tap >= 3) + (tap >= 6), dx = tap - 3 * dy;
     const int yy = y + dy - 1, xx = x + dx - 1;
-    if (yy < 0 || yy >= a.H || xx < 0 || xx >= a.W) return z;
+    if (yy < 0 || yy >= a.H || xx < 0 || xx >= a.W) return zero;
     // the neighbour is pixel p + (dy - 1) W + (dx - 1) of the same image
     const long long q = (long long)p + (dy - 1) * a.W + (dx - 1);
-    return ci < a.c1 ? ld16(a.x1 + q * a.s1 + ci) : ld16(a.x2 + q * a.s2 + (ci - a.c1));
+    return ci < a.c1 ? a.x1 + q * a.s1 + ci : a.x2 + q * a.s2 + (ci - a.c1);
   } else if (MODE == M_TFWD) {
-    if (k0 >= a.c1) return z;
-    return ld16(a.x1 + p * a.s1 + k0);
+    if (k0 >= a.c1) return zero;
+    return a.x1 + p * a.s1 + k0;
   } else {
-    if (tap >= 4) return z;
+    if (tap >= 4) return zero;
     const size_t q = (size_t(b) * 2 * a.H + 2 * y + (tap >> 1)) * size_t(2 * a.W) + 2 * x + (tap & 1);
-    return ld16(a.x1 + q * a.s1 + ci);
+    return a.x1 + q * a.s1 + ci;
   }
 }
 
+// 16 bytes per lane from global memory straight into LDS: lane i's bytes land at
+// lds + 16 i (lds is the same for the whole wave)
+__device__ __forceinline__ void ld16_lds(const bf16* src, bf16* lds) {
+  __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (__attribute__((address_space(3))) void*)(lds), 16,
+                                   0, 0);
+}
+
 template <int MODE, int NT>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+__global__ __launch_bounds__(256, NT == 32 ? 7 : 5) void k_conv(ConvArgs a) {
   // LDS tiles [row][KS] without padding; the four 16-byte chunks of row r are
-  // stored in the order chunk ^ ((r / 2) mod 4), so that the 16-byte stores (two
-  // rows per eight lanes) and the MFMA operand reads (eight rows per eight lanes)
-  // are free of bank conflicts
+  // stored in the order chunk ^ ((r / 2) mod 4), so that the MFMA operand reads
+  // (eight rows per eight lanes) are free of bank conflicts
   constexpr int MT = 128, KS = 32, LD = KS;
-  __shared__ __align__(16) bf16 As[2 * MT * LD];
-  __shared__ __align__(16) bf16 Bs[2 * NT * LD];
+  // two buffers per operand, as separate objects: the compiler can then tell the
+  // reads of one from the loads into the other and does not wait for those loads
+  __shared__ __align__(16) bf16 As0[MT * LD], As1[MT * LD];
+  __shared__ __align__(16) bf16 Bs0[NT * LD], Bs1[NT * LD];
   auto tl = [](int row, int chunk) { return row * LD + ((chunk ^ ((row >> 1) & 3)) << 3); };
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // the channel tiles of one pixel tile are consecutive blocks of one XCD (they
@@ -122,9 +136,12 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int p0 = (lb / gy) * MT, n0 = (lb - (lb / gy) * gy) * NT;
   const int M = a.B * a.H * a.W;
   const int nsteps = a.kpad / KS;
-  uint4 ra[2], rb = {0u, 0u, 0u, 0u};
-  // this thread's two A rows (pixels p0 + tid/4 and 64 further) and its K offset
-  // (tid % 4) * 8 + s KS, the same for both rows
+  // the operand pieces go from global memory straight into LDS, 16 bytes per lane
+  // at the lane's slot of the tile: thread tid fills slot tid % 4 of A rows tid / 4
+  // and 64 + tid / 4 (pixels p0 + row) and, below 4 NT threads, of B row tid / 4.
+  // The slot holds logical K chunk lc of the step (the swizzle of the row), so the
+  // thread loads K offset lc * 8 + s KS.
+  const int lc = (tid & 3) ^ ((tid >> 3) & 3);
   int pb_[2], py_[2], px_[2];
   bool pin[2];
 #pragma unroll
@@ -138,7 +155,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     px_[j] = r - py_[j] * a.W;
   }
   const int ct = max(1, MODE == M_CONV3 ? a.c1 + a.c2 : a.c1);
-  int ktap = ((tid & 3) * 8) / ct, kci = (tid & 3) * 8 - ktap * ct;
+  int ktap = (lc * 8) / ct, kci = lc * 8 - ktap * ct;
   // 3x3 layers whose source widths are multiples of KS (all but the input layer):
   // every K step is one tap of one source for the whole block, so the tap, its
   // pixel offset and the source are uniform; per thread only a precomputed
@@ -147,7 +164,6 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   int utap = 0, ucib = 0;
   long long o1[2] = {0, 0}, o2[2] = {0, 0};
   unsigned tmask[2] = {0u, 0u};
-  bool rok[2] = {true, true};  // ra[j] holds data (else zeros are stored)
   if (uni) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -160,19 +176,19 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
       }
     }
   }
-  auto gload = [&](int s) {  // called for s = 0, 1, 2, ... in turn
+  const bf16* zero = reinterpret_cast<const bf16*>(&g_zero16);
+  // issues step s's loads into the LDS buffers Ab, Bb; called for s = 0, 1, 2, ... in turn
+  auto gload = [&](int s, bf16* Ab, bf16* Bb) {
     if (uni) {
       const int dy = (utap >= 3) + (utap >= 6), dx = utap - 3 * dy;
       const bool first = ucib < a.c1;
       const bf16* base = first ? a.x1 : a.x2;
       const long long toff = (long long)((dy - 1) * a.W + (dx - 1)) * (first ? a.s1 : a.s2) +
-                             (first ? ucib : ucib - a.c1) + (tid & 3) * 8;
+                             (first ? ucib : ucib - a.c1) + lc * 8;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        // the load is issued from an in-bounds address in every case and masked
-        // where it is stored to LDS, so that no branch or wait follows it
-        rok[j] = (tmask[j] >> utap) & 1u;
-        ra[j] = ld16(rok[j] ? base + (first ? o1[j] : o2[j]) + toff : a.x1);
+        const bool ok = (tmask[j] >> utap) & 1u;
+        ld16_lds(ok ? base + (first ? o1[j] : o2[j]) + toff : zero, Ab + (j * 256 + w * 64) * 8);
       }
       ucib += KS;
       if (ucib >= ct) {
@@ -180,54 +196,52 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         ++utap;
       }
     } else {
-      const int k0 = s * KS + (tid & 3) * 8;
+      const int k0 = s * KS + lc * 8;
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        ra[j] = conv_a_at<MODE>(a, pin[j], size_t(p0 + ((tid + 256 * j) >> 2)), pb_[j], py_[j], px_[j], k0, ktap, kci);
+        ld16_lds(conv_a_src<MODE>(a, pin[j], size_t(p0 + ((tid + 256 * j) >> 2)), pb_[j], py_[j], px_[j], k0, ktap,
+                                  kci),
+                 Ab + (j * 256 + w * 64) * 8);
       kci += KS;
       while (kci >= ct) {
         kci -= ct;
         ++ktap;
       }
     }
-    if (tid < NT * 4) rb = ld16(a.w + size_t(n0 + (tid >> 2)) * a.kpad + s * KS + (tid & 3) * 8);
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int v = tid + 256 * j;
-      const uint4 r = ra[j];
-      *reinterpret_cast<uint4*>(&As[buf * MT * LD + tl(v >> 2, v & 3)]) =
-          uint4{rok[j] ? r.x : 0u, rok[j] ? r.y : 0u, rok[j] ? r.z : 0u, rok[j] ? r.w : 0u};
-    }
-    if (tid < NT * 4) *reinterpret_cast<uint4*>(&Bs[buf * NT * LD + tl(tid >> 2, tid & 3)]) = rb;
+    if (tid < NT * 4)  // whole waves
+      ld16_lds(a.w + size_t(n0 + (tid >> 2)) * a.kpad + s * KS + lc * 8, Bb + w * 64 * 8);
   };
   f32x4 acc[2][NT / 16];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < NT / 16; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int s = 0; s < nsteps; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nsteps) gload(s + 1);
+  // step s multiplies the operands in (Ar, Br) while step s + 1's load into (Aw, Bw),
+  // which were last read before the previous barrier
+  auto step = [&](int s, const bf16* Ar, const bf16* Br, bf16* Aw, bf16* Bw) {
+    if (s + 1 < nsteps) gload(s + 1, Aw, Bw);
     bf16x8 bv[NT / 16];
 #pragma unroll
     for (int ni = 0; ni < NT / 16; ++ni)
-      bv[ni] = *reinterpret_cast<const bf16x8*>(&Bs[buf * NT * LD + tl(ni * 16 + (lane & 15), lane >> 4)]);
+      bv[ni] = *reinterpret_cast<const bf16x8*>(&Br[tl(ni * 16 + (lane & 15), lane >> 4)]);
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&As[buf * MT * LD + tl(w * 32 + mi * 16 + (lane & 15), lane >> 4)]);
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&Ar[tl(w * 32 + mi * 16 + (lane & 15), lane >> 4)]);
       // weights as the first operand: the accumulator of lane l holds output
       // channels 4 (l / 16) + i, i < 4, of pixel l mod 16 of the 16 x 16 tile
 #pragma unroll
       for (int ni = 0; ni < NT / 16; ++ni)
         acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bv[ni], av, acc[mi][ni], 0, 0, 0);
     }
-    if (s + 1 < nsteps) lstore(buf ^ 1);
+    __builtin_amdgcn_s_waitcnt(0);  // the next buffers' loads have landed
     __syncthreads();
+  };
+  gload(0, As0, Bs0);
+  __builtin_amdgcn_s_waitcnt(0);  // the LDS-bound loads have landed
+  __syncthreads();
+  for (int s = 0; s < nsteps; s += 2) {
+    step(s, As0, Bs0, As1, Bs1);
+    if (s + 1 < nsteps) step(s + 1, As1, Bs1, As0, Bs0);
   }
   // epilogue: bias, ReLU, BF16; each lane stores its 4 consecutive channels of a
   // pixel as one 8-byte vector (channel counts are multiples of 8)
