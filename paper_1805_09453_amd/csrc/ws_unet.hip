@@ -23,7 +23,8 @@
 //            store) and backward-data (K gathers the 2x2 output block).
 //   k_wgrad  weight gradients as D[m][k] = sum_p A[p][m] B[p][k] with the
 //            pixel sum split over blocks (FP32 atomics into the blob);
-//            operands staged transposed in LDS.
+//            pixel-major operand tiles loaded straight into LDS, MFMA
+//            fragments read with transposing LDS reads.
 //   elementwise: input packing, pooling, ReLU and skip backward, head, loss,
 //            channel sums (bias gradients), Adam, weight packing, resampling.
 #include <hip/hip_runtime.h>
@@ -303,10 +304,8 @@ struct WgArgs {
 };
 
 // Address of 8 consecutive k entries of the k operand at pixel (b, y, x), k = tap ck +
-// c.  Entries outside the image or past the taps are zero: ok is false and the
-// address is the first vector of x1, so that the load is issued unconditionally
-// and masked where it is stored (a load under a branch makes the compiler wait for
-// the loads before it).
+// c.  Entries outside the image or past the taps are zero: ok is false (and the
+// address the first vector of x1); the caller then reads the zero vector instead.
 template <int MODE>
 __device__ __forceinline__ const bf16* wg_k_src(const WgArgs& a, int b, int y, int x, int tap, int c, bool& ok) {
   if (MODE == W_CONV3) {
@@ -322,22 +321,28 @@ __device__ __forceinline__ const bf16* wg_k_src(const WgArgs& a, int b, int y, i
     return ok ? a.x1 + q * a.s1 + c : a.x1;
   }
 }
-__device__ __forceinline__ uint4 masked(bool ok, uint4 v) {
-  return uint4{ok ? v.x : 0u, ok ? v.y : 0u, ok ? v.z : 0u, ok ? v.w : 0u};
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+// gfx950 transposing LDS read: in each group of 16 lanes whose addresses cover a
+// 4 x 16 block of 16-bit values (lane j: row j / 4, columns 4 (j mod 4) .. + 3),
+// lane i receives column i of the four rows
+__device__ __forceinline__ s16x4 ld_tr16(const bf16* p) {
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4*)(p));
 }
 
 template <int MODE>
 __global__ __launch_bounds__(256, 6) void k_wgrad(WgArgs a) {
-  // 64 pixels per step (two K = 32 MFMA blocks between barriers); the operands
-  // of the next step are loaded into registers while this step's MFMAs run.
-  // (128-pixel steps with 8-byte stores measured no faster.)  The [row][pixel]
-  // tiles hold each row's eight 8-pixel chunks in the order chunk ^ (row / 8 mod 8):
-  // the transposing 4-byte stores of the eight lanes that share a pixel pair then
-  // fall in distinct banks, and the 16-byte MFMA operand reads of eight
-  // consecutive rows stay conflict-free.
-  constexpr int PS = 64, LD = PS + 8;
-  __shared__ __align__(16) bf16 At[64 * LD];  // [m][p]
-  __shared__ __align__(16) bf16 Bt[64 * LD];  // [k][p]
+  // Tiles of 64 pixels per step, pixel-major as in memory: At[p][m] (64 m
+  // channels) and Bt[p][k] (64 k entries), 128-byte rows whose 16-byte chunks are
+  // stored in the order chunk ^ 2 (p mod 4).  Both are loaded straight into LDS
+  // (16 bytes per lane; pieces outside the image, the taps or the channels read a
+  // zero vector), double-buffered as separate LDS objects with the loop unrolled by
+  // two, so the loads of the next step overlap this step's MFMAs.  The MFMA
+  // fragments (8 consecutive pixels of one channel per lane) are two transposing
+  // reads of 4 x 16 blocks each; with the chunk order above these are free of bank
+  // conflicts.  Wave w computes m rows 16 w .. + 16 of the 64 x 64 (m, k) tile.
+  constexpr int PS = 64, TS = PS * 64;
+  __shared__ __align__(16) bf16 At0[TS], At1[TS], Bt0[TS], Bt1[TS];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // the (m, k) tiles of one pixel chunk are consecutive blocks of one XCD (they
   // read the same pixels)
@@ -350,91 +355,84 @@ __global__ __launch_bounds__(256, 6) void k_wgrad(WgArgs a) {
   f32x4 acc[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // this thread's pixels 2 px and 2 px + 1 of a step (adjacent in the [m][p] tiles, so each
-  // channel's pair is one 4-byte LDS store), channels 8q..8q+7
-  const int px = tid >> 3, q = tid & 7;
-  const int ktap = (k0 + 8 * q) / a.ck, kc = (k0 + 8 * q) - ktap * a.ck;
-  // m rows at or beyond c1m (layers with 32 output channels fill half the tile)
-  // are neither staged nor multiplied: no wave reads them
-  const bool arow = m0 + 8 * q < a.c1m, wact = m0 + w * 16 < a.c1m;
-  // the four loads of a step are issued without branches; okA / okB say which hold
-  // data (the others are zeroed where they are stored)
-  bool okA[2], okB[2];
-  auto load = [&](int p, int b, int y, int x, V8& va, V8& vb, bool& oka, bool& okb) {
-    const bool in = p < pe;
-    oka = in && arow;
-    va.u = ld16(oka ? a.t1 + size_t(p) * a.s1m + m0 + 8 * q : a.t1);
-    bool ok;
-    const bf16* src = wg_k_src<MODE>(a, b, y, x, ktap, kc, ok);
-    okb = in && ok;
-    vb.u = ld16(okb ? src : a.x1);
-  };
-  // (b, y, x) of the thread's first pixel of a step, moved on by whole steps
-  // without divisions; the second pixel is the next one in raster order
-  int cb, cy, cx;
-  {
-    const int p = pb + 2 * px, hw = a.H * a.W;
-    cb = p / hw;
-    const int r = p - cb * hw;
-    cy = r / a.W;
-    cx = r - cy * a.W;
-  }
-  auto load2 = [&](int p, V8& va0, V8& vb0, V8& va1, V8& vb1) {
-    load(p, cb, cy, cx, va0, vb0, okA[0], okB[0]);
-    int b1 = cb, y1 = cy, x1 = cx + 1;
-    if (x1 == a.W) {
-      x1 = 0;
-      if (++y1 == a.H) {
-        y1 = 0;
-        ++b1;
-      }
-    }
-    load(p + 1, b1, y1, x1, va1, vb1, okA[1], okB[1]);
-  };
-  auto advance = [&](int d) {
-    cx += d;
-    while (cx >= a.W) {
-      cx -= a.W;
-      if (++cy == a.H) {
-        cy = 0;
-        ++cb;
-      }
-    }
-  };
-  auto pack = [](bf16 lo, bf16 hi) {
-    return uint32_t(__builtin_bit_cast(unsigned short, lo)) | (uint32_t(__builtin_bit_cast(unsigned short, hi)) << 16);
-  };
-  V8 a0, b0, a1, b1;
-  load2(pb + 2 * px, a0, b0, a1, b1);
-  for (int ps = pb; ps < pe; ps += PS) {
-    __syncthreads();  // the previous step's operand reads are done
-    a0.u = masked(okA[0], a0.u);
-    a1.u = masked(okA[1], a1.u);
-    b0.u = masked(okB[0], b0.u);
-    b1.u = masked(okB[1], b1.u);
+  // this thread's two pieces of a step: pixel rows pr[j] = 32 j + 8 w + lane / 8 of
+  // the tile, physical chunk lane % 8, holding logical chunk lc (channels / k
+  // entries 8 lc .. + 7); the LDS slot of piece j is 16 (256 j + tid) bytes
+  const int lc = (lane & 7) ^ (2 * ((lane >> 3) & 3));
+  const bool mok = m0 + 8 * lc < a.c1m;
+  const int ktap = (k0 + 8 * lc) / a.ck, kc = (k0 + 8 * lc) - ktap * a.ck;
+  const bool wact = m0 + w * 16 < a.c1m;
+  const bf16* zero = reinterpret_cast<const bf16*>(&g_zero16);
+  // (b, y, x) of each piece's pixel, moved on by whole steps without divisions
+  int cb[2], cy[2], cx[2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      // row 8q + j, 8-pixel chunk px / 4 stored at chunk (px / 4) ^ q
-      const int e = (8 * q + j) * LD + (((px >> 2) ^ q) << 3) + 2 * (px & 3);
-      if (arow) *reinterpret_cast<uint32_t*>(&At[e]) = pack(a0.h[j], a1.h[j]);
-      *reinterpret_cast<uint32_t*>(&Bt[e]) = pack(b0.h[j], b1.h[j]);
+  for (int j = 0; j < 2; ++j) {
+    const int p = pb + 32 * j + 8 * w + (lane >> 3), hw = a.H * a.W;
+    cb[j] = p / hw;
+    const int r = p - cb[j] * hw;
+    cy[j] = r / a.W;
+    cx[j] = r - cy[j] * a.W;
+  }
+  auto advance = [&]() {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cx[j] += PS;
+      while (cx[j] >= a.W) {
+        cx[j] -= a.W;
+        if (++cy[j] == a.H) {
+          cy[j] = 0;
+          ++cb[j];
+        }
+      }
     }
-    __syncthreads();
-    advance(PS);
-    load2(ps + PS + 2 * px, a0, b0, a1, b1);
+  };
+  // issues the loads of the step at pixel ps (the pixel state is at ps) into (Aw, Bw)
+  auto gload = [&](int ps, bf16* Aw, bf16* Bw) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int p = ps + 32 * j + 8 * w + (lane >> 3);
+      const bool in = p < pe;
+      ld16_lds(in && mok ? a.t1 + size_t(p) * a.s1m + m0 + 8 * lc : zero, Aw + (256 * j + 64 * w) * 8);
+      bool ok;
+      const bf16* src = wg_k_src<MODE>(a, cb[j], cy[j], cx[j], ktap, kc, ok);
+      ld16_lds(in && ok ? src : zero, Bw + (256 * j + 64 * w) * 8);
+    }
+  };
+  // element offset of a transposing read's 8 bytes for lane i of its group: rows
+  // rb + i / 4, logical columns cb0 + 4 (i mod 4) .. + 3
+  auto tra = [](int rb, int cb0, int i) {
+    const int row = rb + (i >> 2), col = cb0 + 4 * (i & 3);
+    return row * 64 + ((((col >> 3) ^ (2 * (row & 3)))) << 3) + (col & 7);
+  };
+  auto step = [&](int ps, const bf16* Ar, const bf16* Br, bf16* Aw, bf16* Bw) {
+    if (ps + PS < pe) {
+      advance();
+      gload(ps + PS, Aw, Bw);
+    }
     if (wact) {
+      const int g = lane >> 4, i = lane & 15;
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
-        const int c8 = kk * 4 + (lane >> 4), ma = w * 16 + (lane & 15);
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(&At[ma * LD + ((c8 ^ (ma >> 3)) << 3)]);
+        const int rb = kk * 32 + 8 * g;
+        const s16x4 a0 = ld_tr16(Ar + tra(rb, w * 16, i)), a1 = ld_tr16(Ar + tra(rb + 4, w * 16, i));
+        const bf16x8 av = __builtin_bit_cast(bf16x8, __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7));
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) {
-          const int kb = ni * 16 + (lane & 15);
-          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Bt[kb * LD + ((c8 ^ (kb >> 3)) << 3)]);
+          const s16x4 b0 = ld_tr16(Br + tra(rb, ni * 16, i)), b1 = ld_tr16(Br + tra(rb + 4, ni * 16, i));
+          const bf16x8 bv = __builtin_bit_cast(bf16x8, __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7));
           acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
         }
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the next buffers' loads have landed
+    __syncthreads();
+  };
+  gload(pb, At0, Bt0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int ps = pb; ps < pe; ps += 2 * PS) {
+    step(ps, At0, Bt0, At1, Bt1);
+    if (ps + PS < pe) step(ps + PS, At1, Bt1, At0, Bt0);
   }
 #pragma unroll
   for (int ni = 0; ni < 4; ++ni)
