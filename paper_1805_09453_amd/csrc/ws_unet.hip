@@ -331,7 +331,7 @@ __device__ __forceinline__ s16x4 ld_tr16(const bf16* p) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256, 6) void k_wgrad(WgArgs a) {
+__global__ __launch_bounds__(256, 5) void k_wgrad(WgArgs a) {
   // Tiles of 64 pixels per step, pixel-major as in memory: At[p][m] (64 m
   // channels) and Bt[p][k] (64 k entries), 128-byte rows whose 16-byte chunks are
   // stored in the order chunk ^ 2 (p mod 4).  Both are loaded straight into LDS
