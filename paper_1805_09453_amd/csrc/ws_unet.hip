@@ -584,7 +584,19 @@ __global__ __launch_bounds__(256) void k_chsum(const bf16* __restrict__ g, int C
   const int G = C / 8, per = 256 / G;  // vectors per pixel; pixels side by side
   const int q = threadIdx.x % G, r = threadIdx.x / G;
   float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (size_t p = size_t(blockIdx.x) * per + r; p < P; p += size_t(gridDim.x) * per) {
+  // four independent 16-byte loads in flight per thread and trip
+  const size_t stride = size_t(gridDim.x) * per;
+  size_t p = size_t(blockIdx.x) * per + r;
+  for (; p + 3 * stride < P; p += 4 * stride) {
+    V8 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u].u = ld16(g + (p + u * stride) * S + 8 * q);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += b2f(v[u].h[j]);
+  }
+  for (; p < P; p += stride) {
     V8 v;
     v.u = ld16(g + p * S + 8 * q);
 #pragma unroll
@@ -886,7 +898,7 @@ int chsum(ws_net* net, hipStream_t s, const bf16* g, int C, int S, size_t P, flo
   if (C < 8 || C > 256 || (C & (C - 1)) || S % 8) return GP_EINVAL;  // the network's widths are 32 ... 256
   const int per = 256 / (C / 8);  // pixels per block and step; about 16 steps per thread
   size_t blocks = (P + per * 16 - 1) / (per * 16);
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 512) blocks = 512;  // every block adds C atomics to the same C floats
   hipLaunchKernelGGL(k_chsum, dim3(blocks ? blocks : 1), dim3(256), 0, s, g, C, S, P, out);
   WLAUNCH(net);
   return GP_OK;
