@@ -378,7 +378,8 @@ typedef struct {
 
 long long ws_param_count(void);
 /* Network on ctx's stream for batches of up to max_batch inputs of ny x nx
- * (multiples of 8, <= 4096; the native resolution).  Parameters start at 0. */
+ * (multiples of 8, <= 4096; the native resolution; max_batch * ny * nx below 2^31, else
+ * GP_EUNSUPPORTED).  Parameters start at 0. */
 int ws_create(gp_ctx* ctx, ws_net** net, int max_batch, int ny, int nx);
 int ws_destroy(ws_net* net);
 /* Copy the FP32 blob (device) in (resets the Adam state) or out. */

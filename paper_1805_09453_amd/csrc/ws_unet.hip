@@ -484,11 +484,12 @@ __global__ void k_pool(const bf16* __restrict__ x, int B, int H, int W, int C, b
 }
 
 // out[p][c] = dy[p * sdy + c] * (y[p * C + c] > 0)   (in place allowed when out == dy, sdy == C)
+// (the network's channel counts are powers of two: the vector index splits by shifts)
 __global__ void k_relu_bwd(const bf16* dy, int sdy, const bf16* __restrict__ y, size_t P, int C, bf16* out) {
-  const int cv = C / 8;
+  const int cv = C / 8, lcv = __builtin_ctz(unsigned(cv));
   GRID_STRIDE(i, P * cv) {
-    const size_t p = i / cv;
-    const int c = int(i % cv) * 8;
+    const size_t p = i >> lcv;
+    const int c = int(i & size_t(cv - 1)) * 8;
     V8 g, a, o;
     g.u = ld16(dy + p * sdy + c);
     a.u = ld16(y + p * C + c);
@@ -502,12 +503,14 @@ __global__ void k_relu_bwd(const bf16* dy, int sdy, const bf16* __restrict__ y, 
 // out = (pool^T dpool + dcat[:, off:off+C]) * (S > 0)
 __global__ void k_skip_bwd(const bf16* __restrict__ dpool, const bf16* __restrict__ dcat, int scat,
                            const bf16* __restrict__ S, int B, int H, int W, int C, bf16* __restrict__ out) {
-  const int cv = C / 8;
+  const int cv = C / 8, lcv = __builtin_ctz(unsigned(cv));  // C a power of two
   const size_t n = size_t(B) * H * W * cv;
   GRID_STRIDE(i, n) {
-    const int c = int(i % cv) * 8;
-    const size_t p = i / cv;
-    const int x = int(p % W), y = int((p / W) % H), b = int(p / (size_t(W) * H));
+    const int c = int(i & size_t(cv - 1)) * 8;
+    const size_t p = i >> lcv;
+    // pixel coordinates in 32-bit arithmetic (B H W < 2^32 for any network size)
+    const unsigned pu = unsigned(p), q = pu / unsigned(W);
+    const int x = int(pu - q * unsigned(W)), y = int(q % unsigned(H)), b = int(q / unsigned(H));
     V8 gp, gc, s, o;
     gp.u = ld16(dpool + ((size_t(b) * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
     gc.u = ld16(dcat + p * scat + c);
@@ -1087,6 +1090,10 @@ int create(ws_net** out, int max_batch, int ny, int nx, char* err, size_t errlen
   if (max_batch < 1 || ny < 8 || nx < 8 || ny % 8 || nx % 8 || ny > 4096 || nx > 4096) {
     std::snprintf(err, errlen, "network size %dx%d (batch %d) unsupported: multiples of 8 up to 4096", ny, nx,
                   max_batch);
+    return GP_EUNSUPPORTED;
+  }
+  if (size_t(max_batch) * size_t(ny) * size_t(nx) >= (size_t(1) << 31)) {  // pixel indices are 32-bit
+    std::snprintf(err, errlen, "network batch %d x %dx%d has 2^31 or more pixels", max_batch, ny, nx);
     return GP_EUNSUPPORTED;
   }
   ws_net* n = new (std::nothrow) ws_net();

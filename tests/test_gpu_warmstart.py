@@ -406,3 +406,18 @@ def test_params_file_and_train_step(gpctx, tmp_path):
         a.close()
         b.close()
         c.close()
+
+
+@pytest.mark.gpu
+def test_network_size_limits(gpctx):
+    """ws_create refuses sizes its kernels cannot index (2^31 or more pixels per batch,
+    sides not multiples of 8) before allocating anything."""
+    from paper_1805_09453_amd import GPError, WarmStart
+    from paper_1805_09453_amd._lib import GP_EUNSUPPORTED
+    announce("ws_create size limits")
+    for batch, n in ((128, 4096), (1, 100)):
+        with pytest.raises(GPError) as e:
+            WarmStart(gpctx, batch, n, n)
+        assert e.value.code == GP_EUNSUPPORTED
+    w = WarmStart(gpctx, 127, 64, 64)  # 2^19 pixels: accepted
+    w.close()
